@@ -1,0 +1,469 @@
+/*
+ * ORACLE — test infrastructure only.
+ *
+ * A plain, slow, obviously correct CPU evaluator of SPARQL basic graph
+ * patterns over an RDF triple set, and of the matrix-algebra primitives the
+ * method is built from. Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load it. It shares no code with the HIP
+ * engine and reads nothing the engine writes.
+ *
+ * Definitions followed (gSmart, arXiv 2106.14038):
+ *  - Data (Section 2.2.1): a dataset is a SET of triples <s,p,o>; the RDF
+ *    matrix A is N x N with A(s,o) carrying label p (Section 1), subjects and
+ *    objects 0-based, predicates 1-based (Section 6.2.1, encoding step).
+ *    Several labels may sit on the same (s,o) pair; each distinct triple is
+ *    one labelled nonzero.
+ *  - Query (Section 2.2.1): a basic graph pattern, i.e. a set of triple
+ *    patterns over variables and constants; its result is every assignment of
+ *    data vertices to the variables under which every pattern is a triple of
+ *    the dataset (conjunctive semantics, Section 2.2.3). Two variables may take
+ *    the same vertex (homomorphism). Output rows list the variables in
+ *    ascending query-vertex index.
+ *  - Eq. (4)/(5): y = A (x) u_p and y = A^T (x) u_p, the rows / columns of A
+ *    holding label p, with (x) the boolean semiring product.
+ *  - Eq. (14)-(16): the binding vector of y is the OR of the rows of M_xy, and
+ *    M_yz keeps label-p entries of the rows of A selected by it; the vector of
+ *    reachable z is therefore OR over selected rows i of [A(i,j) == p].
+ *  - LSpM (Section 6.2): row-wise storage with a pointer array, a value
+ *    (label) array and a column array; here the full matrix, rows sorted by
+ *    (label, column).
+ *
+ * Algorithms (plain, written from the definitions, not from the paper's
+ * parallel executor):
+ *  - or_eval: backtracking over variables in a fixed order. A variable's
+ *    candidates are the label-p neighbours of an already-bound endpoint of
+ *    its first such edge (else every vertex); every edge whose endpoints are
+ *    all bound is checked by set membership.
+ *  - or_count_acyclic: exact counting by message passing over the query
+ *    forest (parallel edges between two variables bundled into one pairwise
+ *    constraint). Unsigned 128-bit arithmetic, saturating.
+ *
+ * Parity pins for every function live in the CPU test suite (brute force,
+ * closed forms, the paper's worked examples, invariants).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct { int32_t a, p, b; } otrip;   /* (a, p, b): spo order or ops order */
+
+typedef struct {
+  int64_t n; int32_t P; int64_t m;
+  otrip *spo;      /* (s, p, o) sorted lexicographically, unique */
+  otrip *ops;      /* (o, p, s) sorted lexicographically, unique */
+} oracle_graph;
+
+static int cmp_trip(const void *x, const void *y) {
+  const otrip *u = (const otrip *)x, *v = (const otrip *)y;
+  if (u->a != v->a) return u->a < v->a ? -1 : 1;
+  if (u->p != v->p) return u->p < v->p ? -1 : 1;
+  if (u->b != v->b) return u->b < v->b ? -1 : 1;
+  return 0;
+}
+
+static int64_t sort_unique(otrip *t, int64_t m) {
+  qsort(t, (size_t)m, sizeof(otrip), cmp_trip);
+  int64_t k = 0;
+  for (int64_t i = 0; i < m; ++i)
+    if (k == 0 || cmp_trip(&t[k - 1], &t[i]) != 0) t[k++] = t[i];
+  return k;
+}
+
+/* Build the triple set. Returns NULL on bad ids (s/o outside [0,n), p outside [1,P]). */
+oracle_graph *or_graph_new(const int32_t *triples, int64_t m, int64_t n, int32_t P) {
+  if (n < 0 || P < 0 || m < 0) return NULL;
+  for (int64_t i = 0; i < m; ++i) {
+    int32_t s = triples[3 * i], p = triples[3 * i + 1], o = triples[3 * i + 2];
+    if (s < 0 || s >= n || o < 0 || o >= n || p < 1 || p > P) return NULL;
+  }
+  oracle_graph *g = (oracle_graph *)calloc(1, sizeof *g);
+  g->n = n; g->P = P;
+  g->spo = (otrip *)malloc(sizeof(otrip) * (size_t)(m ? m : 1));
+  g->ops = (otrip *)malloc(sizeof(otrip) * (size_t)(m ? m : 1));
+  for (int64_t i = 0; i < m; ++i) {
+    g->spo[i].a = triples[3 * i]; g->spo[i].p = triples[3 * i + 1]; g->spo[i].b = triples[3 * i + 2];
+    g->ops[i].a = triples[3 * i + 2]; g->ops[i].p = triples[3 * i + 1]; g->ops[i].b = triples[3 * i];
+  }
+  g->m = sort_unique(g->spo, m);
+  sort_unique(g->ops, m);
+  return g;
+}
+
+void or_graph_free(oracle_graph *g) { if (g) { free(g->spo); free(g->ops); free(g); } }
+int64_t or_graph_m(const oracle_graph *g) { return g->m; }
+
+/* first index in t[0..m) not less than (a, p, b) */
+static int64_t lower(const otrip *t, int64_t m, int32_t a, int32_t p, int32_t b) {
+  int64_t lo = 0, hi = m;
+  otrip key = {a, p, b};
+  while (lo < hi) {
+    int64_t mid = lo + (hi - lo) / 2;
+    if (cmp_trip(&t[mid], &key) < 0) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+/* Is (s, p, o) in the set? */
+static int has_triple(const oracle_graph *g, int32_t s, int32_t p, int32_t o) {
+  int64_t i = lower(g->spo, g->m, s, p, o);
+  return i < g->m && g->spo[i].a == s && g->spo[i].p == p && g->spo[i].b == o;
+}
+
+/* Neighbours of v along label p: dir 0 = objects of (v, p, *), dir 1 = subjects of (*, p, v).
+ * Returns the range [*lo, *hi) in spo (dir 0) or ops (dir 1); neighbour = .b */
+static const otrip *adj(const oracle_graph *g, int32_t v, int32_t p, int dir, int64_t *cnt) {
+  const otrip *t = dir ? g->ops : g->spo;
+  int64_t lo = lower(t, g->m, v, p, INT32_MIN), hi = lower(t, g->m, v, p + 1, INT32_MIN);
+  *cnt = hi - lo;
+  return t + lo;
+}
+
+/* ---------------------------------------------------- LSpM (Section 6.2) */
+/* Row-wise storage of the whole matrix: row_ptr[n+1], col[m], lab[m] (1-based
+ * labels), each row's entries in (label, column) order. */
+void or_csr(const oracle_graph *g, int64_t *row_ptr, int32_t *col, int32_t *lab) {
+  int64_t k = 0;
+  for (int64_t r = 0; r <= g->n; ++r) {
+    while (k < g->m && g->spo[k].a < r) ++k;
+    row_ptr[r] = k;
+  }
+  for (int64_t i = 0; i < g->m; ++i) { col[i] = g->spo[i].b; lab[i] = g->spo[i].p; }
+}
+/* Column-wise storage: col_ptr[n+1], row[m], lab[m], each column in (label, row) order. */
+void or_csc(const oracle_graph *g, int64_t *col_ptr, int32_t *row, int32_t *lab) {
+  int64_t k = 0;
+  for (int64_t c = 0; c <= g->n; ++c) {
+    while (k < g->m && g->ops[k].a < c) ++k;
+    col_ptr[c] = k;
+  }
+  for (int64_t i = 0; i < g->m; ++i) { row[i] = g->ops[i].b; lab[i] = g->ops[i].p; }
+}
+
+/* ---------------------------------------------- algebra (Section 2.1) */
+/* Eq. (4) (dir 0): y(i) = OR_j [A(i,j) == p]; Eq. (5) (dir 1): y(j) = OR_i [A(i,j) == p].
+ * Written as the definition: one pass over every nonzero. */
+void or_label_exists(const oracle_graph *g, int32_t p, int dir, uint8_t *y) {
+  memset(y, 0, (size_t)g->n);
+  for (int64_t k = 0; k < g->m; ++k)
+    if (g->spo[k].p == p) y[dir ? g->spo[k].b : g->spo[k].a] = 1;
+}
+
+/* Eq. (14)-(16): the binding vector reachable from the selected rows F along label p.
+ * dir 0: y(j) = OR_i F(i) and A(i,j) == p   (rows of diag(F) A)
+ * dir 1: y(i) = OR_j F(j) and A(i,j) == p   (columns of A diag(F)) */
+void or_frontier_domain(const oracle_graph *g, const uint8_t *F, int32_t p, int dir, uint8_t *y) {
+  memset(y, 0, (size_t)g->n);
+  for (int64_t k = 0; k < g->m; ++k) {
+    const otrip *t = &g->spo[k];
+    if (t->p != p) continue;
+    if (dir == 0 && F[t->a]) y[t->b] = 1;
+    if (dir == 1 && F[t->b]) y[t->a] = 1;
+  }
+}
+
+/* ------------------------------------------------ query normalisation */
+#define OR_MAXQV 128
+#define OR_MAXE 128
+
+typedef struct {
+  int32_t n_qv, n_edges;
+  int32_t cst[OR_MAXQV];          /* -1 variable, else constant vertex */
+  int32_t e[OR_MAXE][3];          /* (src, label, dst), duplicates removed */
+  int32_t nvar, var_of[OR_MAXQV]; /* query vertex -> variable rank (ascending index) or -1 */
+  int32_t qv_of[OR_MAXQV];        /* variable rank -> query vertex */
+} nq_t;
+
+/* Returns 0 ok, -1 malformed, -2 label or constant out of range. */
+static int normalise(const oracle_graph *g, int32_t n_qv, const int32_t *qv_const, int32_t n_edges,
+                     const int32_t *edges, nq_t *q) {
+  if (n_qv < 0 || n_qv > OR_MAXQV || n_edges < 1 || n_edges > OR_MAXE) return -1;
+  memset(q, 0, sizeof *q);
+  q->n_qv = n_qv;
+  for (int i = 0; i < n_qv; ++i) {
+    q->cst[i] = qv_const ? qv_const[i] : -1;
+    if (q->cst[i] < -1 || q->cst[i] >= g->n) return -2;
+  }
+  for (int k = 0; k < n_edges; ++k) {
+    int32_t s = edges[3 * k], p = edges[3 * k + 1], o = edges[3 * k + 2];
+    if (s < 0 || s >= n_qv || o < 0 || o >= n_qv) return -1;
+    if (p < 1 || p > g->P) return -2;
+    int dup = 0;
+    for (int j = 0; j < q->n_edges; ++j) dup |= (q->e[j][0] == s && q->e[j][1] == p && q->e[j][2] == o);
+    if (!dup) { q->e[q->n_edges][0] = s; q->e[q->n_edges][1] = p; q->e[q->n_edges][2] = o; q->n_edges++; }
+  }
+  q->nvar = 0;
+  for (int i = 0; i < n_qv; ++i) {
+    q->var_of[i] = -1;
+    if (q->cst[i] < 0) { q->var_of[i] = q->nvar; q->qv_of[q->nvar++] = i; }
+  }
+  return 0;
+}
+
+/* Edges between two constants hold? */
+static int constant_edges_hold(const oracle_graph *g, const nq_t *q) {
+  for (int k = 0; k < q->n_edges; ++k) {
+    int32_t s = q->e[k][0], o = q->e[k][2];
+    if (q->cst[s] >= 0 && q->cst[o] >= 0 && !has_triple(g, q->cst[s], q->e[k][1], q->cst[o])) return 0;
+  }
+  return 1;
+}
+
+/* ------------------------------------------------ backtracking evaluator */
+typedef struct {
+  const oracle_graph *g; const nq_t *q;
+  int32_t order[OR_MAXQV];        /* query vertices (variables) in binding order */
+  int32_t val[OR_MAXQV];          /* current value per query vertex (constants preset) */
+  uint8_t bound[OR_MAXQV];
+  int32_t restrict_qv; const uint8_t *restrict_mask;
+  int64_t count; int32_t *rows; int64_t rows_cap;
+  int64_t work, work_cap; int aborted;
+} bt_t;
+
+static int edges_hold_at(bt_t *B, int32_t x) {
+  const nq_t *q = B->q;
+  for (int k = 0; k < q->n_edges; ++k) {
+    int32_t s = q->e[k][0], o = q->e[k][2];
+    if (s != x && o != x) continue;
+    if (!B->bound[s] || !B->bound[o]) continue;
+    if (!has_triple(B->g, B->val[s], q->e[k][1], B->val[o])) return 0;
+  }
+  return 1;
+}
+
+static void emit(bt_t *B) {
+  if (B->rows && B->count < B->rows_cap) {
+    int32_t *r = B->rows + (size_t)B->count * B->q->nvar;
+    for (int v = 0; v < B->q->nvar; ++v) r[v] = B->val[B->q->qv_of[v]];
+  }
+  B->count++;
+}
+
+static void assign(bt_t *B, int i) {
+  if (B->aborted) return;
+  const nq_t *q = B->q;
+  if (i == q->nvar) { emit(B); return; }
+  int32_t x = B->order[i];
+  /* candidates: first edge of x whose other endpoint is bound (a constant or an earlier variable) */
+  int cand_k = -1, cand_dir = 0; int32_t anchor = -1;
+  for (int k = 0; k < q->n_edges && cand_k < 0; ++k) {
+    int32_t s = q->e[k][0], o = q->e[k][2];
+    if (s == x && o != x && B->bound[o]) { cand_k = k; cand_dir = 1; anchor = B->val[o]; }
+    else if (o == x && s != x && B->bound[s]) { cand_k = k; cand_dir = 0; anchor = B->val[s]; }
+  }
+  B->bound[x] = 1;
+  if (cand_k >= 0) {
+    int64_t cnt; const otrip *nb = adj(B->g, anchor, q->e[cand_k][1], cand_dir, &cnt);
+    for (int64_t t = 0; t < cnt; ++t) {
+      if (B->work_cap && ++B->work > B->work_cap) { B->aborted = 1; break; }
+      int32_t c = nb[t].b;
+      if (x == B->restrict_qv && !B->restrict_mask[c]) continue;
+      B->val[x] = c;
+      if (edges_hold_at(B, x)) assign(B, i + 1);
+    }
+  } else {
+    for (int64_t c = 0; c < B->g->n; ++c) {
+      if (B->work_cap && ++B->work > B->work_cap) { B->aborted = 1; break; }
+      if (x == B->restrict_qv && !B->restrict_mask[c]) continue;
+      B->val[x] = (int32_t)c;
+      if (edges_hold_at(B, x)) assign(B, i + 1);
+    }
+  }
+  B->bound[x] = 0;
+}
+
+/* Default order: breadth-first over the undirected query graph, starting from
+ * the lowest-index variable adjacent to a constant (else the lowest-index
+ * variable), restarting from the lowest unvisited variable for each further
+ * component. */
+static void default_order(const nq_t *q, int32_t *order) {
+  uint8_t seen[OR_MAXQV] = {0};
+  int head = 0, tail = 0;
+  int32_t start = -1;
+  for (int v = 0; v < q->n_qv && start < 0; ++v) {
+    if (q->cst[v] >= 0) continue;
+    for (int k = 0; k < q->n_edges; ++k) {
+      int32_t s = q->e[k][0], o = q->e[k][2];
+      if ((s == v && q->cst[o] >= 0) || (o == v && q->cst[s] >= 0)) { start = v; break; }
+    }
+  }
+  for (;;) {
+    if (start < 0) for (int v = 0; v < q->n_qv; ++v) if (q->cst[v] < 0 && !seen[v]) { start = v; break; }
+    if (start < 0) break;
+    seen[start] = 1; order[tail++] = start; start = -1;
+    while (head < tail) {
+      int32_t v = order[head++];
+      for (int k = 0; k < q->n_edges; ++k) {
+        int32_t s = q->e[k][0], o = q->e[k][2], w = -1;
+        if (s == v) w = o; else if (o == v) w = s;
+        if (w >= 0 && q->cst[w] < 0 && !seen[w]) { seen[w] = 1; order[tail++] = w; }
+      }
+    }
+  }
+}
+
+static int cmp_rows_k;
+static int cmp_rows(const void *x, const void *y) {
+  const int32_t *a = (const int32_t *)x, *b = (const int32_t *)y;
+  for (int i = 0; i < cmp_rows_k; ++i) if (a[i] != b[i]) return a[i] < b[i] ? -1 : 1;
+  return 0;
+}
+
+/* Evaluate a query.
+ *  order: binding order as query-vertex indices of every variable, or NULL for the default.
+ *  restrict_qv / restrict_mask: optionally keep only rows whose query vertex restrict_qv takes
+ *    a value c with restrict_mask[c] != 0 (restrict_qv < 0: no restriction).
+ *  rows: if non-NULL, up to rows_cap rows of width nvar are written, sorted lexicographically.
+ *  work_cap: 0 = unlimited; else abort after that many candidate visits (returns -4).
+ * Returns 0 ok, -1 malformed query, -2 out of range, -3 bad order, -4 aborted on work cap. */
+int or_eval(const oracle_graph *g, int32_t n_qv, const int32_t *qv_const, int32_t n_edges, const int32_t *edges,
+            const int32_t *order, int32_t restrict_qv, const uint8_t *restrict_mask,
+            int64_t *count, int32_t *rows, int64_t rows_cap, int64_t work_cap, int32_t *n_vars_out) {
+  nq_t q;
+  int rc = normalise(g, n_qv, qv_const, n_edges, edges, &q);
+  if (rc) return rc;
+  if (n_vars_out) *n_vars_out = q.nvar;
+  bt_t B; memset(&B, 0, sizeof B);
+  B.g = g; B.q = &q; B.rows = rows; B.rows_cap = rows_cap; B.work_cap = work_cap;
+  B.restrict_qv = (restrict_qv >= 0 && restrict_mask) ? restrict_qv : -1; B.restrict_mask = restrict_mask;
+  if (order) {
+    uint8_t seen[OR_MAXQV] = {0};
+    for (int i = 0; i < q.nvar; ++i) {
+      int32_t v = order[i];
+      if (v < 0 || v >= n_qv || q.cst[v] >= 0 || seen[v]) return -3;
+      seen[v] = 1; B.order[i] = v;
+    }
+  } else {
+    default_order(&q, B.order);
+  }
+  for (int v = 0; v < n_qv; ++v) if (q.cst[v] >= 0) { B.bound[v] = 1; B.val[v] = q.cst[v]; }
+  *count = 0;
+  if (!constant_edges_hold(g, &q)) return 0;
+  /* constant self-loops and constant-constant edges are covered above; variables start unbound */
+  assign(&B, 0);
+  if (B.aborted) return -4;
+  *count = B.count;
+  if (rows && q.nvar > 0) {
+    int64_t nr = B.count < rows_cap ? B.count : rows_cap;
+    cmp_rows_k = q.nvar;
+    qsort(rows, (size_t)nr, sizeof(int32_t) * q.nvar, cmp_rows);
+  }
+  return 0;
+}
+
+/* ------------------------------------------------ exact counting (acyclic) */
+typedef unsigned __int128 u128;
+#define U128_CAP (((u128)1) << 120)
+static u128 sat_add(u128 a, u128 b) { u128 s = a + b; return s > U128_CAP ? U128_CAP : s; }
+static u128 sat_mul(u128 a, u128 b) {
+  if (a == 0 || b == 0) return 0;
+  if (a > U128_CAP / b) return U128_CAP;
+  return a * b;
+}
+
+/* pair constraint between variables u and v: list of (label, dir) where dir 0 means (u, p, v), 1 means (v, p, u) */
+typedef struct { int32_t u, v, n; int32_t lab[OR_MAXE], dir[OR_MAXE]; } bundle_t;
+
+/* does value cu of u and cv of v satisfy every edge of the bundle? */
+static int bundle_holds(const oracle_graph *g, const bundle_t *b, int32_t cu, int32_t cv) {
+  for (int i = 0; i < b->n; ++i) {
+    int ok = b->dir[i] == 0 ? has_triple(g, cu, b->lab[i], cv) : has_triple(g, cv, b->lab[i], cu);
+    if (!ok) return 0;
+  }
+  return 1;
+}
+
+/* unary constraints of query vertex x: self loops and edges to constants */
+static int unary_holds(const oracle_graph *g, const nq_t *q, int32_t x, int32_t c) {
+  for (int k = 0; k < q->n_edges; ++k) {
+    int32_t s = q->e[k][0], p = q->e[k][1], o = q->e[k][2];
+    if (s == x && o == x) { if (!has_triple(g, c, p, c)) return 0; }
+    else if (s == x && q->cst[o] >= 0) { if (!has_triple(g, c, p, q->cst[o])) return 0; }
+    else if (o == x && q->cst[s] >= 0) { if (!has_triple(g, q->cst[s], p, c)) return 0; }
+  }
+  return 1;
+}
+
+typedef struct { const oracle_graph *g; const nq_t *q; bundle_t *B; int nb; uint8_t *done; } dp_t;
+
+/* message of subtree rooted at x (entered from parent bundle pb, -1 for root): msg[c] for all c */
+static u128 *dp_message(dp_t *D, int32_t x, int pb) {
+  const oracle_graph *g = D->g;
+  u128 *msg = (u128 *)malloc(sizeof(u128) * (size_t)g->n);
+  for (int64_t c = 0; c < g->n; ++c) msg[c] = unary_holds(g, D->q, x, (int32_t)c) ? 1 : 0;
+  D->done[x] = 1;
+  for (int bi = 0; bi < D->nb; ++bi) {
+    if (bi == pb) continue;
+    bundle_t *b = &D->B[bi];
+    int32_t w;
+    if (b->u == x) w = b->v; else if (b->v == x) w = b->u; else continue;
+    u128 *cm = dp_message(D, w, bi);
+    /* sum over values d of w adjacent to c through the bundle's first edge, then check the rest */
+    int x_is_u = (b->u == x);
+    for (int64_t c = 0; c < g->n; ++c) {
+      if (!msg[c]) continue;
+      /* first edge, oriented from x: dir 0 with x == u means (x, p, w): neighbours of c along out-edges */
+      int d0 = b->dir[0];
+      int out_from_x = x_is_u ? (d0 == 0) : (d0 == 1);
+      int64_t cnt; const otrip *nb = adj(g, (int32_t)c, b->lab[0], out_from_x ? 0 : 1, &cnt);
+      u128 s = 0;
+      for (int64_t t = 0; t < cnt; ++t) {
+        int32_t d = nb[t].b;
+        if (!cm[d]) continue;
+        int ok = x_is_u ? bundle_holds(g, b, (int32_t)c, d) : bundle_holds(g, b, d, (int32_t)c);
+        if (ok) s = sat_add(s, cm[d]);
+      }
+      msg[c] = sat_mul(msg[c], s);
+    }
+    free(cm);
+  }
+  return msg;
+}
+
+/* Exact count of an acyclic query (the variable graph, after bundling parallel
+ * edges, is a forest). Returns 0 ok, -1 malformed, -2 out of range, -5 cyclic.
+ * *saturated is set when the count exceeds 2^63-1 (then *count = INT64_MAX). */
+int or_count_acyclic(const oracle_graph *g, int32_t n_qv, const int32_t *qv_const, int32_t n_edges,
+                     const int32_t *edges, int64_t *count, int32_t *saturated) {
+  nq_t q;
+  int rc = normalise(g, n_qv, qv_const, n_edges, edges, &q);
+  if (rc) return rc;
+  *count = 0; if (saturated) *saturated = 0;
+  if (!constant_edges_hold(g, &q)) return 0;
+  bundle_t *B = (bundle_t *)calloc(OR_MAXE, sizeof(bundle_t));
+  int nb = 0;
+  for (int k = 0; k < q.n_edges; ++k) {
+    int32_t s = q.e[k][0], p = q.e[k][1], o = q.e[k][2];
+    if (s == o || q.cst[s] >= 0 || q.cst[o] >= 0) continue;   /* unary */
+    int found = -1;
+    for (int j = 0; j < nb; ++j)
+      if ((B[j].u == s && B[j].v == o) || (B[j].u == o && B[j].v == s)) found = j;
+    if (found < 0) { found = nb++; B[found].u = s; B[found].v = o; }
+    bundle_t *b = &B[found];
+    b->lab[b->n] = p; b->dir[b->n] = (b->u == s) ? 0 : 1; b->n++;
+  }
+  /* forest test: union-find over variables */
+  int32_t parent[OR_MAXQV];
+  for (int i = 0; i < n_qv; ++i) parent[i] = i;
+  for (int j = 0; j < nb; ++j) {
+    int32_t a = B[j].u, b = B[j].v;
+    while (parent[a] != a) a = parent[a];
+    while (parent[b] != b) b = parent[b];
+    if (a == b) { free(B); return -5; }
+    parent[a] = b;
+  }
+  uint8_t done[OR_MAXQV] = {0};
+  dp_t D = {g, &q, B, nb, done};
+  u128 total = 1;
+  for (int x = 0; x < n_qv; ++x) {
+    if (q.cst[x] >= 0 || done[x]) continue;
+    u128 *msg = dp_message(&D, x, -1);
+    u128 s = 0;
+    for (int64_t c = 0; c < g->n; ++c) s = sat_add(s, msg[c]);
+    free(msg);
+    total = sat_mul(total, s);
+  }
+  free(B);
+  if (total > (u128)INT64_MAX) { *count = INT64_MAX; if (saturated) *saturated = 1; }
+  else *count = (int64_t)total;
+  return 0;
+}

@@ -1,0 +1,77 @@
+"""Test-side helpers: a brute-force evaluator written directly from the
+definition of a basic graph pattern's result (every assignment of vertices to
+variables under which every triple pattern is in the dataset), and seeded
+random query graphs. Independent of both the oracle and the engine."""
+from __future__ import annotations
+
+import itertools
+import random
+
+import numpy as np
+
+
+def dense_tensor(triples, n, n_labels):
+    """A[p][s][o] = True iff (s, p, o) is a triple (p 1-based; index 0 unused)."""
+    A = np.zeros((n_labels + 1, n, n), dtype=bool)
+    t = np.asarray(triples, dtype=np.int64).reshape(-1, 3)
+    if len(t):
+        A[t[:, 1], t[:, 0], t[:, 2]] = True
+    return A
+
+
+def brute_force(triples, n, n_labels, q):
+    """All rows (variables in ascending query-vertex index), sorted; every assignment in [0,n)^k."""
+    A = dense_tensor(triples, n, n_labels)
+    consts = q["qv_const"]
+    var_qv = [i for i, c in enumerate(consts) if c < 0]
+    k = len(var_qv)
+    if k == 0:
+        grid = np.zeros((1, 0), dtype=np.int64)
+    else:
+        grid = np.array(list(itertools.product(range(n), repeat=k)), dtype=np.int64).reshape(-1, k)
+    ok = np.ones(len(grid), dtype=bool)
+
+    def col(v):
+        if consts[v] >= 0:
+            return np.full(len(grid), consts[v], dtype=np.int64)
+        return grid[:, var_qv.index(v)]
+
+    for (s, p, o) in q["edges"]:
+        ok &= A[p, col(s), col(o)]
+    rows = grid[ok]
+    if k == 0:
+        return np.zeros((int(ok.sum()), 0), np.int32)
+    order = np.lexsort(rows.T[::-1])
+    return rows[order].astype(np.int32)
+
+
+def random_query(rng: random.Random, n, n_labels, n_vars, n_consts=0, n_edges=None, connected=True,
+                 allow_self=True):
+    nqv = n_vars + n_consts
+    qv_const = [-1] * nqv
+    cpos = rng.sample(range(nqv), n_consts) if n_consts else []
+    for c in cpos:
+        qv_const[c] = rng.randrange(n)
+    if n_edges is None:
+        n_edges = rng.randint(max(1, nqv - 1), nqv + 2)
+    edges = []
+    verts = list(range(nqv))
+    rng.shuffle(verts)
+    if connected and nqv > 1:
+        for i in range(1, nqv):
+            a, b = verts[i], verts[rng.randrange(i)]
+            if rng.random() < 0.5:
+                a, b = b, a
+            edges.append((a, rng.randint(1, n_labels), b))
+    while len(edges) < n_edges:
+        a = rng.randrange(nqv)
+        b = rng.randrange(nqv) if allow_self or nqv == 1 else rng.choice([v for v in range(nqv) if v != a])
+        edges.append((a, rng.randint(1, n_labels), b))
+    return {"n_qv": nqv, "qv_const": qv_const, "edges": edges}
+
+
+def sort_rows(rows):
+    rows = np.asarray(rows, dtype=np.int64)
+    if rows.ndim == 1 or rows.shape[1] == 0 or len(rows) == 0:
+        return rows.astype(np.int32)
+    return rows[np.lexsort(rows.T[::-1])].astype(np.int32)

@@ -1,0 +1,136 @@
+"""Seeded synthetic inputs: RDF graphs, query graphs and arrival traces.
+
+Shared by the engine's tests and benchmark and by the oracle's tests. The
+module only draws inputs (Philox4x32-10 counter streams, see ``gen.c``); it
+evaluates no query.
+
+Queries are plain dicts, the Python form of ``gs_query``::
+
+    {"n_qv": 4, "qv_const": [-1, -1, 7, -1], "edges": [(0, 3, 1), (1, 2, 2), ...]}
+
+``qv_const[i] == -1`` marks a variable, any other value is a constant vertex
+id. Edges are (src, label, dst) over query-vertex indices, labels 1-based.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "libgswork.so")
+_lib = None
+
+SHAPES = {"chain4": 0, "star5": 1, "snowflake8": 2, "triangle": 3, "c0star": 4, "mixed": 5}
+
+
+def build() -> str:
+    """Compile gen.c into libgswork.so (gcc, OpenMP)."""
+    src = os.path.join(_HERE, "gen.c")
+    cmd = ["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c11", "-Wall", "-Wno-unused-function",
+           "-o", _SO + ".tmp", src, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(_SO + ".tmp", _SO)
+    return _SO
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_SO):
+        build()
+    lib = ctypes.CDLL(_SO)
+    i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+    u32p = np.ctypeslib.ndpointer(np.uint32, flags="C_CONTIGUOUS")
+    f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+    lib.gsw_philox4x32_10.argtypes = [u32p, u32p, u32p]
+    lib.gsw_uniform_graph.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64, i32p]
+    lib.gsw_uniform_graph.restype = ctypes.c_int
+    lib.gsw_chunglu_graph.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64,
+                                      ctypes.c_double, ctypes.c_double, ctypes.c_int32, i32p]
+    lib.gsw_chunglu_graph.restype = ctypes.c_int
+    lib.gsw_query_record_words.restype = ctypes.c_int
+    lib.gsw_walk_queries.argtypes = [i32p, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64, ctypes.c_int32,
+                                     ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, i32p]
+    lib.gsw_walk_queries.restype = ctypes.c_int
+    lib.gsw_poisson_arrivals.argtypes = [ctypes.c_uint64, ctypes.c_double, ctypes.c_double, ctypes.c_int64, f64p]
+    lib.gsw_poisson_arrivals.restype = ctypes.c_int64
+    _lib = lib
+    return lib
+
+
+def philox4x32_10(counter, key) -> np.ndarray:
+    out = np.zeros(4, np.uint32)
+    _load().gsw_philox4x32_10(np.asarray(counter, np.uint32), np.asarray(key, np.uint32), out)
+    return out
+
+
+def uniform_graph(seed: int, n: int, n_labels: int, m: int) -> np.ndarray:
+    """m distinct triples, s/o uniform over [0,n), p uniform over [1,n_labels]; (m,3) int32."""
+    out = np.empty((m, 3), np.int32)
+    rc = _load().gsw_uniform_graph(seed, n, n_labels, m, out)
+    if rc != 0:
+        raise ValueError(f"gsw_uniform_graph failed ({rc})")
+    return out
+
+
+def chunglu_graph(seed: int, n: int, n_labels: int, m: int, beta: float = 2.1, zipf_s: float = 1.1,
+                  domain_mod: int = 5) -> np.ndarray:
+    """m distinct Chung-Lu triples with Zipf labels and typed object domains; (m,3) int32."""
+    out = np.empty((m, 3), np.int32)
+    rc = _load().gsw_chunglu_graph(seed, n, n_labels, m, beta, zipf_s, domain_mod, out)
+    if rc != 0:
+        raise ValueError(f"gsw_chunglu_graph failed ({rc})")
+    return out
+
+
+def _decode(rec: np.ndarray) -> dict:
+    maxqv = 16
+    nqv, ne = int(rec[0]), int(rec[1])
+    consts = [int(x) for x in rec[2:2 + nqv]]
+    e = rec[2 + maxqv:2 + maxqv + 3 * ne].reshape(ne, 3)
+    return {"n_qv": nqv, "qv_const": consts, "edges": [tuple(int(v) for v in row) for row in e]}
+
+
+def walk_queries(triples: np.ndarray, n: int, seed: int, shape: str, nq: int, const_prob: float = 0.5,
+                 first: int = 0, max_consts: int = 2) -> list:
+    """nq query graphs of the given shape from seeded walks (candidates first .. first+nq-1)."""
+    lib = _load()
+    w = lib.gsw_query_record_words()
+    out = np.zeros(max(nq, 1) * w, np.int32)
+    t = np.ascontiguousarray(triples, dtype=np.int32).reshape(-1)
+    got = lib.gsw_walk_queries(t, len(triples), n, seed, SHAPES[shape], first, nq, const_prob, max_consts, out)
+    if got < 0:
+        raise ValueError(f"gsw_walk_queries failed ({got})")
+    return [_decode(out[i * w:(i + 1) * w]) for i in range(got)]
+
+
+def c0_star_query(triples: np.ndarray, n: int, seed: int = 0) -> dict:
+    """The 3-edge star (?x,p1,?a),(?x,p2,?b),(?x,p3,c) with c a constant, from a seeded walk."""
+    return walk_queries(triples, n, seed, "c0star", 1)[0]
+
+
+def poisson_arrivals(seed: int, rate: float, duration: float) -> np.ndarray:
+    cap = int(rate * duration * 2 + 1000)
+    out = np.zeros(cap, np.float64)
+    k = _load().gsw_poisson_arrivals(seed, rate, duration, cap, out)
+    return out[:k].copy()
+
+
+# Workload recipes (sizes of the configurations the tests and the benchmark use).
+C0 = dict(seed=0, n=10_000, n_labels=16, m=100_000)
+C1 = dict(seed=1, n=10_000_000, n_labels=256, m=100_000_000, beta=2.1, zipf_s=1.1, domain_mod=5)
+
+
+def c0_graph() -> np.ndarray:
+    return uniform_graph(C0["seed"], C0["n"], C0["n_labels"], C0["m"])
+
+
+def c1_graph(scale: float = 1.0) -> np.ndarray:
+    """The power-law graph; `scale` < 1 shrinks n and m together (tests)."""
+    n = max(16, int(C1["n"] * scale))
+    m = max(16, int(C1["m"] * scale))
+    return chunglu_graph(C1["seed"], n, C1["n_labels"], m, C1["beta"], C1["zipf_s"], C1["domain_mod"])
