@@ -1,0 +1,279 @@
+/*
+ * gsmart.h — C ABI of an MI355X engine for SPARQL basic graph patterns by
+ * grouped incident-edge evaluation over a label-carrying sparse RDF matrix
+ * (after gSmart, arXiv 2106.14038).
+ *
+ * Problem statement followed (paper Sections 1, 2.2 and 6.2):
+ *  - An RDF dataset is a SET of triples <s,p,o> (Section 2.2.1). It is held as
+ *    an N x N sparse matrix A whose nonzero (s,o) carries the label p
+ *    (Section 1); subjects and objects are 0-based vertex ids, predicates are
+ *    1-based (Section 6.2.1, encoding step). Several labels may sit on one
+ *    (s,o) pair: every distinct triple is one labelled nonzero.
+ *  - A query is a basic graph pattern given as a query graph (Section 2.2.1):
+ *    query vertices are variables or constants, every edge (src, label, dst)
+ *    is a triple pattern. Its result is every assignment of data vertices to
+ *    the variables under which every pattern is a triple of the dataset
+ *    (conjunctive semantics, Section 2.2.3); two variables may take the same
+ *    vertex. A result row lists the variables in ascending query-vertex index.
+ *  - The engine evaluates the query vertices in the order of the degree-driven
+ *    traversal (Section 6.1.2), all unevaluated incident edges of a vertex
+ *    together (Section 5, Eq. 17-24), storing bindings in a tree whose level j
+ *    holds the bindings of the j-th vertex (Section 7.1).
+ *
+ * Conventions for every call:
+ *  - Every call returns gs_status; GS_OK == 0. No C++ exception crosses the
+ *    ABI. On failure gs_last_error() returns a message for the calling thread.
+ *  - The caller owns every input buffer; inputs are copied or consumed before
+ *    the call returns. Pointers to device memory are accepted where a
+ *    mem_kind argument says GS_MEM_DEVICE.
+ *  - The library owns engines, results and servers until the matching
+ *    destroy/free/stop call. A gs_engine is not re-entrant: calls on one
+ *    engine must not overlap, except the gs_server_* calls, which lock.
+ *  - Work runs on the stream given in gs_options (NULL: the library's own).
+ *    Calls that return host data synchronise that stream.
+ */
+#ifndef GSMART_H
+#define GSMART_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GS_OK = 0,
+  GS_EINVAL = 1,        /* malformed argument: NULL pointer, bad endpoint, no edges */
+  GS_ERANGE = 2,        /* id out of range: s/o outside [0,N), p outside [1,P], N > 2^31-1 */
+  GS_ENOMEM = 3,        /* device or host memory exhausted (one query exceeds the budget) */
+  GS_EDEVICE = 4,       /* HIP runtime error or no usable device */
+  GS_ESTATE = 5,        /* call out of order: second load, query before load, server stopped */
+  GS_EUNSUPPORTED = 6,  /* outside the supported subset (more than 64 edges or 64 variables,
+                           rows requested from a count-only result) */
+  GS_EAGAIN = 7         /* result not ready yet (gs_poll) */
+} gs_status;
+
+typedef struct gs_engine gs_engine;   /* owns the device-resident matrix (both orientations) */
+typedef struct gs_result gs_result;   /* owns one query's binding tree and counters */
+typedef struct gs_server gs_server;   /* a continuous-batching request loop on one engine */
+
+/* One triple <s,p,o>: s, o in [0, N); p in [1, P]. */
+typedef struct { int32_t s, p, o; } gs_triple;
+
+/* One query edge (triple pattern): src and dst are query-vertex indices,
+ * label is a predicate id in [1, P]. Predicate variables are not supported. */
+typedef struct { int32_t src, label, dst; } gs_edge;
+
+/* A query graph. qv_const[i] == -1 makes query vertex i a variable, any value
+ * in [0, N) makes it that constant vertex. 1..64 edges, at most 64 variables.
+ * Duplicate edges are ignored (a pattern set). */
+typedef struct {
+  int32_t n_qv;
+  const int32_t *qv_const;   /* length n_qv */
+  int32_t n_edges;
+  const gs_edge *edges;      /* length n_edges */
+} gs_query;
+
+enum { GS_MEM_HOST = 0, GS_MEM_DEVICE = 1 };
+
+/* Query flags (gs_query_run, gs_batch_run, gs_submit). */
+enum {
+  GS_COUNT_ONLY = 1u,        /* do not store the last tree level: count only, no rows */
+  GS_PRUNE = 2u              /* after the last level, prune the tree to nodes with a
+                                surviving leaf below them (Section 7.2.2 / 8.1) */
+};
+
+/* Frontier-domain mode for edges that close a cycle to already-bound vertices
+ * (Eq. 14-16): the vertices reachable from the distinct bindings of the bound
+ * end. GS_DOMAIN_AUTO picks per edge between push (sparse-frontier product)
+ * and pull (masked product) by estimated work; the other modes force one side,
+ * or skip the domain and rely on the exact per-binding check alone. All modes
+ * give identical results. */
+enum { GS_DOMAIN_AUTO = 0, GS_DOMAIN_PUSH = 1, GS_DOMAIN_PULL = 2, GS_DOMAIN_OFF = 3 };
+
+typedef struct {
+  int device;                 /* HIP device ordinal */
+  void *hip_stream;           /* hipStream_t to run on; NULL = a stream the engine creates */
+  uint64_t tree_bytes;        /* device arena for binding trees; 0 = default (1/4 of free memory) */
+  uint64_t scratch_bytes;     /* device arena for per-step temporaries; 0 = default (1/16 of free) */
+  /* optional allocator for every device allocation the engine makes (e.g. a
+     framework's caching allocator); both NULL = hipMalloc / hipFree */
+  void *(*alloc)(void *ctx, size_t bytes);
+  void (*free)(void *ctx, void *ptr);
+  void *alloc_ctx;
+  int32_t domain_mode;        /* GS_DOMAIN_* */
+  float push_pull_theta;      /* push when est. push work < theta * est. pull work; 0 = 1.0 */
+  int32_t grid_blocks;        /* workgroups of the fixed-grid kernels; 0 = 8 per compute unit */
+  int32_t use_graphs;         /* batched form: capture each step's launches in a hipGraph (1) or not (0) */
+} gs_options;
+
+/* Per-query counters, filled by gs_result_stats. T counts LSpM nonzeros read
+ * by the kernels ("traversed triples"); bytes are algorithmic bytes. */
+typedef struct {
+  int64_t count;              /* number of result rows */
+  int32_t n_levels;           /* tree levels (= variables) */
+  int32_t n_domains;          /* cycle-closing edges given a frontier domain */
+  int64_t level_nodes[64];    /* nodes per tree level before pruning */
+  int64_t t_expand;           /* candidate entries read while growing the tree */
+  int64_t t_seed;             /* entries read to seed constant filters */
+  int64_t t_push;             /* entries read by push domain products */
+  int64_t t_pull;             /* entries read by pull domain products */
+  int64_t t_probe;            /* entries touched by binary-search membership checks */
+  int64_t t_total;            /* sum of the above */
+  int64_t bytes_alg;          /* algorithmic HBM bytes of the evaluation */
+  int32_t domain_push;        /* domains evaluated by push */
+  int32_t domain_pull;        /* domains evaluated by pull */
+  double gpu_ms;              /* device time of the evaluation (events around its launches) */
+} gs_query_stats;
+
+/* ---- engine ---------------------------------------------------------------- */
+
+/* Create an engine on options->device (NULL options: defaults, device 0).
+ * Allocates the two device arenas. Errors: GS_EDEVICE, GS_ENOMEM, GS_EINVAL. */
+gs_status gs_engine_create(const gs_options *options, gs_engine **out);
+
+/* Release every device allocation and the engine. NULL is ignored. Results
+ * created by the engine must be freed before. */
+void gs_engine_destroy(gs_engine *engine);
+
+/* Load the dataset: m triples (host or device memory per mem_kind), n vertices,
+ * n_labels predicates. Builds the light-weight sparse matrix of Section 6.2 in
+ * both orientations on the device — row-wise (pointer, column, label arrays;
+ * each row sorted by (label, column)) and column-wise (pointer, row, label
+ * arrays; each column sorted by (label, row)) — after removing duplicate
+ * triples (a dataset is a set), plus the label-existence vectors of Eq. (4)
+ * and (5) for every label. Only once per engine (GS_ESTATE otherwise).
+ * Errors: GS_ERANGE (ids), GS_EINVAL, GS_ENOMEM, GS_EDEVICE. */
+gs_status gs_load_triples(gs_engine *engine, int64_t n_vertices, int32_t n_labels,
+                          const gs_triple *triples, int64_t m, int mem_kind);
+
+/* Sizes after loading: vertices, labels, distinct triples, device bytes held. */
+gs_status gs_graph_info(const gs_engine *engine, int64_t *n, int32_t *n_labels, int64_t *m_distinct,
+                        uint64_t *device_bytes);
+
+/* Copy one orientation of the stored matrix to host buffers: orientation 0 =
+ * row-wise (ptr[n+1], idx = column of each nonzero, label), 1 = column-wise
+ * (ptr[n+1], idx = row, label). Labels come back 1-based. Buffers sized n+1
+ * and m_distinct. Section 6.2. */
+gs_status gs_lspm_export(gs_engine *engine, int orientation, int64_t *ptr, int32_t *idx, int32_t *label);
+
+/* Per-label statistics: nonzeros, rows holding the label, columns holding it.
+ * Each array has n_labels entries (index p-1). */
+gs_status gs_label_stats(gs_engine *engine, int64_t *nnz, int64_t *rows, int64_t *cols);
+
+/* ---- matrix-algebra primitives (Section 2.1) --------------------------------- */
+
+/* Eq. (4) (direction 0) or Eq. (5) (direction 1): bit i of the result is set
+ * iff row (column) i of A holds label p. Bitmap of ceil(n/64) 64-bit words,
+ * bit i = word i/64, bit i%64; written to host_words. */
+gs_status gs_label_exists(gs_engine *engine, int32_t label, int direction, uint64_t *host_words);
+
+/* Eq. (14)-(16) / (22): the vertices reachable from the frontier F along
+ * label p — direction 0: objects of (b,p,*) for b in F (rows of diag(F) A);
+ * direction 1: subjects of (*,p,b) (columns of A diag(F)). mode is
+ * GS_DOMAIN_PUSH or GS_DOMAIN_PULL; with pull, only candidates in mask are
+ * tested (mask NULL = all vertices) and the result is restricted to mask.
+ * Bitmaps as in gs_label_exists, host memory. */
+gs_status gs_frontier_domain(gs_engine *engine, const uint64_t *frontier_words, int32_t label,
+                             int direction, int mode, const uint64_t *mask_words, uint64_t *out_words);
+
+/* Eq. (10) with compaction: the ascending ids of the bits set in every one of
+ * the k host bitmaps. out (capacity n ids) receives *count ids. */
+gs_status gs_bitmap_and_compact(gs_engine *engine, const uint64_t *const *bitmaps, int32_t k, int32_t *out,
+                                int64_t *count);
+
+/* ---- planner (Section 6.1.2, host only, no device needed) -------------------- */
+
+typedef struct {
+  int32_t n_vars;             /* variables (tree levels) */
+  int32_t order[64];          /* query vertices in binding order (tree level j -> query vertex) */
+  int32_t parent_edge[64];    /* per level: index of the edge that generates its candidates,
+                                 -1 = none (a new component: candidates independent of level j-1) */
+  int32_t n_groups;           /* edge groups, one per popped vertex that evaluated edges */
+  int32_t group_vertex[64];   /* popped query vertex of each group */
+  int32_t edge_group[64];     /* per input edge: group that evaluates it, -1 = duplicate edge */
+  int32_t n_roots;            /* traversal roots (Section 6.1, step 2) */
+  int32_t roots[64];
+} gs_plan_info;
+
+/* Degree-driven traversal with the constants rule (Section 6.1.2): the order in
+ * which query vertices are visited and their incident edges evaluated.
+ * Errors: GS_EINVAL, GS_EUNSUPPORTED. */
+gs_status gs_plan_query(const gs_query *query, gs_plan_info *out);
+
+/* ---- plain and batched evaluation ------------------------------------------- */
+
+/* Evaluate one query (one at a time). *out receives a result to be freed with
+ * gs_result_free. Errors: GS_ESTATE (no data), GS_EINVAL, GS_ERANGE,
+ * GS_EUNSUPPORTED, GS_ENOMEM (tree exceeds the arena). */
+gs_status gs_query_run(gs_engine *engine, const gs_query *query, uint32_t flags, gs_result **out);
+
+/* Evaluate nq queries together: each vertex step of every query runs in the
+ * same launches (one launch sequence per step for the whole batch). outs[i]
+ * receives query i's result; results are identical to gs_query_run's. On
+ * error no result is returned (all outs[i] = NULL). */
+gs_status gs_batch_run(gs_engine *engine, const gs_query *queries, int32_t nq, uint32_t flags,
+                       gs_result **outs);
+
+/* Number of result rows (bindings). */
+gs_status gs_result_count(const gs_result *result, int64_t *count);
+
+/* Row width: number of variables of the query. */
+gs_status gs_result_width(const gs_result *result, int32_t *n_vars);
+
+/* Copy rows [first, first+n) to dst (host or device per mem_kind), each row
+ * n_vars int32 in ascending query-vertex order of the variables. Row order is
+ * unspecified but fixed for one result. *n_written = rows copied.
+ * Errors: GS_EUNSUPPORTED for count-only results, GS_ERANGE for first > count. */
+gs_status gs_result_rows(gs_result *result, int64_t first, int64_t n, void *dst, int mem_kind,
+                         int64_t *n_written);
+
+/* Counters of the evaluation (size = sizeof(gs_query_stats)). */
+gs_status gs_result_stats(const gs_result *result, gs_query_stats *stats);
+
+/* Copy tree level j to host: parent index into level j-1 (0 at level 0) and
+ * the bound vertex of level j's query vertex; *n = nodes. With par/vid NULL
+ * only *n is returned. Section 7.1. */
+gs_status gs_result_level(gs_result *result, int32_t level, int32_t *par, int32_t *vid, int64_t *n);
+
+/* Free a result. NULL is ignored. */
+void gs_result_free(gs_result *result);
+
+/* ---- served form -------------------------------------------------------------- */
+
+typedef struct {
+  int32_t max_active;         /* queries evaluated together at most; 0 = 1024 */
+  uint64_t tree_budget_bytes; /* admit while the sum of estimated tree bytes fits; 0 = arena size */
+  uint32_t flags;             /* GS_COUNT_ONLY applies to every request when set */
+} gs_server_options;
+
+typedef struct {
+  int64_t submitted, completed, iterations;
+  int64_t max_active_seen;
+  int64_t rejected;           /* requests failed with an error (e.g. GS_ENOMEM) */
+  int64_t requeued;           /* requests re-run after an arena overflow */
+} gs_server_stats;
+
+/* Start the request loop on its own host thread. The engine must be loaded and
+ * must not be used directly until gs_server_stop. */
+gs_status gs_server_start(gs_engine *engine, const gs_server_options *options, gs_server **out);
+
+/* Enqueue a request; *ticket identifies it. Thread-safe. */
+gs_status gs_submit(gs_server *server, const gs_query *query, uint32_t flags, uint64_t *ticket);
+
+/* GS_EAGAIN while the request is pending; GS_OK with *out (caller frees) when
+ * done, or the request's own error status. Each ticket is returned once. */
+gs_status gs_poll(gs_server *server, uint64_t ticket, gs_result **out);
+
+/* Wait until every submitted request is done, then stop the loop. Results not
+ * polled yet are freed. */
+gs_status gs_server_stop(gs_server *server, gs_server_stats *stats);
+
+/* Thread-local message of the last failing call ("" if none). */
+const char *gs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GSMART_H */

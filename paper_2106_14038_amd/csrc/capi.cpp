@@ -1,0 +1,384 @@
+// The C ABI (include/gsmart.h) over the host engine.
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "engine.hpp"
+#include "gsmart.h"
+#include "query.hpp"
+
+namespace gs {
+const char *last_error();
+int server_start(Engine *E, const gs_server_options *o, gs_server **out);
+int server_submit(gs_server *S, const gs_query *q, uint32_t flags, uint64_t *ticket);
+int server_poll(gs_server *S, uint64_t ticket, gs_result **out);
+int server_stop(gs_server *S, gs_server_stats *st);
+}  // namespace gs
+
+using namespace gs;
+
+struct gs_engine { Engine e; };
+
+
+#define HIPRET(expr)                                                                 \
+  do {                                                                               \
+    hipError_t _e = (expr);                                                          \
+    if (_e != hipSuccess) {                                                          \
+      set_error(std::string("HIP error: ") + hipGetErrorString(_e));                 \
+      return GS_EDEVICE;                                                             \
+    }                                                                                \
+  } while (0)
+
+namespace {
+
+// Temporary device buffers released on scope exit.
+struct Temps {
+  Engine &E;
+  std::vector<void *> v;
+  explicit Temps(Engine &e) : E(e) {}
+  void *get(size_t bytes) { void *p = E.dmalloc(bytes); v.push_back(p); return p; }
+  bool ok() const { for (void *p : v) if (!p) return false; return true; }
+  ~Temps() { for (void *p : v) E.dfree(p); }
+};
+
+gs_result *wrap(Result *r) {
+  // gs_result is an opaque handle for a Result
+  return reinterpret_cast<gs_result *>(r);
+}
+Result *unwrap(gs_result *r) { return reinterpret_cast<Result *>(r); }
+const Result *unwrap(const gs_result *r) { return reinterpret_cast<const Result *>(r); }
+
+}  // namespace
+
+extern "C" {
+
+const char *gs_last_error(void) { return gs::last_error(); }
+
+gs_status gs_engine_create(const gs_options *options, gs_engine **out) {
+  if (!out) { set_error("null output"); return GS_EINVAL; }
+  *out = nullptr;
+  gs_options o{};
+  if (options) o = *options;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) { set_error("no HIP device"); return GS_EDEVICE; }
+  if (o.device < 0 || o.device >= ndev) { set_error("device ordinal out of range"); return GS_EINVAL; }
+  gs_engine *ge = new (std::nothrow) gs_engine();
+  if (!ge) return GS_ENOMEM;
+  Engine &E = ge->e;
+  E.opt = o;
+  E.device = o.device;
+  if (hipSetDevice(E.device) != hipSuccess) { delete ge; set_error("hipSetDevice failed"); return GS_EDEVICE; }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, E.device) == hipSuccess) E.cus = prop.multiProcessorCount;
+  E.grid = o.grid_blocks > 0 ? o.grid_blocks : 8 * E.cus;
+  if (E.grid > 8192) E.grid = 8192;
+  if (o.hip_stream) {
+    E.stream = (hipStream_t)o.hip_stream;
+  } else {
+    if (hipStreamCreateWithFlags(&E.stream, hipStreamNonBlocking) != hipSuccess) {
+      delete ge; set_error("stream creation failed"); return GS_EDEVICE;
+    }
+    E.own_stream = true;
+  }
+  size_t free_b = 0, total_b = 0;
+  (void)hipMemGetInfo(&free_b, &total_b);
+  uint64_t tree = o.tree_bytes ? o.tree_bytes : std::min<uint64_t>(64ull << 30, free_b / 4);
+  uint64_t scratch = o.scratch_bytes ? o.scratch_bytes : std::min<uint64_t>(16ull << 30, free_b / 16);
+  tree = std::max<uint64_t>(tree, 1 << 20);
+  scratch = std::max<uint64_t>(scratch, 1 << 20);
+  E.tree_base = (char *)E.dmalloc(tree);
+  E.scratch_base = (char *)E.dmalloc(scratch);
+  E.d_arenas = (DArena *)E.dmalloc(sizeof(DArena) * 2);
+  if (!E.tree_base || !E.scratch_base || !E.d_arenas) {
+    delete ge; set_error("cannot allocate the device arenas"); return GS_ENOMEM;
+  }
+  E.tree_cap = tree;
+  E.scratch_cap = scratch;
+  *out = ge;
+  return GS_OK;
+}
+
+void gs_engine_destroy(gs_engine *engine) { delete engine; }
+
+gs_status gs_load_triples(gs_engine *engine, int64_t n_vertices, int32_t n_labels, const gs_triple *triples,
+                          int64_t m, int mem_kind) {
+  if (!engine) { set_error("null engine"); return GS_EINVAL; }
+  if (mem_kind != GS_MEM_HOST && mem_kind != GS_MEM_DEVICE) { set_error("bad mem_kind"); return GS_EINVAL; }
+  std::lock_guard<std::mutex> lk(engine->e.mu);
+  return (gs_status)load_triples(engine->e, n_vertices, n_labels, triples, m, mem_kind);
+}
+
+gs_status gs_graph_info(const gs_engine *engine, int64_t *n, int32_t *n_labels, int64_t *m_distinct,
+                        uint64_t *device_bytes) {
+  if (!engine) { set_error("null engine"); return GS_EINVAL; }
+  const Engine &E = engine->e;
+  if (!E.loaded) { set_error("no dataset loaded"); return GS_ESTATE; }
+  if (n) *n = E.g.n;
+  if (n_labels) *n_labels = E.g.P;
+  if (m_distinct) *m_distinct = E.g.m;
+  if (device_bytes) *device_bytes = E.graph_bytes;
+  return GS_OK;
+}
+
+gs_status gs_lspm_export(gs_engine *engine, int orientation, int64_t *ptr, int32_t *idx, int32_t *label) {
+  if (!engine || orientation < 0 || orientation > 1) { set_error("bad argument"); return GS_EINVAL; }
+  Engine &E = engine->e;
+  if (!E.loaded) { set_error("no dataset loaded"); return GS_ESTATE; }
+  HIPRET(hipSetDevice(E.device));
+  if (ptr) HIPRET(hipMemcpy(ptr, E.d_ptr[orientation], sizeof(int64_t) * (E.g.n + 1), hipMemcpyDeviceToHost));
+  if (idx && E.g.m) HIPRET(hipMemcpy(idx, E.d_idx[orientation], sizeof(int32_t) * E.g.m, hipMemcpyDeviceToHost));
+  if (label && E.g.m) {
+    std::vector<uint16_t> l(E.g.m);
+    HIPRET(hipMemcpy(l.data(), E.d_lab[orientation], sizeof(uint16_t) * E.g.m, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < E.g.m; ++i) label[i] = (int32_t)l[i] + 1;
+  }
+  return GS_OK;
+}
+
+gs_status gs_label_stats(gs_engine *engine, int64_t *nnz, int64_t *rows, int64_t *cols) {
+  if (!engine) { set_error("null engine"); return GS_EINVAL; }
+  Engine &E = engine->e;
+  if (!E.loaded) { set_error("no dataset loaded"); return GS_ESTATE; }
+  const size_t P = E.stats.nnz.size();
+  if (nnz) memcpy(nnz, E.stats.nnz.data(), 8 * P);
+  if (rows) memcpy(rows, E.stats.rows.data(), 8 * P);
+  if (cols) memcpy(cols, E.stats.cols.data(), 8 * P);
+  return GS_OK;
+}
+
+gs_status gs_label_exists(gs_engine *engine, int32_t label, int direction, uint64_t *host_words) {
+  if (!engine || !host_words || direction < 0 || direction > 1) { set_error("bad argument"); return GS_EINVAL; }
+  Engine &E = engine->e;
+  if (!E.loaded) { set_error("no dataset loaded"); return GS_ESTATE; }
+  if (label < 1 || label > E.g.P) { set_error("label out of range"); return GS_ERANGE; }
+  HIPRET(hipSetDevice(E.device));
+  HIPRET(hipMemcpy(host_words, E.g.bm[direction] + (int64_t)(label - 1) * E.g.words, 8 * E.g.words,
+                   hipMemcpyDeviceToHost));
+  return GS_OK;
+}
+
+gs_status gs_frontier_domain(gs_engine *engine, const uint64_t *frontier_words, int32_t label, int direction,
+                             int mode, const uint64_t *mask_words, uint64_t *out_words) {
+  if (!engine || !frontier_words || !out_words || direction < 0 || direction > 1 ||
+      (mode != GS_DOMAIN_PUSH && mode != GS_DOMAIN_PULL)) { set_error("bad argument"); return GS_EINVAL; }
+  Engine &E = engine->e;
+  if (!E.loaded) { set_error("no dataset loaded"); return GS_ESTATE; }
+  if (label < 1 || label > E.g.P) { set_error("label out of range"); return GS_ERANGE; }
+  std::lock_guard<std::mutex> lk(E.mu);
+  HIPRET(hipSetDevice(E.device));
+  hipStream_t s = E.stream;
+  const size_t wb = 8 * (size_t)E.g.words;
+  Temps T(E);
+  uint64_t *F = (uint64_t *)T.get(wb), *D = (uint64_t *)T.get(wb), *M = (uint64_t *)T.get(wb);
+  DDomain *dm = (DDomain *)T.get(sizeof(DDomain));
+  const uint64_t **ft = (const uint64_t **)T.get(sizeof(void *));
+  IterScalars *it = (IterScalars *)T.get(sizeof(IterScalars));
+  int64_t *qs = (int64_t *)T.get(8 * QS_N), *fc = (int64_t *)T.get(8);
+  if (!T.ok()) { set_error("out of device memory"); return GS_ENOMEM; }
+  HIPRET(hipMemcpyAsync(F, frontier_words, wb, hipMemcpyHostToDevice, s));
+  HIPRET(hipMemsetAsync(D, 0, wb, s));
+  HIPRET(hipMemsetAsync(it, 0, sizeof(IterScalars), s));
+  HIPRET(hipMemsetAsync(qs, 0, 8 * QS_N, s));
+  HIPRET(hipMemsetAsync(fc, 0, 8, s));
+  DDomain h{};
+  h.F = F; h.D = D; h.label = label - 1; h.dir = direction; h.mode = mode == GS_DOMAIN_PUSH ? 1 : 2;
+  h.filt0 = 0; h.nfilt = 0; h.q = 0; h.theta = 1.0f;
+  if (mask_words) {
+    HIPRET(hipMemcpyAsync(M, mask_words, wb, hipMemcpyHostToDevice, s));
+    const uint64_t *mp = M;
+    HIPRET(hipMemcpyAsync(ft, &mp, sizeof(void *), hipMemcpyHostToDevice, s));
+    h.nfilt = 1;
+  }
+  HIPRET(hipMemcpyAsync(dm, &h, sizeof h, hipMemcpyHostToDevice, s));
+  IterArgs A{};
+  A.g = E.g; A.D = 1; A.doms = dm; A.fcount = fc; A.filt = ft; A.it = it; A.qstats = qs; A.grid = E.grid;
+  HIPRET(launch_domain_only(A, s));
+  HIPRET(hipMemcpyAsync(out_words, D, wb, hipMemcpyDeviceToHost, s));
+  HIPRET(hipStreamSynchronize(s));
+  return GS_OK;
+}
+
+gs_status gs_bitmap_and_compact(gs_engine *engine, const uint64_t *const *bitmaps, int32_t k, int32_t *out,
+                                int64_t *count) {
+  if (!engine || k < 0 || (k > 0 && !bitmaps) || !count) { set_error("bad argument"); return GS_EINVAL; }
+  Engine &E = engine->e;
+  if (!E.loaded) { set_error("no dataset loaded"); return GS_ESTATE; }
+  std::lock_guard<std::mutex> lk(E.mu);
+  HIPRET(hipSetDevice(E.device));
+  hipStream_t s = E.stream;
+  const size_t wb = 8 * (size_t)E.g.words;
+  Temps T(E);
+  std::vector<const uint64_t *> dptr(std::max(k, 1));
+  for (int i = 0; i < k; ++i) dptr[i] = (const uint64_t *)T.get(wb);
+  const uint64_t **ft = (const uint64_t **)T.get(sizeof(void *) * std::max(k, 1));
+  DStep *st = (DStep *)T.get(sizeof(DStep));
+  DEntry *en = (DEntry *)T.get(sizeof(DEntry));
+  EState *es = (EState *)T.get(sizeof(EState));
+  IterScalars *it = (IterScalars *)T.get(sizeof(IterScalars));
+  int32_t **lp = (int32_t **)T.get(sizeof(void *) * kMaxLevels);
+  int64_t *ln = (int64_t *)T.get(8 * kMaxLevels);
+  int64_t *blk = (int64_t *)T.get(8 * 4 * (size_t)E.grid);
+  int64_t *qs = (int64_t *)T.get(8 * QS_N);
+  if (!T.ok()) { set_error("out of device memory"); return GS_ENOMEM; }
+  for (int i = 0; i < k; ++i) HIPRET(hipMemcpyAsync((void *)dptr[i], bitmaps[i], wb, hipMemcpyHostToDevice, s));
+  HIPRET(hipMemcpyAsync(ft, dptr.data(), sizeof(void *) * k, hipMemcpyHostToDevice, s));
+  DStep hs{};
+  hs.kind = STEP_LIST; hs.filt0 = 0; hs.nfilt = k; hs.list_nfilt = k;
+  DEntry he{0, 0, 0, 0, 0, 0};
+  HIPRET(hipMemcpyAsync(st, &hs, sizeof hs, hipMemcpyHostToDevice, s));
+  HIPRET(hipMemcpyAsync(en, &he, sizeof he, hipMemcpyHostToDevice, s));
+  HIPRET(hipMemsetAsync(lp, 0, sizeof(void *) * kMaxLevels, s));
+  HIPRET(hipMemsetAsync(ln, 0, 8 * kMaxLevels, s));
+  DArena ar[2];
+  ar[0] = {E.tree_cap, E.tree_cap, 0, 0};
+  ar[1] = {0, E.scratch_cap, 0, 0};
+  HIPRET(hipMemcpyAsync(E.d_arenas, ar, sizeof ar, hipMemcpyHostToDevice, s));
+  IterArgs A{};
+  A.g = E.g; A.ent = en; A.E = 1; A.grid = E.grid; A.steps = st; A.filt = ft; A.es = es; A.it = it;
+  A.lvl_ptr = lp; A.lvl_n = ln; A.qstats = qs; A.scratch = E.d_arenas + 1; A.scratch_base = E.scratch_base;
+  A.tree = E.d_arenas; A.tree_base = E.tree_base; A.has_list = 1;
+  A.blk_a = blk; A.blk_b = blk + E.grid; A.blk_off_a = blk + 2 * E.grid; A.blk_off_b = blk + 3 * E.grid;
+  HIPRET(launch_list_only(A, s));
+  IterScalars h{};
+  HIPRET(hipMemcpyAsync(&h, it, sizeof h, hipMemcpyDeviceToHost, s));
+  HIPRET(hipStreamSynchronize(s));
+  if (h.abort) { set_error("scratch arena overflow"); return GS_ENOMEM; }
+  *count = h.list_total;
+  if (out && h.list_total) HIPRET(hipMemcpy(out, h.list_buf, 4 * h.list_total, hipMemcpyDeviceToHost));
+  return GS_OK;
+}
+
+gs_status gs_plan_query(const gs_query *query, gs_plan_info *out) {
+  if (!query || !out) { set_error("null argument"); return GS_EINVAL; }
+  if (query->n_edges > 0 && !query->edges) { set_error("query edges missing"); return GS_EINVAL; }
+  std::vector<int32_t> e3(3 * (size_t)std::max(query->n_edges, 0));
+  for (int k = 0; k < query->n_edges; ++k) {
+    e3[3 * k] = query->edges[k].src; e3[3 * k + 1] = query->edges[k].label; e3[3 * k + 2] = query->edges[k].dst;
+  }
+  NormQuery q;
+  Plan P;
+  std::string msg;
+  int rc = normalise_query(query->n_qv, query->qv_const, query->n_edges, e3.data(), -1, -1, q, msg);
+  if (rc == GS_OK) rc = build_plan(q, nullptr, false, P, msg);
+  if (rc != GS_OK) { set_error(msg); return (gs_status)rc; }
+  memset(out, 0, sizeof *out);
+  out->n_vars = P.n_vars;
+  std::vector<int32_t> first_input(q.edges.size(), -1);
+  for (size_t k = 0; k < q.edge_map.size(); ++k)
+    if (first_input[q.edge_map[k]] < 0) first_input[q.edge_map[k]] = (int32_t)k;
+  for (int j = 0; j < P.n_vars && j < 64; ++j) {
+    out->order[j] = P.order[j];
+    const int pe = P.steps[j].parent_edge;
+    out->parent_edge[j] = (pe >= 0 && P.steps[j].kind == STEP_SEG) ? first_input[pe] : -1;
+  }
+  out->n_groups = (int32_t)std::min<size_t>(P.group_vertex.size(), 64);
+  for (int g = 0; g < out->n_groups; ++g) out->group_vertex[g] = P.group_vertex[g];
+  for (size_t k = 0; k < q.edge_map.size() && k < 64; ++k)
+    out->edge_group[k] = q.edge_first[k] ? P.edge_group[q.edge_map[k]] : -1;
+  out->n_roots = (int32_t)std::min<size_t>(P.roots.size(), 64);
+  for (int r = 0; r < out->n_roots; ++r) out->roots[r] = P.roots[r];
+  return GS_OK;
+}
+
+gs_status gs_query_run(gs_engine *engine, const gs_query *query, uint32_t flags, gs_result **out) {
+  if (!engine || !query || !out) { set_error("null argument"); return GS_EINVAL; }
+  *out = nullptr;
+  std::lock_guard<std::mutex> lk(engine->e.mu);
+  std::vector<Result *> rs;
+  double ms = 0;
+  int rc = run_batch(engine->e, query, 1, flags, rs, &ms);
+  if (rc != GS_OK) return (gs_status)rc;
+  *out = wrap(rs[0]);
+  return GS_OK;
+}
+
+gs_status gs_batch_run(gs_engine *engine, const gs_query *queries, int32_t nq, uint32_t flags, gs_result **outs) {
+  if (!engine || !queries || !outs || nq <= 0) { set_error("bad argument"); return GS_EINVAL; }
+  for (int i = 0; i < nq; ++i) outs[i] = nullptr;
+  std::lock_guard<std::mutex> lk(engine->e.mu);
+  std::vector<Result *> rs;
+  double ms = 0;
+  int rc = run_batch(engine->e, queries, nq, flags, rs, &ms);
+  if (rc != GS_OK) return (gs_status)rc;
+  for (int i = 0; i < nq; ++i) outs[i] = wrap(rs[i]);
+  return GS_OK;
+}
+
+gs_status gs_result_count(const gs_result *result, int64_t *count) {
+  if (!result || !count) { set_error("null argument"); return GS_EINVAL; }
+  *count = unwrap(result)->count;
+  return GS_OK;
+}
+
+gs_status gs_result_width(const gs_result *result, int32_t *n_vars) {
+  if (!result || !n_vars) { set_error("null argument"); return GS_EINVAL; }
+  *n_vars = unwrap(result)->n_vars;
+  return GS_OK;
+}
+
+gs_status gs_result_rows(gs_result *result, int64_t first, int64_t n, void *dst, int mem_kind,
+                         int64_t *n_written) {
+  if (!result) { set_error("null result"); return GS_EINVAL; }
+  Result &R = *unwrap(result);
+  std::lock_guard<std::mutex> lk(R.eng->mu);
+  return (gs_status)result_rows(R, first, n, dst, mem_kind, n_written);
+}
+
+gs_status gs_result_stats(const gs_result *result, gs_query_stats *stats) {
+  if (!result || !stats) { set_error("null argument"); return GS_EINVAL; }
+  *stats = unwrap(result)->stats;
+  return GS_OK;
+}
+
+gs_status gs_result_level(gs_result *result, int32_t level, int32_t *par, int32_t *vid, int64_t *n) {
+  if (!result || !n) { set_error("null argument"); return GS_EINVAL; }
+  Result &R = *unwrap(result);
+  if (level < 0 || level >= R.k) { set_error("level out of range"); return GS_ERANGE; }
+  *n = R.lvl_n[level];
+  if (!par && !vid) return GS_OK;
+  if (!R.lvl_ptr[level]) {
+    if (R.lvl_n[level] == 0) return GS_OK;
+    set_error("level not stored (count-only)");
+    return GS_EUNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lk(R.eng->mu);
+  HIPRET(hipSetDevice(R.eng->device));
+  const int64_t cnt = R.lvl_n[level];
+  if (par) HIPRET(hipMemcpy(par, R.lvl_ptr[level], 4 * cnt, hipMemcpyDeviceToHost));
+  if (vid) HIPRET(hipMemcpy(vid, R.lvl_ptr[level] + cnt, 4 * cnt, hipMemcpyDeviceToHost));
+  return GS_OK;
+}
+
+void gs_result_free(gs_result *result) {
+  if (!result) return;
+  Result *R = unwrap(result);
+  if (R->eng) {
+    std::lock_guard<std::mutex> lk(R->eng->mu);
+    result_free(R);
+  } else {
+    delete R;
+  }
+}
+
+gs_status gs_server_start(gs_engine *engine, const gs_server_options *options, gs_server **out) {
+  if (!engine || !out) { set_error("null argument"); return GS_EINVAL; }
+  return (gs_status)server_start(&engine->e, options, out);
+}
+
+gs_status gs_submit(gs_server *server, const gs_query *query, uint32_t flags, uint64_t *ticket) {
+  if (!server || !query || !ticket) { set_error("null argument"); return GS_EINVAL; }
+  return (gs_status)server_submit(server, query, flags, ticket);
+}
+
+gs_status gs_poll(gs_server *server, uint64_t ticket, gs_result **out) {
+  if (!server || !out) { set_error("null argument"); return GS_EINVAL; }
+  return (gs_status)server_poll(server, ticket, out);
+}
+
+gs_status gs_server_stop(gs_server *server, gs_server_stats *stats) {
+  if (!server) { set_error("null server"); return GS_EINVAL; }
+  return (gs_status)server_stop(server, stats);
+}
+
+}  // extern "C"

@@ -1,0 +1,583 @@
+// Host engine: loads the light-weight sparse matrix, plans queries, compiles
+// their step programs into device tables and drives the per-level launch
+// sequence for a whole batch of queries.
+#include "engine.hpp"
+
+#include <algorithm>
+#include <cstring>
+
+#include "lspm.hpp"
+#include "query.hpp"
+
+namespace gs {
+
+thread_local std::string g_last_error;
+void set_error(const std::string &msg) { g_last_error = msg; }
+const char *last_error() { return g_last_error.c_str(); }
+
+#define HIPCHK(expr)                                                                  \
+  do {                                                                                \
+    hipError_t _e = (expr);                                                           \
+    if (_e != hipSuccess) {                                                           \
+      set_error(std::string("HIP error: ") + hipGetErrorString(_e) + " at " #expr);   \
+      return GS_EDEVICE;                                                              \
+    }                                                                                 \
+  } while (0)
+
+static uint64_t align256(uint64_t x) { return (x + 255ull) & ~255ull; }
+
+void *Engine::dmalloc(size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  if (opt.alloc) return opt.alloc(opt.alloc_ctx, bytes);
+  void *p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  return p;
+}
+
+void Engine::dfree(void *p) {
+  if (!p) return;
+  if (opt.free) opt.free(opt.alloc_ctx, p);
+  else (void)hipFree(p);
+}
+
+Engine::~Engine() {
+  (void)hipSetDevice(device);
+  if (stream) (void)hipStreamSynchronize(stream);
+  for (int o = 0; o < 2; ++o) { dfree(d_ptr[o]); dfree(d_idx[o]); dfree(d_lab[o]); dfree(d_bm[o]); }
+  dfree(tree_base);
+  dfree(scratch_base);
+  dfree(d_arenas);
+  if (own_stream && stream) (void)hipStreamDestroy(stream);
+}
+
+// ------------------------------------------------------------------ loading
+struct LoadCtx { Engine *E; int64_t n; int32_t P; int64_t words; };
+
+static hipError_t alloc_orientation(void *vctx, int orient, int64_t m2, LspmOut &out) {
+  LoadCtx *c = (LoadCtx *)vctx;
+  Engine &E = *c->E;
+  out.words = c->words;
+  E.d_ptr[orient] = (int64_t *)E.dmalloc(sizeof(int64_t) * (c->n + 1));
+  E.d_idx[orient] = (int32_t *)E.dmalloc(sizeof(int32_t) * std::max<int64_t>(m2, 1));
+  E.d_lab[orient] = (uint16_t *)E.dmalloc(sizeof(uint16_t) * std::max<int64_t>(m2, 1));
+  E.d_bm[orient] = (uint64_t *)E.dmalloc(sizeof(uint64_t) * c->words * c->P);
+  if (!E.d_ptr[orient] || !E.d_idx[orient] || !E.d_lab[orient] || !E.d_bm[orient]) return hipErrorOutOfMemory;
+  out.ptr = E.d_ptr[orient];
+  out.idx = E.d_idx[orient];
+  out.lab = E.d_lab[orient];
+  out.bm = E.d_bm[orient];
+  return hipSuccess;
+}
+
+int load_triples(Engine &E, int64_t n, int32_t P, const gs_triple *t, int64_t m, int mem_kind) {
+  if (E.loaded) { set_error("dataset already loaded"); return GS_ESTATE; }
+  if (n <= 0 || n > 2147483647LL) { set_error("vertex count must be in [1, 2^31-1]"); return GS_ERANGE; }
+  if (P <= 0 || P > 65536) { set_error("label count must be in [1, 65536]"); return GS_ERANGE; }
+  if (m < 0 || (m > 0 && !t)) { set_error("bad triple buffer"); return GS_EINVAL; }
+  HIPCHK(hipSetDevice(E.device));
+  hipStream_t s = E.stream;
+  const int64_t words = (n + 63) / 64;
+  const int G = E.grid;
+  // temporaries
+  std::vector<void *> tmp;
+  auto take = [&](size_t bytes) { void *p = E.dmalloc(bytes); tmp.push_back(p); return p; };
+  auto release = [&]() { for (void *p : tmp) E.dfree(p); tmp.clear(); };
+  const int64_t mm = std::max<int64_t>(m, 1);
+  const int32_t *d_trip = (const int32_t *)t;
+  if (mem_kind == GS_MEM_HOST && m > 0) {
+    int32_t *d = (int32_t *)take(sizeof(gs_triple) * mm);
+    if (!d) { release(); set_error("out of device memory for the triples"); return GS_ENOMEM; }
+    hipError_t e = hipMemcpyAsync(d, t, sizeof(gs_triple) * m, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) { release(); set_error(hipGetErrorString(e)); return GS_EDEVICE; }
+    d_trip = d;
+  }
+  LspmBuildArgs a{};
+  a.triples = d_trip; a.m = m; a.n = n; a.P = P; a.grid = G; a.stream = s;
+  a.hi0 = (uint64_t *)take(8 * mm); a.hi1 = (uint64_t *)take(8 * mm);
+  a.lo0 = (uint32_t *)take(4 * mm); a.lo1 = (uint32_t *)take(4 * mm);
+  a.row = (int32_t *)take(4 * mm);
+  a.hist = (uint32_t *)take(4 * 256 * (size_t)G);
+  a.off = (int64_t *)take(8 * 256 * (size_t)G);
+  a.blk = (int64_t *)take(8 * (size_t)G);
+  a.total = (int64_t *)take(64);
+  a.err = (int32_t *)take(64);
+  a.nnz = (int64_t *)take(8 * (size_t)P);
+  int64_t *holders0 = (int64_t *)take(8 * (size_t)P), *holders1 = (int64_t *)take(8 * (size_t)P);
+  for (void *p : tmp) if (!p) { release(); set_error("out of device memory while loading"); return GS_ENOMEM; }
+  HIPCHK(hipMemsetAsync(a.err, 0, 4, s));
+  HIPCHK(hipMemsetAsync(a.nnz, 0, 8 * (size_t)P, s));
+  LoadCtx ctx{&E, n, P, words};
+  a.alloc_out = alloc_orientation;
+  a.alloc_ctx = &ctx;
+  int64_t m2[2] = {0, 0};
+  for (int o = 0; o < 2; ++o) {
+    LspmOut out;
+    out.holders = o == 0 ? holders0 : holders1;
+    hipError_t e = lspm_build_orientation(a, o, out, &m2[o]);
+    if (e != hipSuccess) {
+      release();
+      set_error(e == hipErrorOutOfMemory ? "out of device memory for the matrix" : hipGetErrorString(e));
+      return e == hipErrorOutOfMemory ? GS_ENOMEM : GS_EDEVICE;
+    }
+    if (o == 0) {   // stop early on bad ids
+      int32_t err = 0;
+      HIPCHK(hipMemcpyAsync(&err, a.err, 4, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      if (err) {
+        release();
+        for (int k = 0; k < 2; ++k) {
+          E.dfree(E.d_ptr[k]); E.dfree(E.d_idx[k]); E.dfree(E.d_lab[k]); E.dfree(E.d_bm[k]);
+          E.d_ptr[k] = nullptr; E.d_idx[k] = nullptr; E.d_lab[k] = nullptr; E.d_bm[k] = nullptr;
+        }
+        set_error("a triple has s/o outside [0, n) or p outside [1, P]");
+        return GS_ERANGE;
+      }
+    }
+  }
+  E.stats.n = n;
+  E.stats.nnz.assign(P, 0);
+  E.stats.rows.assign(P, 0);
+  E.stats.cols.assign(P, 0);
+  HIPCHK(hipMemcpyAsync(E.stats.nnz.data(), a.nnz, 8 * (size_t)P, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(E.stats.rows.data(), holders0, 8 * (size_t)P, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(E.stats.cols.data(), holders1, 8 * (size_t)P, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  release();
+  if (m2[0] != m2[1]) { set_error("orientations disagree on the distinct count"); return GS_EDEVICE; }
+  DevGraph g;
+  g.n = n; g.m = m2[0]; g.words = words; g.P = P;
+  for (int o = 0; o < 2; ++o) { g.ptr[o] = E.d_ptr[o]; g.idx[o] = E.d_idx[o]; g.lab[o] = E.d_lab[o]; g.bm[o] = E.d_bm[o]; }
+  E.g = g;
+  E.graph_bytes = 2 * ((uint64_t)(n + 1) * 8 + (uint64_t)g.m * 6 + (uint64_t)words * 8 * P);
+  E.loaded = true;
+  return GS_OK;
+}
+
+// ------------------------------------------------------------------ batches
+namespace {
+
+struct QInfo {
+  NormQuery nq;
+  Plan plan;
+  int32_t step0 = 0;
+  int32_t seed0 = 0, nseed = 0;
+  int32_t dom0 = 0;
+  bool zero = false;
+};
+
+template <class T>
+uint64_t push_bytes(std::vector<char> &buf, const std::vector<T> &v) {
+  uint64_t off = align256(buf.size());
+  buf.resize(off + sizeof(T) * v.size());
+  if (!v.empty()) memcpy(buf.data() + off, v.data(), sizeof(T) * v.size());
+  return off;
+}
+
+__global__ void k_zero_bytes(uint64_t *p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0;
+}
+
+__global__ void k_const_only(DevGraph g, const DConst *cc, int n, int64_t *out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    int64_t ok = 1;
+    for (int k = 0; k < n && ok; ++k) {
+      int64_t a = g.ptr[0][cc[k].a], e = g.ptr[0][cc[k].a + 1];
+      int64_t x = a;
+      while (x < e && (g.lab[0][x] < (uint32_t)cc[k].label || (g.lab[0][x] == (uint32_t)cc[k].label && g.idx[0][x] < cc[k].b))) ++x;
+      ok = (x < e && g.lab[0][x] == (uint32_t)cc[k].label && g.idx[0][x] == cc[k].b);
+    }
+    *out = ok;
+  }
+}
+
+double est_holders(const Engine &E, const FilterRef &f, const std::vector<SeedSpec> &seeds) {
+  const LabelStats &st = E.stats;
+  if (f.kind == F_LABEL_OUT) return (double)st.rows[f.arg];
+  if (f.kind == F_LABEL_IN) return (double)st.cols[f.arg];
+  if (f.kind == F_SEED) {
+    const SeedSpec &s = seeds[f.arg];
+    double h = (double)(s.dir == 0 ? st.rows[s.label] : st.cols[s.label]);
+    return h > 0 ? (double)st.nnz[s.label] / h : 0.0;
+  }
+  return (double)E.g.n;
+}
+
+double avg_seg(const Engine &E, int label, int dir) {
+  double h = (double)(dir == 0 ? E.stats.rows[label] : E.stats.cols[label]);
+  return h > 0 ? (double)E.stats.nnz[label] / h : 0.0;
+}
+
+}  // namespace
+
+int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector<Result *> &out, double *ms_out) {
+  if (!E.loaded) { set_error("no dataset loaded"); return GS_ESTATE; }
+  if (nq <= 0 || !qs) { set_error("empty batch"); return GS_EINVAL; }
+  HIPCHK(hipSetDevice(E.device));
+  hipStream_t s = E.stream;
+  const bool count_only = flags & GS_COUNT_ONLY;
+  const bool want_dom = E.opt.domain_mode != GS_DOMAIN_OFF;
+  const int64_t words = E.g.words;
+
+  // 1. plan every query
+  std::vector<QInfo> Q(nq);
+  int maxk = 0;
+  for (int i = 0; i < nq; ++i) {
+    std::string msg;
+    std::vector<int32_t> e3(3 * (size_t)std::max(qs[i].n_edges, 0));
+    if (qs[i].n_edges > 0 && !qs[i].edges) { set_error("query edges missing"); return GS_EINVAL; }
+    for (int k = 0; k < qs[i].n_edges; ++k) {
+      e3[3 * k] = qs[i].edges[k].src; e3[3 * k + 1] = qs[i].edges[k].label; e3[3 * k + 2] = qs[i].edges[k].dst;
+    }
+    int rc = normalise_query(qs[i].n_qv, qs[i].qv_const, qs[i].n_edges, e3.data(), E.g.n, E.g.P, Q[i].nq, msg);
+    if (rc == GS_OK) rc = build_plan(Q[i].nq, &E.stats, want_dom, Q[i].plan, msg);
+    if (rc != GS_OK) { set_error("query " + std::to_string(i) + ": " + msg); return rc; }
+    Q[i].zero = Q[i].plan.n_vars == 0;
+    maxk = std::max(maxk, Q[i].plan.n_vars);
+  }
+
+  // 2. compile step programs
+  std::vector<DStep> steps;
+  std::vector<const uint64_t *> filt;
+  std::vector<DCheck> checks;
+  std::vector<int32_t> ints;
+  std::vector<DConst> cconst;
+  std::vector<DSeed> seeds;
+  std::vector<DDomain> doms_all;      // in (query, plan order)
+  std::vector<int32_t> dom_iter;      // iteration of each domain
+  std::vector<int32_t> var_ranks;
+  std::vector<int32_t> vr_off(nq, 0);
+  int64_t n_bitmaps = 0;
+  for (int i = 0; i < nq; ++i) n_bitmaps += (int64_t)Q[i].plan.seeds.size() + 2 * (int64_t)Q[i].plan.domains.size();
+
+  // arena layout (host side): bitmaps, then tables, then device-written tables
+  uint64_t off = align256(E.tree_top);
+  const uint64_t bm_off = off;
+  off += align256((uint64_t)n_bitmaps * words * 8);
+  auto bm_ptr = [&](int64_t k) { return (uint64_t *)(E.tree_base + bm_off + (uint64_t)k * words * 8); };
+  int64_t next_bm = 0;
+
+  for (int i = 0; i < nq; ++i) {
+    QInfo &qi = Q[i];
+    const Plan &P = qi.plan;
+    vr_off[i] = (int32_t)var_ranks.size();
+    var_ranks.insert(var_ranks.end(), P.var_rank.begin(), P.var_rank.end());
+    qi.step0 = (int32_t)steps.size();
+    qi.seed0 = (int32_t)seeds.size();
+    std::vector<int32_t> seed_bm(P.seeds.size());
+    for (size_t k = 0; k < P.seeds.size(); ++k) {
+      DSeed d{bm_ptr(next_bm), P.seeds[k].c, P.seeds[k].label, P.seeds[k].dir, i};
+      seed_bm[k] = (int32_t)seeds.size();
+      seeds.push_back(d);
+      ++next_bm;
+    }
+    qi.nseed = (int32_t)P.seeds.size();
+    qi.dom0 = (int32_t)doms_all.size();
+    std::vector<DDomain> qd(P.domains.size());
+    for (size_t k = 0; k < P.domains.size(); ++k) {
+      qd[k].F = bm_ptr(next_bm++);
+      qd[k].D = bm_ptr(next_bm++);
+    }
+    auto filter_ptr = [&](const FilterRef &f) -> const uint64_t * {
+      switch (f.kind) {
+        case F_LABEL_OUT: return E.g.bm[0] + (int64_t)f.arg * words;
+        case F_LABEL_IN: return E.g.bm[1] + (int64_t)f.arg * words;
+        case F_SEED: return seeds[seed_bm[f.arg]].bm;
+        default: return qd[f.arg].D;
+      }
+    };
+    auto col_of = [&](int level, int at) {
+      if (level == at) return 1;
+      const std::vector<int32_t> &c = P.steps[at].carried;
+      return 2 + (int)(std::find(c.begin(), c.end(), level) - c.begin());
+    };
+    for (int j = 0; j < P.n_vars; ++j) {
+      const PlanStep &ps = P.steps[j];
+      DStep d{};
+      d.kind = ps.kind;
+      d.label = ps.label;
+      d.dir = ps.dir;
+      d.src = ps.kind == STEP_SEG ? col_of(ps.src_level, j - 1) : (ps.kind == STEP_SEG_CONST ? ps.src_const : 0);
+      d.filt0 = (int32_t)filt.size();
+      for (const FilterRef &f : ps.filters) filt.push_back(filter_ptr(f));
+      d.nfilt = (int32_t)ps.filters.size();
+      d.list_nfilt = ps.kind == STEP_LIST ? d.nfilt : 0;
+      d.chk0 = (int32_t)checks.size();
+      for (const CheckRef &c : ps.checks) checks.push_back({col_of(c.level, j - 1), c.label, c.dir, 0});
+      d.nchk = (int32_t)ps.checks.size();
+      d.self0 = (int32_t)ints.size();
+      for (int32_t l : ps.self_labels) ints.push_back(l);
+      d.nself = (int32_t)ps.self_labels.size();
+      d.copy0 = (int32_t)ints.size();
+      for (int32_t l : ps.carried) ints.push_back(col_of(l, j - 1));
+      d.ncopy = (int32_t)ps.carried.size();
+      d.ncols_out = (count_only && j == P.n_vars - 1) ? 0 : 2 + d.ncopy;
+      d.ncols_prev = j == 0 ? 0 : 2 + (int32_t)P.steps[j - 1].carried.size();
+      if (j == 0) {
+        d.cc0 = (int32_t)cconst.size();
+        for (const ConstCheck &c : P.cchecks) cconst.push_back({c.a, c.label, c.b, 0});
+        d.ncc = (int32_t)P.cchecks.size();
+      }
+      steps.push_back(d);
+    }
+    for (size_t k = 0; k < P.domains.size(); ++k) {
+      const DomainSpec &ds = P.domains[k];
+      DDomain &dd = qd[k];
+      dd.col = col_of(ds.level, ds.step - 1);
+      dd.label = ds.label;
+      dd.dir = ds.dir;
+      dd.filt0 = (int32_t)filt.size();
+      double mask = (double)E.g.n;
+      for (const FilterRef &f : ds.mask) { filt.push_back(filter_ptr(f)); mask = std::min(mask, est_holders(E, f, P.seeds)); }
+      dd.nfilt = (int32_t)ds.mask.size();
+      dd.mode = E.opt.domain_mode == GS_DOMAIN_PUSH ? 1 : (E.opt.domain_mode == GS_DOMAIN_PULL ? 2 : 0);
+      dd.q = i;
+      dd.deg_push = (float)avg_seg(E, ds.label, ds.dir);
+      dd.deg_pull = (float)avg_seg(E, ds.label, 1 - ds.dir);
+      dd.mask_est = (float)mask;
+      dd.theta = E.opt.push_pull_theta > 0 ? E.opt.push_pull_theta : 1.0f;
+      doms_all.push_back(dd);
+      dom_iter.push_back(ds.step);
+    }
+  }
+
+  // 3. per-iteration work lists
+  std::vector<DEntry> ents;
+  std::vector<DDomain> doms;
+  std::vector<uint64_t *> clears;
+  std::vector<int32_t> ent_off(maxk + 1, 0), dom_off(maxk + 1, 0), clr_off(maxk + 1, 0), has_list(maxk, 0);
+  int max_e = 1, max_d = 1;
+  for (int t = 0; t < maxk; ++t) {
+    ent_off[t] = (int32_t)ents.size();
+    dom_off[t] = (int32_t)doms.size();
+    clr_off[t] = (int32_t)clears.size();
+    if (t == 0) for (const DSeed &d : seeds) clears.push_back(d.bm);
+    for (int i = 0; i < nq; ++i) {
+      const QInfo &qi = Q[i];
+      if (qi.plan.n_vars <= t) continue;
+      DEntry e{i, t, qi.step0 + t, (int32_t)doms.size() - dom_off[t], 0, 0};
+      for (size_t k = 0; k < qi.plan.domains.size(); ++k) {
+        if (dom_iter[qi.dom0 + k] != t) continue;
+        doms.push_back(doms_all[qi.dom0 + k]);
+        clears.push_back(doms_all[qi.dom0 + k].F);
+        clears.push_back(doms_all[qi.dom0 + k].D);
+        e.ndom++;
+      }
+      if (qi.plan.steps[t].kind == STEP_LIST) has_list[t] = 1;
+      ents.push_back(e);
+    }
+    max_e = std::max(max_e, (int)ents.size() - ent_off[t]);
+    max_d = std::max(max_d, (int)doms.size() - dom_off[t]);
+  }
+  ent_off[maxk] = (int32_t)ents.size();
+  dom_off[maxk] = (int32_t)doms.size();
+  clr_off[maxk] = (int32_t)clears.size();
+
+  // 4. pack the constant tables
+  std::vector<char> buf;
+  const uint64_t o_steps = push_bytes(buf, steps), o_filt = push_bytes(buf, filt), o_chk = push_bytes(buf, checks);
+  const uint64_t o_ints = push_bytes(buf, ints), o_cc = push_bytes(buf, cconst), o_seeds = push_bytes(buf, seeds);
+  const uint64_t o_doms = push_bytes(buf, doms), o_ents = push_bytes(buf, ents), o_clr = push_bytes(buf, clears);
+  const uint64_t o_vr = push_bytes(buf, var_ranks);
+  const uint64_t tab_off = align256(off);
+  off = tab_off + align256(buf.size());
+  // device-written tables
+  const uint64_t o_lvlp = off; off += align256(sizeof(int32_t *) * kMaxLevels * (uint64_t)nq);
+  const uint64_t o_lvln = off; off += align256(sizeof(int64_t) * kMaxLevels * (uint64_t)nq);
+  const uint64_t o_qs = off; off += align256(sizeof(int64_t) * QS_N * (uint64_t)nq);
+  const uint64_t o_zero = off; off += 256;   // zero-variable query results
+  const uint64_t zero_end = off;
+  const uint64_t o_fc = off; off += align256(sizeof(int64_t) * max_d);
+  const uint64_t o_es = off; off += align256(sizeof(EState) * max_e);
+  const uint64_t o_it = off; off += align256(sizeof(IterScalars));
+  const uint64_t o_blk = off; off += align256(sizeof(int64_t) * 4 * (uint64_t)E.grid);
+  if (off > E.tree_cap) { set_error("tree arena too small for the batch tables"); return GS_ENOMEM; }
+  char *base = E.tree_base;
+  auto dp = [&](uint64_t o) { return (void *)(base + o); };
+  HIPCHK(hipMemcpyAsync(base + tab_off, buf.data(), buf.size(), hipMemcpyHostToDevice, s));
+  {
+    const int64_t n64 = (int64_t)((zero_end - o_lvlp) / 8);
+    hipLaunchKernelGGL(k_zero_bytes, dim3(64), dim3(256), 0, s, (uint64_t *)dp(o_lvlp), n64);
+  }
+  DArena ar[2];
+  ar[0] = {off, E.tree_cap, 0, 0};
+  ar[1] = {0, E.scratch_cap, 0, 0};
+  HIPCHK(hipMemcpyAsync(E.d_arenas, ar, sizeof(ar), hipMemcpyHostToDevice, s));
+
+  hipEvent_t ev0, ev1;
+  HIPCHK(hipEventCreate(&ev0));
+  HIPCHK(hipEventCreate(&ev1));
+  HIPCHK(hipEventRecord(ev0, s));
+  // 5. iterations
+  for (int t = 0; t < maxk; ++t) {
+    IterArgs A{};
+    A.g = E.g;
+    A.ent = (const DEntry *)dp(tab_off + o_ents) + ent_off[t];
+    A.E = ent_off[t + 1] - ent_off[t];
+    A.S = t == 0 ? (int32_t)seeds.size() : 0;
+    A.D = dom_off[t + 1] - dom_off[t];
+    A.nclear = clr_off[t + 1] - clr_off[t];
+    A.has_list = has_list[t];
+    A.grid = E.grid;
+    A.steps = (const DStep *)dp(tab_off + o_steps);
+    A.filt = (const uint64_t *const *)dp(tab_off + o_filt);
+    A.checks = (const DCheck *)dp(tab_off + o_chk);
+    A.ints = (const int32_t *)dp(tab_off + o_ints);
+    A.cconst = (const DConst *)dp(tab_off + o_cc);
+    A.seeds = (const DSeed *)dp(tab_off + o_seeds);
+    A.doms = (const DDomain *)dp(tab_off + o_doms) + dom_off[t];
+    A.fcount = (int64_t *)dp(o_fc);
+    A.clear = (uint64_t *const *)dp(tab_off + o_clr) + clr_off[t];
+    A.es = (EState *)dp(o_es);
+    A.it = (IterScalars *)dp(o_it);
+    A.lvl_ptr = (int32_t **)dp(o_lvlp);
+    A.lvl_n = (int64_t *)dp(o_lvln);
+    A.qstats = (int64_t *)dp(o_qs);
+    A.scratch = E.d_arenas + 1;
+    A.scratch_base = E.scratch_base;
+    A.tree = E.d_arenas + 0;
+    A.tree_base = E.tree_base;
+    int64_t *blk = (int64_t *)dp(o_blk);
+    A.blk_a = blk; A.blk_b = blk + E.grid; A.blk_off_a = blk + 2 * E.grid; A.blk_off_b = blk + 3 * E.grid;
+    hipError_t e = launch_iteration(A, s);
+    if (e != hipSuccess) { set_error(std::string("launch: ") + hipGetErrorString(e)); return GS_EDEVICE; }
+  }
+  // constant-only queries
+  std::vector<int64_t> zero_res(nq, 0);
+  for (int i = 0; i < nq; ++i) {
+    if (!Q[i].zero) continue;
+    std::vector<DConst> cc;
+    for (const ConstCheck &c : Q[i].plan.cchecks) cc.push_back({c.a, c.label, c.b, 0});
+    DConst *d_cc = (DConst *)E.dmalloc(sizeof(DConst) * std::max<size_t>(cc.size(), 1));
+    int64_t *d_o = (int64_t *)E.dmalloc(8);
+    if (!d_cc || !d_o) { E.dfree(d_cc); E.dfree(d_o); set_error("out of device memory"); return GS_ENOMEM; }
+    HIPCHK(hipMemcpyAsync(d_cc, cc.data(), sizeof(DConst) * cc.size(), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_const_only, dim3(1), dim3(64), 0, s, E.g, (const DConst *)d_cc, (int)cc.size(), d_o);
+    HIPCHK(hipMemcpyAsync(&zero_res[i], d_o, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    E.dfree(d_cc);
+    E.dfree(d_o);
+  }
+  HIPCHK(hipEventRecord(ev1, s));
+
+  // 6. read back sizes and counters
+  std::vector<int64_t> lvl_n((size_t)nq * kMaxLevels), qst((size_t)nq * QS_N);
+  std::vector<int32_t *> lvl_p((size_t)nq * kMaxLevels);
+  HIPCHK(hipMemcpyAsync(lvl_n.data(), dp(o_lvln), 8 * lvl_n.size(), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(lvl_p.data(), dp(o_lvlp), 8 * lvl_p.size(), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(qst.data(), dp(o_qs), 8 * qst.size(), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(ar, E.d_arenas, sizeof(ar), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  float ms = 0;
+  HIPCHK(hipEventElapsedTime(&ms, ev0, ev1));
+  (void)hipEventDestroy(ev0);
+  (void)hipEventDestroy(ev1);
+  if (ms_out) *ms_out = ms;
+  if (ar[1].overflow) {
+    set_error("scratch arena overflow: a level's temporaries exceed the scratch arena");
+    return GS_ENOMEM;
+  }
+  for (int i = 0; i < nq; ++i)
+    for (int j = 0; j < Q[i].plan.n_vars; ++j)
+      if (lvl_n[(size_t)i * kMaxLevels + j] < 0) {
+        set_error("query " + std::to_string(i) + ": binding tree exceeds the tree arena (level " + std::to_string(j) + ")");
+        return GS_ENOMEM;
+      }
+
+  // 7. results
+  const int run_id = ++E.run_counter;
+  for (int i = 0; i < nq; ++i) {
+    Result *R = new Result();
+    R->eng = &E;
+    R->run_id = run_id;
+    const Plan &P = Q[i].plan;
+    R->k = P.n_vars;
+    R->n_vars = P.n_vars;
+    R->count_only = count_only;
+    R->zero_vars = Q[i].zero;
+    R->var_rank = P.var_rank;
+    if (Q[i].zero) {
+      R->count = zero_res[i];
+    } else {
+      for (int j = 0; j < P.n_vars; ++j) {
+        R->lvl_ptr.push_back(lvl_p[(size_t)i * kMaxLevels + j]);
+        R->lvl_n.push_back(lvl_n[(size_t)i * kMaxLevels + j]);
+      }
+      R->count = R->lvl_n.back();
+      R->d_lvl_ptr = (int32_t **)dp(o_lvlp) + (size_t)i * kMaxLevels;
+      R->d_lvl_n = (int64_t *)dp(o_lvln) + (size_t)i * kMaxLevels;
+      R->d_var_rank = (int32_t *)dp(tab_off + o_vr) + vr_off[i];
+    }
+    gs_query_stats &st = R->stats;
+    memset(&st, 0, sizeof st);
+    st.count = R->count;
+    st.n_levels = R->k;
+    st.n_domains = (int32_t)P.domains.size();
+    for (int j = 0; j < R->k && j < 64; ++j) st.level_nodes[j] = R->lvl_n[j];
+    const int64_t *c = &qst[(size_t)i * QS_N];
+    st.t_expand = c[QS_EXPAND];
+    st.t_seed = c[QS_SEED];
+    st.t_push = c[QS_PUSH];
+    st.t_pull = c[QS_PULL];
+    st.t_probe = c[QS_PROBE];
+    st.t_total = st.t_expand + st.t_seed + st.t_push + st.t_pull + st.t_probe;
+    st.domain_push = (int32_t)c[QS_DOMPUSH];
+    st.domain_pull = (int32_t)c[QS_DOMPULL];
+    int64_t nodes_written = 0, nodes_read = 0;
+    for (int j = 0; j < R->k; ++j) {
+      const int64_t cols = (count_only && j == R->k - 1) ? 0 : 2 + (int64_t)P.steps[j].carried.size();
+      nodes_written += R->lvl_n[j] * cols;
+      if (j + 1 < R->k) nodes_read += R->lvl_n[j];
+    }
+    // id reads (4 B) for every traversed entry, labels touched by probes (2 B), offset pairs per
+    // segment lookup (16 B), tree columns written (4 B each) and parent bindings read (4 B)
+    st.bytes_alg = 4 * (st.t_expand + st.t_seed + st.t_push + st.t_pull) + 6 * st.t_probe + 16 * nodes_read +
+                   4 * nodes_written + 4 * nodes_read;
+    st.gpu_ms = ms;
+    out.push_back(R);
+  }
+  E.tree_top = ar[0].top;
+  E.live_results += nq;
+  return GS_OK;
+}
+
+int result_rows(Result &R, int64_t first, int64_t n, void *dst, int mem_kind, int64_t *written) {
+  if (written) *written = 0;
+  if (R.count_only && !R.zero_vars) { set_error("rows of a count-only result"); return GS_EUNSUPPORTED; }
+  if (first < 0 || n < 0 || first > R.count) { set_error("row range outside the result"); return GS_ERANGE; }
+  n = std::min(n, R.count - first);
+  if (n == 0 || R.n_vars == 0) { if (written) *written = n; return GS_OK; }
+  if (!dst) { set_error("null destination"); return GS_EINVAL; }
+  Engine &E = *R.eng;
+  HIPCHK(hipSetDevice(E.device));
+  hipStream_t s = E.stream;
+  const int k = R.k;
+  if (mem_kind == GS_MEM_DEVICE) {
+    hipError_t e = launch_enumerate(R.d_lvl_ptr, R.d_lvl_n, k, R.d_var_rank, first, n, (int32_t *)dst, s);
+    if (e != hipSuccess) { set_error(hipGetErrorString(e)); return GS_EDEVICE; }
+    HIPCHK(hipStreamSynchronize(s));
+  } else {
+    const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(n, (int64_t)(64ll << 20) / (4 * k)));
+    int32_t *tmp = (int32_t *)E.dmalloc(sizeof(int32_t) * (size_t)chunk * k);
+    if (!tmp) { set_error("out of device memory for rows"); return GS_ENOMEM; }
+    for (int64_t r = 0; r < n; r += chunk) {
+      const int64_t c = std::min(chunk, n - r);
+      hipError_t e = launch_enumerate(R.d_lvl_ptr, R.d_lvl_n, k, R.d_var_rank, first + r, c, tmp, s);
+      if (e == hipSuccess) e = hipMemcpyAsync((int32_t *)dst + r * k, tmp, sizeof(int32_t) * c * k, hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) { E.dfree(tmp); set_error(hipGetErrorString(e)); return GS_EDEVICE; }
+    }
+    E.dfree(tmp);
+  }
+  if (written) *written = n;
+  return GS_OK;
+}
+
+void result_free(Result *R) {
+  if (!R) return;
+  Engine *E = R->eng;
+  if (R->own) E->dfree(R->own);
+  else if (E && E->live_results > 0 && --E->live_results == 0) E->tree_top = 0;
+  delete R;
+}
+
+}  // namespace gs

@@ -1,0 +1,163 @@
+// Device helpers shared by the engine's kernels (wave64 / workgroup scans,
+// reductions, segment lookup in the light-weight sparse matrix).
+#pragma once
+#include "gs_device.hpp"
+
+namespace gs {
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const int lane = threadIdx.x & 63;
+  return (1ull << lane) - 1ull;
+}
+
+__device__ __forceinline__ int64_t wave_incl_scan_i64(int64_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    int64_t u = __shfl_up(v, off, 64);
+    if (lane >= off) v += u;
+  }
+  return v;
+}
+
+__device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Exclusive scan of one int64 per thread over a kBlock workgroup. lds holds kWaves entries.
+__device__ __forceinline__ int64_t block_excl_scan_i64(int64_t v, int64_t &total, int64_t *lds) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int64_t inc = wave_incl_scan_i64(v);
+  if (lane == 63) lds[w] = inc;
+  __syncthreads();
+  int64_t off = 0;
+  total = 0;
+#pragma unroll
+  for (int i = 0; i < kWaves; ++i) {
+    int64_t c = lds[i];
+    if (i < w) off += c;
+    total += c;
+  }
+  __syncthreads();
+  return off + inc - v;
+}
+
+// Exclusive rank of a flag over a kBlock workgroup (ballot + popcount). lds: kWaves ints.
+__device__ __forceinline__ int block_excl_flag(bool f, int &total, int *lds) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint64_t b = __ballot(f);
+  int r = __popcll(b & lanemask_lt());
+  if (lane == 0) lds[w] = __popcll(b);
+  __syncthreads();
+  int off = 0;
+  total = 0;
+#pragma unroll
+  for (int i = 0; i < kWaves; ++i) {
+    int c = lds[i];
+    if (i < w) off += c;
+    total += c;
+  }
+  __syncthreads();
+  return off + r;
+}
+
+__device__ __forceinline__ int64_t block_sum_i64(int64_t v, int64_t *lds) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  v = wave_sum_i64(v);
+  if (lane == 0) lds[w] = v;
+  __syncthreads();
+  int64_t t = 0;
+#pragma unroll
+  for (int i = 0; i < kWaves; ++i) t += lds[i];
+  __syncthreads();
+  return t;
+}
+
+// Exclusive scan over an index space [0, L) by one workgroup of any size.
+// get(i) returns the value, set(i, prefix) stores the exclusive prefix.
+// lds: blockDim.x int64 entries. Returns the total.
+template <class Get, class Set>
+__device__ int64_t wg_scan(int64_t L, Get get, Set set, int64_t *lds) {
+  const int t = threadIdx.x, T = blockDim.x;
+  const int64_t per = (L + T - 1) / T;
+  const int64_t b = min(L, (int64_t)t * per), e = min(L, b + per);
+  int64_t s = 0;
+  for (int64_t i = b; i < e; ++i) s += get(i);
+  lds[t] = s;
+  __syncthreads();
+  for (int off = 1; off < T; off <<= 1) {
+    int64_t v = (t >= off) ? lds[t - off] : 0;
+    __syncthreads();
+    lds[t] += v;
+    __syncthreads();
+  }
+  const int64_t total = lds[T - 1];
+  int64_t run = lds[t] - s;
+  __syncthreads();
+  for (int64_t i = b; i < e; ++i) {
+    int64_t v = get(i);
+    set(i, run);
+    run += v;
+  }
+  __syncthreads();
+  return total;
+}
+
+// Block g of gridDim.x takes the contiguous share [lo, hi) of [0, total).
+__device__ __forceinline__ void block_share(int64_t total, int64_t &lo, int64_t &hi) {
+  const int64_t G = gridDim.x, g = blockIdx.x;
+  // index spaces here stay far below 2^63 / 8192
+  lo = total * g / G;
+  hi = total * (g + 1) / G;
+}
+
+__device__ __forceinline__ int64_t lower_bound_u16(const uint16_t *a, int64_t lo, int64_t hi, uint32_t key,
+                                                   int &probes) {
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    ++probes;
+    if (a[mid] < key) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// Entries of vertex b with label `label` in orientation dir: [lo, hi).
+__device__ __forceinline__ void seg_find(const DevGraph &g, int dir, int32_t b, int32_t label, int64_t &lo,
+                                         int64_t &hi, int &probes) {
+  const int64_t a = g.ptr[dir][b], e = g.ptr[dir][b + 1];
+  const uint16_t *lab = g.lab[dir];
+  if (e - a <= 8) {          // short rows: one linear pass
+    int64_t x = a;
+    while (x < e && lab[x] < (uint32_t)label) ++x;
+    int64_t y = x;
+    while (y < e && lab[y] == (uint32_t)label) ++y;
+    probes += (int)(y - a + (y < e));
+    lo = x; hi = y;
+    return;
+  }
+  lo = lower_bound_u16(lab, a, e, (uint32_t)label, probes);
+  hi = lower_bound_u16(lab, lo, e, (uint32_t)label + 1, probes);
+}
+
+// Is c among the entries of vertex b with label `label` (orientation dir)?
+__device__ __forceinline__ bool seg_has(const DevGraph &g, int dir, int32_t b, int32_t label, int32_t c,
+                                        int &probes) {
+  int64_t lo, hi;
+  seg_find(g, dir, b, label, lo, hi, probes);
+  const int32_t *idx = g.idx[dir];
+  int64_t x = lo, y = hi;
+  while (x < y) {
+    int64_t mid = (x + y) >> 1;
+    ++probes;
+    if (idx[mid] < c) x = mid + 1; else y = mid;
+  }
+  return x < hi && idx[x] == c;
+}
+
+__device__ __forceinline__ bool bit_test(const uint64_t *bm, int32_t c) {
+  return (bm[c >> 6] >> (c & 63)) & 1ull;
+}
+
+}  // namespace gs

@@ -1,0 +1,710 @@
+// Query-evaluation kernels. One launch sequence advances every active query
+// of an iteration by one tree level (one query vertex, Section 7.1):
+//
+//   setup      per-entry previous level, node tiles, scratch reset
+//   clear      zero the seed / frontier / domain bitmaps used this iteration
+//   seed       constant edges: segment of the constant -> bitmap (light queries)
+//   list_*     root or new-component candidates: AND of bitmaps + compaction
+//              (Eq. 17 / 21: v_x = AND of the label-existence vectors)
+//   dom_*      cycle-closing edges: frontier F of distinct bindings of the bound
+//              end, then D = vertices reachable from F (Eq. 14-16 / 22), by push
+//              over F or by a masked pull over the candidates
+//   lookup     per tree node: the label-p segment of its parent binding
+//              (the row or column selection of Eq. 18 / 22)
+//   nz_write   compact the nodes with a non-empty segment
+//   expand_*   per candidate: bitmap filters, exact checks against bound
+//              vertices, self loops; count, scan, write (parent, vertex,
+//              carried bindings) in node order (Eq. 19 / 23)
+//
+// Every kernel runs on a fixed grid and reads its sizes from device memory,
+// so an iteration needs no host round trip. Index spaces are cut into tiles
+// that never straddle two queries; block g of G takes a contiguous share of
+// the tiles, so results come out in a fixed order.
+#include "kernels_common.hpp"
+#include "planner.hpp"
+#include "query.hpp"
+
+namespace gs {
+
+__device__ __forceinline__ void *arena_alloc(DArena *a, char *base, uint64_t bytes) {
+  const uint64_t sz = (bytes + 255ull) & ~255ull;
+  if (sz == 0) return base;
+  const uint64_t at = atomicAdd((unsigned long long *)&a->top, (unsigned long long)sz);
+  if (at + sz > a->cap) { atomicOr(&a->overflow, 1); return nullptr; }
+  return base + at;
+}
+
+// last entry e with key(e) <= t (key non-decreasing)
+template <class Key>
+__device__ __forceinline__ int last_le(int E, int64_t t, Key key) {
+  int lo = 0, hi = E;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (key(mid) <= t) lo = mid + 1; else hi = mid;
+  }
+  return lo - 1;
+}
+
+__device__ __forceinline__ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ------------------------------------------------------------------ setup
+__global__ __launch_bounds__(1024) void k_it_setup(const IterArgs A) {
+  __shared__ int64_t lds[1024];
+  IterScalars *it = A.it;
+  EState *es = A.es;
+  if (threadIdx.x == 0) {
+    A.scratch->top = 0;
+    A.scratch->overflow = 0;
+    it->n_entries = A.E;
+    it->abort = 0;
+  }
+  for (int e = threadIdx.x; e < A.E; e += blockDim.x) {
+    const DEntry d = A.ent[e];
+    const DStep S = A.steps[d.step];
+    EState z{};
+    if (d.level == 0) {
+      z.prev = nullptr;
+      z.prev_n = 1;
+    } else {
+      const int64_t n = A.lvl_n[(int64_t)d.q * kMaxLevels + d.level - 1];
+      z.prev = A.lvl_ptr[(int64_t)d.q * kMaxLevels + d.level - 1];
+      z.prev_n = n < 0 ? 0 : n;
+    }
+    z.list_words = (S.kind == STEP_LIST && z.prev_n > 0) ? A.g.words : 0;
+    es[e] = z;
+  }
+  for (int d = threadIdx.x; d < A.D; d += blockDim.x) A.fcount[d] = 0;
+  __syncthreads();
+  const int64_t nodes = wg_scan(A.E, [&](int64_t i) { return es[i].prev_n; },
+                                [&](int64_t i, int64_t v) { es[i].node0 = v; }, lds);
+  const int64_t ntiles = wg_scan(A.E, [&](int64_t i) { return ceil_div(es[i].prev_n, kTileNodes); },
+                                 [&](int64_t i, int64_t v) { es[i].node_tile0 = v; }, lds);
+  const int64_t ltiles = wg_scan(A.E, [&](int64_t i) { return ceil_div(es[i].list_words, kTileWords); },
+                                 [&](int64_t i, int64_t v) { es[i].list_tile0 = v; }, lds);
+  if (threadIdx.x == 0) {
+    it->nodes_total = nodes;
+    it->node_tiles = ntiles;
+    it->list_tiles = ltiles;
+    it->lo = (int64_t *)arena_alloc(A.scratch, A.scratch_base, sizeof(int64_t) * nodes);
+    it->len = (int64_t *)arena_alloc(A.scratch, A.scratch_base, sizeof(int64_t) * nodes);
+    if (A.scratch->overflow) it->abort = 1;
+  }
+}
+
+// Zero every bitmap on the iteration's clear list.
+__global__ __launch_bounds__(kBlock) void k_clear(const IterArgs A) {
+  const int64_t W = A.g.words, total = (int64_t)A.nclear * W;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x)
+    A.clear[i / W][i % W] = 0ull;
+}
+
+// Constant edges (c, p, x) / (x, p, c): the segment of c -> bitmap of x's candidates.
+__global__ __launch_bounds__(kBlock) void k_seed(const IterArgs A) {
+  for (int s = blockIdx.x; s < A.S; s += gridDim.x) {
+    const DSeed sd = A.seeds[s];
+    int64_t lo, hi;
+    int probes = 0;
+    seg_find(A.g, sd.dir, sd.c, sd.label, lo, hi, probes);
+    const int32_t *idx = A.g.idx[sd.dir];
+    for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
+      const int32_t c = idx[k];
+      atomicOr((unsigned long long *)&sd.bm[c >> 6], 1ull << (c & 63));
+    }
+    if (threadIdx.x == 0) atomicAdd((unsigned long long *)&A.qstats[(int64_t)sd.q * QS_N + QS_SEED],
+                                    (unsigned long long)(hi - lo));
+  }
+}
+
+// ------------------------------------------------------------------ lists
+__device__ __forceinline__ uint64_t list_word(const IterArgs &A, const DStep &S, int64_t w) {
+  uint64_t x = ~0ull;
+  for (int f = 0; f < S.list_nfilt; ++f) x &= A.filt[S.filt0 + f][w];
+  if (w == A.g.words - 1 && (A.g.n & 63)) x &= (1ull << (A.g.n & 63)) - 1ull;
+  return x;
+}
+
+__global__ __launch_bounds__(kBlock) void k_list_count(const IterArgs A) {
+  __shared__ int64_t lds[kWaves];
+  __shared__ int sh_e;
+  IterScalars *it = A.it;
+  if (it->abort) return;
+  EState *es = A.es;
+  int64_t tb, te;
+  block_share(it->list_tiles, tb, te);
+  int64_t bsum = 0;
+  for (int64_t t = tb; t < te; ++t) {
+    if (threadIdx.x == 0) sh_e = last_le(A.E, t, [&](int i) { return es[i].list_tile0; });
+    __syncthreads();
+    const int e = sh_e;
+    const DStep S = A.steps[A.ent[e].step];
+    const int64_t w = (t - es[e].list_tile0) * kTileWords + threadIdx.x;
+    int64_t c = 0;
+    if (w < es[e].list_words) c = __popcll(list_word(A, S, w));
+    c = block_sum_i64(c, lds);
+    if (threadIdx.x == 0 && c) atomicAdd((unsigned long long *)&es[e].list_n, (unsigned long long)c);
+    bsum += c;
+  }
+  if (threadIdx.x == 0) A.blk_a[blockIdx.x] = bsum;
+}
+
+__global__ __launch_bounds__(1024) void k_list_scan(const IterArgs A) {
+  __shared__ int64_t lds[1024];
+  IterScalars *it = A.it;
+  if (it->abort) return;
+  EState *es = A.es;
+  wg_scan(A.grid, [&](int64_t i) { return A.blk_a[i]; }, [&](int64_t i, int64_t v) { A.blk_off_a[i] = v; }, lds);
+  const int64_t total = wg_scan(A.E, [&](int64_t i) { return es[i].list_n; },
+                                [&](int64_t i, int64_t v) { es[i].list_base = v; }, lds);
+  __shared__ int32_t *buf;
+  if (threadIdx.x == 0) {
+    it->list_total = total;
+    buf = (int32_t *)arena_alloc(A.scratch, A.scratch_base, sizeof(int32_t) * total);
+    it->list_buf = buf;
+    if (A.scratch->overflow) it->abort = 1;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < A.E; e += blockDim.x) es[e].list = buf ? buf + es[e].list_base : nullptr;
+}
+
+__global__ __launch_bounds__(kBlock) void k_list_write(const IterArgs A) {
+  __shared__ int64_t lds[kWaves];
+  __shared__ int sh_e;
+  IterScalars *it = A.it;
+  if (it->abort) return;
+  EState *es = A.es;
+  int64_t tb, te;
+  block_share(it->list_tiles, tb, te);
+  int64_t run = A.blk_off_a[blockIdx.x];
+  for (int64_t t = tb; t < te; ++t) {
+    if (threadIdx.x == 0) sh_e = last_le(A.E, t, [&](int i) { return es[i].list_tile0; });
+    __syncthreads();
+    const int e = sh_e;
+    const DStep S = A.steps[A.ent[e].step];
+    const int64_t w = (t - es[e].list_tile0) * kTileWords + threadIdx.x;
+    uint64_t x = 0;
+    if (w < es[e].list_words) x = list_word(A, S, w);
+    int64_t tot;
+    int64_t pos = block_excl_scan_i64(__popcll(x), tot, lds);
+    int32_t *out = it->list_buf + (run + pos);
+    while (x) {
+      const int b = __ffsll((unsigned long long)x) - 1;
+      *out++ = (int32_t)(w * 64 + b);
+      x &= x - 1;
+    }
+    run += tot;
+  }
+}
+
+// ------------------------------------------------------------------ domains
+__device__ __forceinline__ int node_entry(const IterArgs &A, int64_t t) {
+  return last_le(A.E, t, [&](int i) { return A.es[i].node_tile0; });
+}
+
+// F = distinct bindings of the bound end of each cycle-closing edge.
+__global__ __launch_bounds__(kBlock) void k_dom_frontier(const IterArgs A) {
+  __shared__ int64_t lds[kWaves];
+  __shared__ int sh_e;
+  IterScalars *it = A.it;
+  if (it->abort || A.D == 0) return;
+  EState *es = A.es;
+  int64_t tb, te;
+  block_share(it->node_tiles, tb, te);
+  for (int64_t t = tb; t < te; ++t) {
+    if (threadIdx.x == 0) sh_e = node_entry(A, t);
+    __syncthreads();
+    const int e = sh_e;
+    __syncthreads();
+    const DEntry d = A.ent[e];
+    if (d.ndom == 0) continue;   // uniform across the block
+    const int64_t i0 = (t - es[e].node_tile0) * kTileNodes, pn = es[e].prev_n;
+    for (int k = 0; k < d.ndom; ++k) {
+      const DDomain dm = A.doms[d.dom0 + k];
+      int64_t fresh = 0;
+      for (int r = 0; r < kTileNodes / kBlock; ++r) {
+        const int64_t i = i0 + r * kBlock + threadIdx.x;
+        if (i < pn) {
+          const int32_t b = es[e].prev[(int64_t)dm.col * pn + i];
+          const uint64_t bit = 1ull << (b & 63);
+          const uint64_t old = atomicOr((unsigned long long *)&dm.F[b >> 6], bit);
+          fresh += (old & bit) ? 0 : 1;
+        }
+      }
+      fresh = block_sum_i64(fresh, lds);
+      if (threadIdx.x == 0 && fresh) atomicAdd((unsigned long long *)&A.fcount[d.dom0 + k], (unsigned long long)fresh);
+    }
+  }
+}
+
+__device__ __forceinline__ int dom_mode(const IterArgs &A, int d) {
+  const DDomain &dm = A.doms[d];
+  if (dm.mode == 1 || dm.mode == 2) return dm.mode;
+  const double push = (double)A.fcount[d] * dm.deg_push;
+  const double pull = (double)dm.mask_est * dm.deg_pull;
+  return push <= (double)dm.theta * pull ? 1 : 2;
+}
+
+// Push: for every b in F, OR the label-p segment of b into D (sparse-frontier product).
+__global__ __launch_bounds__(kBlock) void k_dom_push(const IterArgs A) {
+  __shared__ int64_t lds[kWaves];
+  if (A.it->abort || A.D == 0) return;
+  const int64_t W = A.g.words, tpd = ceil_div(W, kTileWords);
+  const int64_t NT = (int64_t)A.D * tpd;
+  for (int64_t t = blockIdx.x; t < NT; t += gridDim.x) {
+    const int d = (int)(t / tpd);
+    if (dom_mode(A, d) != 1) continue;
+    const DDomain dm = A.doms[d];
+    const int64_t w = (t % tpd) * kTileWords + threadIdx.x;
+    int64_t work = 0;
+    if (w < W) {
+      uint64_t x = dm.F[w];
+      if (w == W - 1 && (A.g.n & 63)) x &= (1ull << (A.g.n & 63)) - 1ull;   // no vertex ids >= n
+      const int32_t *idx = A.g.idx[dm.dir];
+      while (x) {
+        const int b = __ffsll((unsigned long long)x) - 1;
+        x &= x - 1;
+        int64_t lo, hi;
+        int probes = 0;
+        seg_find(A.g, dm.dir, (int32_t)(w * 64 + b), dm.label, lo, hi, probes);
+        for (int64_t k = lo; k < hi; ++k) {
+          const int32_t c = idx[k];
+          atomicOr((unsigned long long *)&dm.D[c >> 6], 1ull << (c & 63));
+        }
+        work += hi - lo;
+      }
+    }
+    work = block_sum_i64(work, lds);
+    if (threadIdx.x == 0) {
+      if (work) atomicAdd((unsigned long long *)&A.qstats[(int64_t)dm.q * QS_N + QS_PUSH], (unsigned long long)work);
+      if (t % tpd == 0) atomicAdd((unsigned long long *)&A.qstats[(int64_t)dm.q * QS_N + QS_DOMPUSH], 1ull);
+    }
+  }
+}
+
+// Pull: for every candidate c of the mask, D(c) = OR over b in seg(c, p, opposite) of F(b).
+__global__ __launch_bounds__(kBlock) void k_dom_pull(const IterArgs A) {
+  __shared__ int64_t lds[kWaves];
+  if (A.it->abort || A.D == 0) return;
+  const int64_t W = A.g.words, tpd = ceil_div(W, kTileWords);
+  const int64_t NT = (int64_t)A.D * tpd;
+  for (int64_t t = blockIdx.x; t < NT; t += gridDim.x) {
+    const int d = (int)(t / tpd);
+    if (dom_mode(A, d) != 2) continue;
+    const DDomain dm = A.doms[d];
+    const int64_t w = (t % tpd) * kTileWords + threadIdx.x;
+    int64_t work = 0;
+    if (w < W) {
+      uint64_t x = ~0ull;
+      for (int f = 0; f < dm.nfilt; ++f) x &= A.filt[dm.filt0 + f][w];
+      if (w == W - 1 && (A.g.n & 63)) x &= (1ull << (A.g.n & 63)) - 1ull;
+      const int od = 1 - dm.dir;
+      const int32_t *idx = A.g.idx[od];
+      uint64_t out = 0;
+      while (x) {
+        const int b = __ffsll((unsigned long long)x) - 1;
+        x &= x - 1;
+        int64_t lo, hi;
+        int probes = 0;
+        seg_find(A.g, od, (int32_t)(w * 64 + b), dm.label, lo, hi, probes);
+        int64_t k = lo;
+        for (; k < hi; ++k)
+          if (bit_test(dm.F, idx[k])) { out |= 1ull << b; ++k; break; }
+        work += k - lo;
+      }
+      dm.D[w] = out;
+    }
+    work = block_sum_i64(work, lds);
+    if (threadIdx.x == 0) {
+      if (work) atomicAdd((unsigned long long *)&A.qstats[(int64_t)dm.q * QS_N + QS_PULL], (unsigned long long)work);
+      if (t % tpd == 0) atomicAdd((unsigned long long *)&A.qstats[(int64_t)dm.q * QS_N + QS_DOMPULL], 1ull);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ lookup
+__device__ __forceinline__ bool const_checks_hold(const IterArgs &A, const DStep &S) {
+  for (int k = 0; k < S.ncc; ++k) {
+    const DConst c = A.cconst[S.cc0 + k];
+    int probes = 0;
+    if (!seg_has(A.g, 0, c.a, c.label, c.b, probes)) return false;
+  }
+  return true;
+}
+
+__global__ __launch_bounds__(kBlock) void k_lookup(const IterArgs A) {
+  __shared__ int64_t lds[kWaves];
+  __shared__ int sh_e, sh_ok;
+  IterScalars *it = A.it;
+  if (it->abort) return;
+  EState *es = A.es;
+  int64_t tb, te;
+  block_share(it->node_tiles, tb, te);
+  int64_t bnz = 0, bw = 0;
+  for (int64_t t = tb; t < te; ++t) {
+    if (threadIdx.x == 0) sh_e = node_entry(A, t);
+    __syncthreads();
+    const int e = sh_e;
+    const DEntry d = A.ent[e];
+    const DStep S = A.steps[d.step];
+    if (threadIdx.x == 0) sh_ok = (d.level == 0 && S.ncc > 0) ? const_checks_hold(A, S) : 1;
+    __syncthreads();
+    const int64_t i0 = (t - es[e].node_tile0) * kTileNodes, pn = es[e].prev_n;
+    int64_t cnz = 0, cw = 0;
+    for (int r = 0; r < kTileNodes / kBlock; ++r) {
+      const int64_t i = i0 + r * kBlock + threadIdx.x;
+      if (i >= pn) break;
+      int64_t lo = 0, hi = 0;
+      int probes = 0;
+      if (S.kind == STEP_SEG) {
+        seg_find(A.g, S.dir, es[e].prev[(int64_t)S.src * pn + i], S.label, lo, hi, probes);
+      } else if (S.kind == STEP_SEG_CONST) {
+        seg_find(A.g, S.dir, S.src, S.label, lo, hi, probes);
+      } else {
+        hi = es[e].list_n;
+      }
+      if (!sh_ok) hi = lo;
+      const int64_t gn = es[e].node0 + i;
+      it->lo[gn] = lo;
+      it->len[gn] = hi - lo;
+      cnz += (hi > lo);
+      cw += hi - lo;
+    }
+    cnz = block_sum_i64(cnz, lds);
+    cw = block_sum_i64(cw, lds);
+    if (threadIdx.x == 0) {
+      if (cnz) atomicAdd((unsigned long long *)&es[e].nz, (unsigned long long)cnz);
+      if (cw) atomicAdd((unsigned long long *)&es[e].w, (unsigned long long)cw);
+    }
+    bnz += cnz;
+    bw += cw;
+  }
+  if (threadIdx.x == 0) { A.blk_a[blockIdx.x] = bnz; A.blk_b[blockIdx.x] = bw; }
+}
+
+__global__ __launch_bounds__(1024) void k_scan_nodes(const IterArgs A) {
+  __shared__ int64_t lds[1024];
+  IterScalars *it = A.it;
+  if (it->abort) return;
+  EState *es = A.es;
+  wg_scan(A.grid, [&](int64_t i) { return A.blk_a[i]; }, [&](int64_t i, int64_t v) { A.blk_off_a[i] = v; }, lds);
+  wg_scan(A.grid, [&](int64_t i) { return A.blk_b[i]; }, [&](int64_t i, int64_t v) { A.blk_off_b[i] = v; }, lds);
+  const int64_t nz = wg_scan(A.E, [&](int64_t i) { return es[i].nz; }, [&](int64_t i, int64_t v) { es[i].nz_base = v; }, lds);
+  const int64_t w = wg_scan(A.E, [&](int64_t i) { return es[i].w; }, [&](int64_t i, int64_t v) { es[i].w_base = v; }, lds);
+  const int64_t wt = wg_scan(A.E, [&](int64_t i) { return ceil_div(es[i].w, kTileWork); },
+                             [&](int64_t i, int64_t v) { es[i].w_tile0 = v; }, lds);
+  if (threadIdx.x == 0) {
+    it->nz_total = nz;
+    it->w_total = w;
+    it->work_tiles = wt;
+    it->nz_node = (int32_t *)arena_alloc(A.scratch, A.scratch_base, sizeof(int32_t) * nz);
+    it->nz_lo = (int64_t *)arena_alloc(A.scratch, A.scratch_base, sizeof(int64_t) * nz);
+    it->nz_woff = (int64_t *)arena_alloc(A.scratch, A.scratch_base, sizeof(int64_t) * nz);
+    it->valid = (uint32_t *)arena_alloc(A.scratch, A.scratch_base, (uint64_t)wt * (kTileWork / 8));
+    if (A.scratch->overflow) it->abort = 1;
+  }
+  for (int e = threadIdx.x; e < A.E; e += blockDim.x) {
+    const DEntry d = A.ent[e];
+    if (A.steps[d.step].kind != STEP_LIST && es[e].w)
+      atomicAdd((unsigned long long *)&A.qstats[(int64_t)d.q * QS_N + QS_EXPAND], (unsigned long long)es[e].w);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_nz_write(const IterArgs A) {
+  __shared__ int64_t lds[kWaves];
+  __shared__ int ldi[kWaves];
+  __shared__ int sh_e;
+  IterScalars *it = A.it;
+  if (it->abort) return;
+  EState *es = A.es;
+  int64_t tb, te;
+  block_share(it->node_tiles, tb, te);
+  int64_t run_nz = A.blk_off_a[blockIdx.x], run_w = A.blk_off_b[blockIdx.x];
+  for (int64_t t = tb; t < te; ++t) {
+    if (threadIdx.x == 0) sh_e = node_entry(A, t);
+    __syncthreads();
+    const int e = sh_e;
+    const int64_t i0 = (t - es[e].node_tile0) * kTileNodes, pn = es[e].prev_n;
+    for (int r = 0; r < kTileNodes / kBlock; ++r) {
+      const int64_t i = i0 + r * kBlock + threadIdx.x;
+      int64_t len = 0, lo = 0;
+      if (i < pn) { const int64_t gn = es[e].node0 + i; len = it->len[gn]; lo = it->lo[gn]; }
+      int ftot;
+      const int pos = block_excl_flag(len > 0, ftot, ldi);
+      int64_t wtot;
+      const int64_t wpos = block_excl_scan_i64(len, wtot, lds);
+      if (len > 0) {
+        const int64_t k = run_nz + pos;
+        it->nz_node[k] = (int32_t)i;
+        it->nz_lo[k] = lo;
+        it->nz_woff[k] = run_w + wpos - es[e].w_base;
+      }
+      run_nz += ftot;
+      run_w += wtot;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ expansion
+struct TileNz {
+  int64_t woff[kTileWork + 1];
+  int64_t lo[kTileWork + 1];
+  int32_t node[kTileWork + 1];
+  int count;
+  int e;
+  int64_t a, b;
+};
+
+__device__ __forceinline__ int64_t last_le_global(const int64_t *v, int64_t lo, int64_t hi, int64_t key) {
+  // last index k in [lo, hi) with v[k] <= key (v[lo] <= key holds)
+  while (hi - lo > 1) {
+    int64_t mid = (lo + hi) >> 1;
+    if (v[mid] <= key) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Load the non-empty nodes covering work tile t into LDS.
+__device__ __forceinline__ void load_tile(const IterArgs &A, int64_t t, TileNz &T) {
+  IterScalars *it = A.it;
+  EState *es = A.es;
+  __shared__ int64_t k0s, k1s;
+  if (threadIdx.x == 0) {
+    const int e = last_le(A.E, t, [&](int i) { return es[i].w_tile0; });
+    T.e = e;
+    T.a = (t - es[e].w_tile0) * kTileWork;
+    T.b = min(T.a + kTileWork, es[e].w);
+    const int64_t nb = es[e].nz_base, ne = nb + es[e].nz;
+    k0s = last_le_global(it->nz_woff, nb, ne, T.a);
+    k1s = last_le_global(it->nz_woff, k0s, ne, T.b - 1);
+    T.count = (int)(k1s - k0s + 1);
+  }
+  __syncthreads();
+  const int64_t k0 = k0s;
+  for (int k = threadIdx.x; k < T.count; k += blockDim.x) {
+    T.woff[k] = it->nz_woff[k0 + k];
+    T.lo[k] = it->nz_lo[k0 + k];
+    T.node[k] = it->nz_node[k0 + k];
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ int tile_find(const TileNz &T, int64_t w) {
+  int lo = 0, hi = T.count;   // last k with woff[k] <= w
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (T.woff[mid] <= w) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int32_t candidate(const IterArgs &A, const EState &E, const DStep &S, const TileNz &T,
+                                             int k, int64_t w) {
+  const int64_t off = w - T.woff[k];
+  if (S.kind == STEP_LIST) return E.list[off];
+  return A.g.idx[S.dir][T.lo[k] + off];
+}
+
+__device__ __forceinline__ bool test_candidate(const IterArgs &A, const EState &E, const DStep &S, int32_t node,
+                                               int32_t c, int &probes) {
+  for (int f = S.list_nfilt; f < S.nfilt; ++f)
+    if (!bit_test(A.filt[S.filt0 + f], c)) return false;
+  for (int k = 0; k < S.nchk; ++k) {
+    const DCheck ck = A.checks[S.chk0 + k];
+    const int32_t b = E.prev[(int64_t)ck.col * E.prev_n + node];
+    if (!seg_has(A.g, ck.dir, b, ck.label, c, probes)) return false;
+  }
+  for (int k = 0; k < S.nself; ++k)
+    if (!seg_has(A.g, 0, c, A.ints[S.self0 + k], c, probes)) return false;
+  return true;
+}
+
+__global__ __launch_bounds__(kBlock) void k_expand_count(const IterArgs A) {
+  __shared__ TileNz T;
+  __shared__ int64_t lds[kWaves];
+  IterScalars *it = A.it;
+  if (it->abort) return;
+  EState *es = A.es;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int64_t tb, te;
+  block_share(it->work_tiles, tb, te);
+  int64_t bsum = 0;
+  for (int64_t t = tb; t < te; ++t) {
+    load_tile(A, t, T);
+    const int e = T.e;
+    const EState E = es[e];
+    const DEntry d = A.ent[e];
+    const DStep S = A.steps[d.step];
+    int64_t c_tile = 0;
+    int probes = 0;
+    for (int r = 0; r < kTileWork / kBlock; ++r) {
+      const int64_t w = T.a + r * kBlock + threadIdx.x;
+      bool ok = false;
+      if (w < T.b) {
+        const int k = tile_find(T, w);
+        const int32_t c = candidate(A, E, S, T, k, w);
+        ok = test_candidate(A, E, S, T.node[k], c, probes);
+      }
+      const uint64_t bal = __ballot(ok);
+      if (lane == 0) {
+        uint32_t *vw = it->valid + t * (kTileWork / 32) + (r * kBlock + wv * 64) / 32;
+        vw[0] = (uint32_t)bal;
+        vw[1] = (uint32_t)(bal >> 32);
+      }
+      c_tile += ok;
+    }
+    c_tile = block_sum_i64(c_tile, lds);
+    int64_t pr = block_sum_i64(probes, lds);
+    if (threadIdx.x == 0) {
+      if (c_tile) atomicAdd((unsigned long long *)&es[e].cnt, (unsigned long long)c_tile);
+      if (pr) atomicAdd((unsigned long long *)&A.qstats[(int64_t)d.q * QS_N + QS_PROBE], (unsigned long long)pr);
+    }
+    bsum += c_tile;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) A.blk_a[blockIdx.x] = bsum;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_expand(const IterArgs A) {
+  __shared__ int64_t lds[1024];
+  IterScalars *it = A.it;
+  if (it->abort) return;
+  EState *es = A.es;
+  wg_scan(A.grid, [&](int64_t i) { return A.blk_a[i]; }, [&](int64_t i, int64_t v) { A.blk_off_a[i] = v; }, lds);
+  const int64_t tot = wg_scan(A.E, [&](int64_t i) { return es[i].cnt; },
+                              [&](int64_t i, int64_t v) { es[i].out_base = v; }, lds);
+  if (threadIdx.x == 0) it->cnt_total = tot;
+  for (int e = threadIdx.x; e < A.E; e += blockDim.x) {
+    const DEntry d = A.ent[e];
+    const DStep S = A.steps[d.step];
+    const int64_t cnt = es[e].cnt;
+    int32_t *out = nullptr;
+    int64_t n_rec = cnt;
+    if (cnt > 0 && S.ncols_out > 0) {
+      out = (int32_t *)arena_alloc(A.tree, A.tree_base, sizeof(int32_t) * (uint64_t)cnt * S.ncols_out);
+      if (!out) {
+        n_rec = -1;
+        A.qstats[(int64_t)d.q * QS_N + QS_OVERFLOW] = 1;
+      }
+    }
+    if (cnt > 2147483647LL && S.ncols_out > 0) {   // parent indices are int32
+      out = nullptr;
+      n_rec = -1;
+      A.qstats[(int64_t)d.q * QS_N + QS_OVERFLOW] = 2;
+    }
+    es[e].out = out;
+    A.lvl_ptr[(int64_t)d.q * kMaxLevels + d.level] = out;
+    A.lvl_n[(int64_t)d.q * kMaxLevels + d.level] = n_rec;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_expand_write(const IterArgs A) {
+  __shared__ TileNz T;
+  __shared__ int ldi[kWaves];
+  IterScalars *it = A.it;
+  if (it->abort) return;
+  EState *es = A.es;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int64_t tb, te;
+  block_share(it->work_tiles, tb, te);
+  int64_t run = A.blk_off_a[blockIdx.x];
+  for (int64_t t = tb; t < te; ++t) {
+    load_tile(A, t, T);
+    const int e = T.e;
+    const EState E = es[e];
+    const DStep S = A.steps[A.ent[e].step];
+    for (int r = 0; r < kTileWork / kBlock; ++r) {
+      const uint32_t *vw = it->valid + t * (kTileWork / 32) + (r * kBlock + wv * 64) / 32;
+      const uint64_t bal = (uint64_t)vw[0] | ((uint64_t)vw[1] << 32);
+      const bool ok = (bal >> lane) & 1ull;
+      int tot;
+      const int pos = block_excl_flag(ok, tot, ldi);
+      if (ok && E.out) {
+        const int64_t w = T.a + r * kBlock + threadIdx.x;
+        const int k = tile_find(T, w);
+        const int32_t c = candidate(A, E, S, T, k, w);
+        const int64_t li = run + pos - E.out_base;
+        const int64_t cnt = E.cnt;
+        const int32_t node = T.node[k];
+        E.out[li] = node;
+        E.out[cnt + li] = c;
+        for (int j = 0; j < S.ncopy; ++j)
+          E.out[(int64_t)(2 + j) * cnt + li] = E.prev[(int64_t)A.ints[S.copy0 + j] * E.prev_n + node];
+      }
+      run += tot;
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ results
+// Rows [first, first + n) of one query: walk each leaf's parents to the root.
+__global__ __launch_bounds__(kBlock) void k_enumerate(int32_t *const *lvl_ptr, const int64_t *lvl_n, int k,
+                                                      const int32_t *var_rank, int64_t first, int64_t n,
+                                                      int32_t *rows) {
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+    int64_t node = first + r;
+    for (int j = k - 1; j >= 0; --j) {
+      const int32_t *L = lvl_ptr[j];
+      const int64_t nj = lvl_n[j];
+      rows[r * k + var_rank[j]] = L[nj + node];
+      node = L[node];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+hipError_t launch_iteration(const IterArgs &A, hipStream_t s) {
+  const dim3 G(A.grid), B(kBlock), W1(1024);
+  hipLaunchKernelGGL(k_it_setup, dim3(1), W1, 0, s, A);
+  if (A.nclear) hipLaunchKernelGGL(k_clear, G, B, 0, s, A);
+  if (A.S) hipLaunchKernelGGL(k_seed, G, B, 0, s, A);
+  if (A.has_list) {
+    hipLaunchKernelGGL(k_list_count, G, B, 0, s, A);
+    hipLaunchKernelGGL(k_list_scan, dim3(1), W1, 0, s, A);
+    hipLaunchKernelGGL(k_list_write, G, B, 0, s, A);
+  }
+  if (A.D) {
+    hipLaunchKernelGGL(k_dom_frontier, G, B, 0, s, A);
+    hipLaunchKernelGGL(k_dom_push, G, B, 0, s, A);
+    hipLaunchKernelGGL(k_dom_pull, G, B, 0, s, A);
+  }
+  hipLaunchKernelGGL(k_lookup, G, B, 0, s, A);
+  hipLaunchKernelGGL(k_scan_nodes, dim3(1), W1, 0, s, A);
+  hipLaunchKernelGGL(k_nz_write, G, B, 0, s, A);
+  hipLaunchKernelGGL(k_expand_count, G, B, 0, s, A);
+  hipLaunchKernelGGL(k_scan_expand, dim3(1), W1, 0, s, A);
+  hipLaunchKernelGGL(k_expand_write, G, B, 0, s, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_enumerate(int32_t *const *lvl_ptr, const int64_t *lvl_n, int k, const int32_t *var_rank,
+                            int64_t first, int64_t n, int32_t *rows, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t g = (n + kBlock - 1) / kBlock;
+  if (g > 8192) g = 8192;
+  hipLaunchKernelGGL(k_enumerate, dim3((unsigned)g), dim3(kBlock), 0, s, lvl_ptr, lvl_n, k, var_rank, first, n,
+                     rows);
+  return hipGetLastError();
+}
+
+}  // namespace gs
+
+namespace gs {
+
+// Standalone pieces of an iteration, used by the matrix-algebra primitives of the ABI.
+hipError_t launch_list_only(const IterArgs &A, hipStream_t s) {
+  const dim3 G(A.grid), B(kBlock), W1(1024);
+  hipLaunchKernelGGL(k_it_setup, dim3(1), W1, 0, s, A);
+  hipLaunchKernelGGL(k_list_count, G, B, 0, s, A);
+  hipLaunchKernelGGL(k_list_scan, dim3(1), W1, 0, s, A);
+  hipLaunchKernelGGL(k_list_write, G, B, 0, s, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_domain_only(const IterArgs &A, hipStream_t s) {
+  const dim3 G(A.grid), B(kBlock);
+  hipLaunchKernelGGL(k_dom_push, G, B, 0, s, A);
+  hipLaunchKernelGGL(k_dom_pull, G, B, 0, s, A);
+  return hipGetLastError();
+}
+
+}  // namespace gs

@@ -1,0 +1,46 @@
+// Launchers and argument block of the query-evaluation kernels (query.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "gs_device.hpp"
+
+namespace gs {
+
+// Everything one iteration's kernels read, passed by value to each kernel.
+struct IterArgs {
+  DevGraph g;
+  const DEntry *ent;
+  int32_t E;               // entries (queries advancing this iteration)
+  int32_t S;               // seeds to fill
+  int32_t D;               // domains
+  int32_t nclear;          // bitmaps to zero
+  int32_t has_list;        // any LIST step among the entries
+  int32_t grid;            // workgroups of the fixed-grid kernels
+  const DStep *steps;
+  const uint64_t *const *filt;
+  const DCheck *checks;
+  const int32_t *ints;     // self-loop labels and copy columns
+  const DConst *cconst;
+  const DSeed *seeds;
+  const DDomain *doms;
+  int64_t *fcount;         // per domain: |F|
+  uint64_t *const *clear;
+  EState *es;
+  IterScalars *it;
+  int32_t **lvl_ptr;       // [q * kMaxLevels + level]
+  int64_t *lvl_n;          // [q * kMaxLevels + level], -1 = overflow
+  int64_t *qstats;         // [q * QS_N + counter]
+  DArena *scratch;
+  char *scratch_base;
+  DArena *tree;
+  char *tree_base;
+  int64_t *blk_a, *blk_b, *blk_off_a, *blk_off_b;   // grid entries each
+};
+
+hipError_t launch_iteration(const IterArgs &A, hipStream_t s);
+hipError_t launch_list_only(const IterArgs &A, hipStream_t s);
+hipError_t launch_domain_only(const IterArgs &A, hipStream_t s);
+hipError_t launch_enumerate(int32_t *const *lvl_ptr, const int64_t *lvl_n, int k, const int32_t *var_rank,
+                            int64_t first, int64_t n, int32_t *rows, hipStream_t s);
+
+}  // namespace gs

@@ -75,3 +75,31 @@ def sort_rows(rows):
     if rows.ndim == 1 or rows.shape[1] == 0 or len(rows) == 0:
         return rows.astype(np.int32)
     return rows[np.lexsort(rows.T[::-1])].astype(np.int32)
+
+
+def pack_bits(v):
+    """uint8 0/1 vector -> uint64 words, bit i = word i//64, bit i%64."""
+    v = np.asarray(v, dtype=np.uint8)
+    n = len(v)
+    w = (n + 63) // 64
+    pad = np.zeros(w * 64, np.uint8)
+    pad[:n] = v
+    bits = pad.reshape(w, 64).astype(np.uint64)
+    return (bits << np.arange(64, dtype=np.uint64)).sum(axis=1).astype(np.uint64)
+
+
+def unpack_bits(words, n):
+    words = np.asarray(words, dtype=np.uint64)
+    bits = ((words[:, None] >> np.arange(64, dtype=np.uint64)) & np.uint64(1)).astype(np.uint8)
+    return bits.reshape(-1)[:n]
+
+
+def engine_rows(gs, engine, q, flags=0):
+    """Run one query through the C-ABI; (count, rows sorted lexicographically)."""
+    r = gs.gs_query_run(engine, q, flags)
+    try:
+        cnt = gs.gs_result_count(r)
+        rows = gs.gs_result_rows(r) if not (flags & gs.GS_COUNT_ONLY) else None
+    finally:
+        gs.gs_result_free(r)
+    return cnt, (sort_rows(rows) if rows is not None else None)

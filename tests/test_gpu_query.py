@@ -1,0 +1,238 @@
+"""Whole-query parity: the HIP engine's rows and counts against the oracle
+(and brute force on tiny graphs), element by element after sorting."""
+import json
+import os
+import random
+
+import numpy as np
+import pytest
+
+import oracle
+import workload
+from helpers import brute_force, engine_rows, random_query, sort_rows
+
+gs = pytest.importorskip("paper_2106_14038_amd")
+pytestmark = pytest.mark.gpu
+
+SMALL = dict(tree_bytes=2 << 30, scratch_bytes=1 << 30)
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def make_engine(trip, n, P, **kw):
+    e = gs.gs_engine_create(gs.options(**{**SMALL, **kw}))
+    gs.gs_load_triples(e, n, P, trip)
+    return e
+
+
+def has_isolated_var(q):
+    deg = [0] * q["n_qv"]
+    for a, _, b in q["edges"]:
+        deg[a] += 1
+        deg[b] += 1
+    return any(d == 0 and q["qv_const"][i] < 0 for i, d in enumerate(deg))
+
+
+def test_reconstructed_example_query():
+    ex = json.load(open(os.path.join(GOLD, "query_example_7_2.json")))
+    lsp = json.load(open(os.path.join(GOLD, "lspm_example_6_3.json")))
+    trip = []
+    for i in range(lsp["n"]):
+        if lsp["Mr"][i + 1] - lsp["Mr"][i] == 1:
+            r = lsp["Mr"][i]
+            trip += [(i, lsp["Val"][k], lsp["Col"][k]) for k in range(lsp["Pr"][r], lsp["Pr"][r + 1])]
+    trip = np.array(trip, np.int32)
+    q = ex["query"]
+    q = {"n_qv": q["n_qv"], "qv_const": q["qv_const"], "edges": [tuple(x) for x in q["edges"]]}
+    for mode in (gs.GS_DOMAIN_AUTO, gs.GS_DOMAIN_PUSH, gs.GS_DOMAIN_PULL, gs.GS_DOMAIN_OFF):
+        e = make_engine(trip, ex["n"], ex["n_labels"], domain_mode=mode)
+        try:
+            cnt, rows = engine_rows(gs, e, q)
+            assert cnt == 2 and rows.tolist() == ex["expect_rows"], mode
+            r = gs.gs_query_run(e, q)
+            st = gs.gs_result_stats(r)
+            assert st.n_domains == 1 and st.level_nodes[0] == 1   # only v2 = 1 survives level 0
+            gs.gs_result_free(r)
+        finally:
+            gs.gs_engine_destroy(e)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_random_tiny_graphs_vs_brute_force(seed):
+    rng = random.Random(500 + seed)
+    for case in range(40):
+        n, P = rng.randint(1, 9), rng.randint(1, 4)
+        m = rng.randint(1, n * n * P)
+        trip = workload.uniform_graph(rng.randrange(1 << 30), n, P, m)
+        e = make_engine(trip, n, P, domain_mode=rng.choice([0, 1, 2, 3]))
+        try:
+            for _ in range(5):
+                nv = rng.randint(1, 4)
+                q = random_query(rng, n, P, nv, rng.randint(0, 2), connected=rng.random() < 0.8)
+                if has_isolated_var(q):
+                    continue
+                print(f"[tiny] seed={seed} case={case} q={q}", flush=True)
+                bf = brute_force(trip, n, P, q)
+                cnt, rows = engine_rows(gs, e, q)
+                assert cnt == len(bf), q
+                assert np.array_equal(rows.reshape(-1, nv), bf.reshape(-1, nv)), q
+        finally:
+            gs.gs_engine_destroy(e)
+
+
+def test_constant_only_queries():
+    trip = np.array([[0, 1, 1], [1, 2, 2], [2, 1, 2]], np.int32)
+    e = make_engine(trip, 3, 2)
+    try:
+        for q, expect in [({"n_qv": 2, "qv_const": [0, 1], "edges": [(0, 1, 1)]}, 1),
+                          ({"n_qv": 2, "qv_const": [0, 1], "edges": [(1, 1, 0)]}, 0),
+                          ({"n_qv": 1, "qv_const": [2], "edges": [(0, 1, 0)]}, 1),
+                          ({"n_qv": 3, "qv_const": [-1, 0, 1], "edges": [(0, 1, 0), (1, 2, 2)]}, 0),
+                          ({"n_qv": 3, "qv_const": [-1, 0, 1], "edges": [(2, 2, 0), (1, 1, 2)]}, 1)]:
+            cnt, rows = engine_rows(gs, e, q)
+            assert cnt == expect, q
+    finally:
+        gs.gs_engine_destroy(e)
+
+
+@pytest.fixture(scope="module")
+def c0():
+    trip = workload.c0_graph()
+    n, P = workload.C0["n"], workload.C0["n_labels"]
+    return trip, n, P, oracle.Graph(trip, n, P)
+
+
+def c0_queries(trip, n, nper=12):
+    qs = [workload.c0_star_query(trip, n)]
+    for shape in ("chain4", "star5", "snowflake8", "triangle", "mixed"):
+        qs += workload.walk_queries(trip, n, 7, shape, nper)
+    return qs
+
+
+def test_c0_star_query(c0):
+    trip, n, P, G = c0
+    q = workload.c0_star_query(trip, n)
+    ocnt, orows = G.eval(q)
+    e = make_engine(trip, n, P)
+    try:
+        cnt, rows = engine_rows(gs, e, q)
+        assert cnt == ocnt and np.array_equal(rows, orows)
+    finally:
+        gs.gs_engine_destroy(e)
+
+
+@pytest.mark.parametrize("mode", [gs.GS_DOMAIN_AUTO, gs.GS_DOMAIN_PUSH, gs.GS_DOMAIN_PULL, gs.GS_DOMAIN_OFF])
+def test_c0_walk_queries_all_domain_modes(c0, mode):
+    trip, n, P, G = c0
+    e = make_engine(trip, n, P, domain_mode=mode)
+    try:
+        for i, q in enumerate(c0_queries(trip, n)):
+            ocnt, _ = G.eval(q, rows=False, work_cap=50_000_000)
+            if ocnt > 2_000_000:
+                continue
+            print(f"[c0] mode={mode} i={i} count={ocnt} q={q}", flush=True)
+            ocnt, orows = G.eval(q, rows_cap=ocnt + 1)
+            cnt, rows = engine_rows(gs, e, q)
+            assert cnt == ocnt, (i, q)
+            assert np.array_equal(rows, orows), (i, q)
+    finally:
+        gs.gs_engine_destroy(e)
+
+
+def test_batch_equals_alone_and_count_only(c0):
+    trip, n, P, G = c0
+    qs = [q for q in c0_queries(trip, n, nper=6) if G.eval(q, rows=False, work_cap=20_000_000)[0] < 500_000]
+    e = make_engine(trip, n, P)
+    try:
+        alone = [engine_rows(gs, e, q) for q in qs]
+        rs = gs.gs_batch_run(e, qs)
+        try:
+            for (cnt, rows), r, q in zip(alone, rs, qs):
+                assert gs.gs_result_count(r) == cnt
+                assert np.array_equal(sort_rows(gs.gs_result_rows(r)), rows), q
+        finally:
+            for r in rs:
+                gs.gs_result_free(r)
+        rs = gs.gs_batch_run(e, qs, gs.GS_COUNT_ONLY)
+        try:
+            for (cnt, _), r in zip(alone, rs):
+                assert gs.gs_result_count(r) == cnt
+            with pytest.raises(gs.GsError) as err:
+                gs.gs_result_rows(rs[0])
+            assert err.value.status == gs.GS_EUNSUPPORTED
+        finally:
+            for r in rs:
+                gs.gs_result_free(r)
+    finally:
+        gs.gs_engine_destroy(e)
+
+
+def test_tree_levels_are_a_valid_binding_tree(c0):
+    trip, n, P, G = c0
+    q = workload.walk_queries(trip, n, 3, "snowflake8", 1)[0]
+    e = make_engine(trip, n, P)
+    try:
+        r = gs.gs_query_run(e, q)
+        info = gs.gs_plan_query(q)
+        k = info.n_vars
+        levels = [gs.gs_result_level(r, j) for j in range(k)]
+        for j in range(1, k):
+            par, vid = levels[j]
+            npar = len(levels[j - 1][0])
+            assert np.all(par >= 0) and np.all(par < npar)
+            assert np.all(np.diff(par) >= 0)          # children of a node are contiguous, in node order
+        # leaf paths are the rows
+        par_last, vid_last = levels[-1]
+        rows = np.zeros((len(vid_last), k), np.int64)
+        node = np.arange(len(vid_last))
+        for j in range(k - 1, -1, -1):
+            par, vid = levels[j]
+            rows[:, j] = vid[node]
+            node = par[node]
+        var_rank = np.argsort(np.argsort(np.array(info.order[:k])))
+        ordered = np.zeros_like(rows)
+        ordered[:, var_rank] = rows
+        assert np.array_equal(sort_rows(ordered), sort_rows(gs.gs_result_rows(r)))
+        st = gs.gs_result_stats(r)
+        assert st.count == len(vid_last) and st.t_expand > 0 and st.bytes_alg > 0
+        gs.gs_result_free(r)
+    finally:
+        gs.gs_engine_destroy(e)
+
+
+def test_hub_rows_span_many_tiles():
+    # a hub with 20k out-edges on one label and 5k in-edges: segments far longer than a tile
+    rng = np.random.default_rng(9)
+    n = 30000
+    hub = np.stack([np.zeros(20000, np.int32), np.ones(20000, np.int32), rng.permutation(n)[:20000].astype(np.int32)], 1)
+    back = np.stack([rng.permutation(n)[:5000].astype(np.int32), np.full(5000, 2, np.int32), np.zeros(5000, np.int32)], 1)
+    noise = workload.uniform_graph(4, n, 3, 60000)
+    trip = np.unique(np.concatenate([hub, back, noise]), axis=0)
+    G = oracle.Graph(trip, n, 3)
+    e = make_engine(trip, n, 3)
+    try:
+        qs = [{"n_qv": 2, "qv_const": [-1, -1], "edges": [(0, 1, 1)]},
+              {"n_qv": 3, "qv_const": [-1, -1, -1], "edges": [(0, 1, 1), (2, 2, 0)]},
+              {"n_qv": 3, "qv_const": [0, -1, -1], "edges": [(0, 1, 1), (1, 3, 2)]},
+              {"n_qv": 3, "qv_const": [-1, -1, -1], "edges": [(0, 1, 1), (1, 3, 2), (2, 2, 0)]},
+              {"n_qv": 4, "qv_const": [-1, -1, -1, -1], "edges": [(0, 1, 1), (1, 1, 2), (3, 2, 0)]}]
+        for q in qs:
+            ocnt, orows = G.eval(q, rows_cap=50_000_000)
+            print(f"[hub] count={ocnt} q={q}", flush=True)
+            cnt, rows = engine_rows(gs, e, q)
+            assert cnt == ocnt and np.array_equal(rows, orows), q
+    finally:
+        gs.gs_engine_destroy(e)
+
+
+def test_query_errors():
+    trip = np.array([[0, 1, 1]], np.int32)
+    e = make_engine(trip, 2, 1)
+    try:
+        for q, st in [({"n_qv": 2, "qv_const": [-1, -1], "edges": [(0, 2, 1)]}, gs.GS_ERANGE),
+                      ({"n_qv": 2, "qv_const": [-1, 7], "edges": [(0, 1, 1)]}, gs.GS_ERANGE),
+                      ({"n_qv": 2, "qv_const": [-1, -1], "edges": [(0, 1, 3)]}, gs.GS_EINVAL)]:
+            with pytest.raises(gs.GsError) as err:
+                gs.gs_query_run(e, q)
+            assert err.value.status == st
+    finally:
+        gs.gs_engine_destroy(e)
