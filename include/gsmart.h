@@ -106,6 +106,7 @@ typedef struct {
   float push_pull_theta;      /* push when est. push work < theta * est. pull work; 0 = 1.0 */
   int32_t grid_blocks;        /* workgroups of the fixed-grid kernels; 0 = 8 per compute unit */
   int32_t use_graphs;         /* batched form: capture each step's launches in a hipGraph (1) or not (0) */
+  int32_t profile_kernels;    /* record HIP events around every kernel launch (gs_kernel_stats) */
 } gs_options;
 
 /* Per-query counters, filled by gs_result_stats. T counts LSpM nonzeros read
@@ -236,6 +237,20 @@ gs_status gs_result_stats(const gs_result *result, gs_query_stats *stats);
  * the bound vertex of level j's query vertex; *n = nodes. With par/vid NULL
  * only *n is returned. Section 7.1. */
 gs_status gs_result_level(gs_result *result, int32_t level, int32_t *par, int32_t *vid, int64_t *n);
+
+/* Kernel timing, available when gs_options.profile_kernels was set: per
+ * kernel of the evaluation, launches, device milliseconds (HIP events on the
+ * engine's stream around each launch) and algorithmic bytes moved (ids and
+ * bitmap words read, tree columns written, as counted by the kernels). Fills
+ * up to cap entries, *n = kernels with at least one launch; reset != 0 clears
+ * the counters after reading. */
+typedef struct {
+  const char *name;           /* static string */
+  int64_t launches;
+  double ms;
+  double bytes_alg;           /* 0 where no byte model is kept */
+} gs_kernel_stat;
+gs_status gs_kernel_stats(gs_engine *engine, gs_kernel_stat *out, int32_t cap, int32_t *n, int reset);
 
 /* Free a result. NULL is ignored. */
 void gs_result_free(gs_result *result);

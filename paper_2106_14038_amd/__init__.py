@@ -55,7 +55,7 @@ class gs_options(ctypes.Structure):
                 ("scratch_bytes", ctypes.c_uint64), ("alloc", ALLOC_FN), ("free", FREE_FN),
                 ("alloc_ctx", ctypes.c_void_p), ("domain_mode", ctypes.c_int32),
                 ("push_pull_theta", ctypes.c_float), ("grid_blocks", ctypes.c_int32),
-                ("use_graphs", ctypes.c_int32)]
+                ("use_graphs", ctypes.c_int32), ("profile_kernels", ctypes.c_int32)]
 
 
 class gs_query_stats(ctypes.Structure):
@@ -70,6 +70,11 @@ class gs_plan_info(ctypes.Structure):
     _fields_ = [("n_vars", ctypes.c_int32), ("order", ctypes.c_int32 * 64), ("parent_edge", ctypes.c_int32 * 64),
                 ("n_groups", ctypes.c_int32), ("group_vertex", ctypes.c_int32 * 64),
                 ("edge_group", ctypes.c_int32 * 64), ("n_roots", ctypes.c_int32), ("roots", ctypes.c_int32 * 64)]
+
+
+class gs_kernel_stat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char_p), ("launches", ctypes.c_int64), ("ms", ctypes.c_double),
+                ("bytes_alg", ctypes.c_double)]
 
 
 class gs_server_options(ctypes.Structure):
@@ -107,6 +112,7 @@ SIGNATURES = {
     "gs_submit": ([_vp, _P(gs_query), _u32, _P(_u64)], ctypes.c_int),
     "gs_poll": ([_vp, _u64, _P(_vp)], ctypes.c_int),
     "gs_server_stop": ([_vp, _P(gs_server_stats)], ctypes.c_int),
+    "gs_kernel_stats": ([_vp, _P(gs_kernel_stat), _i32, _P(_i32), ctypes.c_int], ctypes.c_int),
     "gs_last_error": ([], ctypes.c_char_p),
 }
 
@@ -288,6 +294,14 @@ def gs_result_level(result, level: int):
     vid = np.zeros(max(n.value, 1), np.int32)
     _check(lib().gs_result_level(result, level, par.ctypes.data, vid.ctypes.data, ctypes.byref(n)))
     return par[:n.value], vid[:n.value]
+
+
+def gs_kernel_stats(engine, reset: bool = False) -> dict:
+    arr = (gs_kernel_stat * 32)()
+    n = ctypes.c_int32()
+    _check(lib().gs_kernel_stats(engine, arr, 32, ctypes.byref(n), int(reset)))
+    return {arr[i].name.decode(): {"launches": arr[i].launches, "ms": arr[i].ms, "bytes_alg": arr[i].bytes_alg}
+            for i in range(min(n.value, 32))}
 
 
 def gs_result_free(result):

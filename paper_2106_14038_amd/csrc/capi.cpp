@@ -361,6 +361,30 @@ void gs_result_free(gs_result *result) {
   }
 }
 
+static const char *kSlotNames[KS_N] = {"setup", "clear", "seed", "list_count", "list_scan", "list_write",
+                                       "dom_frontier", "dom_push", "dom_pull", "lookup", "scan_nodes", "nz_write",
+                                       "expand_count", "scan_expand", "expand_write"};
+
+gs_status gs_kernel_stats(gs_engine *engine, gs_kernel_stat *out, int32_t cap, int32_t *n, int reset) {
+  if (!engine || !n || (cap > 0 && !out)) { set_error("bad argument"); return GS_EINVAL; }
+  Engine &E = engine->e;
+  std::lock_guard<std::mutex> lk(E.mu);
+  int k = 0;
+  for (int i = 0; i < KS_N; ++i) {
+    if (E.kstat[i].launches == 0) continue;
+    if (k < cap) {
+      out[k].name = kSlotNames[i];
+      out[k].launches = E.kstat[i].launches;
+      out[k].ms = E.kstat[i].ms;
+      out[k].bytes_alg = E.kstat[i].bytes;
+    }
+    ++k;
+  }
+  *n = k;
+  if (reset) for (int i = 0; i < KS_N; ++i) E.kstat[i] = Engine::KStat();
+  return GS_OK;
+}
+
 gs_status gs_server_start(gs_engine *engine, const gs_server_options *options, gs_server **out) {
   if (!engine || !out) { set_error("null argument"); return GS_EINVAL; }
   return (gs_status)server_start(&engine->e, options, out);

@@ -47,6 +47,7 @@ Engine::~Engine() {
   dfree(tree_base);
   dfree(scratch_base);
   dfree(d_arenas);
+  for (hipEvent_t e : events) (void)hipEventDestroy(e);
   if (own_stream && stream) (void)hipStreamDestroy(stream);
 }
 
@@ -388,7 +389,7 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
   const uint64_t zero_end = off;
   const uint64_t o_fc = off; off += align256(sizeof(int64_t) * max_d);
   const uint64_t o_es = off; off += align256(sizeof(EState) * max_e);
-  const uint64_t o_it = off; off += align256(sizeof(IterScalars));
+  const uint64_t o_it = off; off += align256(sizeof(IterScalars) * (uint64_t)std::max(maxk, 1));
   const uint64_t o_blk = off; off += align256(sizeof(int64_t) * 4 * (uint64_t)E.grid);
   if (off > E.tree_cap) { set_error("tree arena too small for the batch tables"); return GS_ENOMEM; }
   char *base = E.tree_base;
@@ -408,6 +409,15 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
   HIPCHK(hipEventCreate(&ev1));
   HIPCHK(hipEventRecord(ev0, s));
   // 5. iterations
+  const bool prof = E.opt.profile_kernels != 0;
+  if (prof) {
+    const size_t need = (size_t)2 * KS_N * std::max(maxk, 1);
+    while (E.events.size() < need) {
+      hipEvent_t ev;
+      HIPCHK(hipEventCreate(&ev));
+      E.events.push_back(ev);
+    }
+  }
   for (int t = 0; t < maxk; ++t) {
     IterArgs A{};
     A.g = E.g;
@@ -428,7 +438,7 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
     A.fcount = (int64_t *)dp(o_fc);
     A.clear = (uint64_t *const *)dp(tab_off + o_clr) + clr_off[t];
     A.es = (EState *)dp(o_es);
-    A.it = (IterScalars *)dp(o_it);
+    A.it = (IterScalars *)dp(o_it) + t;
     A.lvl_ptr = (int32_t **)dp(o_lvlp);
     A.lvl_n = (int64_t *)dp(o_lvln);
     A.qstats = (int64_t *)dp(o_qs);
@@ -438,7 +448,7 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
     A.tree_base = E.tree_base;
     int64_t *blk = (int64_t *)dp(o_blk);
     A.blk_a = blk; A.blk_b = blk + E.grid; A.blk_off_a = blk + 2 * E.grid; A.blk_off_b = blk + 3 * E.grid;
-    hipError_t e = launch_iteration(A, s);
+    hipError_t e = launch_iteration(A, s, prof ? &E.events[(size_t)2 * KS_N * t] : nullptr);
     if (e != hipSuccess) { set_error(std::string("launch: ") + hipGetErrorString(e)); return GS_EDEVICE; }
   }
   // constant-only queries
@@ -469,6 +479,48 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
   HIPCHK(hipStreamSynchronize(s));
   float ms = 0;
   HIPCHK(hipEventElapsedTime(&ms, ev0, ev1));
+  if (prof) {
+    std::vector<IterScalars> its(std::max(maxk, 1));
+    HIPCHK(hipMemcpy(its.data(), dp(o_it), sizeof(IterScalars) * its.size(), hipMemcpyDeviceToHost));
+    for (int t = 0; t < maxk; ++t) {
+      const IterScalars &I = its[t];
+      bool ran[KS_N];
+      for (int k = 0; k < KS_N; ++k) ran[k] = true;
+      ran[KS_CLEAR] = clr_off[t + 1] > clr_off[t];
+      ran[KS_SEED] = t == 0 && !seeds.empty();
+      ran[KS_LIST_COUNT] = ran[KS_LIST_SCAN] = ran[KS_LIST_WRITE] = has_list[t] != 0;
+      ran[KS_DOM_FRONTIER] = ran[KS_DOM_PUSH] = ran[KS_DOM_PULL] = dom_off[t + 1] > dom_off[t];
+      // rows written this iteration, weighted by the columns each query writes
+      double wbytes = 0;
+      for (int i = 0; i < nq; ++i) {
+        if (Q[i].plan.n_vars <= t) continue;
+        const DStep &d = steps[Q[i].step0 + t];
+        const int64_t c = std::max<int64_t>(lvl_n[(size_t)i * kMaxLevels + t], 0);
+        if (d.ncols_out > 0) wbytes += (double)c * (4.0 * d.ncols_out + 4.0 * d.ncopy + 4.0);
+      }
+      for (int k = 0; k < KS_N; ++k) {
+        if (!ran[k]) continue;
+        float kms = 0;
+        if (hipEventElapsedTime(&kms, E.events[(size_t)2 * KS_N * t + 2 * k], E.events[(size_t)2 * KS_N * t + 2 * k + 1]) != hipSuccess) continue;
+        double b = 0;
+        const double W = (double)I.w_total, nz = (double)I.nz_total;
+        switch (k) {
+          case KS_EXPAND_COUNT:   // candidate ids, staged node records, filter words, parent bindings, probes, valid bits
+            b = 4 * W + 20 * nz + 8.0 * I.ftests + 4.0 * I.ctests + 4.0 * I.probes + W / 8; break;
+          case KS_EXPAND_WRITE:   // valid bits, staged node records, candidate ids + copies read + columns written
+            b = W / 8 + 20 * nz + wbytes; break;
+          case KS_LOOKUP:         // parent binding, offset pair, segment written
+            b = 36.0 * I.nodes_total; break;
+          case KS_NZ_WRITE:
+            b = 16.0 * I.nodes_total + 20 * nz; break;
+          default: break;
+        }
+        E.kstat[k].launches += 1;
+        E.kstat[k].ms += kms;
+        E.kstat[k].bytes += b;
+      }
+    }
+  }
   (void)hipEventDestroy(ev0);
   (void)hipEventDestroy(ev1);
   if (ms_out) *ms_out = ms;

@@ -67,6 +67,11 @@ struct Engine {
   void *work = nullptr;
   size_t work_bytes = 0;
 
+  // optional kernel timing (gs_options.profile_kernels)
+  struct KStat { int64_t launches = 0; double ms = 0, bytes = 0; };
+  KStat kstat[KS_N];
+  std::vector<hipEvent_t> events;  // pool, 2 * KS_N per iteration
+
   std::mutex mu;                   // serialises runs (server vs. direct use is documented as exclusive)
 
   void *dmalloc(size_t bytes);

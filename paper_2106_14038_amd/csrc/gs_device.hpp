@@ -97,7 +97,16 @@ struct IterScalars {
   int64_t *nz_lo, *nz_woff;// their segment start and entry-local work offset
   uint32_t *valid;         // expansion validity bits, kTileWork bits per work tile
   int32_t *list_buf;
+  // work counters of the expansion count pass (for algorithmic-byte accounting)
+  int64_t ftests;          // bitmap filter words tested
+  int64_t ctests;          // exact checks started (each reads one parent binding)
+  int64_t probes;          // label / id entries touched by binary searches
 };
+
+// Kernel slots of one iteration, for optional event timing.
+enum KSlot { KS_SETUP = 0, KS_CLEAR, KS_SEED, KS_LIST_COUNT, KS_LIST_SCAN, KS_LIST_WRITE, KS_DOM_FRONTIER,
+             KS_DOM_PUSH, KS_DOM_PULL, KS_LOOKUP, KS_SCAN_NODES, KS_NZ_WRITE, KS_EXPAND_COUNT, KS_SCAN_EXPAND,
+             KS_EXPAND_WRITE, KS_N };
 
 // Bump allocator over one device region; top and cap in bytes.
 struct DArena {

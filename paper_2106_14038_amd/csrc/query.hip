@@ -57,6 +57,9 @@ __global__ __launch_bounds__(1024) void k_it_setup(const IterArgs A) {
     A.scratch->overflow = 0;
     it->n_entries = A.E;
     it->abort = 0;
+    it->ftests = 0;
+    it->ctests = 0;
+    it->probes = 0;
   }
   for (int e = threadIdx.x; e < A.E; e += blockDim.x) {
     const DEntry d = A.ent[e];
@@ -504,10 +507,13 @@ __device__ __forceinline__ int32_t candidate(const IterArgs &A, const EState &E,
 }
 
 __device__ __forceinline__ bool test_candidate(const IterArgs &A, const EState &E, const DStep &S, int32_t node,
-                                               int32_t c, int &probes) {
-  for (int f = S.list_nfilt; f < S.nfilt; ++f)
+                                               int32_t c, int &probes, int &ftests, int &ctests) {
+  for (int f = S.list_nfilt; f < S.nfilt; ++f) {
+    ++ftests;
     if (!bit_test(A.filt[S.filt0 + f], c)) return false;
+  }
   for (int k = 0; k < S.nchk; ++k) {
+    ++ctests;
     const DCheck ck = A.checks[S.chk0 + k];
     const int32_t b = E.prev[(int64_t)ck.col * E.prev_n + node];
     if (!seg_has(A.g, ck.dir, b, ck.label, c, probes)) return false;
@@ -534,14 +540,14 @@ __global__ __launch_bounds__(kBlock) void k_expand_count(const IterArgs A) {
     const DEntry d = A.ent[e];
     const DStep S = A.steps[d.step];
     int64_t c_tile = 0;
-    int probes = 0;
+    int probes = 0, ftests = 0, ctests = 0;
     for (int r = 0; r < kTileWork / kBlock; ++r) {
       const int64_t w = T.a + r * kBlock + threadIdx.x;
       bool ok = false;
       if (w < T.b) {
         const int k = tile_find(T, w);
         const int32_t c = candidate(A, E, S, T, k, w);
-        ok = test_candidate(A, E, S, T.node[k], c, probes);
+        ok = test_candidate(A, E, S, T.node[k], c, probes, ftests, ctests);
       }
       const uint64_t bal = __ballot(ok);
       if (lane == 0) {
@@ -552,10 +558,17 @@ __global__ __launch_bounds__(kBlock) void k_expand_count(const IterArgs A) {
       c_tile += ok;
     }
     c_tile = block_sum_i64(c_tile, lds);
-    int64_t pr = block_sum_i64(probes, lds);
+    const int64_t pr = block_sum_i64(probes, lds);
+    const int64_t ft = block_sum_i64(ftests, lds);
+    const int64_t ct = block_sum_i64(ctests, lds);
     if (threadIdx.x == 0) {
       if (c_tile) atomicAdd((unsigned long long *)&es[e].cnt, (unsigned long long)c_tile);
-      if (pr) atomicAdd((unsigned long long *)&A.qstats[(int64_t)d.q * QS_N + QS_PROBE], (unsigned long long)pr);
+      if (pr) {
+        atomicAdd((unsigned long long *)&A.qstats[(int64_t)d.q * QS_N + QS_PROBE], (unsigned long long)pr);
+        atomicAdd((unsigned long long *)&it->probes, (unsigned long long)pr);
+      }
+      if (ft) atomicAdd((unsigned long long *)&it->ftests, (unsigned long long)ft);
+      if (ct) atomicAdd((unsigned long long *)&it->ctests, (unsigned long long)ct);
     }
     bsum += c_tile;
     __syncthreads();
@@ -652,27 +665,35 @@ __global__ __launch_bounds__(kBlock) void k_enumerate(int32_t *const *lvl_ptr, c
 }
 
 // ---------------------------------------------------------------- launchers
-hipError_t launch_iteration(const IterArgs &A, hipStream_t s) {
+hipError_t launch_iteration(const IterArgs &A, hipStream_t s, hipEvent_t *ev) {
   const dim3 G(A.grid), B(kBlock), W1(1024);
-  hipLaunchKernelGGL(k_it_setup, dim3(1), W1, 0, s, A);
-  if (A.nclear) hipLaunchKernelGGL(k_clear, G, B, 0, s, A);
-  if (A.S) hipLaunchKernelGGL(k_seed, G, B, 0, s, A);
+  auto mark = [&](int slot, int end) { if (ev) (void)hipEventRecord(ev[2 * slot + end], s); };
+#define GS_LAUNCH(slot, kern, grid, block)                          \
+  do {                                                              \
+    mark(slot, 0);                                                  \
+    hipLaunchKernelGGL(kern, grid, block, 0, s, A);                 \
+    mark(slot, 1);                                                  \
+  } while (0)
+  GS_LAUNCH(KS_SETUP, k_it_setup, dim3(1), W1);
+  if (A.nclear) GS_LAUNCH(KS_CLEAR, k_clear, G, B);
+  if (A.S) GS_LAUNCH(KS_SEED, k_seed, G, B);
   if (A.has_list) {
-    hipLaunchKernelGGL(k_list_count, G, B, 0, s, A);
-    hipLaunchKernelGGL(k_list_scan, dim3(1), W1, 0, s, A);
-    hipLaunchKernelGGL(k_list_write, G, B, 0, s, A);
+    GS_LAUNCH(KS_LIST_COUNT, k_list_count, G, B);
+    GS_LAUNCH(KS_LIST_SCAN, k_list_scan, dim3(1), W1);
+    GS_LAUNCH(KS_LIST_WRITE, k_list_write, G, B);
   }
   if (A.D) {
-    hipLaunchKernelGGL(k_dom_frontier, G, B, 0, s, A);
-    hipLaunchKernelGGL(k_dom_push, G, B, 0, s, A);
-    hipLaunchKernelGGL(k_dom_pull, G, B, 0, s, A);
+    GS_LAUNCH(KS_DOM_FRONTIER, k_dom_frontier, G, B);
+    GS_LAUNCH(KS_DOM_PUSH, k_dom_push, G, B);
+    GS_LAUNCH(KS_DOM_PULL, k_dom_pull, G, B);
   }
-  hipLaunchKernelGGL(k_lookup, G, B, 0, s, A);
-  hipLaunchKernelGGL(k_scan_nodes, dim3(1), W1, 0, s, A);
-  hipLaunchKernelGGL(k_nz_write, G, B, 0, s, A);
-  hipLaunchKernelGGL(k_expand_count, G, B, 0, s, A);
-  hipLaunchKernelGGL(k_scan_expand, dim3(1), W1, 0, s, A);
-  hipLaunchKernelGGL(k_expand_write, G, B, 0, s, A);
+  GS_LAUNCH(KS_LOOKUP, k_lookup, G, B);
+  GS_LAUNCH(KS_SCAN_NODES, k_scan_nodes, dim3(1), W1);
+  GS_LAUNCH(KS_NZ_WRITE, k_nz_write, G, B);
+  GS_LAUNCH(KS_EXPAND_COUNT, k_expand_count, G, B);
+  GS_LAUNCH(KS_SCAN_EXPAND, k_scan_expand, dim3(1), W1);
+  GS_LAUNCH(KS_EXPAND_WRITE, k_expand_write, G, B);
+#undef GS_LAUNCH
   return hipGetLastError();
 }
 

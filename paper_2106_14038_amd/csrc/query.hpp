@@ -37,7 +37,8 @@ struct IterArgs {
   int64_t *blk_a, *blk_b, *blk_off_a, *blk_off_b;   // grid entries each
 };
 
-hipError_t launch_iteration(const IterArgs &A, hipStream_t s);
+// ev: null, or 2 * KS_N events recorded around each launch (slot k: ev[2k], ev[2k+1]).
+hipError_t launch_iteration(const IterArgs &A, hipStream_t s, hipEvent_t *ev = nullptr);
 hipError_t launch_list_only(const IterArgs &A, hipStream_t s);
 hipError_t launch_domain_only(const IterArgs &A, hipStream_t s);
 hipError_t launch_enumerate(int32_t *const *lvl_ptr, const int64_t *lvl_n, int k, const int32_t *var_rank,

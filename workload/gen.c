@@ -125,8 +125,10 @@ typedef struct { trip_t *slot; uint64_t part_slots; } tset_t;
 static inline uint64_t trip_hash(uint32_t s, uint32_t p, uint32_t o) {
   return mix64(((uint64_t)s << 32 | o) ^ mix64((uint64_t)p + 0x51ED27ull));
 }
+/* A round inserts at most its draws, and only the last round keeps fewer
+ * than it inserts, so 2m + 8192 entries bound the set; slots are twice that. */
 static int tset_init(tset_t *t, int64_t m) {
-  uint64_t per = 64; while (per < (uint64_t)(2 * m / NPART + 64)) per <<= 1;
+  uint64_t per = 64; while (per < (uint64_t)(2 * (2 * m + 8192) / NPART + 64)) per <<= 1;
   t->part_slots = per;
   t->slot = (trip_t *)malloc(sizeof(trip_t) * per * NPART);
   if (!t->slot) return -1;
@@ -137,12 +139,13 @@ static int tset_init(tset_t *t, int64_t m) {
 static int tset_insert(tset_t *t, uint64_t h, uint32_t s, uint32_t p, uint32_t o) {
   uint64_t part = h % NPART, mask = t->part_slots - 1, i = (h >> 8) & mask;
   trip_t *base = t->slot + part * t->part_slots;
-  for (;;) {
+  for (uint64_t probes = 0; probes < t->part_slots; ++probes) {
     trip_t *e = base + i;
     if (e->s == 0xFFFFFFFFu) { e->s = s; e->p = p; e->o = o; return 1; }
     if (e->s == s && e->p == p && e->o == o) return 0;
     i = (i + 1) & mask;
   }
+  return -1;   /* partition full */
 }
 
 typedef void (*draw_fn)(const void *ctx, uint64_t idx, int32_t out[3]);
@@ -164,11 +167,16 @@ static int draw_distinct(const void *ctx, draw_fn fn, int64_t m, int32_t *out) {
       fn(ctx, next + (uint64_t)i, buf + 3 * i);
       if (buf[3 * i] >= 0) hv[i] = trip_hash((uint32_t)buf[3 * i], (uint32_t)buf[3 * i + 1], (uint32_t)buf[3 * i + 2]);
     }
-#pragma omp parallel for schedule(dynamic, 1)
+    int full = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : full)
     for (int part = 0; part < NPART; ++part)
       for (int64_t i = 0; i < D; ++i)
-        if (buf[3 * i] >= 0 && hv[i] % NPART == (uint64_t)part)
-          isnew[i] = (uint8_t)tset_insert(&set, hv[i], (uint32_t)buf[3 * i], (uint32_t)buf[3 * i + 1], (uint32_t)buf[3 * i + 2]);
+        if (buf[3 * i] >= 0 && hv[i] % NPART == (uint64_t)part) {
+          int r = tset_insert(&set, hv[i], (uint32_t)buf[3 * i], (uint32_t)buf[3 * i + 1], (uint32_t)buf[3 * i + 2]);
+          if (r < 0) { full = 1; r = 0; }
+          isnew[i] = (uint8_t)r;
+        }
+    if (full) { free(buf); free(hv); free(isnew); free(set.slot); return -4; }
     for (int64_t i = 0; i < D && have < m; ++i)
       if (isnew[i]) { memcpy(out + 3 * have, buf + 3 * i, 12); ++have; }
     next += (uint64_t)D;

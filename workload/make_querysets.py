@@ -1,0 +1,104 @@
+"""Write the query sets of the power-law workload with their exact counts.
+
+Candidates come from the seeded walk generator (``gen.c``); every count comes
+from the oracle (message-passing count for acyclic queries, backtracking with a
+work cap for cyclic ones). Queries whose count exceeds the cap, or that the
+oracle cannot count within its work cap, are skipped; the next candidate of the
+same stream is tried. Run from the repository root:
+
+    python -m workload.make_querysets [--scale 1.0] [--per-shape 25]
+
+Output: workload/data/c1_queries.json (scale 1) or c1s<scale>_queries.json.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import multiprocessing as mp
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+import workload  # noqa: E402
+
+SHAPES = ["chain4", "star5", "snowflake8", "triangle"]
+_G = None
+
+
+def _is_acyclic(q):
+    parent = list(range(q["n_qv"]))
+
+    def find(x):
+        while parent[x] != x:
+            x = parent[x]
+        return x
+    pairs = set()
+    for a, _, b in q["edges"]:
+        if a == b or q["qv_const"][a] >= 0 or q["qv_const"][b] >= 0:
+            continue
+        pairs.add((min(a, b), max(a, b)))
+    for a, b in pairs:
+        ra, rb = find(a), find(b)
+        if ra == rb:
+            return False
+        parent[ra] = rb
+    return True
+
+
+def _count(q, work_cap):
+    try:
+        if _is_acyclic(q):
+            return _G.count_acyclic(q)
+        return _G.eval(q, rows=False, work_cap=work_cap)[0]
+    except (oracle.OracleError, OverflowError):
+        return -1
+
+
+def main():
+    global _G
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--scale", type=float, default=1.0)
+    ap.add_argument("--per-shape", type=int, default=25)
+    ap.add_argument("--cap", type=int, default=1_000_000_000)
+    ap.add_argument("--work-cap", type=int, default=300_000_000)
+    ap.add_argument("--procs", type=int, default=min(8, os.cpu_count() or 1))
+    args = ap.parse_args()
+    t0 = time.time()
+    trip = workload.c1_graph(args.scale)
+    n = max(16, int(workload.C1["n"] * args.scale))
+    print(f"graph: {len(trip)} triples, {time.time() - t0:.1f}s", flush=True)
+    _G = oracle.Graph(trip, n, workload.C1["n_labels"])
+    print(f"oracle index: {time.time() - t0:.1f}s", flush=True)
+    out = {"workload": "c1", "scale": args.scale, "n": n, "m": int(len(trip)), "n_labels": workload.C1["n_labels"],
+           "seed": workload.C1["seed"], "count_cap": args.cap,
+           "note": "counts written by the oracle (workload/make_querysets.py)", "queries": []}
+    ctx = mp.get_context("fork")
+    with ctx.Pool(args.procs) as pool:
+        for shape in SHAPES:
+            got, first = [], 0
+            while len(got) < args.per_shape and first < 4000:
+                batch = workload.walk_queries(trip, n, workload.C1["seed"], shape, 32, first=first)
+                counts = pool.starmap(_count, [(q, args.work_cap) for q in batch])
+                for i, (q, c) in enumerate(zip(batch, counts)):
+                    if 1 <= c <= args.cap and len(got) < args.per_shape:
+                        got.append({"shape": shape, "candidate": first + i, "count": int(c), "query": q})
+                first += 32
+            print(f"{shape}: {len(got)} queries from {first} candidates, counts "
+                  f"{sorted(g['count'] for g in got)} ({time.time() - t0:.0f}s)", flush=True)
+            out["queries"] += got
+    name = "c1_queries.json" if args.scale == 1.0 else f"c1s{args.scale:g}_queries.json"
+    path = os.path.join(ROOT, "workload", "data", name)
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w") as f:
+        json.dump(out, f)
+    print("wrote", path)
+
+
+if __name__ == "__main__":
+    main()
