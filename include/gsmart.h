@@ -126,6 +126,7 @@ typedef struct {
   int32_t domain_push;        /* domains evaluated by push */
   int32_t domain_pull;        /* domains evaluated by pull */
   double gpu_ms;              /* device time of the evaluation (events around its launches) */
+  double latency_ms;          /* served form: submission to rows on the host; else 0 */
 } gs_query_stats;
 
 /* ---- engine ---------------------------------------------------------------- */

@@ -63,7 +63,7 @@ class gs_query_stats(ctypes.Structure):
                 ("level_nodes", ctypes.c_int64 * 64), ("t_expand", ctypes.c_int64), ("t_seed", ctypes.c_int64),
                 ("t_push", ctypes.c_int64), ("t_pull", ctypes.c_int64), ("t_probe", ctypes.c_int64),
                 ("t_total", ctypes.c_int64), ("bytes_alg", ctypes.c_int64), ("domain_push", ctypes.c_int32),
-                ("domain_pull", ctypes.c_int32), ("gpu_ms", ctypes.c_double)]
+                ("domain_pull", ctypes.c_int32), ("gpu_ms", ctypes.c_double), ("latency_ms", ctypes.c_double)]
 
 
 class gs_plan_info(ctypes.Structure):

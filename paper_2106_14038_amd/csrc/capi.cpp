@@ -321,6 +321,7 @@ gs_status gs_result_rows(gs_result *result, int64_t first, int64_t n, void *dst,
                          int64_t *n_written) {
   if (!result) { set_error("null result"); return GS_EINVAL; }
   Result &R = *unwrap(result);
+  if (R.host_owned) return (gs_status)result_rows(R, first, n, dst, mem_kind, n_written);
   std::lock_guard<std::mutex> lk(R.eng->mu);
   return (gs_status)result_rows(R, first, n, dst, mem_kind, n_written);
 }
@@ -353,8 +354,10 @@ gs_status gs_result_level(gs_result *result, int32_t level, int32_t *par, int32_
 void gs_result_free(gs_result *result) {
   if (!result) return;
   Result *R = unwrap(result);
-  if (R->eng) {
+  if (R->eng && !R->host_owned) {
     std::lock_guard<std::mutex> lk(R->eng->mu);
+    result_free(R);
+  } else if (R->eng) {
     result_free(R);
   } else {
     delete R;

@@ -155,26 +155,15 @@ int load_triples(Engine &E, int64_t n, int32_t P, const gs_triple *t, int64_t m,
 }
 
 // ------------------------------------------------------------------ batches
-namespace {
-
-struct QInfo {
-  NormQuery nq;
-  Plan plan;
-  int32_t step0 = 0;
-  int32_t seed0 = 0, nseed = 0;
-  int32_t dom0 = 0;
-  bool zero = false;
-};
-
 template <class T>
-uint64_t push_bytes(std::vector<char> &buf, const std::vector<T> &v) {
+static uint64_t push_bytes(std::vector<char> &buf, const std::vector<T> &v) {
   uint64_t off = align256(buf.size());
   buf.resize(off + sizeof(T) * v.size());
   if (!v.empty()) memcpy(buf.data() + off, v.data(), sizeof(T) * v.size());
   return off;
 }
 
-__global__ void k_zero_bytes(uint64_t *p, int64_t n) {
+__global__ void k_zero_words(uint64_t *p, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0;
 }
 
@@ -191,7 +180,18 @@ __global__ void k_const_only(DevGraph g, const DConst *cc, int n, int64_t *out) 
   }
 }
 
-double est_holders(const Engine &E, const FilterRef &f, const std::vector<SeedSpec> &seeds) {
+hipError_t zero_words(uint64_t *p, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_words, dim3(64), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_const_only(const DevGraph &g, const DConst *cc, int n, int64_t *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_const_only, dim3(1), dim3(64), 0, s, g, cc, n, out);
+  return hipGetLastError();
+}
+
+static double est_holders(const Engine &E, const FilterRef &f, const std::vector<SeedSpec> &seeds) {
   const LabelStats &st = E.stats;
   if (f.kind == F_LABEL_OUT) return (double)st.rows[f.arg];
   if (f.kind == F_LABEL_IN) return (double)st.cols[f.arg];
@@ -203,12 +203,158 @@ double est_holders(const Engine &E, const FilterRef &f, const std::vector<SeedSp
   return (double)E.g.n;
 }
 
-double avg_seg(const Engine &E, int label, int dir) {
+static double avg_seg(const Engine &E, int label, int dir) {
   double h = (double)(dir == 0 ? E.stats.rows[label] : E.stats.cols[label]);
   return h > 0 ? (double)E.stats.nnz[label] / h : 0.0;
 }
 
-}  // namespace
+int plan_query(const Engine &E, const gs_query &q, QInfo &qi, std::string &msg) {
+  std::vector<int32_t> e3(3 * (size_t)std::max(q.n_edges, 0));
+  if (q.n_edges > 0 && !q.edges) { msg = "query edges missing"; return GS_EINVAL; }
+  for (int k = 0; k < q.n_edges; ++k) {
+    e3[3 * k] = q.edges[k].src; e3[3 * k + 1] = q.edges[k].label; e3[3 * k + 2] = q.edges[k].dst;
+  }
+  int rc = normalise_query(q.n_qv, q.qv_const, q.n_edges, e3.data(), E.g.n, E.g.P, qi.nq, msg);
+  if (rc == GS_OK) rc = build_plan(qi.nq, &E.stats, E.opt.domain_mode != GS_DOMAIN_OFF, qi.plan, msg);
+  qi.zero = rc == GS_OK && qi.plan.n_vars == 0;
+  return rc;
+}
+
+// Append query qi's step programs to T; its counters and tree levels use slot `slot`.
+void compile_query(const Engine &E, QInfo &qi, bool count_only, int slot, Tables &T,
+                   const std::function<uint64_t *()> &next_bitmap) {
+  const Plan &P = qi.plan;
+  const int64_t words = E.g.words;
+  qi.slot = slot;
+  qi.vr0 = (int32_t)T.var_rank.size();
+  T.var_rank.insert(T.var_rank.end(), P.var_rank.begin(), P.var_rank.end());
+  qi.step0 = (int32_t)T.steps.size();
+  qi.seed0 = (int32_t)T.seeds.size();
+  std::vector<int32_t> seed_at(P.seeds.size());
+  for (size_t k = 0; k < P.seeds.size(); ++k) {
+    seed_at[k] = (int32_t)T.seeds.size();
+    T.seeds.push_back({next_bitmap(), P.seeds[k].c, P.seeds[k].label, P.seeds[k].dir, slot});
+  }
+  qi.nseed = (int32_t)P.seeds.size();
+  qi.dom0 = (int32_t)T.doms.size();
+  qi.ndom = (int32_t)P.domains.size();
+  std::vector<DDomain> qd(P.domains.size());
+  for (size_t k = 0; k < P.domains.size(); ++k) { qd[k].F = next_bitmap(); qd[k].D = next_bitmap(); }
+  auto filter_ptr = [&](const FilterRef &f) -> const uint64_t * {
+    switch (f.kind) {
+      case F_LABEL_OUT: return E.g.bm[0] + (int64_t)f.arg * words;
+      case F_LABEL_IN: return E.g.bm[1] + (int64_t)f.arg * words;
+      case F_SEED: return T.seeds[seed_at[f.arg]].bm;
+      default: return qd[f.arg].D;
+    }
+  };
+  auto col_of = [&](int level, int at) {
+    if (level == at) return 1;
+    const std::vector<int32_t> &c = P.steps[at].carried;
+    return 2 + (int)(std::find(c.begin(), c.end(), level) - c.begin());
+  };
+  for (int j = 0; j < P.n_vars; ++j) {
+    const PlanStep &ps = P.steps[j];
+    DStep d{};
+    d.kind = ps.kind;
+    d.label = ps.label;
+    d.dir = ps.dir;
+    d.src = ps.kind == STEP_SEG ? col_of(ps.src_level, j - 1) : (ps.kind == STEP_SEG_CONST ? ps.src_const : 0);
+    d.filt0 = (int32_t)T.filt.size();
+    for (const FilterRef &f : ps.filters) T.filt.push_back(filter_ptr(f));
+    d.nfilt = (int32_t)ps.filters.size();
+    d.list_nfilt = ps.kind == STEP_LIST ? d.nfilt : 0;
+    d.chk0 = (int32_t)T.checks.size();
+    for (const CheckRef &c : ps.checks) T.checks.push_back({col_of(c.level, j - 1), c.label, c.dir, 0});
+    d.nchk = (int32_t)ps.checks.size();
+    d.self0 = (int32_t)T.ints.size();
+    for (int32_t l : ps.self_labels) T.ints.push_back(l);
+    d.nself = (int32_t)ps.self_labels.size();
+    d.copy0 = (int32_t)T.ints.size();
+    for (int32_t l : ps.carried) T.ints.push_back(col_of(l, j - 1));
+    d.ncopy = (int32_t)ps.carried.size();
+    d.ncols_out = (count_only && j == P.n_vars - 1) ? 0 : 2 + d.ncopy;
+    d.ncols_prev = j == 0 ? 0 : 2 + (int32_t)P.steps[j - 1].carried.size();
+    if (j == 0) {
+      d.cc0 = (int32_t)T.cconst.size();
+      for (const ConstCheck &c : P.cchecks) T.cconst.push_back({c.a, c.label, c.b, 0});
+      d.ncc = (int32_t)P.cchecks.size();
+    }
+    T.steps.push_back(d);
+  }
+  for (size_t k = 0; k < P.domains.size(); ++k) {
+    const DomainSpec &ds = P.domains[k];
+    DDomain &dd = qd[k];
+    dd.col = col_of(ds.level, ds.step - 1);
+    dd.label = ds.label;
+    dd.dir = ds.dir;
+    dd.filt0 = (int32_t)T.filt.size();
+    double mask = (double)E.g.n;
+    for (const FilterRef &f : ds.mask) { T.filt.push_back(filter_ptr(f)); mask = std::min(mask, est_holders(E, f, P.seeds)); }
+    dd.nfilt = (int32_t)ds.mask.size();
+    dd.mode = E.opt.domain_mode == GS_DOMAIN_PUSH ? 1 : (E.opt.domain_mode == GS_DOMAIN_PULL ? 2 : 0);
+    dd.q = slot;
+    dd.deg_push = (float)avg_seg(E, ds.label, ds.dir);
+    dd.deg_pull = (float)avg_seg(E, ds.label, 1 - ds.dir);
+    dd.mask_est = (float)mask;
+    dd.theta = E.opt.push_pull_theta > 0 ? E.opt.push_pull_theta : 1.0f;
+    T.doms.push_back(dd);
+    T.dom_step.push_back(ds.step);
+  }
+}
+
+// Work lists of one iteration: query qs[i] produces its level `level[i]`.
+void build_iteration(const Tables &T, const std::vector<const QInfo *> &qs, const std::vector<int> &level,
+                     IterLists &L) {
+  L.ents.clear(); L.doms.clear(); L.clears.clear(); L.seeds.clear(); L.has_list = 0;
+  for (size_t i = 0; i < qs.size(); ++i) {
+    const QInfo &qi = *qs[i];
+    const int t = level[i];
+    if (t == 0)
+      for (int k = 0; k < qi.nseed; ++k) { L.seeds.push_back(T.seeds[qi.seed0 + k]); L.clears.push_back(T.seeds[qi.seed0 + k].bm); }
+    DEntry e{qi.slot, t, qi.step0 + t, (int32_t)L.doms.size(), 0, 0};
+    for (int k = 0; k < qi.ndom; ++k) {
+      if (T.dom_step[qi.dom0 + k] != t) continue;
+      L.doms.push_back(T.doms[qi.dom0 + k]);
+      L.clears.push_back(T.doms[qi.dom0 + k].F);
+      L.clears.push_back(T.doms[qi.dom0 + k].D);
+      e.ndom++;
+    }
+    if (qi.plan.steps[t].kind == STEP_LIST) L.has_list = 1;
+    L.ents.push_back(e);
+  }
+}
+
+// Accumulate per-kernel times and algorithmic bytes of one iteration (profiling).
+void account_iteration(Engine &E, const hipEvent_t *ev, const IterScalars &I, const IterLists &L, double write_bytes) {
+  bool ran[KS_N];
+  for (int k = 0; k < KS_N; ++k) ran[k] = true;
+  ran[KS_CLEAR] = !L.clears.empty();
+  ran[KS_SEED] = !L.seeds.empty();
+  ran[KS_LIST_COUNT] = ran[KS_LIST_SCAN] = ran[KS_LIST_WRITE] = L.has_list != 0;
+  ran[KS_DOM_FRONTIER] = ran[KS_DOM_PUSH] = ran[KS_DOM_PULL] = !L.doms.empty();
+  for (int k = 0; k < KS_N; ++k) {
+    if (!ran[k]) continue;
+    float kms = 0;
+    if (hipEventElapsedTime(&kms, ev[2 * k], ev[2 * k + 1]) != hipSuccess) continue;
+    double b = 0;
+    const double W = (double)I.w_total, nz = (double)I.nz_total;
+    switch (k) {
+      case KS_EXPAND_COUNT:   // candidate ids, staged node records, filter words, parent bindings, probes, valid bits
+        b = 4 * W + 20 * nz + 8.0 * I.ftests + 4.0 * I.ctests + 4.0 * I.probes + W / 8; break;
+      case KS_EXPAND_WRITE:   // valid bits, staged node records, candidate ids + copies read + columns written
+        b = W / 8 + 20 * nz + write_bytes; break;
+      case KS_LOOKUP:         // parent binding, offset pair, segment written
+        b = 36.0 * I.nodes_total; break;
+      case KS_NZ_WRITE:
+        b = 16.0 * I.nodes_total + 20 * nz; break;
+      default: break;
+    }
+    E.kstat[k].launches += 1;
+    E.kstat[k].ms += kms;
+    E.kstat[k].bytes += b;
+  }
+}
 
 int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector<Result *> &out, double *ms_out) {
   if (!E.loaded) { set_error("no dataset loaded"); return GS_ESTATE; }
@@ -216,7 +362,6 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
   HIPCHK(hipSetDevice(E.device));
   hipStream_t s = E.stream;
   const bool count_only = flags & GS_COUNT_ONLY;
-  const bool want_dom = E.opt.domain_mode != GS_DOMAIN_OFF;
   const int64_t words = E.g.words;
 
   // 1. plan every query
@@ -224,168 +369,60 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
   int maxk = 0;
   for (int i = 0; i < nq; ++i) {
     std::string msg;
-    std::vector<int32_t> e3(3 * (size_t)std::max(qs[i].n_edges, 0));
-    if (qs[i].n_edges > 0 && !qs[i].edges) { set_error("query edges missing"); return GS_EINVAL; }
-    for (int k = 0; k < qs[i].n_edges; ++k) {
-      e3[3 * k] = qs[i].edges[k].src; e3[3 * k + 1] = qs[i].edges[k].label; e3[3 * k + 2] = qs[i].edges[k].dst;
-    }
-    int rc = normalise_query(qs[i].n_qv, qs[i].qv_const, qs[i].n_edges, e3.data(), E.g.n, E.g.P, Q[i].nq, msg);
-    if (rc == GS_OK) rc = build_plan(Q[i].nq, &E.stats, want_dom, Q[i].plan, msg);
+    int rc = plan_query(E, qs[i], Q[i], msg);
     if (rc != GS_OK) { set_error("query " + std::to_string(i) + ": " + msg); return rc; }
-    Q[i].zero = Q[i].plan.n_vars == 0;
     maxk = std::max(maxk, Q[i].plan.n_vars);
   }
 
-  // 2. compile step programs
-  std::vector<DStep> steps;
-  std::vector<const uint64_t *> filt;
-  std::vector<DCheck> checks;
-  std::vector<int32_t> ints;
-  std::vector<DConst> cconst;
-  std::vector<DSeed> seeds;
-  std::vector<DDomain> doms_all;      // in (query, plan order)
-  std::vector<int32_t> dom_iter;      // iteration of each domain
-  std::vector<int32_t> var_ranks;
-  std::vector<int32_t> vr_off(nq, 0);
+  // 2. compile step programs; bitmaps at the front of this run's arena block
   int64_t n_bitmaps = 0;
   for (int i = 0; i < nq; ++i) n_bitmaps += (int64_t)Q[i].plan.seeds.size() + 2 * (int64_t)Q[i].plan.domains.size();
-
-  // arena layout (host side): bitmaps, then tables, then device-written tables
   uint64_t off = align256(E.tree_top);
   const uint64_t bm_off = off;
   off += align256((uint64_t)n_bitmaps * words * 8);
-  auto bm_ptr = [&](int64_t k) { return (uint64_t *)(E.tree_base + bm_off + (uint64_t)k * words * 8); };
   int64_t next_bm = 0;
+  auto next_bitmap = [&]() { return (uint64_t *)(E.tree_base + bm_off + (uint64_t)(next_bm++) * words * 8); };
+  Tables T;
+  for (int i = 0; i < nq; ++i) compile_query(E, Q[i], count_only, i, T, next_bitmap);
 
-  for (int i = 0; i < nq; ++i) {
-    QInfo &qi = Q[i];
-    const Plan &P = qi.plan;
-    vr_off[i] = (int32_t)var_ranks.size();
-    var_ranks.insert(var_ranks.end(), P.var_rank.begin(), P.var_rank.end());
-    qi.step0 = (int32_t)steps.size();
-    qi.seed0 = (int32_t)seeds.size();
-    std::vector<int32_t> seed_bm(P.seeds.size());
-    for (size_t k = 0; k < P.seeds.size(); ++k) {
-      DSeed d{bm_ptr(next_bm), P.seeds[k].c, P.seeds[k].label, P.seeds[k].dir, i};
-      seed_bm[k] = (int32_t)seeds.size();
-      seeds.push_back(d);
-      ++next_bm;
-    }
-    qi.nseed = (int32_t)P.seeds.size();
-    qi.dom0 = (int32_t)doms_all.size();
-    std::vector<DDomain> qd(P.domains.size());
-    for (size_t k = 0; k < P.domains.size(); ++k) {
-      qd[k].F = bm_ptr(next_bm++);
-      qd[k].D = bm_ptr(next_bm++);
-    }
-    auto filter_ptr = [&](const FilterRef &f) -> const uint64_t * {
-      switch (f.kind) {
-        case F_LABEL_OUT: return E.g.bm[0] + (int64_t)f.arg * words;
-        case F_LABEL_IN: return E.g.bm[1] + (int64_t)f.arg * words;
-        case F_SEED: return seeds[seed_bm[f.arg]].bm;
-        default: return qd[f.arg].D;
-      }
-    };
-    auto col_of = [&](int level, int at) {
-      if (level == at) return 1;
-      const std::vector<int32_t> &c = P.steps[at].carried;
-      return 2 + (int)(std::find(c.begin(), c.end(), level) - c.begin());
-    };
-    for (int j = 0; j < P.n_vars; ++j) {
-      const PlanStep &ps = P.steps[j];
-      DStep d{};
-      d.kind = ps.kind;
-      d.label = ps.label;
-      d.dir = ps.dir;
-      d.src = ps.kind == STEP_SEG ? col_of(ps.src_level, j - 1) : (ps.kind == STEP_SEG_CONST ? ps.src_const : 0);
-      d.filt0 = (int32_t)filt.size();
-      for (const FilterRef &f : ps.filters) filt.push_back(filter_ptr(f));
-      d.nfilt = (int32_t)ps.filters.size();
-      d.list_nfilt = ps.kind == STEP_LIST ? d.nfilt : 0;
-      d.chk0 = (int32_t)checks.size();
-      for (const CheckRef &c : ps.checks) checks.push_back({col_of(c.level, j - 1), c.label, c.dir, 0});
-      d.nchk = (int32_t)ps.checks.size();
-      d.self0 = (int32_t)ints.size();
-      for (int32_t l : ps.self_labels) ints.push_back(l);
-      d.nself = (int32_t)ps.self_labels.size();
-      d.copy0 = (int32_t)ints.size();
-      for (int32_t l : ps.carried) ints.push_back(col_of(l, j - 1));
-      d.ncopy = (int32_t)ps.carried.size();
-      d.ncols_out = (count_only && j == P.n_vars - 1) ? 0 : 2 + d.ncopy;
-      d.ncols_prev = j == 0 ? 0 : 2 + (int32_t)P.steps[j - 1].carried.size();
-      if (j == 0) {
-        d.cc0 = (int32_t)cconst.size();
-        for (const ConstCheck &c : P.cchecks) cconst.push_back({c.a, c.label, c.b, 0});
-        d.ncc = (int32_t)P.cchecks.size();
-      }
-      steps.push_back(d);
-    }
-    for (size_t k = 0; k < P.domains.size(); ++k) {
-      const DomainSpec &ds = P.domains[k];
-      DDomain &dd = qd[k];
-      dd.col = col_of(ds.level, ds.step - 1);
-      dd.label = ds.label;
-      dd.dir = ds.dir;
-      dd.filt0 = (int32_t)filt.size();
-      double mask = (double)E.g.n;
-      for (const FilterRef &f : ds.mask) { filt.push_back(filter_ptr(f)); mask = std::min(mask, est_holders(E, f, P.seeds)); }
-      dd.nfilt = (int32_t)ds.mask.size();
-      dd.mode = E.opt.domain_mode == GS_DOMAIN_PUSH ? 1 : (E.opt.domain_mode == GS_DOMAIN_PULL ? 2 : 0);
-      dd.q = i;
-      dd.deg_push = (float)avg_seg(E, ds.label, ds.dir);
-      dd.deg_pull = (float)avg_seg(E, ds.label, 1 - ds.dir);
-      dd.mask_est = (float)mask;
-      dd.theta = E.opt.push_pull_theta > 0 ? E.opt.push_pull_theta : 1.0f;
-      doms_all.push_back(dd);
-      dom_iter.push_back(ds.step);
-    }
-  }
-
-  // 3. per-iteration work lists
+  // 3. per-iteration work lists (every query advances one level per iteration)
+  std::vector<IterLists> its(maxk);
   std::vector<DEntry> ents;
   std::vector<DDomain> doms;
   std::vector<uint64_t *> clears;
-  std::vector<int32_t> ent_off(maxk + 1, 0), dom_off(maxk + 1, 0), clr_off(maxk + 1, 0), has_list(maxk, 0);
+  std::vector<DSeed> seeds;
+  std::vector<int32_t> ent_off(maxk + 1, 0), dom_off(maxk + 1, 0), clr_off(maxk + 1, 0), seed_off(maxk + 1, 0);
   int max_e = 1, max_d = 1;
   for (int t = 0; t < maxk; ++t) {
-    ent_off[t] = (int32_t)ents.size();
-    dom_off[t] = (int32_t)doms.size();
-    clr_off[t] = (int32_t)clears.size();
-    if (t == 0) for (const DSeed &d : seeds) clears.push_back(d.bm);
-    for (int i = 0; i < nq; ++i) {
-      const QInfo &qi = Q[i];
-      if (qi.plan.n_vars <= t) continue;
-      DEntry e{i, t, qi.step0 + t, (int32_t)doms.size() - dom_off[t], 0, 0};
-      for (size_t k = 0; k < qi.plan.domains.size(); ++k) {
-        if (dom_iter[qi.dom0 + k] != t) continue;
-        doms.push_back(doms_all[qi.dom0 + k]);
-        clears.push_back(doms_all[qi.dom0 + k].F);
-        clears.push_back(doms_all[qi.dom0 + k].D);
-        e.ndom++;
-      }
-      if (qi.plan.steps[t].kind == STEP_LIST) has_list[t] = 1;
-      ents.push_back(e);
-    }
-    max_e = std::max(max_e, (int)ents.size() - ent_off[t]);
-    max_d = std::max(max_d, (int)doms.size() - dom_off[t]);
+    std::vector<const QInfo *> act;
+    std::vector<int> lev;
+    for (int i = 0; i < nq; ++i) if (Q[i].plan.n_vars > t) { act.push_back(&Q[i]); lev.push_back(t); }
+    build_iteration(T, act, lev, its[t]);
+    ent_off[t] = (int32_t)ents.size(); dom_off[t] = (int32_t)doms.size();
+    clr_off[t] = (int32_t)clears.size(); seed_off[t] = (int32_t)seeds.size();
+    ents.insert(ents.end(), its[t].ents.begin(), its[t].ents.end());
+    doms.insert(doms.end(), its[t].doms.begin(), its[t].doms.end());
+    clears.insert(clears.end(), its[t].clears.begin(), its[t].clears.end());
+    seeds.insert(seeds.end(), its[t].seeds.begin(), its[t].seeds.end());
+    max_e = std::max(max_e, (int)its[t].ents.size());
+    max_d = std::max(max_d, (int)its[t].doms.size());
   }
-  ent_off[maxk] = (int32_t)ents.size();
-  dom_off[maxk] = (int32_t)doms.size();
-  clr_off[maxk] = (int32_t)clears.size();
+  ent_off[maxk] = (int32_t)ents.size(); dom_off[maxk] = (int32_t)doms.size();
+  clr_off[maxk] = (int32_t)clears.size(); seed_off[maxk] = (int32_t)seeds.size();
 
   // 4. pack the constant tables
   std::vector<char> buf;
-  const uint64_t o_steps = push_bytes(buf, steps), o_filt = push_bytes(buf, filt), o_chk = push_bytes(buf, checks);
-  const uint64_t o_ints = push_bytes(buf, ints), o_cc = push_bytes(buf, cconst), o_seeds = push_bytes(buf, seeds);
+  const uint64_t o_steps = push_bytes(buf, T.steps), o_filt = push_bytes(buf, T.filt), o_chk = push_bytes(buf, T.checks);
+  const uint64_t o_ints = push_bytes(buf, T.ints), o_cc = push_bytes(buf, T.cconst), o_seeds = push_bytes(buf, seeds);
   const uint64_t o_doms = push_bytes(buf, doms), o_ents = push_bytes(buf, ents), o_clr = push_bytes(buf, clears);
-  const uint64_t o_vr = push_bytes(buf, var_ranks);
+  const uint64_t o_vr = push_bytes(buf, T.var_rank);
   const uint64_t tab_off = align256(off);
   off = tab_off + align256(buf.size());
   // device-written tables
   const uint64_t o_lvlp = off; off += align256(sizeof(int32_t *) * kMaxLevels * (uint64_t)nq);
   const uint64_t o_lvln = off; off += align256(sizeof(int64_t) * kMaxLevels * (uint64_t)nq);
   const uint64_t o_qs = off; off += align256(sizeof(int64_t) * QS_N * (uint64_t)nq);
-  const uint64_t o_zero = off; off += 256;   // zero-variable query results
+  const uint64_t o_zero = off; off += align256(sizeof(int64_t) * (uint64_t)nq);
   const uint64_t zero_end = off;
   const uint64_t o_fc = off; off += align256(sizeof(int64_t) * max_d);
   const uint64_t o_es = off; off += align256(sizeof(EState) * max_e);
@@ -395,10 +432,7 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
   char *base = E.tree_base;
   auto dp = [&](uint64_t o) { return (void *)(base + o); };
   HIPCHK(hipMemcpyAsync(base + tab_off, buf.data(), buf.size(), hipMemcpyHostToDevice, s));
-  {
-    const int64_t n64 = (int64_t)((zero_end - o_lvlp) / 8);
-    hipLaunchKernelGGL(k_zero_bytes, dim3(64), dim3(256), 0, s, (uint64_t *)dp(o_lvlp), n64);
-  }
+  HIPCHK(zero_words((uint64_t *)dp(o_lvlp), (int64_t)((zero_end - o_lvlp) / 8), s));
   DArena ar[2];
   ar[0] = {off, E.tree_cap, 0, 0};
   ar[1] = {0, E.scratch_cap, 0, 0};
@@ -408,6 +442,7 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
   HIPCHK(hipEventCreate(&ev0));
   HIPCHK(hipEventCreate(&ev1));
   HIPCHK(hipEventRecord(ev0, s));
+
   // 5. iterations
   const bool prof = E.opt.profile_kernels != 0;
   if (prof) {
@@ -423,17 +458,17 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
     A.g = E.g;
     A.ent = (const DEntry *)dp(tab_off + o_ents) + ent_off[t];
     A.E = ent_off[t + 1] - ent_off[t];
-    A.S = t == 0 ? (int32_t)seeds.size() : 0;
+    A.S = seed_off[t + 1] - seed_off[t];
     A.D = dom_off[t + 1] - dom_off[t];
     A.nclear = clr_off[t + 1] - clr_off[t];
-    A.has_list = has_list[t];
+    A.has_list = its[t].has_list;
     A.grid = E.grid;
     A.steps = (const DStep *)dp(tab_off + o_steps);
     A.filt = (const uint64_t *const *)dp(tab_off + o_filt);
     A.checks = (const DCheck *)dp(tab_off + o_chk);
     A.ints = (const int32_t *)dp(tab_off + o_ints);
     A.cconst = (const DConst *)dp(tab_off + o_cc);
-    A.seeds = (const DSeed *)dp(tab_off + o_seeds);
+    A.seeds = (const DSeed *)dp(tab_off + o_seeds) + seed_off[t];
     A.doms = (const DDomain *)dp(tab_off + o_doms) + dom_off[t];
     A.fcount = (int64_t *)dp(o_fc);
     A.clear = (uint64_t *const *)dp(tab_off + o_clr) + clr_off[t];
@@ -451,79 +486,50 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
     hipError_t e = launch_iteration(A, s, prof ? &E.events[(size_t)2 * KS_N * t] : nullptr);
     if (e != hipSuccess) { set_error(std::string("launch: ") + hipGetErrorString(e)); return GS_EDEVICE; }
   }
-  // constant-only queries
-  std::vector<int64_t> zero_res(nq, 0);
+  // constant-only queries (no variable): every pattern between constants must hold
   for (int i = 0; i < nq; ++i) {
     if (!Q[i].zero) continue;
+    const int ncc = (int)Q[i].plan.cchecks.size();
     std::vector<DConst> cc;
     for (const ConstCheck &c : Q[i].plan.cchecks) cc.push_back({c.a, c.label, c.b, 0});
-    DConst *d_cc = (DConst *)E.dmalloc(sizeof(DConst) * std::max<size_t>(cc.size(), 1));
-    int64_t *d_o = (int64_t *)E.dmalloc(8);
-    if (!d_cc || !d_o) { E.dfree(d_cc); E.dfree(d_o); set_error("out of device memory"); return GS_ENOMEM; }
-    HIPCHK(hipMemcpyAsync(d_cc, cc.data(), sizeof(DConst) * cc.size(), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_const_only, dim3(1), dim3(64), 0, s, E.g, (const DConst *)d_cc, (int)cc.size(), d_o);
-    HIPCHK(hipMemcpyAsync(&zero_res[i], d_o, 8, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    DConst *d_cc = (DConst *)E.dmalloc(sizeof(DConst) * std::max(ncc, 1));
+    if (!d_cc) { set_error("out of device memory"); return GS_ENOMEM; }
+    hipError_t e = hipMemcpyAsync(d_cc, cc.data(), sizeof(DConst) * ncc, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_const_only(E.g, d_cc, ncc, (int64_t *)dp(o_zero) + i, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
     E.dfree(d_cc);
-    E.dfree(d_o);
+    if (e != hipSuccess) { set_error(hipGetErrorString(e)); return GS_EDEVICE; }
   }
   HIPCHK(hipEventRecord(ev1, s));
 
   // 6. read back sizes and counters
-  std::vector<int64_t> lvl_n((size_t)nq * kMaxLevels), qst((size_t)nq * QS_N);
+  std::vector<int64_t> lvl_n((size_t)nq * kMaxLevels), qst((size_t)nq * QS_N), zero_res(nq);
   std::vector<int32_t *> lvl_p((size_t)nq * kMaxLevels);
   HIPCHK(hipMemcpyAsync(lvl_n.data(), dp(o_lvln), 8 * lvl_n.size(), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(lvl_p.data(), dp(o_lvlp), 8 * lvl_p.size(), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(qst.data(), dp(o_qs), 8 * qst.size(), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(zero_res.data(), dp(o_zero), 8 * zero_res.size(), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(ar, E.d_arenas, sizeof(ar), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   float ms = 0;
   HIPCHK(hipEventElapsedTime(&ms, ev0, ev1));
-  if (prof) {
-    std::vector<IterScalars> its(std::max(maxk, 1));
-    HIPCHK(hipMemcpy(its.data(), dp(o_it), sizeof(IterScalars) * its.size(), hipMemcpyDeviceToHost));
-    for (int t = 0; t < maxk; ++t) {
-      const IterScalars &I = its[t];
-      bool ran[KS_N];
-      for (int k = 0; k < KS_N; ++k) ran[k] = true;
-      ran[KS_CLEAR] = clr_off[t + 1] > clr_off[t];
-      ran[KS_SEED] = t == 0 && !seeds.empty();
-      ran[KS_LIST_COUNT] = ran[KS_LIST_SCAN] = ran[KS_LIST_WRITE] = has_list[t] != 0;
-      ran[KS_DOM_FRONTIER] = ran[KS_DOM_PUSH] = ran[KS_DOM_PULL] = dom_off[t + 1] > dom_off[t];
-      // rows written this iteration, weighted by the columns each query writes
-      double wbytes = 0;
-      for (int i = 0; i < nq; ++i) {
-        if (Q[i].plan.n_vars <= t) continue;
-        const DStep &d = steps[Q[i].step0 + t];
-        const int64_t c = std::max<int64_t>(lvl_n[(size_t)i * kMaxLevels + t], 0);
-        if (d.ncols_out > 0) wbytes += (double)c * (4.0 * d.ncols_out + 4.0 * d.ncopy + 4.0);
-      }
-      for (int k = 0; k < KS_N; ++k) {
-        if (!ran[k]) continue;
-        float kms = 0;
-        if (hipEventElapsedTime(&kms, E.events[(size_t)2 * KS_N * t + 2 * k], E.events[(size_t)2 * KS_N * t + 2 * k + 1]) != hipSuccess) continue;
-        double b = 0;
-        const double W = (double)I.w_total, nz = (double)I.nz_total;
-        switch (k) {
-          case KS_EXPAND_COUNT:   // candidate ids, staged node records, filter words, parent bindings, probes, valid bits
-            b = 4 * W + 20 * nz + 8.0 * I.ftests + 4.0 * I.ctests + 4.0 * I.probes + W / 8; break;
-          case KS_EXPAND_WRITE:   // valid bits, staged node records, candidate ids + copies read + columns written
-            b = W / 8 + 20 * nz + wbytes; break;
-          case KS_LOOKUP:         // parent binding, offset pair, segment written
-            b = 36.0 * I.nodes_total; break;
-          case KS_NZ_WRITE:
-            b = 16.0 * I.nodes_total + 20 * nz; break;
-          default: break;
-        }
-        E.kstat[k].launches += 1;
-        E.kstat[k].ms += kms;
-        E.kstat[k].bytes += b;
-      }
-    }
-  }
   (void)hipEventDestroy(ev0);
   (void)hipEventDestroy(ev1);
   if (ms_out) *ms_out = ms;
+  if (prof) {
+    std::vector<IterScalars> iv(std::max(maxk, 1));
+    HIPCHK(hipMemcpy(iv.data(), dp(o_it), sizeof(IterScalars) * iv.size(), hipMemcpyDeviceToHost));
+    for (int t = 0; t < maxk; ++t) {
+      double wbytes = 0;   // rows written this iteration, weighted by the columns each query writes
+      for (int i = 0; i < nq; ++i) {
+        if (Q[i].plan.n_vars <= t) continue;
+        const DStep &d = T.steps[Q[i].step0 + t];
+        const int64_t c = std::max<int64_t>(lvl_n[(size_t)i * kMaxLevels + t], 0);
+        if (d.ncols_out > 0) wbytes += (double)c * (4.0 * d.ncols_out + 4.0 * d.ncopy + 4.0);
+      }
+      account_iteration(E, &E.events[(size_t)2 * KS_N * t], iv[t], its[t], wbytes);
+    }
+  }
   if (ar[1].overflow) {
     set_error("scratch arena overflow: a level's temporaries exceed the scratch arena");
     return GS_ENOMEM;
@@ -541,55 +547,57 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
     Result *R = new Result();
     R->eng = &E;
     R->run_id = run_id;
-    const Plan &P = Q[i].plan;
-    R->k = P.n_vars;
-    R->n_vars = P.n_vars;
-    R->count_only = count_only;
-    R->zero_vars = Q[i].zero;
-    R->var_rank = P.var_rank;
-    if (Q[i].zero) {
-      R->count = zero_res[i];
-    } else {
-      for (int j = 0; j < P.n_vars; ++j) {
-        R->lvl_ptr.push_back(lvl_p[(size_t)i * kMaxLevels + j]);
-        R->lvl_n.push_back(lvl_n[(size_t)i * kMaxLevels + j]);
-      }
-      R->count = R->lvl_n.back();
-      R->d_lvl_ptr = (int32_t **)dp(o_lvlp) + (size_t)i * kMaxLevels;
-      R->d_lvl_n = (int64_t *)dp(o_lvln) + (size_t)i * kMaxLevels;
-      R->d_var_rank = (int32_t *)dp(tab_off + o_vr) + vr_off[i];
-    }
-    gs_query_stats &st = R->stats;
-    memset(&st, 0, sizeof st);
-    st.count = R->count;
-    st.n_levels = R->k;
-    st.n_domains = (int32_t)P.domains.size();
-    for (int j = 0; j < R->k && j < 64; ++j) st.level_nodes[j] = R->lvl_n[j];
-    const int64_t *c = &qst[(size_t)i * QS_N];
-    st.t_expand = c[QS_EXPAND];
-    st.t_seed = c[QS_SEED];
-    st.t_push = c[QS_PUSH];
-    st.t_pull = c[QS_PULL];
-    st.t_probe = c[QS_PROBE];
-    st.t_total = st.t_expand + st.t_seed + st.t_push + st.t_pull + st.t_probe;
-    st.domain_push = (int32_t)c[QS_DOMPUSH];
-    st.domain_pull = (int32_t)c[QS_DOMPULL];
-    int64_t nodes_written = 0, nodes_read = 0;
-    for (int j = 0; j < R->k; ++j) {
-      const int64_t cols = (count_only && j == R->k - 1) ? 0 : 2 + (int64_t)P.steps[j].carried.size();
-      nodes_written += R->lvl_n[j] * cols;
-      if (j + 1 < R->k) nodes_read += R->lvl_n[j];
-    }
-    // id reads (4 B) for every traversed entry, labels touched by probes (2 B), offset pairs per
-    // segment lookup (16 B), tree columns written (4 B each) and parent bindings read (4 B)
-    st.bytes_alg = 4 * (st.t_expand + st.t_seed + st.t_push + st.t_pull) + 6 * st.t_probe + 16 * nodes_read +
-                   4 * nodes_written + 4 * nodes_read;
-    st.gpu_ms = ms;
+    fill_result(*R, Q[i], count_only, &lvl_p[(size_t)i * kMaxLevels], &lvl_n[(size_t)i * kMaxLevels],
+                &qst[(size_t)i * QS_N], zero_res[i], ms);
+    R->d_lvl_ptr = (int32_t **)dp(o_lvlp) + (size_t)i * kMaxLevels;
+    R->d_lvl_n = (int64_t *)dp(o_lvln) + (size_t)i * kMaxLevels;
+    R->d_var_rank = (int32_t *)dp(tab_off + o_vr) + Q[i].vr0;
     out.push_back(R);
   }
   E.tree_top = ar[0].top;
   E.live_results += nq;
   return GS_OK;
+}
+
+void fill_result(Result &R, const QInfo &qi, bool count_only, int32_t *const *lvl_p, const int64_t *lvl_n,
+                 const int64_t *c, int64_t zero_res, double ms) {
+  const Plan &P = qi.plan;
+  R.k = P.n_vars;
+  R.n_vars = P.n_vars;
+  R.count_only = count_only;
+  R.zero_vars = qi.zero;
+  R.var_rank = P.var_rank;
+  if (qi.zero) {
+    R.count = zero_res;
+  } else {
+    for (int j = 0; j < P.n_vars; ++j) { R.lvl_ptr.push_back(lvl_p[j]); R.lvl_n.push_back(lvl_n[j]); }
+    R.count = R.lvl_n.back();
+  }
+  gs_query_stats &st = R.stats;
+  memset(&st, 0, sizeof st);
+  st.count = R.count;
+  st.n_levels = R.k;
+  st.n_domains = (int32_t)P.domains.size();
+  for (int j = 0; j < R.k && j < 64; ++j) st.level_nodes[j] = R.lvl_n[j];
+  st.t_expand = c[QS_EXPAND];
+  st.t_seed = c[QS_SEED];
+  st.t_push = c[QS_PUSH];
+  st.t_pull = c[QS_PULL];
+  st.t_probe = c[QS_PROBE];
+  st.t_total = st.t_expand + st.t_seed + st.t_push + st.t_pull + st.t_probe;
+  st.domain_push = (int32_t)c[QS_DOMPUSH];
+  st.domain_pull = (int32_t)c[QS_DOMPULL];
+  int64_t nodes_written = 0, nodes_read = 0;
+  for (int j = 0; j < R.k; ++j) {
+    const int64_t cols = (count_only && j == R.k - 1) ? 0 : 2 + (int64_t)P.steps[j].carried.size();
+    nodes_written += R.lvl_n[j] * cols;
+    if (j + 1 < R.k) nodes_read += R.lvl_n[j];
+  }
+  // id reads (4 B) for every traversed entry, labels and ids touched by probes (6 B), offset pairs per
+  // segment lookup (16 B), tree columns written (4 B each) and parent bindings read (4 B)
+  st.bytes_alg = 4 * (st.t_expand + st.t_seed + st.t_push + st.t_pull) + 6 * st.t_probe + 16 * nodes_read +
+                 4 * nodes_written + 4 * nodes_read;
+  st.gpu_ms = ms;
 }
 
 int result_rows(Result &R, int64_t first, int64_t n, void *dst, int mem_kind, int64_t *written) {
@@ -599,6 +607,14 @@ int result_rows(Result &R, int64_t first, int64_t n, void *dst, int mem_kind, in
   n = std::min(n, R.count - first);
   if (n == 0 || R.n_vars == 0) { if (written) *written = n; return GS_OK; }
   if (!dst) { set_error("null destination"); return GS_EINVAL; }
+  if (R.host_owned) {
+    const size_t bytes = sizeof(int32_t) * (size_t)n * R.k;
+    const int32_t *src = R.host_rows.data() + (size_t)first * R.k;
+    if (mem_kind == GS_MEM_DEVICE) HIPCHK(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
+    else memcpy(dst, src, bytes);
+    if (written) *written = n;
+    return GS_OK;
+  }
   Engine &E = *R.eng;
   HIPCHK(hipSetDevice(E.device));
   hipStream_t s = E.stream;
@@ -628,7 +644,7 @@ void result_free(Result *R) {
   if (!R) return;
   Engine *E = R->eng;
   if (R->own) E->dfree(R->own);
-  else if (E && E->live_results > 0 && --E->live_results == 0) E->tree_top = 0;
+  else if (!R->host_owned && E && E->live_results > 0 && --E->live_results == 0) E->tree_top = 0;
   delete R;
 }
 

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -30,7 +31,9 @@ struct Result {
   int32_t **d_lvl_ptr = nullptr;   // device copies for enumeration (in the run's arena block)
   int64_t *d_lvl_n = nullptr;
   int32_t *d_var_rank = nullptr;
-  void *own = nullptr;             // memory owned by this result (server results), else arena
+  void *own = nullptr;             // device memory owned by this result, else arena
+  bool host_owned = false;         // rows live in host_rows (served results), no arena reference
+  std::vector<int32_t> host_rows;
   int run_id = -1;                 // arena run this result lives in
   gs_query_stats stats{};
 };
@@ -78,6 +81,45 @@ struct Engine {
   void dfree(void *p);
   ~Engine();
 };
+
+struct QInfo {                      // one planned query and where its tables sit
+  NormQuery nq;
+  Plan plan;
+  int32_t slot = 0;                  // index of its level / counter tables
+  int32_t step0 = 0, seed0 = 0, nseed = 0, dom0 = 0, ndom = 0, vr0 = 0;
+  bool zero = false;                 // no variable: constant patterns only
+};
+
+struct Tables {                      // compiled step programs of a set of queries (host copy)
+  std::vector<DStep> steps;
+  std::vector<const uint64_t *> filt;
+  std::vector<DCheck> checks;
+  std::vector<int32_t> ints;
+  std::vector<DConst> cconst;
+  std::vector<DSeed> seeds;
+  std::vector<DDomain> doms;
+  std::vector<int32_t> dom_step;
+  std::vector<int32_t> var_rank;
+};
+
+struct IterLists {                   // host work lists of one iteration
+  std::vector<DEntry> ents;
+  std::vector<DDomain> doms;
+  std::vector<uint64_t *> clears;
+  std::vector<DSeed> seeds;
+  int32_t has_list = 0;
+};
+
+int plan_query(const Engine &E, const gs_query &q, QInfo &qi, std::string &msg);
+void compile_query(const Engine &E, QInfo &qi, bool count_only, int slot, Tables &T,
+                   const std::function<uint64_t *()> &next_bitmap);
+void build_iteration(const Tables &T, const std::vector<const QInfo *> &qs, const std::vector<int> &level,
+                     IterLists &L);
+void account_iteration(Engine &E, const hipEvent_t *ev, const IterScalars &I, const IterLists &L, double write_bytes);
+void fill_result(Result &R, const QInfo &qi, bool count_only, int32_t *const *lvl_p, const int64_t *lvl_n,
+                 const int64_t *qstats, int64_t zero_res, double ms);
+hipError_t zero_words(uint64_t *p, int64_t n, hipStream_t s);
+hipError_t launch_const_only(const DevGraph &g, const DConst *cc, int n, int64_t *out, hipStream_t s);
 
 // Plan-compile-run a batch; results appended to out (one per query).
 int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector<Result *> &out, double *ms);

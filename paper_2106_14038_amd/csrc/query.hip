@@ -451,10 +451,17 @@ struct TileNz {
   int64_t woff[kTileWork + 1];
   int64_t lo[kTileWork + 1];
   int32_t node[kTileWork + 1];
+  uint16_t kmap[kTileWork];   // item of the tile -> index of its node in the arrays above
+  int32_t wmax[kWaves];
   int count;
   int e;
   int64_t a, b;
 };
+
+// A step whose candidates face no test: every candidate entry becomes a child.
+__device__ __forceinline__ bool test_free(const DStep &S) {
+  return S.nfilt == S.list_nfilt && S.nchk == 0 && S.nself == 0;
+}
 
 __device__ __forceinline__ int64_t last_le_global(const int64_t *v, int64_t lo, int64_t hi, int64_t key) {
   // last index k in [lo, hi) with v[k] <= key (v[lo] <= key holds)
@@ -482,22 +489,37 @@ __device__ __forceinline__ void load_tile(const IterArgs &A, int64_t t, TileNz &
   }
   __syncthreads();
   const int64_t k0 = k0s;
+  constexpr int per = kTileWork / kBlock;
+  for (int i = 0; i < per; ++i) T.kmap[threadIdx.x * per + i] = 0;
+  __syncthreads();
   for (int k = threadIdx.x; k < T.count; k += blockDim.x) {
-    T.woff[k] = it->nz_woff[k0 + k];
+    const int64_t wo = it->nz_woff[k0 + k];
+    T.woff[k] = wo;
     T.lo[k] = it->nz_lo[k0 + k];
     T.node[k] = it->nz_node[k0 + k];
+    if (k > 0) T.kmap[wo - T.a] = (uint16_t)k;   // node k starts inside the tile (node 0 may start before it)
   }
+  __syncthreads();
+  // forward fill: each item takes the last node start at or before it (a max-scan, node starts ascend)
+  int v[per];
+  int m = 0;
+  for (int i = 0; i < per; ++i) { m = max(m, (int)T.kmap[threadIdx.x * per + i]); v[i] = m; }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int incl = m;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int u = __shfl_up(incl, off, 64);
+    if (lane >= off) incl = max(incl, u);
+  }
+  if (lane == 63) T.wmax[wv] = incl;
+  __syncthreads();
+  int pre = __shfl_up(incl, 1, 64);
+  if (lane == 0) pre = 0;
+  for (int i = 0; i < wv; ++i) pre = max(pre, T.wmax[i]);
+  for (int i = 0; i < per; ++i) T.kmap[threadIdx.x * per + i] = (uint16_t)max(pre, v[i]);
   __syncthreads();
 }
 
-__device__ __forceinline__ int tile_find(const TileNz &T, int64_t w) {
-  int lo = 0, hi = T.count;   // last k with woff[k] <= w
-  while (hi - lo > 1) {
-    int mid = (lo + hi) >> 1;
-    if (T.woff[mid] <= w) lo = mid; else hi = mid;
-  }
-  return lo;
-}
+__device__ __forceinline__ int tile_find(const TileNz &T, int64_t w) { return T.kmap[w - T.a]; }
 
 __device__ __forceinline__ int32_t candidate(const IterArgs &A, const EState &E, const DStep &S, const TileNz &T,
                                              int k, int64_t w) {
@@ -534,6 +556,21 @@ __global__ __launch_bounds__(kBlock) void k_expand_count(const IterArgs A) {
   block_share(it->work_tiles, tb, te);
   int64_t bsum = 0;
   for (int64_t t = tb; t < te; ++t) {
+    __shared__ int sh_e;
+    if (threadIdx.x == 0) sh_e = last_le(A.E, t, [&](int i) { return es[i].w_tile0; });
+    __syncthreads();
+    {
+      const int e = sh_e;
+      const DStep S0 = A.steps[A.ent[e].step];
+      __syncthreads();
+      if (test_free(S0)) {   // every candidate is a child: the tile count is its size
+        const int64_t a = (t - es[e].w_tile0) * kTileWork;
+        const int64_t c = min(a + kTileWork, es[e].w) - a;
+        if (threadIdx.x == 0) atomicAdd((unsigned long long *)&es[e].cnt, (unsigned long long)c);
+        bsum += c;
+        continue;
+      }
+    }
     load_tile(A, t, T);
     const int e = T.e;
     const EState E = es[e];
@@ -624,10 +661,16 @@ __global__ __launch_bounds__(kBlock) void k_expand_write(const IterArgs A) {
     const int e = T.e;
     const EState E = es[e];
     const DStep S = A.steps[A.ent[e].step];
+    const bool all = test_free(S);
     for (int r = 0; r < kTileWork / kBlock; ++r) {
-      const uint32_t *vw = it->valid + t * (kTileWork / 32) + (r * kBlock + wv * 64) / 32;
-      const uint64_t bal = (uint64_t)vw[0] | ((uint64_t)vw[1] << 32);
-      const bool ok = (bal >> lane) & 1ull;
+      bool ok;
+      if (all) {
+        ok = T.a + r * kBlock + threadIdx.x < T.b;
+      } else {
+        const uint32_t *vw = it->valid + t * (kTileWork / 32) + (r * kBlock + wv * 64) / 32;
+        const uint64_t bal = (uint64_t)vw[0] | ((uint64_t)vw[1] << 32);
+        ok = (bal >> lane) & 1ull;
+      }
       int tot;
       const int pos = block_excl_flag(ok, tot, ldi);
       if (ok && E.out) {
