@@ -399,15 +399,18 @@ static u128 *dp_message(dp_t *D, int32_t x, int pb) {
     u128 *cm = dp_message(D, w, bi);
     /* sum over values d of w adjacent to c through the bundle's first edge, then check the rest */
     int x_is_u = (b->u == x);
+    /* first edge, oriented from x: dir 0 with x == u means (x, p, w): neighbours of c along out-edges */
+    int d0 = b->dir[0];
+    int out_from_x = x_is_u ? (d0 == 0) : (d0 == 1);
+    const otrip *tt = out_from_x ? g->spo : g->ops;
+    const int32_t p0 = b->lab[0];
+    int64_t k = 0;   /* cursor into the sorted triples: c ascends, so (c, p0) ranges come in order */
     for (int64_t c = 0; c < g->n; ++c) {
+      while (k < g->m && (tt[k].a < c || (tt[k].a == c && tt[k].p < p0))) ++k;
       if (!msg[c]) continue;
-      /* first edge, oriented from x: dir 0 with x == u means (x, p, w): neighbours of c along out-edges */
-      int d0 = b->dir[0];
-      int out_from_x = x_is_u ? (d0 == 0) : (d0 == 1);
-      int64_t cnt; const otrip *nb = adj(g, (int32_t)c, b->lab[0], out_from_x ? 0 : 1, &cnt);
       u128 s = 0;
-      for (int64_t t = 0; t < cnt; ++t) {
-        int32_t d = nb[t].b;
+      for (int64_t t = k; t < g->m && tt[t].a == c && tt[t].p == p0; ++t) {
+        int32_t d = tt[t].b;
         if (!cm[d]) continue;
         int ok = x_is_u ? bundle_holds(g, b, (int32_t)c, d) : bundle_holds(g, b, d, (int32_t)c);
         if (ok) s = sat_add(s, cm[d]);

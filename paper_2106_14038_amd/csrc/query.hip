@@ -47,6 +47,28 @@ __device__ __forceinline__ int last_le(int E, int64_t t, Key key) {
 
 __device__ __forceinline__ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Per-workgroup accumulation of per-entry counters: a workgroup walks a
+// contiguous range of tiles, so it meets few entries; adding to the entry's
+// counter only when the entry changes keeps global atomics off the per-tile
+// path (one counter address would otherwise serialise every tile of a level).
+struct EntryAcc {
+  int e = -1;
+  int64_t v0 = 0, v1 = 0;
+  __device__ void add(int en, int64_t a, int64_t b, int64_t *p0, int64_t *p1, int64_t stride) {
+    if (en != e) { flush(p0, p1, stride); e = en; }
+    v0 += a; v1 += b;
+  }
+  __device__ void flush(int64_t *p0, int64_t *p1, int64_t stride) {
+    if (e >= 0) {
+      if (v0 && p0) atomicAdd((unsigned long long *)(p0 + (int64_t)e * stride), (unsigned long long)v0);
+      if (v1 && p1) atomicAdd((unsigned long long *)(p1 + (int64_t)e * stride), (unsigned long long)v1);
+    }
+    v0 = v1 = 0;
+  }
+};
+static_assert(sizeof(EState) % sizeof(int64_t) == 0, "EState must be a whole number of int64");
+constexpr int64_t kEsStride = sizeof(EState) / sizeof(int64_t);
+
 // ------------------------------------------------------------------ setup
 __global__ __launch_bounds__(1024) void k_it_setup(const IterArgs A) {
   __shared__ int64_t lds[1024];
@@ -135,6 +157,8 @@ __global__ __launch_bounds__(kBlock) void k_list_count(const IterArgs A) {
   int64_t tb, te;
   block_share(it->list_tiles, tb, te);
   int64_t bsum = 0;
+  EntryAcc acc;
+  int64_t *p_list_n = &es[0].list_n;
   for (int64_t t = tb; t < te; ++t) {
     if (threadIdx.x == 0) sh_e = last_le(A.E, t, [&](int i) { return es[i].list_tile0; });
     __syncthreads();
@@ -144,10 +168,10 @@ __global__ __launch_bounds__(kBlock) void k_list_count(const IterArgs A) {
     int64_t c = 0;
     if (w < es[e].list_words) c = __popcll(list_word(A, S, w));
     c = block_sum_i64(c, lds);
-    if (threadIdx.x == 0 && c) atomicAdd((unsigned long long *)&es[e].list_n, (unsigned long long)c);
+    if (threadIdx.x == 0) acc.add(e, c, 0, p_list_n, nullptr, kEsStride);
     bsum += c;
   }
-  if (threadIdx.x == 0) A.blk_a[blockIdx.x] = bsum;
+  if (threadIdx.x == 0) { acc.flush(p_list_n, nullptr, kEsStride); A.blk_a[blockIdx.x] = bsum; }
 }
 
 __global__ __launch_bounds__(1024) void k_list_scan(const IterArgs A) {
@@ -342,6 +366,8 @@ __global__ __launch_bounds__(kBlock) void k_lookup(const IterArgs A) {
   int64_t tb, te;
   block_share(it->node_tiles, tb, te);
   int64_t bnz = 0, bw = 0;
+  EntryAcc acc;
+  int64_t *p_nz = &es[0].nz, *p_w = &es[0].w;
   for (int64_t t = tb; t < te; ++t) {
     if (threadIdx.x == 0) sh_e = node_entry(A, t);
     __syncthreads();
@@ -373,14 +399,11 @@ __global__ __launch_bounds__(kBlock) void k_lookup(const IterArgs A) {
     }
     cnz = block_sum_i64(cnz, lds);
     cw = block_sum_i64(cw, lds);
-    if (threadIdx.x == 0) {
-      if (cnz) atomicAdd((unsigned long long *)&es[e].nz, (unsigned long long)cnz);
-      if (cw) atomicAdd((unsigned long long *)&es[e].w, (unsigned long long)cw);
-    }
+    if (threadIdx.x == 0) acc.add(e, cnz, cw, p_nz, p_w, kEsStride);
     bnz += cnz;
     bw += cw;
   }
-  if (threadIdx.x == 0) { A.blk_a[blockIdx.x] = bnz; A.blk_b[blockIdx.x] = bw; }
+  if (threadIdx.x == 0) { acc.flush(p_nz, p_w, kEsStride); A.blk_a[blockIdx.x] = bnz; A.blk_b[blockIdx.x] = bw; }
 }
 
 __global__ __launch_bounds__(1024) void k_scan_nodes(const IterArgs A) {
@@ -547,14 +570,16 @@ __device__ __forceinline__ bool test_candidate(const IterArgs &A, const EState &
 
 __global__ __launch_bounds__(kBlock) void k_expand_count(const IterArgs A) {
   __shared__ TileNz T;
-  __shared__ int64_t lds[kWaves];
+  __shared__ int64_t red4[kWaves][4];
   IterScalars *it = A.it;
   if (it->abort) return;
   EState *es = A.es;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   int64_t tb, te;
   block_share(it->work_tiles, tb, te);
-  int64_t bsum = 0;
+  int64_t bsum = 0, b_pr = 0, b_ft = 0, b_ct = 0;
+  EntryAcc acc, qacc;                    // valid counts per entry, probes per query
+  int64_t *p_cnt = &es[0].cnt, *p_probe = A.qstats + QS_PROBE;
   for (int64_t t = tb; t < te; ++t) {
     __shared__ int sh_e;
     if (threadIdx.x == 0) sh_e = last_le(A.E, t, [&](int i) { return es[i].w_tile0; });
@@ -566,7 +591,7 @@ __global__ __launch_bounds__(kBlock) void k_expand_count(const IterArgs A) {
       if (test_free(S0)) {   // every candidate is a child: the tile count is its size
         const int64_t a = (t - es[e].w_tile0) * kTileWork;
         const int64_t c = min(a + kTileWork, es[e].w) - a;
-        if (threadIdx.x == 0) atomicAdd((unsigned long long *)&es[e].cnt, (unsigned long long)c);
+        if (threadIdx.x == 0) acc.add(e, c, 0, p_cnt, nullptr, kEsStride);
         bsum += c;
         continue;
       }
@@ -594,23 +619,32 @@ __global__ __launch_bounds__(kBlock) void k_expand_count(const IterArgs A) {
       }
       c_tile += ok;
     }
-    c_tile = block_sum_i64(c_tile, lds);
-    const int64_t pr = block_sum_i64(probes, lds);
-    const int64_t ft = block_sum_i64(ftests, lds);
-    const int64_t ct = block_sum_i64(ctests, lds);
+    // one reduction for the four tile counters
+    int64_t v4[4] = {c_tile, probes, ftests, ctests};
+    for (int i = 0; i < 4; ++i) v4[i] = wave_sum_i64(v4[i]);
+    if (lane == 0) for (int i = 0; i < 4; ++i) red4[wv][i] = v4[i];
+    __syncthreads();
+    for (int i = 0; i < 4; ++i) { v4[i] = 0; for (int w2 = 0; w2 < kWaves; ++w2) v4[i] += red4[w2][i]; }
+    c_tile = v4[0];
+    const int64_t pr = v4[1], ft = v4[2], ct = v4[3];
     if (threadIdx.x == 0) {
-      if (c_tile) atomicAdd((unsigned long long *)&es[e].cnt, (unsigned long long)c_tile);
-      if (pr) {
-        atomicAdd((unsigned long long *)&A.qstats[(int64_t)d.q * QS_N + QS_PROBE], (unsigned long long)pr);
-        atomicAdd((unsigned long long *)&it->probes, (unsigned long long)pr);
-      }
-      if (ft) atomicAdd((unsigned long long *)&it->ftests, (unsigned long long)ft);
-      if (ct) atomicAdd((unsigned long long *)&it->ctests, (unsigned long long)ct);
+      acc.add(e, c_tile, 0, p_cnt, nullptr, kEsStride);
+      qacc.add(d.q, pr, 0, p_probe, nullptr, QS_N);
     }
+    b_pr += pr;
+    b_ft += ft;
+    b_ct += ct;
     bsum += c_tile;
     __syncthreads();
   }
-  if (threadIdx.x == 0) A.blk_a[blockIdx.x] = bsum;
+  if (threadIdx.x == 0) {
+    acc.flush(p_cnt, nullptr, kEsStride);
+    qacc.flush(p_probe, nullptr, QS_N);
+    if (b_pr) atomicAdd((unsigned long long *)&it->probes, (unsigned long long)b_pr);
+    if (b_ft) atomicAdd((unsigned long long *)&it->ftests, (unsigned long long)b_ft);
+    if (b_ct) atomicAdd((unsigned long long *)&it->ctests, (unsigned long long)b_ct);
+    A.blk_a[blockIdx.x] = bsum;
+  }
 }
 
 __global__ __launch_bounds__(1024) void k_scan_expand(const IterArgs A) {
@@ -646,13 +680,26 @@ __global__ __launch_bounds__(1024) void k_scan_expand(const IterArgs A) {
   }
 }
 
+__device__ __forceinline__ void write_child(const IterArgs &A, const EState &E, const DStep &S, const TileNz &T,
+                                            int64_t w, int64_t li) {
+  const int k = tile_find(T, w);
+  const int32_t c = candidate(A, E, S, T, k, w);
+  const int64_t cnt = E.cnt;
+  const int32_t node = T.node[k];
+  E.out[li] = node;
+  E.out[cnt + li] = c;
+  for (int j = 0; j < S.ncopy; ++j)
+    E.out[(int64_t)(2 + j) * cnt + li] = E.prev[(int64_t)A.ints[S.copy0 + j] * E.prev_n + node];
+}
+
 __global__ __launch_bounds__(kBlock) void k_expand_write(const IterArgs A) {
   __shared__ TileNz T;
-  __shared__ int ldi[kWaves];
+  __shared__ int wcnt[kTileWork / 64];   // valid items per (round, wave) of the tile
   IterScalars *it = A.it;
   if (it->abort) return;
   EState *es = A.es;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  constexpr int R = kTileWork / kBlock;
   int64_t tb, te;
   block_share(it->work_tiles, tb, te);
   int64_t run = A.blk_off_a[blockIdx.x];
@@ -661,32 +708,36 @@ __global__ __launch_bounds__(kBlock) void k_expand_write(const IterArgs A) {
     const int e = T.e;
     const EState E = es[e];
     const DStep S = A.steps[A.ent[e].step];
-    const bool all = test_free(S);
-    for (int r = 0; r < kTileWork / kBlock; ++r) {
-      bool ok;
-      if (all) {
-        ok = T.a + r * kBlock + threadIdx.x < T.b;
-      } else {
-        const uint32_t *vw = it->valid + t * (kTileWork / 32) + (r * kBlock + wv * 64) / 32;
-        const uint64_t bal = (uint64_t)vw[0] | ((uint64_t)vw[1] << 32);
-        ok = (bal >> lane) & 1ull;
-      }
-      int tot;
-      const int pos = block_excl_flag(ok, tot, ldi);
-      if (ok && E.out) {
-        const int64_t w = T.a + r * kBlock + threadIdx.x;
-        const int k = tile_find(T, w);
-        const int32_t c = candidate(A, E, S, T, k, w);
-        const int64_t li = run + pos - E.out_base;
-        const int64_t cnt = E.cnt;
-        const int32_t node = T.node[k];
-        E.out[li] = node;
-        E.out[cnt + li] = c;
-        for (int j = 0; j < S.ncopy; ++j)
-          E.out[(int64_t)(2 + j) * cnt + li] = E.prev[(int64_t)A.ints[S.copy0 + j] * E.prev_n + node];
-      }
-      run += tot;
+    if (test_free(S)) {   // every candidate is a child: its position is its offset in the tile
+      if (E.out)
+        for (int r = 0; r < R; ++r) {
+          const int64_t w = T.a + r * kBlock + threadIdx.x;
+          if (w < T.b) write_child(A, E, S, T, w, run + (w - T.a) - E.out_base);
+        }
+      run += T.b - T.a;
+      __syncthreads();
+      continue;
     }
+    // rank the valid items of the whole tile with one barrier: per (round, wave) counts
+    uint64_t bal[R];
+    for (int r = 0; r < R; ++r) {
+      const uint32_t *vw = it->valid + t * (kTileWork / 32) + (r * kBlock + wv * 64) / 32;
+      bal[r] = (uint64_t)vw[0] | ((uint64_t)vw[1] << 32);
+      if (lane == 0) wcnt[r * kWaves + wv] = __popcll(bal[r]);
+    }
+    __syncthreads();
+    int before = 0, total = 0;
+    for (int i = 0; i < R * kWaves; ++i) total += wcnt[i];
+    for (int r = 0; r < R; ++r) {
+      int pre = before;
+      for (int w2 = 0; w2 < wv; ++w2) pre += wcnt[r * kWaves + w2];
+      if (E.out && ((bal[r] >> lane) & 1ull)) {
+        const int64_t w = T.a + r * kBlock + threadIdx.x;
+        write_child(A, E, S, T, w, run + pre + __popcll(bal[r] & lanemask_lt()) - E.out_base);
+      }
+      for (int w2 = 0; w2 < kWaves; ++w2) before += wcnt[r * kWaves + w2];
+    }
+    run += total;
     __syncthreads();
   }
 }
