@@ -253,6 +253,20 @@ typedef struct {
 } gs_kernel_stat;
 gs_status gs_kernel_stats(gs_engine *engine, gs_kernel_stat *out, int32_t cap, int32_t *n, int reset);
 
+/* Autotuner: evaluates the given queries (count only, batched) under every
+ * candidate workgroup count of the fixed-grid kernels (2, 4, 8 and 16 per
+ * compute unit) and push/pull threshold (0.25, 1, 4), keeps the fastest pair
+ * for this engine's later calls, and reports it. Results are unchanged by the
+ * choice. Errors as gs_batch_run. */
+typedef struct {
+  int32_t grid_blocks;
+  float push_pull_theta;
+  double best_ms;             /* device time of the calibration batch with the chosen pair */
+  double default_ms;          /* same with the engine's settings before tuning */
+  int32_t n_tried;
+} gs_tune_result;
+gs_status gs_autotune(gs_engine *engine, const gs_query *queries, int32_t nq, gs_tune_result *out);
+
 /* Free a result. NULL is ignored. */
 void gs_result_free(gs_result *result);
 

@@ -77,6 +77,11 @@ class gs_kernel_stat(ctypes.Structure):
                 ("bytes_alg", ctypes.c_double)]
 
 
+class gs_tune_result(ctypes.Structure):
+    _fields_ = [("grid_blocks", ctypes.c_int32), ("push_pull_theta", ctypes.c_float), ("best_ms", ctypes.c_double),
+                ("default_ms", ctypes.c_double), ("n_tried", ctypes.c_int32)]
+
+
 class gs_server_options(ctypes.Structure):
     _fields_ = [("max_active", ctypes.c_int32), ("tree_budget_bytes", ctypes.c_uint64), ("flags", ctypes.c_uint32)]
 
@@ -113,6 +118,7 @@ SIGNATURES = {
     "gs_poll": ([_vp, _u64, _P(_vp)], ctypes.c_int),
     "gs_server_stop": ([_vp, _P(gs_server_stats)], ctypes.c_int),
     "gs_kernel_stats": ([_vp, _P(gs_kernel_stat), _i32, _P(_i32), ctypes.c_int], ctypes.c_int),
+    "gs_autotune": ([_vp, _P(gs_query), _i32, _P(gs_tune_result)], ctypes.c_int),
     "gs_last_error": ([], ctypes.c_char_p),
 }
 
@@ -302,6 +308,13 @@ def gs_kernel_stats(engine, reset: bool = False) -> dict:
     _check(lib().gs_kernel_stats(engine, arr, 32, ctypes.byref(n), int(reset)))
     return {arr[i].name.decode(): {"launches": arr[i].launches, "ms": arr[i].ms, "bytes_alg": arr[i].bytes_alg}
             for i in range(min(n.value, 32))}
+
+
+def gs_autotune(engine, qs: list) -> gs_tune_result:
+    arr = (gs_query * len(qs))(*[make_query(q) for q in qs])
+    out = gs_tune_result()
+    _check(lib().gs_autotune(engine, arr, len(qs), ctypes.byref(out)))
+    return out
 
 
 def gs_result_free(result):

@@ -287,8 +287,11 @@ gs_status gs_query_run(gs_engine *engine, const gs_query *query, uint32_t flags,
   std::lock_guard<std::mutex> lk(engine->e.mu);
   std::vector<Result *> rs;
   double ms = 0;
+  if ((flags & GS_PRUNE) && (flags & GS_COUNT_ONLY)) { set_error("pruning needs the last level"); return GS_EINVAL; }
   int rc = run_batch(engine->e, query, 1, flags, rs, &ms);
   if (rc != GS_OK) return (gs_status)rc;
+  if (flags & GS_PRUNE) rc = result_prune(*rs[0]);
+  if (rc != GS_OK) { result_free(rs[0]); return (gs_status)rc; }
   *out = wrap(rs[0]);
   return GS_OK;
 }
@@ -299,9 +302,61 @@ gs_status gs_batch_run(gs_engine *engine, const gs_query *queries, int32_t nq, u
   std::lock_guard<std::mutex> lk(engine->e.mu);
   std::vector<Result *> rs;
   double ms = 0;
+  if ((flags & GS_PRUNE) && (flags & GS_COUNT_ONLY)) { set_error("pruning needs the last level"); return GS_EINVAL; }
   int rc = run_batch(engine->e, queries, nq, flags, rs, &ms);
   if (rc != GS_OK) return (gs_status)rc;
+  for (int i = 0; i < nq && rc == GS_OK && (flags & GS_PRUNE); ++i) rc = result_prune(*rs[i]);
+  if (rc != GS_OK) { for (Result *r : rs) result_free(r); return (gs_status)rc; }
   for (int i = 0; i < nq; ++i) outs[i] = wrap(rs[i]);
+  return GS_OK;
+}
+
+gs_status gs_autotune(gs_engine *engine, const gs_query *queries, int32_t nq, gs_tune_result *out) {
+  if (!engine || !queries || nq <= 0 || !out) { set_error("bad argument"); return GS_EINVAL; }
+  Engine &E = engine->e;
+  std::lock_guard<std::mutex> lk(E.mu);
+  const int grid0 = E.grid;
+  const float theta0 = E.opt.push_pull_theta;
+  const int prof0 = E.opt.profile_kernels;
+  E.opt.profile_kernels = 0;
+  auto trial = [&](int grid, float theta, double &ms) -> int {
+    E.grid = grid;
+    E.opt.push_pull_theta = theta;
+    double best = 1e300;
+    for (int rep = 0; rep < 2; ++rep) {   // first run warms caches and the allocator
+      std::vector<Result *> rs;
+      double t = 0;
+      int rc = run_batch(E, queries, nq, GS_COUNT_ONLY, rs, &t);
+      for (Result *r : rs) result_free(r);
+      if (rc != GS_OK) return rc;
+      if (rep) best = std::min(best, t);
+    }
+    ms = best;
+    return GS_OK;
+  };
+  double ms0 = 0;
+  int rc = trial(grid0, theta0, ms0);
+  memset(out, 0, sizeof *out);
+  out->grid_blocks = grid0;
+  out->push_pull_theta = theta0 > 0 ? theta0 : 1.0f;
+  out->best_ms = ms0;
+  out->default_ms = ms0;
+  const int mults[] = {2, 4, 8, 16};
+  const float thetas[] = {0.25f, 1.0f, 4.0f};
+  for (int m : mults) {
+    for (float th : thetas) {
+      if (rc != GS_OK) break;
+      const int grid = std::min(8192, m * E.cus);
+      double ms = 0;
+      rc = trial(grid, th, ms);
+      out->n_tried++;
+      if (rc == GS_OK && ms < out->best_ms) { out->best_ms = ms; out->grid_blocks = grid; out->push_pull_theta = th; }
+    }
+  }
+  E.opt.profile_kernels = prof0;
+  if (rc != GS_OK) { E.grid = grid0; E.opt.push_pull_theta = theta0; return (gs_status)rc; }
+  E.grid = out->grid_blocks;
+  E.opt.push_pull_theta = out->push_pull_theta;
   return GS_OK;
 }
 

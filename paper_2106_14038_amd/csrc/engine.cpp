@@ -48,6 +48,7 @@ Engine::~Engine() {
   dfree(scratch_base);
   dfree(d_arenas);
   for (hipEvent_t e : events) (void)hipEventDestroy(e);
+  for (GraphEntry &g : graphs) { (void)hipGraphExecDestroy(g.exec); (void)hipGraphDestroy(g.graph); }
   if (own_stream && stream) (void)hipStreamDestroy(stream);
 }
 
@@ -340,8 +341,11 @@ void account_iteration(Engine &E, const hipEvent_t *ev, const IterScalars &I, co
     double b = 0;
     const double W = (double)I.w_total, nz = (double)I.nz_total;
     switch (k) {
-      case KS_EXPAND_COUNT:   // candidate ids, staged node records, filter words, parent bindings, probes, valid bits
-        b = 4 * W + 20 * nz + 8.0 * I.ftests + 4.0 * I.ctests + 4.0 * I.probes + W / 8; break;
+      case KS_EXPAND_COUNT: {  // tested levels only: ids, staged node records, filter words, parent bindings,
+        const double Wt = (double)I.w_tested;   // probes, valid bits
+        b = 4 * Wt + 20 * nz * (W > 0 ? Wt / W : 0) + 8.0 * I.ftests + 4.0 * I.ctests + 4.0 * I.probes + Wt / 8;
+        break;
+      }
       case KS_EXPAND_WRITE:   // valid bits, staged node records, candidate ids + copies read + columns written
         b = W / 8 + 20 * nz + write_bytes; break;
       case KS_LOOKUP:         // parent binding, offset pair, segment written
@@ -432,7 +436,6 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
   char *base = E.tree_base;
   auto dp = [&](uint64_t o) { return (void *)(base + o); };
   HIPCHK(hipMemcpyAsync(base + tab_off, buf.data(), buf.size(), hipMemcpyHostToDevice, s));
-  HIPCHK(zero_words((uint64_t *)dp(o_lvlp), (int64_t)((zero_end - o_lvlp) / 8), s));
   DArena ar[2];
   ar[0] = {off, E.tree_cap, 0, 0};
   ar[1] = {0, E.scratch_cap, 0, 0};
@@ -441,10 +444,10 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
   hipEvent_t ev0, ev1;
   HIPCHK(hipEventCreate(&ev0));
   HIPCHK(hipEventCreate(&ev1));
-  HIPCHK(hipEventRecord(ev0, s));
 
   // 5. iterations
   const bool prof = E.opt.profile_kernels != 0;
+  const bool graphs = E.opt.use_graphs != 0 && !prof;
   if (prof) {
     const size_t need = (size_t)2 * KS_N * std::max(maxk, 1);
     while (E.events.size() < need) {
@@ -453,8 +456,10 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
       E.events.push_back(ev);
     }
   }
+  std::vector<IterArgs> iargs(maxk);
   for (int t = 0; t < maxk; ++t) {
-    IterArgs A{};
+    IterArgs &A = iargs[t];
+    A = IterArgs{};
     A.g = E.g;
     A.ent = (const DEntry *)dp(tab_off + o_ents) + ent_off[t];
     A.E = ent_off[t + 1] - ent_off[t];
@@ -483,7 +488,55 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
     A.tree_base = E.tree_base;
     int64_t *blk = (int64_t *)dp(o_blk);
     A.blk_a = blk; A.blk_b = blk + E.grid; A.blk_off_a = blk + 2 * E.grid; A.blk_off_b = blk + 3 * E.grid;
-    hipError_t e = launch_iteration(A, s, prof ? &E.events[(size_t)2 * KS_N * t] : nullptr);
+  }
+  uint64_t *zero_p = (uint64_t *)dp(o_lvlp);
+  const int64_t zero_n = (int64_t)((zero_end - o_lvlp) / 8);
+  auto launch_all = [&]() -> hipError_t {
+    hipError_t e = zero_words(zero_p, zero_n, s);
+    for (int t = 0; t < maxk && e == hipSuccess; ++t)
+      e = launch_iteration(iargs[t], s, prof ? &E.events[(size_t)2 * KS_N * t] : nullptr);
+    return e;
+  };
+  HIPCHK(hipEventRecord(ev0, s));
+  if (graphs) {
+    // FNV-1a over every launch argument: equal keys launch identical kernels with identical arguments
+    uint64_t key = 1469598103934665603ull;
+    auto mix = [&](const void *p, size_t n) {
+      const unsigned char *c = (const unsigned char *)p;
+      for (size_t i = 0; i < n; ++i) { key ^= c[i]; key *= 1099511628211ull; }
+    };
+    mix(&zero_p, sizeof zero_p); mix(&zero_n, sizeof zero_n); mix(&maxk, sizeof maxk);
+    for (const IterArgs &A : iargs) mix(&A, sizeof A);
+    Engine::GraphEntry *ge = nullptr;
+    for (Engine::GraphEntry &g : E.graphs) if (g.key == key) ge = &g;
+    if (!ge) {
+      if (E.graphs.size() >= 64) {   // evict the least recently used
+        auto it = std::min_element(E.graphs.begin(), E.graphs.end(),
+                                   [](const Engine::GraphEntry &a, const Engine::GraphEntry &b) { return a.last_use < b.last_use; });
+        (void)hipGraphExecDestroy(it->exec);
+        (void)hipGraphDestroy(it->graph);
+        E.graphs.erase(it);
+      }
+      Engine::GraphEntry g{key, nullptr, nullptr, 0};
+      HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      hipError_t e = launch_all();
+      hipError_t e2 = hipStreamEndCapture(s, &g.graph);
+      if (e != hipSuccess || e2 != hipSuccess) {
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+        set_error(std::string("graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+        return GS_EDEVICE;
+      }
+      HIPCHK(hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
+      E.graphs.push_back(g);
+      ge = &E.graphs.back();
+      E.graph_builds++;
+    } else {
+      E.graph_hits++;
+    }
+    ge->last_use = ++E.graph_clock;
+    HIPCHK(hipGraphLaunch(ge->exec, s));
+  } else {
+    hipError_t e = launch_all();
     if (e != hipSuccess) { set_error(std::string("launch: ") + hipGetErrorString(e)); return GS_EDEVICE; }
   }
   // constant-only queries (no variable): every pattern between constants must hold
@@ -570,7 +623,11 @@ void fill_result(Result &R, const QInfo &qi, bool count_only, int32_t *const *lv
   if (qi.zero) {
     R.count = zero_res;
   } else {
-    for (int j = 0; j < P.n_vars; ++j) { R.lvl_ptr.push_back(lvl_p[j]); R.lvl_n.push_back(lvl_n[j]); }
+    for (int j = 0; j < P.n_vars; ++j) {
+      R.lvl_ptr.push_back(lvl_p[j]);
+      R.lvl_n.push_back(lvl_n[j]);
+      R.ncols_extra.push_back((int32_t)P.steps[j].carried.size());
+    }
     R.count = R.lvl_n.back();
   }
   gs_query_stats &st = R.stats;
@@ -637,6 +694,54 @@ int result_rows(Result &R, int64_t first, int64_t n, void *dst, int mem_kind, in
     E.dfree(tmp);
   }
   if (written) *written = n;
+  return GS_OK;
+}
+
+int result_prune(Result &R) {
+  if (R.count_only || R.zero_vars || R.host_owned || R.k <= 1) return GS_OK;
+  Engine &E = *R.eng;
+  HIPCHK(hipSetDevice(E.device));
+  hipStream_t s = E.stream;
+  const int k = R.k;
+  int64_t tot = 0;
+  for (int j = 0; j < k; ++j) tot += R.lvl_n[j];
+  uint8_t *alive = (uint8_t *)E.dmalloc((size_t)tot + 64);
+  int32_t *newidx = (int32_t *)E.dmalloc(sizeof(int32_t) * ((size_t)tot + 16));
+  int64_t *blk = (int64_t *)E.dmalloc(sizeof(int64_t) * (2 * (size_t)E.grid + 2));
+  auto cleanup = [&]() { E.dfree(alive); E.dfree(newidx); E.dfree(blk); };
+  if (!alive || !newidx || !blk) { cleanup(); set_error("out of device memory for pruning"); return GS_ENOMEM; }
+  std::vector<int64_t> off(k + 1, 0);
+  for (int j = 0; j < k; ++j) off[j + 1] = off[j] + R.lvl_n[j];
+  hipError_t e = hipMemsetAsync(alive, 0, (size_t)tot, s);
+  if (e == hipSuccess) e = hipMemsetAsync(alive + off[k - 1], 1, (size_t)R.lvl_n[k - 1], s);
+  for (int j = k - 1; j >= 1 && e == hipSuccess; --j)   // a node survives when one of its children does
+    e = launch_prune_mark(R.lvl_ptr[j], R.lvl_n[j], alive + off[j], alive + off[j - 1], s);
+  std::vector<int32_t *> np(k);
+  std::vector<int64_t> nn(k);
+  for (int j = 0; j < k && e == hipSuccess; ++j) {
+    const int ncols = 2 + (int)R.ncols_extra[j];
+    int64_t cnt = 0;
+    e = launch_prune_count(alive + off[j], R.lvl_n[j], blk, E.grid, s);
+    if (e == hipSuccess) e = scan_i64(blk, E.grid, blk + E.grid, blk + 2 * E.grid, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&cnt, blk + 2 * E.grid, 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) break;
+    const uint64_t bytes = align256(sizeof(int32_t) * (uint64_t)cnt * ncols);
+    const uint64_t at = align256(E.tree_top);
+    if (at + bytes > E.tree_cap) { cleanup(); set_error("tree arena too small to prune"); return GS_ENOMEM; }
+    E.tree_top = at + bytes;
+    np[j] = (int32_t *)(E.tree_base + at);
+    nn[j] = cnt;
+    e = launch_prune_write(R.lvl_ptr[j], R.lvl_n[j], ncols, alive + off[j], blk + E.grid,
+                           j ? newidx + off[j - 1] : nullptr, newidx + off[j], np[j], cnt, E.grid, s);
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(R.d_lvl_ptr, np.data(), sizeof(void *) * k, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(R.d_lvl_n, nn.data(), sizeof(int64_t) * k, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  cleanup();
+  if (e != hipSuccess) { set_error(hipGetErrorString(e)); return GS_EDEVICE; }
+  R.lvl_ptr = np;
+  R.lvl_n = nn;
   return GS_OK;
 }
 

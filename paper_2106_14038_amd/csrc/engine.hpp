@@ -28,6 +28,7 @@ struct Result {
   std::vector<int32_t *> lvl_ptr;  // device pointers per level
   std::vector<int64_t> lvl_n;
   std::vector<int32_t> var_rank;
+  std::vector<int32_t> ncols_extra;  // carried columns per level
   int32_t **d_lvl_ptr = nullptr;   // device copies for enumeration (in the run's arena block)
   int64_t *d_lvl_n = nullptr;
   int32_t *d_var_rank = nullptr;
@@ -74,6 +75,12 @@ struct Engine {
   struct KStat { int64_t launches = 0; double ms = 0, bytes = 0; };
   KStat kstat[KS_N];
   std::vector<hipEvent_t> events;  // pool, 2 * KS_N per iteration
+
+  // captured launch sequences of batches (gs_options.use_graphs), keyed by a hash of their launch arguments
+  struct GraphEntry { uint64_t key; hipGraph_t graph; hipGraphExec_t exec; uint64_t last_use; };
+  std::vector<GraphEntry> graphs;
+  uint64_t graph_clock = 0;
+  int64_t graph_hits = 0, graph_builds = 0;
 
   std::mutex mu;                   // serialises runs (server vs. direct use is documented as exclusive)
 
@@ -125,6 +132,7 @@ hipError_t launch_const_only(const DevGraph &g, const DConst *cc, int n, int64_t
 int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector<Result *> &out, double *ms);
 int load_triples(Engine &E, int64_t n, int32_t P, const gs_triple *t, int64_t m, int mem_kind);
 int result_rows(Result &R, int64_t first, int64_t n, void *dst, int mem_kind, int64_t *written);
+int result_prune(Result &R);
 void result_free(Result *R);
 
 }  // namespace gs

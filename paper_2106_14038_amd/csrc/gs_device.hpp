@@ -101,6 +101,7 @@ struct IterScalars {
   int64_t ftests;          // bitmap filter words tested
   int64_t ctests;          // exact checks started (each reads one parent binding)
   int64_t probes;          // label / id entries touched by binary searches
+  int64_t w_tested;        // candidate entries of levels that test their candidates
 };
 
 // Kernel slots of one iteration, for optional event timing.

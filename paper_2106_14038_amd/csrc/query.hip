@@ -66,6 +66,11 @@ struct EntryAcc {
     v0 = v1 = 0;
   }
 };
+// A step whose candidates face no test: every candidate entry becomes a child.
+__device__ __forceinline__ bool test_free(const DStep &S) {
+  return S.nfilt == S.list_nfilt && S.nchk == 0 && S.nself == 0;
+}
+
 static_assert(sizeof(EState) % sizeof(int64_t) == 0, "EState must be a whole number of int64");
 constexpr int64_t kEsStride = sizeof(EState) / sizeof(int64_t);
 
@@ -417,6 +422,13 @@ __global__ __launch_bounds__(1024) void k_scan_nodes(const IterArgs A) {
   const int64_t w = wg_scan(A.E, [&](int64_t i) { return es[i].w; }, [&](int64_t i, int64_t v) { es[i].w_base = v; }, lds);
   const int64_t wt = wg_scan(A.E, [&](int64_t i) { return ceil_div(es[i].w, kTileWork); },
                              [&](int64_t i, int64_t v) { es[i].w_tile0 = v; }, lds);
+  __shared__ int64_t wtest;
+  if (threadIdx.x == 0) wtest = 0;
+  __syncthreads();
+  for (int e = threadIdx.x; e < A.E; e += blockDim.x)
+    if (!test_free(A.steps[A.ent[e].step]) && es[e].w) atomicAdd((unsigned long long *)&wtest, (unsigned long long)es[e].w);
+  __syncthreads();
+  if (threadIdx.x == 0) it->w_tested = wtest;
   if (threadIdx.x == 0) {
     it->nz_total = nz;
     it->w_total = w;
@@ -481,10 +493,7 @@ struct TileNz {
   int64_t a, b;
 };
 
-// A step whose candidates face no test: every candidate entry becomes a child.
-__device__ __forceinline__ bool test_free(const DStep &S) {
-  return S.nfilt == S.list_nfilt && S.nchk == 0 && S.nself == 0;
-}
+
 
 __device__ __forceinline__ int64_t last_le_global(const int64_t *v, int64_t lo, int64_t hi, int64_t key) {
   // last index k in [lo, hi) with v[k] <= key (v[lo] <= key holds)
@@ -495,32 +504,75 @@ __device__ __forceinline__ int64_t last_le_global(const int64_t *v, int64_t lo, 
   return lo;
 }
 
-// Load the non-empty nodes covering work tile t into LDS.
-__device__ __forceinline__ void load_tile(const IterArgs &A, int64_t t, TileNz &T) {
+// Load the non-empty nodes covering work tile t into LDS. A workgroup walks
+// consecutive tiles, so the entry and the first node carry over from the
+// previous tile (cursor): only a workgroup's first tile of an entry searches.
+// The tile's last node comes from a coalesced window of node offsets.
+struct TileCursor { int e = -1; int64_t k_last = -1; int64_t next_tile0 = 0; };
+
+__device__ __forceinline__ void load_tile(const IterArgs &A, int64_t t, TileNz &T, TileCursor &C) {
   IterScalars *it = A.it;
   EState *es = A.es;
-  __shared__ int64_t k0s, k1s;
+  __shared__ int64_t k0s, nwin;
   if (threadIdx.x == 0) {
-    const int e = last_le(A.E, t, [&](int i) { return es[i].w_tile0; });
+    int e = C.e;
+    if (e < 0 || t >= C.next_tile0 || t < es[e].w_tile0) {
+      e = last_le(A.E, t, [&](int i) { return es[i].w_tile0; });
+      C.k_last = -1;
+    }
+    if (e != C.e) {
+      C.e = e;
+      C.k_last = -1;
+      C.next_tile0 = es[e].w_tile0 + (es[e].w + kTileWork - 1) / kTileWork;
+    }
     T.e = e;
     T.a = (t - es[e].w_tile0) * kTileWork;
     T.b = min(T.a + kTileWork, es[e].w);
     const int64_t nb = es[e].nz_base, ne = nb + es[e].nz;
-    k0s = last_le_global(it->nz_woff, nb, ne, T.a);
-    k1s = last_le_global(it->nz_woff, k0s, ne, T.b - 1);
-    T.count = (int)(k1s - k0s + 1);
+    int64_t k0;
+    if (C.k_last >= 0) {   // the previous tile ended inside node k_last: this one starts there or just after
+      k0 = C.k_last;
+      while (k0 + 1 < ne && it->nz_woff[k0 + 1] <= T.a) ++k0;
+    } else {
+      k0 = last_le_global(it->nz_woff, nb, ne, T.a);
+    }
+    k0s = k0;
+    nwin = min((int64_t)kTileWork + 1, ne - k0);
   }
   __syncthreads();
   const int64_t k0 = k0s;
+  const int n = (int)nwin;
+  // node offsets of the tile: a first window of one per thread, extended only when
+  // the tile holds more nodes than that (short segments)
+  const int64_t last = T.b - 1;
+  int n1 = min(n, (int)blockDim.x);
+  if (threadIdx.x < n1) T.woff[threadIdx.x] = it->nz_woff[k0 + threadIdx.x];
+  __syncthreads();
+  const bool more = n1 < n && T.woff[n1 - 1] <= last;   // every loaded node starts in the tile
+  if (more) {
+    for (int k = n1 + threadIdx.x; k < n; k += blockDim.x) T.woff[k] = it->nz_woff[k0 + k];
+    n1 = n;
+    __syncthreads();
+  }
+  // last node of the tile: the last offset <= b - 1 (offsets ascend)
+  for (int k = threadIdx.x; k < n1; k += blockDim.x)
+    if (T.woff[k] <= last && (k + 1 == n1 || T.woff[k + 1] > last)) T.count = k + 1;
+  __syncthreads();
+  const int cnt = T.count;
+  if (threadIdx.x == 0) C.k_last = k0 + cnt - 1;
   constexpr int per = kTileWork / kBlock;
+  if (cnt == 1) {   // one node covers the whole tile: no item map needed
+    if (threadIdx.x == 0) { T.lo[0] = it->nz_lo[k0]; T.node[0] = it->nz_node[k0]; }
+    for (int i = 0; i < per; ++i) T.kmap[threadIdx.x * per + i] = 0;
+    __syncthreads();
+    return;
+  }
   for (int i = 0; i < per; ++i) T.kmap[threadIdx.x * per + i] = 0;
   __syncthreads();
-  for (int k = threadIdx.x; k < T.count; k += blockDim.x) {
-    const int64_t wo = it->nz_woff[k0 + k];
-    T.woff[k] = wo;
+  for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
     T.lo[k] = it->nz_lo[k0 + k];
     T.node[k] = it->nz_node[k0 + k];
-    if (k > 0) T.kmap[wo - T.a] = (uint16_t)k;   // node k starts inside the tile (node 0 may start before it)
+    if (k > 0) T.kmap[T.woff[k] - T.a] = (uint16_t)k;   // node k starts inside the tile (node 0 may start before it)
   }
   __syncthreads();
   // forward fill: each item takes the last node start at or before it (a max-scan, node starts ascend)
@@ -578,6 +630,7 @@ __global__ __launch_bounds__(kBlock) void k_expand_count(const IterArgs A) {
   int64_t tb, te;
   block_share(it->work_tiles, tb, te);
   int64_t bsum = 0, b_pr = 0, b_ft = 0, b_ct = 0;
+  TileCursor cur;
   EntryAcc acc, qacc;                    // valid counts per entry, probes per query
   int64_t *p_cnt = &es[0].cnt, *p_probe = A.qstats + QS_PROBE;
   for (int64_t t = tb; t < te; ++t) {
@@ -596,7 +649,7 @@ __global__ __launch_bounds__(kBlock) void k_expand_count(const IterArgs A) {
         continue;
       }
     }
-    load_tile(A, t, T);
+    load_tile(A, t, T, cur);
     const int e = T.e;
     const EState E = es[e];
     const DEntry d = A.ent[e];
@@ -703,8 +756,9 @@ __global__ __launch_bounds__(kBlock) void k_expand_write(const IterArgs A) {
   int64_t tb, te;
   block_share(it->work_tiles, tb, te);
   int64_t run = A.blk_off_a[blockIdx.x];
+  TileCursor cur;
   for (int64_t t = tb; t < te; ++t) {
-    load_tile(A, t, T);
+    load_tile(A, t, T, cur);
     const int e = T.e;
     const EState E = es[e];
     const DStep S = A.steps[A.ent[e].step];
@@ -819,6 +873,72 @@ hipError_t launch_domain_only(const IterArgs &A, hipStream_t s) {
   const dim3 G(A.grid), B(kBlock);
   hipLaunchKernelGGL(k_dom_push, G, B, 0, s, A);
   hipLaunchKernelGGL(k_dom_pull, G, B, 0, s, A);
+  return hipGetLastError();
+}
+
+}  // namespace gs
+
+// ---------------------------------------------------------------- pruning
+// Explicit tree pruning (Section 7.2.2 / 8.1): a node is kept when a leaf
+// survives below it. Marking runs from the leaves up, compaction from the root
+// down, remapping each child's parent index to its parent's new position.
+namespace gs {
+
+__global__ __launch_bounds__(kBlock) void k_prune_mark(const int32_t *par, int64_t n, const uint8_t *alive,
+                                                       uint8_t *alive_parent) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    if (!alive || alive[i]) alive_parent[par[i]] = 1;
+}
+
+__global__ __launch_bounds__(kBlock) void k_prune_count(const uint8_t *alive, int64_t n, int64_t *blk) {
+  __shared__ int64_t lds[kWaves];
+  int64_t b, e;
+  block_share(n, b, e);
+  int64_t c = 0;
+  for (int64_t i = b + threadIdx.x; i < e; i += kBlock) c += alive[i];
+  c = block_sum_i64(c, lds);
+  if (threadIdx.x == 0) blk[blockIdx.x] = c;
+}
+
+__global__ __launch_bounds__(kBlock) void k_prune_write(const int32_t *L, int64_t n, int ncols, const uint8_t *alive,
+                                                        const int64_t *blkoff, const int32_t *parent_newidx,
+                                                        int32_t *newidx, int32_t *out, int64_t n_out) {
+  __shared__ int lds[kWaves];
+  int64_t b, e;
+  block_share(n, b, e);
+  int64_t run = blkoff[blockIdx.x];
+  for (int64_t r = b; r < e; r += kBlock) {
+    const int64_t i = r + threadIdx.x;
+    const bool f = i < e && alive[i];
+    int tot;
+    const int pos = block_excl_flag(f, tot, lds);
+    if (f) {
+      const int64_t k = run + pos;
+      newidx[i] = (int32_t)k;
+      out[k] = parent_newidx ? parent_newidx[L[i]] : L[i];
+      for (int c = 1; c < ncols; ++c) out[(int64_t)c * n_out + k] = L[(int64_t)c * n + i];
+    }
+    run += tot;
+  }
+}
+
+hipError_t launch_prune_mark(const int32_t *par, int64_t n, const uint8_t *alive, uint8_t *alive_parent, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t g = std::min<int64_t>((n + kBlock - 1) / kBlock, 8192);
+  hipLaunchKernelGGL(k_prune_mark, dim3((unsigned)g), dim3(kBlock), 0, s, par, n, alive, alive_parent);
+  return hipGetLastError();
+}
+
+hipError_t launch_prune_count(const uint8_t *alive, int64_t n, int64_t *blk, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_prune_count, dim3(grid), dim3(kBlock), 0, s, alive, n, blk);
+  return hipGetLastError();
+}
+
+hipError_t launch_prune_write(const int32_t *L, int64_t n, int ncols, const uint8_t *alive, const int64_t *blkoff,
+                              const int32_t *parent_newidx, int32_t *newidx, int32_t *out, int64_t n_out, int grid,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_prune_write, dim3(grid), dim3(kBlock), 0, s, L, n, ncols, alive, blkoff, parent_newidx, newidx,
+                     out, n_out);
   return hipGetLastError();
 }
 

@@ -41,6 +41,11 @@ struct IterArgs {
 hipError_t launch_iteration(const IterArgs &A, hipStream_t s, hipEvent_t *ev = nullptr);
 hipError_t launch_list_only(const IterArgs &A, hipStream_t s);
 hipError_t launch_domain_only(const IterArgs &A, hipStream_t s);
+hipError_t launch_prune_mark(const int32_t *par, int64_t n, const uint8_t *alive, uint8_t *alive_parent, hipStream_t s);
+hipError_t launch_prune_count(const uint8_t *alive, int64_t n, int64_t *blk, int grid, hipStream_t s);
+hipError_t launch_prune_write(const int32_t *L, int64_t n, int ncols, const uint8_t *alive, const int64_t *blkoff,
+                              const int32_t *parent_newidx, int32_t *newidx, int32_t *out, int64_t n_out, int grid,
+                              hipStream_t s);
 hipError_t launch_enumerate(int32_t *const *lvl_ptr, const int64_t *lvl_n, int k, const int32_t *var_rank,
                             int64_t first, int64_t n, int32_t *rows, hipStream_t s);
 

@@ -248,3 +248,34 @@ def test_query_errors():
             assert err.value.status == st
     finally:
         gs.gs_engine_destroy(e)
+
+
+def test_prune_keeps_rows_and_removes_dead_nodes(c0):
+    trip, n, P, G = c0
+    qs = workload.walk_queries(trip, n, 5, "snowflake8", 4) + workload.walk_queries(trip, n, 5, "triangle", 4)
+    e = make_engine(trip, n, P)
+    try:
+        for q in qs:
+            r0 = gs.gs_query_run(e, q)
+            r1 = gs.gs_query_run(e, q, gs.GS_PRUNE)
+            try:
+                k = gs.gs_result_width(r0)
+                assert gs.gs_result_count(r0) == gs.gs_result_count(r1)
+                assert np.array_equal(sort_rows(gs.gs_result_rows(r0)), sort_rows(gs.gs_result_rows(r1)))
+                st = gs.gs_result_stats(r0)
+                lv = [gs.gs_result_level(r1, j) for j in range(k)]
+                for j in range(k):
+                    assert len(lv[j][0]) <= st.level_nodes[j]
+                for j in range(k - 1):
+                    par_next = lv[j + 1][0]
+                    # every kept node has a child, children stay grouped in parent order
+                    assert np.array_equal(np.unique(par_next), np.arange(len(lv[j][0])))
+                    assert np.all(np.diff(par_next) >= 0)
+            finally:
+                gs.gs_result_free(r0)
+                gs.gs_result_free(r1)
+        with pytest.raises(gs.GsError) as err:
+            gs.gs_query_run(e, qs[0], gs.GS_PRUNE | gs.GS_COUNT_ONLY)
+        assert err.value.status == gs.GS_EINVAL
+    finally:
+        gs.gs_engine_destroy(e)

@@ -6,9 +6,13 @@ work cap for cyclic ones). Queries whose count exceeds the cap, or that the
 oracle cannot count within its work cap, are skipped; the next candidate of the
 same stream is tried. Run from the repository root:
 
-    python -m workload.make_querysets [--scale 1.0] [--per-shape 25]
+    python -m workload.make_querysets [--set c1|c2|c3] [--scale 1.0] [--per-shape 25] [--total 1024]
 
-Output: workload/data/c1_queries.json (scale 1) or c1s<scale>_queries.json.
+c1: 25 queries per shape (chain-4, star-5, snowflake-8, triangle), counts in
+[1, 1e9]; c2: the batched set, the four shapes with random constants spread
+over count decades up to 1e7; c3: the served set, mixed walk shapes with 1-12
+edges and 0-2 constants, counts up to 1e7. Output:
+workload/data/<set>[s<scale>]_queries.json.
 """
 from __future__ import annotations
 
@@ -60,11 +64,60 @@ def _count(q, work_cap):
         return -1
 
 
+def _count_bt(q, work_cap):
+    """Backtracking count with a work cap (-1 when the cap is reached)."""
+    try:
+        return _G.eval(q, rows=False, work_cap=work_cap)[0]
+    except oracle.OracleError:
+        return -1
+
+
+def batched_set(trip, n, pool, args, t0):
+    """Queries of the four shapes with random constants, spread over count decades [1,10) .. [1e6,1e7]."""
+    cells = {(sh, d): [] for sh in SHAPES for d in range(7)}
+    per = -(-args.total // len(cells))
+    for si, shape in enumerate(SHAPES):
+        first = 0
+        while first < args.max_candidates and any(len(cells[(shape, d)]) < per for d in range(7)):
+            batch = workload.walk_queries(trip, n, 100 + si, shape, 64, const_prob=args.const_prob, first=first)
+            counts = pool.starmap(_count_bt, [(q, args.work_cap) for q in batch])
+            for i, (q, c) in enumerate(zip(batch, counts)):
+                if 1 <= c <= 10_000_000:
+                    d = min(6, len(str(c)) - 1)
+                    if len(cells[(shape, d)]) < per:
+                        cells[(shape, d)].append({"shape": shape, "candidate": first + i, "count": int(c), "query": q})
+            first += 64
+        print(shape, {d: len(cells[(shape, d)]) for d in range(7)}, f"({time.time() - t0:.0f}s)", flush=True)
+    out = []
+    for d in range(7):   # interleave so that a prefix covers every cell
+        for sh in SHAPES:
+            out += cells[(sh, d)]
+    return out[:args.total]
+
+
+def served_set(trip, n, pool, args, t0):
+    """Mixed walk shapes, 1-12 edges, 0-2 constants, counts in [1, 1e7]."""
+    got, first = [], 0
+    while len(got) < args.total and first < args.max_candidates * 4:
+        batch = workload.walk_queries(trip, n, 200, "mixed", 64, first=first, max_consts=2)
+        counts = pool.starmap(_count_bt, [(q, args.work_cap) for q in batch])
+        for i, (q, c) in enumerate(zip(batch, counts)):
+            if 1 <= c <= 10_000_000 and len(got) < args.total:
+                got.append({"shape": "mixed", "candidate": first + i, "count": int(c), "query": q})
+        first += 64
+    print(f"served: {len(got)} from {first} candidates ({time.time() - t0:.0f}s)", flush=True)
+    return got
+
+
 def main():
     global _G
     ap = argparse.ArgumentParser()
+    ap.add_argument("--set", default="c1", choices=["c1", "c2", "c3"])
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--per-shape", type=int, default=25)
+    ap.add_argument("--total", type=int, default=1024)
+    ap.add_argument("--const-prob", type=float, default=0.5)
+    ap.add_argument("--max-candidates", type=int, default=20000)
     ap.add_argument("--cap", type=int, default=1_000_000_000)
     ap.add_argument("--work-cap", type=int, default=300_000_000)
     ap.add_argument("--procs", type=int, default=min(8, os.cpu_count() or 1))
@@ -79,6 +132,19 @@ def main():
            "seed": workload.C1["seed"], "count_cap": args.cap,
            "note": "counts written by the oracle (workload/make_querysets.py)", "queries": []}
     ctx = mp.get_context("fork")
+    if args.set != "c1":
+        with ctx.Pool(args.procs) as pool:
+            qs = batched_set(trip, n, pool, args, t0) if args.set == "c2" else served_set(trip, n, pool, args, t0)
+        out["workload"] = args.set
+        out["count_cap"] = 10_000_000
+        out["queries"] = qs
+        sc = "" if args.scale == 1.0 else f"s{args.scale:g}"
+        path = os.path.join(ROOT, "workload", "data", f"{args.set}{sc}_queries.json")
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        with open(path, "w") as f:
+            json.dump(out, f)
+        print("wrote", path)
+        return
     with ctx.Pool(args.procs) as pool:
         for shape in SHAPES:
             got, first = [], 0
