@@ -47,6 +47,10 @@ __device__ __forceinline__ int last_le(int E, int64_t t, Key key) {
 
 __device__ __forceinline__ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// An index read from LDS is the same in every lane; saying so lets the compiler
+// load the structs it selects through the scalar unit.
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 // Per-workgroup accumulation of per-entry counters: a workgroup walks a
 // contiguous range of tiles, so it meets few entries; adding to the entry's
 // counter only when the entry changes keeps global atomics off the per-tile
@@ -167,7 +171,7 @@ __global__ __launch_bounds__(kBlock) void k_list_count(const IterArgs A) {
   for (int64_t t = tb; t < te; ++t) {
     if (threadIdx.x == 0) sh_e = last_le(A.E, t, [&](int i) { return es[i].list_tile0; });
     __syncthreads();
-    const int e = sh_e;
+    const int e = uniform(sh_e);
     const DStep S = A.steps[A.ent[e].step];
     const int64_t w = (t - es[e].list_tile0) * kTileWords + threadIdx.x;
     int64_t c = 0;
@@ -210,7 +214,7 @@ __global__ __launch_bounds__(kBlock) void k_list_write(const IterArgs A) {
   for (int64_t t = tb; t < te; ++t) {
     if (threadIdx.x == 0) sh_e = last_le(A.E, t, [&](int i) { return es[i].list_tile0; });
     __syncthreads();
-    const int e = sh_e;
+    const int e = uniform(sh_e);
     const DStep S = A.steps[A.ent[e].step];
     const int64_t w = (t - es[e].list_tile0) * kTileWords + threadIdx.x;
     uint64_t x = 0;
@@ -232,6 +236,19 @@ __device__ __forceinline__ int node_entry(const IterArgs &A, int64_t t) {
   return last_le(A.E, t, [&](int i) { return A.es[i].node_tile0; });
 }
 
+// Entry of node tile t for a workgroup walking its tiles in increasing order.
+struct NodeCursor {
+  int e = -1;
+  int64_t end = 0;
+  __device__ int at(const IterArgs &A, int64_t t) {
+    if (e < 0 || t >= end) {
+      e = node_entry(A, t);
+      end = A.es[e].node_tile0 + ceil_div(A.es[e].prev_n, kTileNodes);
+    }
+    return e;
+  }
+};
+
 // F = distinct bindings of the bound end of each cycle-closing edge.
 __global__ __launch_bounds__(kBlock) void k_dom_frontier(const IterArgs A) {
   __shared__ int64_t lds[kWaves];
@@ -241,10 +258,11 @@ __global__ __launch_bounds__(kBlock) void k_dom_frontier(const IterArgs A) {
   EState *es = A.es;
   int64_t tb, te;
   block_share(it->node_tiles, tb, te);
+  NodeCursor ncur;
   for (int64_t t = tb; t < te; ++t) {
-    if (threadIdx.x == 0) sh_e = node_entry(A, t);
+    if (threadIdx.x == 0) sh_e = ncur.at(A, t);
     __syncthreads();
-    const int e = sh_e;
+    const int e = uniform(sh_e);
     __syncthreads();
     const DEntry d = A.ent[e];
     if (d.ndom == 0) continue;   // uniform across the block
@@ -370,13 +388,14 @@ __global__ __launch_bounds__(kBlock) void k_lookup(const IterArgs A) {
   EState *es = A.es;
   int64_t tb, te;
   block_share(it->node_tiles, tb, te);
+  NodeCursor ncur;
   int64_t bnz = 0, bw = 0;
   EntryAcc acc;
   int64_t *p_nz = &es[0].nz, *p_w = &es[0].w;
   for (int64_t t = tb; t < te; ++t) {
-    if (threadIdx.x == 0) sh_e = node_entry(A, t);
+    if (threadIdx.x == 0) sh_e = ncur.at(A, t);
     __syncthreads();
-    const int e = sh_e;
+    const int e = uniform(sh_e);
     const DEntry d = A.ent[e];
     const DStep S = A.steps[d.step];
     if (threadIdx.x == 0) sh_ok = (d.level == 0 && S.ncc > 0) ? const_checks_hold(A, S) : 1;
@@ -425,8 +444,13 @@ __global__ __launch_bounds__(1024) void k_scan_nodes(const IterArgs A) {
   __shared__ int64_t wtest;
   if (threadIdx.x == 0) wtest = 0;
   __syncthreads();
-  for (int e = threadIdx.x; e < A.E; e += blockDim.x)
-    if (!test_free(A.steps[A.ent[e].step]) && es[e].w) atomicAdd((unsigned long long *)&wtest, (unsigned long long)es[e].w);
+  for (int e = threadIdx.x; e < A.E; e += blockDim.x) {
+    if (!test_free(A.steps[A.ent[e].step])) {
+      if (es[e].w) atomicAdd((unsigned long long *)&wtest, (unsigned long long)es[e].w);
+    } else {
+      es[e].cnt = es[e].w;   // no test: every candidate entry becomes a child
+    }
+  }
   __syncthreads();
   if (threadIdx.x == 0) it->w_tested = wtest;
   if (threadIdx.x == 0) {
@@ -455,11 +479,12 @@ __global__ __launch_bounds__(kBlock) void k_nz_write(const IterArgs A) {
   EState *es = A.es;
   int64_t tb, te;
   block_share(it->node_tiles, tb, te);
+  NodeCursor ncur;
   int64_t run_nz = A.blk_off_a[blockIdx.x], run_w = A.blk_off_b[blockIdx.x];
   for (int64_t t = tb; t < te; ++t) {
-    if (threadIdx.x == 0) sh_e = node_entry(A, t);
+    if (threadIdx.x == 0) sh_e = ncur.at(A, t);
     __syncthreads();
-    const int e = sh_e;
+    const int e = uniform(sh_e);
     const int64_t i0 = (t - es[e].node_tile0) * kTileNodes, pn = es[e].prev_n;
     for (int r = 0; r < kTileNodes / kBlock; ++r) {
       const int64_t i = i0 + r * kBlock + threadIdx.x;
@@ -483,9 +508,9 @@ __global__ __launch_bounds__(kBlock) void k_nz_write(const IterArgs A) {
 
 // ------------------------------------------------------------------ expansion
 struct TileNz {
-  int64_t woff[kTileWork + 1];
-  int64_t lo[kTileWork + 1];
-  int32_t node[kTileWork + 1];
+  int64_t woff[kTileWork + 2];
+  int64_t lo[kTileWork + 2];
+  int32_t node[kTileWork + 2];
   uint16_t kmap[kTileWork];   // item of the tile -> index of its node in the arrays above
   int32_t wmax[kWaves];
   int count;
@@ -508,79 +533,93 @@ __device__ __forceinline__ int64_t last_le_global(const int64_t *v, int64_t lo, 
 // consecutive tiles, so the entry and the first node carry over from the
 // previous tile (cursor): only a workgroup's first tile of an entry searches.
 // The tile's last node comes from a coalesced window of node offsets.
-struct TileCursor { int e = -1; int64_t k_last = -1; int64_t next_tile0 = 0; };
+struct TileCursor {
+  int e = -1;
+  int64_t k_last = -1, next_tile0 = 0;
+  int64_t tile0 = 0, w = 0, nb = 0, ne = 0;   // the entry's first tile, work, non-empty node range
+};
 
 __device__ __forceinline__ void load_tile(const IterArgs &A, int64_t t, TileNz &T, TileCursor &C) {
   IterScalars *it = A.it;
   EState *es = A.es;
-  __shared__ int64_t k0s, nwin;
+  __shared__ int64_t base_s, nwin, kfirst;
   if (threadIdx.x == 0) {
     int e = C.e;
-    if (e < 0 || t >= C.next_tile0 || t < es[e].w_tile0) {
+    if (e < 0 || t >= C.next_tile0 || t < C.tile0) {
       e = last_le(A.E, t, [&](int i) { return es[i].w_tile0; });
       C.k_last = -1;
     }
     if (e != C.e) {
       C.e = e;
       C.k_last = -1;
-      C.next_tile0 = es[e].w_tile0 + (es[e].w + kTileWork - 1) / kTileWork;
+      C.tile0 = es[e].w_tile0;
+      C.w = es[e].w;
+      C.nb = es[e].nz_base;
+      C.ne = C.nb + es[e].nz;
+      C.next_tile0 = C.tile0 + (C.w + kTileWork - 1) / kTileWork;
     }
     T.e = e;
-    T.a = (t - es[e].w_tile0) * kTileWork;
-    T.b = min(T.a + kTileWork, es[e].w);
-    const int64_t nb = es[e].nz_base, ne = nb + es[e].nz;
-    int64_t k0;
-    if (C.k_last >= 0) {   // the previous tile ended inside node k_last: this one starts there or just after
-      k0 = C.k_last;
-      while (k0 + 1 < ne && it->nz_woff[k0 + 1] <= T.a) ++k0;
-    } else {
-      k0 = last_le_global(it->nz_woff, nb, ne, T.a);
-    }
-    k0s = k0;
-    nwin = min((int64_t)kTileWork + 1, ne - k0);
+    T.a = (t - C.tile0) * kTileWork;
+    T.b = min(T.a + kTileWork, C.w);
+    // the window starts at the node the previous tile ended in (this tile starts there or at the next one)
+    const int64_t base = C.k_last >= 0 ? C.k_last : last_le_global(it->nz_woff, C.nb, C.ne, T.a);
+    base_s = base;
+    nwin = min((int64_t)kTileWork + 2, C.ne - base);
   }
   __syncthreads();
-  const int64_t k0 = k0s;
+  const int64_t base = base_s;
   const int n = (int)nwin;
-  // node offsets of the tile: a first window of one per thread, extended only when
-  // the tile holds more nodes than that (short segments)
   const int64_t last = T.b - 1;
+  // offsets, segment starts and nodes of the window, one per thread, extended only for short segments
   int n1 = min(n, (int)blockDim.x);
-  if (threadIdx.x < n1) T.woff[threadIdx.x] = it->nz_woff[k0 + threadIdx.x];
+  if (threadIdx.x < n1) {
+    T.woff[threadIdx.x] = it->nz_woff[base + threadIdx.x];
+    T.lo[threadIdx.x] = it->nz_lo[base + threadIdx.x];
+    T.node[threadIdx.x] = it->nz_node[base + threadIdx.x];
+  }
   __syncthreads();
-  const bool more = n1 < n && T.woff[n1 - 1] <= last;   // every loaded node starts in the tile
-  if (more) {
-    for (int k = n1 + threadIdx.x; k < n; k += blockDim.x) T.woff[k] = it->nz_woff[k0 + k];
+  if (n1 < n && T.woff[n1 - 1] <= last) {   // every loaded node starts in the tile: load the rest
+    for (int k = n1 + threadIdx.x; k < n; k += blockDim.x) {
+      T.woff[k] = it->nz_woff[base + k];
+      T.lo[k] = it->nz_lo[base + k];
+      T.node[k] = it->nz_node[base + k];
+    }
     n1 = n;
     __syncthreads();
   }
-  // last node of the tile: the last offset <= b - 1 (offsets ascend)
-  for (int k = threadIdx.x; k < n1; k += blockDim.x)
-    if (T.woff[k] <= last && (k + 1 == n1 || T.woff[k + 1] > last)) T.count = k + 1;
+  // first node: the last offset <= a; last node: the last offset <= b - 1 (offsets ascend)
+  for (int k = threadIdx.x; k < n1; k += blockDim.x) {
+    const bool next_after = (k + 1 == n1);
+    if (T.woff[k] <= T.a && (next_after || T.woff[k + 1] > T.a)) kfirst = k;
+    if (T.woff[k] <= last && (next_after || T.woff[k + 1] > last)) T.count = k + 1;
+  }
   __syncthreads();
-  const int cnt = T.count;
-  if (threadIdx.x == 0) C.k_last = k0 + cnt - 1;
+  const int k0 = (int)kfirst;
+  const int cnt = T.count - k0;
+  if (threadIdx.x == 0) C.k_last = base + T.count - 1;
   constexpr int per = kTileWork / kBlock;
-  if (cnt == 1) {   // one node covers the whole tile: no item map needed
-    if (threadIdx.x == 0) { T.lo[0] = it->nz_lo[k0]; T.node[0] = it->nz_node[k0]; }
-    for (int i = 0; i < per; ++i) T.kmap[threadIdx.x * per + i] = 0;
+  // shift the window so that node 0 is the tile's first node
+  if (k0 > 0) {
+    int64_t wo[(kTileWork + 2 + kBlock - 1) / kBlock], lo[(kTileWork + 2 + kBlock - 1) / kBlock];
+    int32_t nd[(kTileWork + 2 + kBlock - 1) / kBlock];
+    int m = 0;
+    for (int k = threadIdx.x; k < cnt; k += blockDim.x, ++m) { wo[m] = T.woff[k + k0]; lo[m] = T.lo[k + k0]; nd[m] = T.node[k + k0]; }
     __syncthreads();
-    return;
+    m = 0;
+    for (int k = threadIdx.x; k < cnt; k += blockDim.x, ++m) { T.woff[k] = wo[m]; T.lo[k] = lo[m]; T.node[k] = nd[m]; }
   }
   for (int i = 0; i < per; ++i) T.kmap[threadIdx.x * per + i] = 0;
   __syncthreads();
-  for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
-    T.lo[k] = it->nz_lo[k0 + k];
-    T.node[k] = it->nz_node[k0 + k];
-    if (k > 0) T.kmap[T.woff[k] - T.a] = (uint16_t)k;   // node k starts inside the tile (node 0 may start before it)
-  }
+  if (cnt == 1) return;   // one node covers the whole tile: no item map needed
+  for (int k = 1 + threadIdx.x; k < cnt; k += blockDim.x)
+    T.kmap[T.woff[k] - T.a] = (uint16_t)k;   // node k starts inside the tile (node 0 may start before it)
   __syncthreads();
   // forward fill: each item takes the last node start at or before it (a max-scan, node starts ascend)
   int v[per];
-  int m = 0;
-  for (int i = 0; i < per; ++i) { m = max(m, (int)T.kmap[threadIdx.x * per + i]); v[i] = m; }
+  int mx = 0;
+  for (int i = 0; i < per; ++i) { mx = max(mx, (int)T.kmap[threadIdx.x * per + i]); v[i] = mx; }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  int incl = m;
+  int incl = mx;
   for (int off = 1; off < 64; off <<= 1) {
     const int u = __shfl_up(incl, off, 64);
     if (lane >= off) incl = max(incl, u);
@@ -633,24 +672,30 @@ __global__ __launch_bounds__(kBlock) void k_expand_count(const IterArgs A) {
   TileCursor cur;
   EntryAcc acc, qacc;                    // valid counts per entry, probes per query
   int64_t *p_cnt = &es[0].cnt, *p_probe = A.qstats + QS_PROBE;
-  for (int64_t t = tb; t < te; ++t) {
-    __shared__ int sh_e;
-    if (threadIdx.x == 0) sh_e = last_le(A.E, t, [&](int i) { return es[i].w_tile0; });
-    __syncthreads();
-    {
-      const int e = sh_e;
-      const DStep S0 = A.steps[A.ent[e].step];
-      __syncthreads();
-      if (test_free(S0)) {   // every candidate is a child: the tile count is its size
-        const int64_t a = (t - es[e].w_tile0) * kTileWork;
-        const int64_t c = min(a + kTileWork, es[e].w) - a;
-        if (threadIdx.x == 0) acc.add(e, c, 0, p_cnt, nullptr, kEsStride);
-        bsum += c;
-        continue;
-      }
+  for (int64_t t = tb; t < te;) {
+    __shared__ int sh_e, sh_free;
+    __shared__ int64_t sh_end;
+    if (threadIdx.x == 0) {
+      const int e = last_le(A.E, t, [&](int i) { return es[i].w_tile0; });
+      sh_e = e;
+      sh_free = test_free(A.steps[A.ent[e].step]);
+      sh_end = es[e].w_tile0 + ceil_div(es[e].w, kTileWork);
     }
-    load_tile(A, t, T, cur);
-    const int e = T.e;
+    __syncthreads();
+    const int e0 = uniform(sh_e);
+    const bool free_e = sh_free;
+    const int64_t t_end = min(te, sh_end);
+    __syncthreads();
+    if (free_e) {   // every candidate is a child: the entry's count was set by the node scan
+      const int64_t a = (t - es[e0].w_tile0) * kTileWork;
+      const int64_t b = min((t_end - es[e0].w_tile0) * kTileWork, es[e0].w);
+      bsum += b - a;
+      t = t_end;
+      continue;
+    }
+    const int64_t t_cur = t++;
+    load_tile(A, t_cur, T, cur);
+    const int e = uniform(T.e);
     const EState E = es[e];
     const DEntry d = A.ent[e];
     const DStep S = A.steps[d.step];
@@ -666,7 +711,7 @@ __global__ __launch_bounds__(kBlock) void k_expand_count(const IterArgs A) {
       }
       const uint64_t bal = __ballot(ok);
       if (lane == 0) {
-        uint32_t *vw = it->valid + t * (kTileWork / 32) + (r * kBlock + wv * 64) / 32;
+        uint32_t *vw = it->valid + t_cur * (kTileWork / 32) + (r * kBlock + wv * 64) / 32;
         vw[0] = (uint32_t)bal;
         vw[1] = (uint32_t)(bal >> 32);
       }
@@ -759,7 +804,7 @@ __global__ __launch_bounds__(kBlock) void k_expand_write(const IterArgs A) {
   TileCursor cur;
   for (int64_t t = tb; t < te; ++t) {
     load_tile(A, t, T, cur);
-    const int e = T.e;
+    const int e = uniform(T.e);
     const EState E = es[e];
     const DStep S = A.steps[A.ent[e].step];
     if (test_free(S)) {   // every candidate is a child: its position is its offset in the tile
