@@ -44,6 +44,15 @@ def load_queryset(name):
     return qs
 
 
+def batched_step_on(gs, eng, queries):
+    rs = gs.gs_batch_run(eng, queries)
+    counts = [gs.gs_result_count(r) for r in rs]
+    st = [gs.gs_result_stats(r) for r in rs]
+    for r in rs:
+        gs.gs_result_free(r)
+    return counts, st
+
+
 def graph_for(qs):
     import workload
     scale = qs["scale"]
@@ -77,6 +86,58 @@ def cpu_baseline(trip, qs, per_query_T, budget_s):
             "queries_per_s": done / secs if secs > 0 else None}
 
 
+def serve_leg(gs, eng, qset, rates, seconds, seed=7):
+    """Open-loop Poisson arrivals at each rate, served with continuous batching; the same
+    trace served one query at a time (FIFO) by the plain engine as the baseline."""
+    import workload
+    queries = [q["query"] for q in qset["queries"]]
+    out = {}
+    for rate in rates:
+        arr = workload.poisson_arrivals(seed, rate, seconds)
+        srv = gs.gs_server_start(eng, gs.gs_server_options(max_active=1024, tree_budget_bytes=0,
+                                                           flags=gs.GS_COUNT_ONLY))
+        t0 = time.perf_counter()
+        tickets = []
+        pending = {}
+        lat = []
+        i = 0
+        while i < len(arr) or pending:
+            now = time.perf_counter() - t0
+            while i < len(arr) and arr[i] <= now:
+                tk = gs.gs_submit(srv, queries[i % len(queries)], gs.GS_COUNT_ONLY)
+                pending[tk] = i
+                i += 1
+            for tk, status, r in gs.gs_poll_ready(srv):
+                if r is not None:
+                    lat.append(gs.gs_result_stats(r).latency_ms)
+                    gs.gs_result_free(r)
+                pending.pop(tk, None)
+            if i >= len(arr) and time.perf_counter() - t0 > seconds + 60:
+                break
+        span = time.perf_counter() - t0
+        st = gs.gs_server_stop(srv)
+        lat = np.array(lat)
+        # FIFO baseline: the plain engine takes requests in arrival order
+        t_free, plat = 0.0, []
+        for k, ta in enumerate(arr[:min(len(arr), 2000)]):
+            t_start = max(ta, t_free)
+            t1 = time.perf_counter()
+            r = gs.gs_query_run(eng, queries[k % len(queries)], gs.GS_COUNT_ONLY)
+            gs.gs_result_free(r)
+            t_free = t_start + (time.perf_counter() - t1)
+            plat.append((t_free - ta) * 1e3)
+        plat = np.array(plat)
+        out[str(int(rate))] = {
+            "requests": int(len(arr)), "completed": int(st.completed), "queries_per_s": len(lat) / span,
+            "p50_ms": float(np.percentile(lat, 50)) if len(lat) else None,
+            "p99_ms": float(np.percentile(lat, 99)) if len(lat) else None,
+            "max_active": int(st.max_active_seen), "iterations": int(st.iterations),
+            "plain_fifo_p50_ms": float(np.percentile(plat, 50)), "plain_fifo_p99_ms": float(np.percentile(plat, 99)),
+            "plain_fifo_queries_per_s": len(plat) / max(t_free - arr[0], 1e-9) if len(plat) else None}
+        log(f"served {rate}/s: {out[str(int(rate))]}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +147,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=2.0)
+    ap.add_argument("--no-graphs", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for {args.gpus})",
@@ -115,12 +179,7 @@ def main():
     log(f"load {load_ms:.1f} ms")
 
     def batched_step():
-        rs = gs.gs_batch_run(eng, queries)
-        counts = [gs.gs_result_count(r) for r in rs]
-        st = [gs.gs_result_stats(r) for r in rs]
-        for r in rs:
-            gs.gs_result_free(r)
-        return counts, st
+        return batched_step_on(gs, eng, queries)
 
     for _ in range(args.warmup):
         counts, st = batched_step()
@@ -167,6 +226,31 @@ def main():
         plain = {"queries_per_s": len(queries) / pe, "triples_per_s": T / pe, "ms_per_pass": pe * 1e3}
         log(f"plain: {pe * 1e3:.1f} ms per pass")
 
+    graphs = None
+    if not args.no_graphs:   # the same step with the launch sequence replayed from a captured hipGraph
+        geng = gs.gs_engine_create(gs.options(device=0, use_graphs=1,
+                                              hip_stream=torch.cuda.current_stream().cuda_stream))
+        gt = torch.from_numpy(trip).cuda()
+        gs.gs_load_triples(geng, qs["n"], qs["n_labels"], gt)
+        del gt
+        for _ in range(max(args.warmup, 1)):
+            gcounts, _ = batched_step_on(gs, geng, queries)
+        assert gcounts == counts
+        torch.cuda.synchronize()
+        tg = time.perf_counter()
+        for _ in range(args.steps):
+            batched_step_on(gs, geng, queries)
+        torch.cuda.synchronize()
+        gms = (time.perf_counter() - tg) * 1e3 / args.steps
+        graphs = {"ms_per_step": gms, "queries_per_s": len(queries) / (gms / 1e3), "triples_per_s": T / (gms / 1e3)}
+        log(f"batched with graphs: {gms:.2f} ms/step")
+        gs.gs_engine_destroy(geng)
+
+    served = None
+    c3 = os.path.join(ROOT, "workload", "data", "c3_queries.json")
+    if not args.no_serve and os.path.exists(c3) and args.workload == "c1":
+        served = serve_leg(gs, eng, load_queryset("c3"), [1000.0, 5000.0, 20000.0], args.serve_seconds)
+
     gs.gs_engine_destroy(eng)
     cpu = None
     if not args.no_cpu_baseline:
@@ -183,6 +267,8 @@ def main():
                    "queries": len(queries), "total_rows": int(sum(counts)), "parallelism": "single GPU"},
         "batched": {"queries_per_s": len(queries) / (ms_step / 1e3), "triples_per_s": value},
         "plain": plain,
+        "batched_graphs": graphs,
+        "served": served,
         "load_ms": load_ms,
         "roofline": roofline,
         "kernels": kernels,

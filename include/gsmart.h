@@ -296,6 +296,12 @@ gs_status gs_submit(gs_server *server, const gs_query *query, uint32_t flags, ui
  * done, or the request's own error status. Each ticket is returned once. */
 gs_status gs_poll(gs_server *server, uint64_t ticket, gs_result **out);
 
+/* Drain finished requests: up to cap of them, in no particular order, each
+ * returned once. tickets[i], statuses[i] and results[i] (NULL on error) describe
+ * request i; *n = number returned (0 when none is ready). */
+gs_status gs_poll_ready(gs_server *server, uint64_t *tickets, int32_t *statuses, gs_result **results, int32_t cap,
+                        int32_t *n);
+
 /* Wait until every submitted request is done, then stop the loop. Results not
  * polled yet are freed. */
 gs_status gs_server_stop(gs_server *server, gs_server_stats *stats);

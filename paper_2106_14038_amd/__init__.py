@@ -117,6 +117,7 @@ SIGNATURES = {
     "gs_submit": ([_vp, _P(gs_query), _u32, _P(_u64)], ctypes.c_int),
     "gs_poll": ([_vp, _u64, _P(_vp)], ctypes.c_int),
     "gs_server_stop": ([_vp, _P(gs_server_stats)], ctypes.c_int),
+    "gs_poll_ready": ([_vp, _vp, _vp, _vp, _i32, _P(_i32)], ctypes.c_int),
     "gs_kernel_stats": ([_vp, _P(gs_kernel_stat), _i32, _P(_i32), ctypes.c_int], ctypes.c_int),
     "gs_autotune": ([_vp, _P(gs_query), _i32, _P(gs_tune_result)], ctypes.c_int),
     "gs_last_error": ([], ctypes.c_char_p),
@@ -341,6 +342,16 @@ def gs_poll(server, ticket: int):
         return None
     _check(st)
     return r
+
+
+def gs_poll_ready(server, cap: int = 4096):
+    """Finished requests: list of (ticket, status, result handle or None)."""
+    t = (ctypes.c_uint64 * cap)()
+    st = (ctypes.c_int32 * cap)()
+    rs = (ctypes.c_void_p * cap)()
+    n = ctypes.c_int32()
+    _check(lib().gs_poll_ready(server, t, st, rs, cap, ctypes.byref(n)))
+    return [(t[i], st[i], ctypes.c_void_p(rs[i]) if rs[i] else None) for i in range(n.value)]
 
 
 def gs_server_stop(server) -> gs_server_stats:

@@ -14,6 +14,7 @@ int server_start(Engine *E, const gs_server_options *o, gs_server **out);
 int server_submit(gs_server *S, const gs_query *q, uint32_t flags, uint64_t *ticket);
 int server_poll(gs_server *S, uint64_t ticket, gs_result **out);
 int server_stop(gs_server *S, gs_server_stats *st);
+int server_poll_ready(gs_server *S, uint64_t *tickets, int32_t *statuses, gs_result **results, int32_t cap, int32_t *n);
 }  // namespace gs
 
 using namespace gs;
@@ -456,6 +457,12 @@ gs_status gs_submit(gs_server *server, const gs_query *query, uint32_t flags, ui
 gs_status gs_poll(gs_server *server, uint64_t ticket, gs_result **out) {
   if (!server || !out) { set_error("null argument"); return GS_EINVAL; }
   return (gs_status)server_poll(server, ticket, out);
+}
+
+gs_status gs_poll_ready(gs_server *server, uint64_t *tickets, int32_t *statuses, gs_result **results, int32_t cap,
+                        int32_t *n) {
+  if (!server || !n || cap < 0 || (cap > 0 && (!tickets || !statuses || !results))) { set_error("bad argument"); return GS_EINVAL; }
+  return (gs_status)server_poll_ready(server, tickets, statuses, results, cap, n);
 }
 
 gs_status gs_server_stop(gs_server *server, gs_server_stats *stats) {

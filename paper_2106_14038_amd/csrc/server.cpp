@@ -534,6 +534,22 @@ int server_poll(gs_server *srv, uint64_t ticket, gs_result **out) {
   return st;
 }
 
+int server_poll_ready(gs_server *srv, uint64_t *tickets, int32_t *statuses, gs_result **results, int32_t cap,
+                      int32_t *n) {
+  ServerImpl &S = srv->s;
+  *n = 0;
+  std::lock_guard<std::mutex> lk(S.mu);
+  auto it = S.done.begin();
+  while (it != S.done.end() && *n < cap) {
+    tickets[*n] = it->first;
+    statuses[*n] = it->second.first;
+    results[*n] = reinterpret_cast<gs_result *>(it->second.second);
+    ++*n;
+    it = S.done.erase(it);
+  }
+  return GS_OK;
+}
+
 int server_stop(gs_server *srv, gs_server_stats *st) {
   ServerImpl &S = srv->s;
   {

@@ -138,3 +138,26 @@ def test_served_errors_and_constant_queries(c0_mix):
             gs.gs_result_free(r)
     finally:
         gs.gs_engine_destroy(eng)
+
+
+def test_poll_ready_drains_every_request_once(c0_mix):
+    trip, n, P, G, qs = c0_mix
+    eng = gs.gs_engine_create(gs.options(tree_bytes=1 << 30, scratch_bytes=1 << 28))
+    try:
+        gs.gs_load_triples(eng, n, P, trip)
+        srv = gs.gs_server_start(eng, None)
+        tickets = {gs.gs_submit(srv, q, gs.GS_COUNT_ONLY): i for i, q in enumerate(qs[:60])}
+        seen = {}
+        deadline = time.time() + 60
+        while len(seen) < len(tickets) and time.time() < deadline:
+            for tk, status, r in gs.gs_poll_ready(srv, cap=7):
+                assert tk in tickets and tk not in seen and status == gs.GS_OK
+                seen[tk] = gs.gs_result_count(r)
+                gs.gs_result_free(r)
+            time.sleep(0.001)
+        gs.gs_server_stop(srv)
+        assert len(seen) == len(tickets)
+        for tk, i in tickets.items():
+            assert seen[tk] == ocount(G, qs[i], 0)
+    finally:
+        gs.gs_engine_destroy(eng)
