@@ -348,7 +348,8 @@ void account_iteration(Engine &E, const hipEvent_t *ev, const IterScalars &I, co
       }
       case KS_EXPAND_WRITE:   // valid bits, staged node records, candidate ids + copies read + columns written
         b = W / 8 + 20 * nz + write_bytes; break;
-      case KS_LOOKUP:         // parent binding, offset pair, segment written
+      case KS_LOOKUP:         // parent binding, offset pair, segment written (the lookups of cycle-closing
+                              // segments at cyclic levels are not counted)
         b = 36.0 * I.nodes_total; break;
       case KS_NZ_WRITE:
         b = 16.0 * I.nodes_total + 20 * nz; break;

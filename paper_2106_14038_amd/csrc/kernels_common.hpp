@@ -5,6 +5,27 @@
 
 namespace gs {
 
+// Workgroup barrier that orders LDS accesses only: outstanding global stores
+// are not waited for. For loops whose waves share nothing through global
+// memory within the kernel.
+__device__ __forceinline__ void lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Loads and stores through the global address space (the table pointers live
+// in device memory, where the compiler cannot see it and would emit flat
+// accesses, which also count against the LDS counter).
+template <class T>
+__device__ __forceinline__ T gld(const T *p) {
+  return *(const __attribute__((address_space(1))) T *)p;
+}
+template <class T>
+__device__ __forceinline__ void gst(T *p, T v) {
+  *(__attribute__((address_space(1))) T *)p = v;
+}
+
 __device__ __forceinline__ uint64_t lanemask_lt() {
   const int lane = threadIdx.x & 63;
   return (1ull << lane) - 1ull;
@@ -118,7 +139,7 @@ __device__ __forceinline__ int64_t lower_bound_u16(const uint16_t *a, int64_t lo
   while (lo < hi) {
     int64_t mid = (lo + hi) >> 1;
     ++probes;
-    if (a[mid] < key) lo = mid + 1; else hi = mid;
+    if (gld(a + mid) < key) lo = mid + 1; else hi = mid;
   }
   return lo;
 }
@@ -126,13 +147,13 @@ __device__ __forceinline__ int64_t lower_bound_u16(const uint16_t *a, int64_t lo
 // Entries of vertex b with label `label` in orientation dir: [lo, hi).
 __device__ __forceinline__ void seg_find(const DevGraph &g, int dir, int32_t b, int32_t label, int64_t &lo,
                                          int64_t &hi, int &probes) {
-  const int64_t a = g.ptr[dir][b], e = g.ptr[dir][b + 1];
+  const int64_t a = gld(g.ptr[dir] + b), e = gld(g.ptr[dir] + b + 1);
   const uint16_t *lab = g.lab[dir];
   if (e - a <= 8) {          // short rows: one linear pass
     int64_t x = a;
-    while (x < e && lab[x] < (uint32_t)label) ++x;
+    while (x < e && gld(lab + x) < (uint32_t)label) ++x;
     int64_t y = x;
-    while (y < e && lab[y] == (uint32_t)label) ++y;
+    while (y < e && gld(lab + y) == (uint32_t)label) ++y;
     probes += (int)(y - a + (y < e));
     lo = x; hi = y;
     return;
@@ -151,13 +172,13 @@ __device__ __forceinline__ bool seg_has(const DevGraph &g, int dir, int32_t b, i
   while (x < y) {
     int64_t mid = (x + y) >> 1;
     ++probes;
-    if (idx[mid] < c) x = mid + 1; else y = mid;
+    if (gld(idx + mid) < c) x = mid + 1; else y = mid;
   }
-  return x < hi && idx[x] == c;
+  return x < hi && gld(idx + x) == c;
 }
 
 __device__ __forceinline__ bool bit_test(const uint64_t *bm, int32_t c) {
-  return (bm[c >> 6] >> (c & 63)) & 1ull;
+  return (gld(bm + (c >> 6)) >> (c & 63)) & 1ull;
 }
 
 }  // namespace gs

@@ -75,6 +75,21 @@ __device__ __forceinline__ bool test_free(const DStep &S) {
   return S.nfilt == S.list_nfilt && S.nchk == 0 && S.nself == 0;
 }
 
+// Per-node segment reference: the start of the segment the node's candidates
+// are read from, the orientation of that segment, and which of the step's
+// bound segments it is (0: the parent edge's, k: exact check k - 1). A level
+// whose new variable is bound by several edges reads its candidates from the
+// shortest of their segments and tests the others; all of them are sorted by
+// id, so the children and their order are the same whichever is read.
+constexpr int kLoBits = 40;
+constexpr int kMaxGen = 63;
+__device__ __forceinline__ int64_t seg_ref(int64_t lo, int dir, int gen) {
+  return lo | ((int64_t)dir << kLoBits) | ((int64_t)gen << (kLoBits + 1));
+}
+__device__ __forceinline__ int64_t ref_lo(int64_t r) { return r & ((1ll << kLoBits) - 1); }
+__device__ __forceinline__ int ref_dir(int64_t r) { return (int)((r >> kLoBits) & 1); }
+__device__ __forceinline__ int ref_gen(int64_t r) { return (int)(r >> (kLoBits + 1)); }
+
 static_assert(sizeof(EState) % sizeof(int64_t) == 0, "EState must be a whole number of int64");
 constexpr int64_t kEsStride = sizeof(EState) / sizeof(int64_t);
 
@@ -293,6 +308,8 @@ __device__ __forceinline__ int dom_mode(const IterArgs &A, int d) {
   return push <= (double)dm.theta * pull ? 1 : 2;
 }
 
+constexpr int64_t kCoopSeg = 32;   // push: segments longer than this are walked by a whole wave
+
 // Push: for every b in F, OR the label-p segment of b into D (sparse-frontier product).
 __global__ __launch_bounds__(kBlock) void k_dom_push(const IterArgs A) {
   __shared__ int64_t lds[kWaves];
@@ -304,22 +321,36 @@ __global__ __launch_bounds__(kBlock) void k_dom_push(const IterArgs A) {
     if (dom_mode(A, d) != 1) continue;
     const DDomain dm = A.doms[d];
     const int64_t w = (t % tpd) * kTileWords + threadIdx.x;
+    const int lane = threadIdx.x & 63;
     int64_t work = 0;
-    if (w < W) {
-      uint64_t x = dm.F[w];
-      if (w == W - 1 && (A.g.n & 63)) x &= (1ull << (A.g.n & 63)) - 1ull;   // no vertex ids >= n
-      const int32_t *idx = A.g.idx[dm.dir];
-      while (x) {
+    uint64_t x = w < W ? dm.F[w] : 0;
+    if (w == W - 1 && (A.g.n & 63)) x &= (1ull << (A.g.n & 63)) - 1ull;   // no vertex ids >= n
+    const int32_t *idx = A.g.idx[dm.dir];
+    // one set bit per lane per round; short segments are walked by their lane,
+    // long ones (hubs) by the whole wave, one after the other
+    while (__ballot(x != 0)) {
+      int64_t lo = 0, hi = 0;
+      bool coop = false;
+      if (x) {
         const int b = __ffsll((unsigned long long)x) - 1;
         x &= x - 1;
-        int64_t lo, hi;
         int probes = 0;
         seg_find(A.g, dm.dir, (int32_t)(w * 64 + b), dm.label, lo, hi, probes);
-        for (int64_t k = lo; k < hi; ++k) {
+        work += hi - lo;
+        coop = hi - lo > kCoopSeg;
+        if (!coop)
+          for (int64_t k = lo; k < hi; ++k) {
+            const int32_t c = idx[k];
+            atomicOr((unsigned long long *)&dm.D[c >> 6], 1ull << (c & 63));
+          }
+      }
+      for (uint64_t m = __ballot(coop); m; m &= m - 1) {
+        const int l = __ffsll((unsigned long long)m) - 1;
+        const int64_t L = __shfl(lo, l, 64), H = __shfl(hi, l, 64);
+        for (int64_t k = L + lane; k < H; k += 64) {
           const int32_t c = idx[k];
           atomicOr((unsigned long long *)&dm.D[c >> 6], 1ull << (c & 63));
         }
-        work += hi - lo;
       }
     }
     work = block_sum_i64(work, lds);
@@ -407,6 +438,7 @@ __global__ __launch_bounds__(kBlock) void k_lookup(const IterArgs A) {
       if (i >= pn) break;
       int64_t lo = 0, hi = 0;
       int probes = 0;
+      int dir = S.dir, gen = 0;
       if (S.kind == STEP_SEG) {
         seg_find(A.g, S.dir, es[e].prev[(int64_t)S.src * pn + i], S.label, lo, hi, probes);
       } else if (S.kind == STEP_SEG_CONST) {
@@ -414,9 +446,16 @@ __global__ __launch_bounds__(kBlock) void k_lookup(const IterArgs A) {
       } else {
         hi = es[e].list_n;
       }
+      if (S.kind != STEP_LIST)   // read the shortest bound segment
+        for (int k = 0; k < min(S.nchk, kMaxGen) && hi > lo; ++k) {
+          const DCheck ck = A.checks[S.chk0 + k];
+          int64_t clo, chi;
+          seg_find(A.g, ck.dir, es[e].prev[(int64_t)ck.col * pn + i], ck.label, clo, chi, probes);
+          if (chi - clo < hi - lo) { lo = clo; hi = chi; dir = ck.dir; gen = k + 1; }
+        }
       if (!sh_ok) hi = lo;
       const int64_t gn = es[e].node0 + i;
-      it->lo[gn] = lo;
+      it->lo[gn] = seg_ref(lo, dir, gen);
       it->len[gn] = hi - lo;
       cnz += (hi > lo);
       cw += hi - lo;
@@ -533,10 +572,12 @@ __device__ __forceinline__ int64_t last_le_global(const int64_t *v, int64_t lo, 
 // consecutive tiles, so the entry and the first node carry over from the
 // previous tile (cursor): only a workgroup's first tile of an entry searches.
 // The tile's last node comes from a coalesced window of node offsets.
+// Held in LDS and used by thread 0 only (keeps it out of every thread's registers).
 struct TileCursor {
-  int e = -1;
-  int64_t k_last = -1, next_tile0 = 0;
-  int64_t tile0 = 0, w = 0, nb = 0, ne = 0;   // the entry's first tile, work, non-empty node range
+  int e;
+  int64_t k_last, next_tile0;
+  int64_t tile0, w, nb, ne;   // the entry's first tile, work, non-empty node range
+  __device__ void init() { e = -1; k_last = -1; next_tile0 = tile0 = w = nb = ne = 0; }
 };
 
 __device__ __forceinline__ void load_tile(const IterArgs &A, int64_t t, TileNz &T, TileCursor &C) {
@@ -566,26 +607,26 @@ __device__ __forceinline__ void load_tile(const IterArgs &A, int64_t t, TileNz &
     base_s = base;
     nwin = min((int64_t)kTileWork + 2, C.ne - base);
   }
-  __syncthreads();
+  lds_sync();
   const int64_t base = base_s;
   const int n = (int)nwin;
   const int64_t last = T.b - 1;
   // offsets, segment starts and nodes of the window, one per thread, extended only for short segments
   int n1 = min(n, (int)blockDim.x);
   if (threadIdx.x < n1) {
-    T.woff[threadIdx.x] = it->nz_woff[base + threadIdx.x];
-    T.lo[threadIdx.x] = it->nz_lo[base + threadIdx.x];
-    T.node[threadIdx.x] = it->nz_node[base + threadIdx.x];
+    T.woff[threadIdx.x] = gld(it->nz_woff + base + threadIdx.x);
+    T.lo[threadIdx.x] = gld(it->nz_lo + base + threadIdx.x);
+    T.node[threadIdx.x] = gld(it->nz_node + base + threadIdx.x);
   }
-  __syncthreads();
+  lds_sync();
   if (n1 < n && T.woff[n1 - 1] <= last) {   // every loaded node starts in the tile: load the rest
     for (int k = n1 + threadIdx.x; k < n; k += blockDim.x) {
-      T.woff[k] = it->nz_woff[base + k];
-      T.lo[k] = it->nz_lo[base + k];
-      T.node[k] = it->nz_node[base + k];
+      T.woff[k] = gld(it->nz_woff + base + k);
+      T.lo[k] = gld(it->nz_lo + base + k);
+      T.node[k] = gld(it->nz_node + base + k);
     }
     n1 = n;
-    __syncthreads();
+    lds_sync();
   }
   // first node: the last offset <= a; last node: the last offset <= b - 1 (offsets ascend)
   for (int k = threadIdx.x; k < n1; k += blockDim.x) {
@@ -593,30 +634,21 @@ __device__ __forceinline__ void load_tile(const IterArgs &A, int64_t t, TileNz &
     if (T.woff[k] <= T.a && (next_after || T.woff[k + 1] > T.a)) kfirst = k;
     if (T.woff[k] <= last && (next_after || T.woff[k + 1] > last)) T.count = k + 1;
   }
-  __syncthreads();
+  lds_sync();
+  // items map to indexes k0 .. T.count - 1 of the window (k0: the node the tile starts in)
   const int k0 = (int)kfirst;
   const int cnt = T.count - k0;
   if (threadIdx.x == 0) C.k_last = base + T.count - 1;
   constexpr int per = kTileWork / kBlock;
-  // shift the window so that node 0 is the tile's first node
-  if (k0 > 0) {
-    int64_t wo[(kTileWork + 2 + kBlock - 1) / kBlock], lo[(kTileWork + 2 + kBlock - 1) / kBlock];
-    int32_t nd[(kTileWork + 2 + kBlock - 1) / kBlock];
-    int m = 0;
-    for (int k = threadIdx.x; k < cnt; k += blockDim.x, ++m) { wo[m] = T.woff[k + k0]; lo[m] = T.lo[k + k0]; nd[m] = T.node[k + k0]; }
-    __syncthreads();
-    m = 0;
-    for (int k = threadIdx.x; k < cnt; k += blockDim.x, ++m) { T.woff[k] = wo[m]; T.lo[k] = lo[m]; T.node[k] = nd[m]; }
-  }
-  for (int i = 0; i < per; ++i) T.kmap[threadIdx.x * per + i] = 0;
-  __syncthreads();
+  for (int i = 0; i < per; ++i) T.kmap[threadIdx.x * per + i] = (uint16_t)k0;
+  lds_sync();
   if (cnt == 1) return;   // one node covers the whole tile: no item map needed
-  for (int k = 1 + threadIdx.x; k < cnt; k += blockDim.x)
-    T.kmap[T.woff[k] - T.a] = (uint16_t)k;   // node k starts inside the tile (node 0 may start before it)
-  __syncthreads();
+  for (int k = k0 + 1 + threadIdx.x; k < T.count; k += blockDim.x)
+    T.kmap[T.woff[k] - T.a] = (uint16_t)k;   // node k starts inside the tile (node k0 may start before it)
+  lds_sync();
   // forward fill: each item takes the last node start at or before it (a max-scan, node starts ascend)
   int v[per];
-  int mx = 0;
+  int mx = k0;
   for (int i = 0; i < per; ++i) { mx = max(mx, (int)T.kmap[threadIdx.x * per + i]); v[i] = mx; }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   int incl = mx;
@@ -625,12 +657,12 @@ __device__ __forceinline__ void load_tile(const IterArgs &A, int64_t t, TileNz &
     if (lane >= off) incl = max(incl, u);
   }
   if (lane == 63) T.wmax[wv] = incl;
-  __syncthreads();
+  lds_sync();
   int pre = __shfl_up(incl, 1, 64);
-  if (lane == 0) pre = 0;
+  if (lane == 0) pre = k0;
   for (int i = 0; i < wv; ++i) pre = max(pre, T.wmax[i]);
   for (int i = 0; i < per; ++i) T.kmap[threadIdx.x * per + i] = (uint16_t)max(pre, v[i]);
-  __syncthreads();
+  lds_sync();
 }
 
 __device__ __forceinline__ int tile_find(const TileNz &T, int64_t w) { return T.kmap[w - T.a]; }
@@ -638,21 +670,33 @@ __device__ __forceinline__ int tile_find(const TileNz &T, int64_t w) { return T.
 __device__ __forceinline__ int32_t candidate(const IterArgs &A, const EState &E, const DStep &S, const TileNz &T,
                                              int k, int64_t w) {
   const int64_t off = w - T.woff[k];
-  if (S.kind == STEP_LIST) return E.list[off];
-  return A.g.idx[S.dir][T.lo[k] + off];
+  if (S.kind == STEP_LIST) return gld(E.list + off);
+  const int64_t r = T.lo[k];
+  return gld(A.g.idx[ref_dir(r)] + ref_lo(r) + off);
 }
 
+// gen: which bound segment the candidate was read from (see seg_ref); that
+// check is replaced by the parent edge's.
 __device__ __forceinline__ bool test_candidate(const IterArgs &A, const EState &E, const DStep &S, int32_t node,
-                                               int32_t c, int &probes, int &ftests, int &ctests) {
+                                               int gen, int32_t c, int &probes, int &ftests, int &ctests) {
   for (int f = S.list_nfilt; f < S.nfilt; ++f) {
     ++ftests;
     if (!bit_test(A.filt[S.filt0 + f], c)) return false;
   }
   for (int k = 0; k < S.nchk; ++k) {
     ++ctests;
-    const DCheck ck = A.checks[S.chk0 + k];
-    const int32_t b = E.prev[(int64_t)ck.col * E.prev_n + node];
-    if (!seg_has(A.g, ck.dir, b, ck.label, c, probes)) return false;
+    int32_t b, label, dir;
+    if (k + 1 == gen) {
+      b = S.kind == STEP_SEG ? gld(E.prev + (int64_t)S.src * E.prev_n + node) : S.src;
+      label = S.label;
+      dir = S.dir;
+    } else {
+      const DCheck ck = A.checks[S.chk0 + k];
+      b = gld(E.prev + (int64_t)ck.col * E.prev_n + node);
+      label = ck.label;
+      dir = ck.dir;
+    }
+    if (!seg_has(A.g, dir, b, label, c, probes)) return false;
   }
   for (int k = 0; k < S.nself; ++k)
     if (!seg_has(A.g, 0, c, A.ints[S.self0 + k], c, probes)) return false;
@@ -669,7 +713,8 @@ __global__ __launch_bounds__(kBlock) void k_expand_count(const IterArgs A) {
   int64_t tb, te;
   block_share(it->work_tiles, tb, te);
   int64_t bsum = 0, b_pr = 0, b_ft = 0, b_ct = 0;
-  TileCursor cur;
+  __shared__ TileCursor cur;
+  if (threadIdx.x == 0) cur.init();
   EntryAcc acc, qacc;                    // valid counts per entry, probes per query
   int64_t *p_cnt = &es[0].cnt, *p_probe = A.qstats + QS_PROBE;
   for (int64_t t = tb; t < te;) {
@@ -681,11 +726,11 @@ __global__ __launch_bounds__(kBlock) void k_expand_count(const IterArgs A) {
       sh_free = test_free(A.steps[A.ent[e].step]);
       sh_end = es[e].w_tile0 + ceil_div(es[e].w, kTileWork);
     }
-    __syncthreads();
+    lds_sync();
     const int e0 = uniform(sh_e);
     const bool free_e = sh_free;
     const int64_t t_end = min(te, sh_end);
-    __syncthreads();
+    lds_sync();
     if (free_e) {   // every candidate is a child: the entry's count was set by the node scan
       const int64_t a = (t - es[e0].w_tile0) * kTileWork;
       const int64_t b = min((t_end - es[e0].w_tile0) * kTileWork, es[e0].w);
@@ -707,7 +752,7 @@ __global__ __launch_bounds__(kBlock) void k_expand_count(const IterArgs A) {
       if (w < T.b) {
         const int k = tile_find(T, w);
         const int32_t c = candidate(A, E, S, T, k, w);
-        ok = test_candidate(A, E, S, T.node[k], c, probes, ftests, ctests);
+        ok = test_candidate(A, E, S, T.node[k], ref_gen(T.lo[k]), c, probes, ftests, ctests);
       }
       const uint64_t bal = __ballot(ok);
       if (lane == 0) {
@@ -721,7 +766,7 @@ __global__ __launch_bounds__(kBlock) void k_expand_count(const IterArgs A) {
     int64_t v4[4] = {c_tile, probes, ftests, ctests};
     for (int i = 0; i < 4; ++i) v4[i] = wave_sum_i64(v4[i]);
     if (lane == 0) for (int i = 0; i < 4; ++i) red4[wv][i] = v4[i];
-    __syncthreads();
+    lds_sync();
     for (int i = 0; i < 4; ++i) { v4[i] = 0; for (int w2 = 0; w2 < kWaves; ++w2) v4[i] += red4[w2][i]; }
     c_tile = v4[0];
     const int64_t pr = v4[1], ft = v4[2], ct = v4[3];
@@ -733,7 +778,7 @@ __global__ __launch_bounds__(kBlock) void k_expand_count(const IterArgs A) {
     b_ft += ft;
     b_ct += ct;
     bsum += c_tile;
-    __syncthreads();
+    lds_sync();
   }
   if (threadIdx.x == 0) {
     acc.flush(p_cnt, nullptr, kEsStride);
@@ -778,19 +823,11 @@ __global__ __launch_bounds__(1024) void k_scan_expand(const IterArgs A) {
   }
 }
 
-__device__ __forceinline__ void write_child(const IterArgs &A, const EState &E, const DStep &S, const TileNz &T,
-                                            int64_t w, int64_t li) {
-  const int k = tile_find(T, w);
-  const int32_t c = candidate(A, E, S, T, k, w);
-  const int64_t cnt = E.cnt;
-  const int32_t node = T.node[k];
-  E.out[li] = node;
-  E.out[cnt + li] = c;
-  for (int j = 0; j < S.ncopy; ++j)
-    E.out[(int64_t)(2 + j) * cnt + li] = E.prev[(int64_t)A.ints[S.copy0 + j] * E.prev_n + node];
-}
-
-__global__ __launch_bounds__(kBlock) void k_expand_write(const IterArgs A) {
+// Children of the tiles: every item's output position is ranked first (its
+// offset in the tile for test-free levels, its rank among the valid items
+// otherwise); then each thread reads the nodes and candidates of all its items
+// before it issues their stores, so that its loads overlap.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_expand_write(const IterArgs A) {
   __shared__ TileNz T;
   __shared__ int wcnt[kTileWork / 64];   // valid items per (round, wave) of the tile
   IterScalars *it = A.it;
@@ -801,43 +838,65 @@ __global__ __launch_bounds__(kBlock) void k_expand_write(const IterArgs A) {
   int64_t tb, te;
   block_share(it->work_tiles, tb, te);
   int64_t run = A.blk_off_a[blockIdx.x];
-  TileCursor cur;
+  __shared__ TileCursor cur;
+  if (threadIdx.x == 0) cur.init();
   for (int64_t t = tb; t < te; ++t) {
     load_tile(A, t, T, cur);
     const int e = uniform(T.e);
     const EState E = es[e];
     const DStep S = A.steps[A.ent[e].step];
-    if (test_free(S)) {   // every candidate is a child: its position is its offset in the tile
-      if (E.out)
-        for (int r = 0; r < R; ++r) {
-          const int64_t w = T.a + r * kBlock + threadIdx.x;
-          if (w < T.b) write_child(A, E, S, T, w, run + (w - T.a) - E.out_base);
-        }
-      run += T.b - T.a;
-      __syncthreads();
-      continue;
-    }
-    // rank the valid items of the whole tile with one barrier: per (round, wave) counts
-    uint64_t bal[R];
-    for (int r = 0; r < R; ++r) {
-      const uint32_t *vw = it->valid + t * (kTileWork / 32) + (r * kBlock + wv * 64) / 32;
-      bal[r] = (uint64_t)vw[0] | ((uint64_t)vw[1] << 32);
-      if (lane == 0) wcnt[r * kWaves + wv] = __popcll(bal[r]);
-    }
-    __syncthreads();
-    int before = 0, total = 0;
-    for (int i = 0; i < R * kWaves; ++i) total += wcnt[i];
-    for (int r = 0; r < R; ++r) {
-      int pre = before;
-      for (int w2 = 0; w2 < wv; ++w2) pre += wcnt[r * kWaves + w2];
-      if (E.out && ((bal[r] >> lane) & 1ull)) {
+    int64_t li[R];   // output position of each item, -1: not a child
+    int total;
+    if (test_free(S)) {
+      for (int r = 0; r < R; ++r) {
         const int64_t w = T.a + r * kBlock + threadIdx.x;
-        write_child(A, E, S, T, w, run + pre + __popcll(bal[r] & lanemask_lt()) - E.out_base);
+        li[r] = w < T.b ? run + (w - T.a) - E.out_base : -1;
       }
-      for (int w2 = 0; w2 < kWaves; ++w2) before += wcnt[r * kWaves + w2];
+      total = (int)(T.b - T.a);
+    } else {
+      // rank the valid items of the whole tile with one barrier: per (round, wave) counts
+      uint64_t bal[R];
+      for (int r = 0; r < R; ++r) {
+        const uint32_t *vw = it->valid + t * (kTileWork / 32) + (r * kBlock + wv * 64) / 32;
+        bal[r] = (uint64_t)gld(vw) | ((uint64_t)gld(vw + 1) << 32);
+        if (lane == 0) wcnt[r * kWaves + wv] = __popcll(bal[r]);
+      }
+      lds_sync();
+      int before = 0;
+      total = 0;
+      for (int i = 0; i < R * kWaves; ++i) total += wcnt[i];
+      for (int r = 0; r < R; ++r) {
+        int pre = before;
+        for (int w2 = 0; w2 < wv; ++w2) pre += wcnt[r * kWaves + w2];
+        li[r] = ((bal[r] >> lane) & 1ull) ? run + pre + __popcll(bal[r] & lanemask_lt()) - E.out_base : -1;
+        for (int w2 = 0; w2 < kWaves; ++w2) before += wcnt[r * kWaves + w2];
+      }
+    }
+    if (E.out) {
+      const int64_t cnt = E.cnt;
+      int32_t node[R], c[R];
+      for (int r = 0; r < R; ++r) {
+        node[r] = 0;
+        c[r] = 0;
+        if (li[r] >= 0) {
+          const int64_t w = T.a + r * kBlock + threadIdx.x;
+          const int k = tile_find(T, w);
+          node[r] = T.node[k];
+          c[r] = candidate(A, E, S, T, k, w);
+        }
+      }
+      for (int r = 0; r < R; ++r)
+        if (li[r] >= 0) { gst(E.out + li[r], node[r]); gst(E.out + cnt + li[r], c[r]); }
+      for (int j = 0; j < S.ncopy; ++j) {
+        const int32_t *col = E.prev + (int64_t)A.ints[S.copy0 + j] * E.prev_n;
+        int32_t v[R];
+        for (int r = 0; r < R; ++r) v[r] = li[r] >= 0 ? gld(col + node[r]) : 0;
+        for (int r = 0; r < R; ++r)
+          if (li[r] >= 0) gst(E.out + (int64_t)(2 + j) * cnt + li[r], v[r]);
+      }
     }
     run += total;
-    __syncthreads();
+    lds_sync();
   }
 }
 
