@@ -74,6 +74,7 @@ gs_status gs_engine_create(const gs_options *options, gs_engine **out) {
   if (hipGetDeviceProperties(&prop, E.device) == hipSuccess) E.cus = prop.multiProcessorCount;
   E.grid = o.grid_blocks > 0 ? o.grid_blocks : 8 * E.cus;
   if (E.grid > 8192) E.grid = 8192;
+  E.wgrid = expand_write_blocks_per_cu() * E.cus;
   if (o.hip_stream) {
     E.stream = (hipStream_t)o.hip_stream;
   } else {
@@ -236,7 +237,7 @@ gs_status gs_bitmap_and_compact(gs_engine *engine, const uint64_t *const *bitmap
   ar[1] = {0, E.scratch_cap, 0, 0};
   HIPRET(hipMemcpyAsync(E.d_arenas, ar, sizeof ar, hipMemcpyHostToDevice, s));
   IterArgs A{};
-  A.g = E.g; A.ent = en; A.E = 1; A.grid = E.grid; A.steps = st; A.filt = ft; A.es = es; A.it = it;
+  A.g = E.g; A.ent = en; A.E = 1; A.grid = E.grid; A.wgrid = E.wgrid; A.steps = st; A.filt = ft; A.es = es; A.it = it;
   A.lvl_ptr = lp; A.lvl_n = ln; A.qstats = qs; A.scratch = E.d_arenas + 1; A.scratch_base = E.scratch_base;
   A.tree = E.d_arenas; A.tree_base = E.tree_base; A.has_list = 1;
   A.blk_a = blk; A.blk_b = blk + E.grid; A.blk_off_a = blk + 2 * E.grid; A.blk_off_b = blk + 3 * E.grid;
@@ -422,7 +423,7 @@ void gs_result_free(gs_result *result) {
 
 static const char *kSlotNames[KS_N] = {"setup", "clear", "seed", "list_count", "list_scan", "list_write",
                                        "dom_frontier", "dom_push", "dom_pull", "lookup", "scan_nodes", "nz_write",
-                                       "expand_count", "scan_expand", "expand_write"};
+                                       "expand_count", "scan_expand", "tile_offsets", "expand_write"};
 
 gs_status gs_kernel_stats(gs_engine *engine, gs_kernel_stat *out, int32_t cap, int32_t *n, int reset) {
   if (!engine || !n || (cap > 0 && !out)) { set_error("bad argument"); return GS_EINVAL; }

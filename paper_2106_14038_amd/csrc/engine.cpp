@@ -469,6 +469,7 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
     A.nclear = clr_off[t + 1] - clr_off[t];
     A.has_list = its[t].has_list;
     A.grid = E.grid;
+    A.wgrid = E.wgrid;
     A.steps = (const DStep *)dp(tab_off + o_steps);
     A.filt = (const uint64_t *const *)dp(tab_off + o_filt);
     A.checks = (const DCheck *)dp(tab_off + o_chk);

@@ -45,6 +45,7 @@ struct Engine {
   bool own_stream = false;
   gs_options opt{};
   int grid = 2048;
+  int wgrid = 1024;   // write-pass workgroups: as many as the device holds at once
   int cus = 256;
 
   // matrix

@@ -85,6 +85,19 @@ struct EState {
   int32_t *list;
 };
 
+// One work tile of the expansion (kTileWork consecutive candidate entries of
+// one entry), written by the non-empty-node pass for the node its first entry
+// belongs to, so that any workgroup can take any tile.
+struct DTile {
+  int64_t k0;    // index (in the non-empty node arrays) of the node holding the first entry
+  int64_t a;     // entry-local position of the first entry
+  int64_t out;   // entry-local output position of the tile's first child (tile-offset pass)
+  int32_t e;     // entry; -1 on the sentinel after the last tile
+  int32_t n;     // entries in the tile
+  int32_t cnt;   // valid entries (count pass; tested levels)
+  int32_t pad;
+};
+
 // Per-iteration scalars written by the scan kernels.
 struct IterScalars {
   int64_t n_entries;
@@ -96,6 +109,7 @@ struct IterScalars {
   int32_t *nz_node;        // compacted non-empty nodes: local node index
   int64_t *nz_lo, *nz_woff;// their segment start and entry-local work offset
   uint32_t *valid;         // expansion validity bits, kTileWork bits per work tile
+  DTile *tiles;            // work_tiles + 1 records (the last one a sentinel)
   int32_t *list_buf;
   // work counters of the expansion count pass (for algorithmic-byte accounting)
   int64_t ftests;          // bitmap filter words tested
@@ -107,7 +121,7 @@ struct IterScalars {
 // Kernel slots of one iteration, for optional event timing.
 enum KSlot { KS_SETUP = 0, KS_CLEAR, KS_SEED, KS_LIST_COUNT, KS_LIST_SCAN, KS_LIST_WRITE, KS_DOM_FRONTIER,
              KS_DOM_PUSH, KS_DOM_PULL, KS_LOOKUP, KS_SCAN_NODES, KS_NZ_WRITE, KS_EXPAND_COUNT, KS_SCAN_EXPAND,
-             KS_EXPAND_WRITE, KS_N };
+             KS_TILE_OFFSETS, KS_EXPAND_WRITE, KS_N };
 
 // Bump allocator over one device region; top and cap in bytes.
 struct DArena {

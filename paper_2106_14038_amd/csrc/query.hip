@@ -500,7 +500,15 @@ __global__ __launch_bounds__(1024) void k_scan_nodes(const IterArgs A) {
     it->nz_lo = (int64_t *)arena_alloc(A.scratch, A.scratch_base, sizeof(int64_t) * nz);
     it->nz_woff = (int64_t *)arena_alloc(A.scratch, A.scratch_base, sizeof(int64_t) * nz);
     it->valid = (uint32_t *)arena_alloc(A.scratch, A.scratch_base, (uint64_t)wt * (kTileWork / 8));
-    if (A.scratch->overflow) it->abort = 1;
+    it->tiles = (DTile *)arena_alloc(A.scratch, A.scratch_base, sizeof(DTile) * (uint64_t)(wt + 1));
+    if (A.scratch->overflow) {
+      it->abort = 1;
+    } else {
+      DTile z{};
+      z.k0 = nz;
+      z.e = -1;
+      it->tiles[wt] = z;
+    }
   }
   for (int e = threadIdx.x; e < A.E; e += blockDim.x) {
     const DEntry d = A.ent[e];
@@ -525,6 +533,7 @@ __global__ __launch_bounds__(kBlock) void k_nz_write(const IterArgs A) {
     __syncthreads();
     const int e = uniform(sh_e);
     const int64_t i0 = (t - es[e].node_tile0) * kTileNodes, pn = es[e].prev_n;
+    const int64_t ew = es[e].w, etile0 = es[e].w_tile0;
     for (int r = 0; r < kTileNodes / kBlock; ++r) {
       const int64_t i = i0 + r * kBlock + threadIdx.x;
       int64_t len = 0, lo = 0;
@@ -535,9 +544,22 @@ __global__ __launch_bounds__(kBlock) void k_nz_write(const IterArgs A) {
       const int64_t wpos = block_excl_scan_i64(len, wtot, lds);
       if (len > 0) {
         const int64_t k = run_nz + pos;
+        const int64_t woff = run_w + wpos - es[e].w_base;
         it->nz_node[k] = (int32_t)i;
         it->nz_lo[k] = lo;
-        it->nz_woff[k] = run_w + wpos - es[e].w_base;
+        it->nz_woff[k] = woff;
+        // the tiles whose first entry falls in this node
+        for (int64_t j = ceil_div(woff, kTileWork); j * kTileWork < woff + len; ++j) {
+          DTile d;
+          d.k0 = k;
+          d.a = j * kTileWork;
+          d.out = 0;
+          d.e = e;
+          d.n = (int32_t)min((int64_t)kTileWork, ew - d.a);
+          d.cnt = 0;
+          d.pad = 0;
+          it->tiles[etile0 + j] = d;
+        }
       }
       run_nz += ftot;
       run_w += wtot;
@@ -546,111 +568,50 @@ __global__ __launch_bounds__(kBlock) void k_nz_write(const IterArgs A) {
 }
 
 // ------------------------------------------------------------------ expansion
+// Staged nodes of one tile. Node i of the tile is non-empty node tiles[t].k0 + i;
+// item p (entry a + p) belongs to node kmap[p] and reads entry base[i] + p of
+// that node's segment (or list).
 struct TileNz {
-  int64_t woff[kTileWork + 2];
-  int64_t lo[kTileWork + 2];
-  int32_t node[kTileWork + 2];
-  uint16_t kmap[kTileWork];   // item of the tile -> index of its node in the arrays above
+  int64_t base[kTileWork + 2];  // segment start minus the node's first item position in the tile
+  int32_t node[kTileWork + 2];  // local node index in the previous level
+  uint8_t dg[kTileWork + 2];    // orientation | generator << 1 (see seg_ref)
+  uint16_t kmap[kTileWork];     // item -> node; all zero between tiles
   int32_t wmax[kWaves];
-  int count;
-  int e;
-  int64_t a, b;
+  int32_t wscat[kWaves];
+  int32_t e, n;
+  int64_t a, out;
 };
 
-
-
-__device__ __forceinline__ int64_t last_le_global(const int64_t *v, int64_t lo, int64_t hi, int64_t key) {
-  // last index k in [lo, hi) with v[k] <= key (v[lo] <= key holds)
-  while (hi - lo > 1) {
-    int64_t mid = (lo + hi) >> 1;
-    if (v[mid] <= key) lo = mid; else hi = mid;
-  }
-  return lo;
-}
-
-// Load the non-empty nodes covering work tile t into LDS. A workgroup walks
-// consecutive tiles, so the entry and the first node carry over from the
-// previous tile (cursor): only a workgroup's first tile of an entry searches.
-// The tile's last node comes from a coalesced window of node offsets.
-// Held in LDS and used by thread 0 only (keeps it out of every thread's registers).
-struct TileCursor {
-  int e;
-  int64_t k_last, next_tile0;
-  int64_t tile0, w, nb, ne;   // the entry's first tile, work, non-empty node range
-  __device__ void init() { e = -1; k_last = -1; next_tile0 = tile0 = w = nb = ne = 0; }
-};
-
-__device__ __forceinline__ void load_tile(const IterArgs &A, int64_t t, TileNz &T, TileCursor &C) {
+// Stage tile t: its nodes, and the item -> node map (a max-scan of node starts).
+// On return kmap holds the map; the item pass reads each entry once and clears it.
+__device__ __forceinline__ void load_tile(const IterArgs &A, int64_t t, TileNz &T) {
   IterScalars *it = A.it;
-  EState *es = A.es;
-  __shared__ int64_t base_s, nwin, kfirst;
-  if (threadIdx.x == 0) {
-    int e = C.e;
-    if (e < 0 || t >= C.next_tile0 || t < C.tile0) {
-      e = last_le(A.E, t, [&](int i) { return es[i].w_tile0; });
-      C.k_last = -1;
-    }
-    if (e != C.e) {
-      C.e = e;
-      C.k_last = -1;
-      C.tile0 = es[e].w_tile0;
-      C.w = es[e].w;
-      C.nb = es[e].nz_base;
-      C.ne = C.nb + es[e].nz;
-      C.next_tile0 = C.tile0 + (C.w + kTileWork - 1) / kTileWork;
-    }
-    T.e = e;
-    T.a = (t - C.tile0) * kTileWork;
-    T.b = min(T.a + kTileWork, C.w);
-    // the window starts at the node the previous tile ended in (this tile starts there or at the next one)
-    const int64_t base = C.k_last >= 0 ? C.k_last : last_le_global(it->nz_woff, C.nb, C.ne, T.a);
-    base_s = base;
-    nwin = min((int64_t)kTileWork + 2, C.ne - base);
+  const DTile d = it->tiles[t], dn = it->tiles[t + 1];
+  // nodes k0 .. the node holding the next tile's first entry (when it is the same entry's)
+  const int nwin = (int)(dn.k0 - d.k0 + (dn.e == d.e ? 1 : 0));
+  int scat = 0;
+  for (int i = threadIdx.x; i < nwin; i += blockDim.x) {
+    const int64_t k = d.k0 + i;
+    const int64_t s = gld(it->nz_woff + k) - d.a;   // first item of the node, relative to the tile
+    const int64_t r = gld(it->nz_lo + k);
+    T.base[i] = ref_lo(r) - s;
+    T.dg[i] = (uint8_t)(ref_dir(r) | (ref_gen(r) << 1));
+    T.node[i] = gld(it->nz_node + k);
+    if (i > 0 && s < d.n) { T.kmap[s] = (uint16_t)i; scat = 1; }
   }
-  lds_sync();
-  const int64_t base = base_s;
-  const int n = (int)nwin;
-  const int64_t last = T.b - 1;
-  // offsets, segment starts and nodes of the window, one per thread, extended only for short segments
-  int n1 = min(n, (int)blockDim.x);
-  if (threadIdx.x < n1) {
-    T.woff[threadIdx.x] = gld(it->nz_woff + base + threadIdx.x);
-    T.lo[threadIdx.x] = gld(it->nz_lo + base + threadIdx.x);
-    T.node[threadIdx.x] = gld(it->nz_node + base + threadIdx.x);
-  }
-  lds_sync();
-  if (n1 < n && T.woff[n1 - 1] <= last) {   // every loaded node starts in the tile: load the rest
-    for (int k = n1 + threadIdx.x; k < n; k += blockDim.x) {
-      T.woff[k] = gld(it->nz_woff + base + k);
-      T.lo[k] = gld(it->nz_lo + base + k);
-      T.node[k] = gld(it->nz_node + base + k);
-    }
-    n1 = n;
-    lds_sync();
-  }
-  // first node: the last offset <= a; last node: the last offset <= b - 1 (offsets ascend)
-  for (int k = threadIdx.x; k < n1; k += blockDim.x) {
-    const bool next_after = (k + 1 == n1);
-    if (T.woff[k] <= T.a && (next_after || T.woff[k + 1] > T.a)) kfirst = k;
-    if (T.woff[k] <= last && (next_after || T.woff[k + 1] > last)) T.count = k + 1;
-  }
-  lds_sync();
-  // items map to indexes k0 .. T.count - 1 of the window (k0: the node the tile starts in)
-  const int k0 = (int)kfirst;
-  const int cnt = T.count - k0;
-  if (threadIdx.x == 0) C.k_last = base + T.count - 1;
-  constexpr int per = kTileWork / kBlock;
-  for (int i = 0; i < per; ++i) T.kmap[threadIdx.x * per + i] = (uint16_t)k0;
-  lds_sync();
-  if (cnt == 1) return;   // one node covers the whole tile: no item map needed
-  for (int k = k0 + 1 + threadIdx.x; k < T.count; k += blockDim.x)
-    T.kmap[T.woff[k] - T.a] = (uint16_t)k;   // node k starts inside the tile (node k0 may start before it)
-  lds_sync();
-  // forward fill: each item takes the last node start at or before it (a max-scan, node starts ascend)
-  int v[per];
-  int mx = k0;
-  for (int i = 0; i < per; ++i) { mx = max(mx, (int)T.kmap[threadIdx.x * per + i]); v[i] = mx; }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const uint64_t sb = __ballot(scat);
+  if (lane == 0) T.wscat[wv] = sb != 0;
+  if (threadIdx.x == 0) { T.e = d.e; T.n = d.n; T.a = d.a; T.out = d.out; }
+  lds_sync();
+  int any = 0;
+  for (int i = 0; i < kWaves; ++i) any |= T.wscat[i];
+  if (!any) return;   // one node covers the whole tile: the map stays zero
+  // forward fill: each item takes the last node start at or before it (node starts ascend)
+  constexpr int per = kTileWork / kBlock;
+  int v[per];
+  int mx = 0;
+  for (int i = 0; i < per; ++i) { mx = max(mx, (int)T.kmap[threadIdx.x * per + i]); v[i] = mx; }
   int incl = mx;
   for (int off = 1; off < 64; off <<= 1) {
     const int u = __shfl_up(incl, off, 64);
@@ -659,20 +620,24 @@ __device__ __forceinline__ void load_tile(const IterArgs &A, int64_t t, TileNz &
   if (lane == 63) T.wmax[wv] = incl;
   lds_sync();
   int pre = __shfl_up(incl, 1, 64);
-  if (lane == 0) pre = k0;
+  if (lane == 0) pre = 0;
   for (int i = 0; i < wv; ++i) pre = max(pre, T.wmax[i]);
   for (int i = 0; i < per; ++i) T.kmap[threadIdx.x * per + i] = (uint16_t)max(pre, v[i]);
   lds_sync();
 }
 
-__device__ __forceinline__ int tile_find(const TileNz &T, int64_t w) { return T.kmap[w - T.a]; }
+// Node of item p of the staged tile; clears the map entry for the next tile
+// (each entry is read by exactly one thread).
+__device__ __forceinline__ int take_node(TileNz &T, int p) {
+  const int k = T.kmap[p];
+  T.kmap[p] = 0;
+  return k;
+}
 
 __device__ __forceinline__ int32_t candidate(const IterArgs &A, const EState &E, const DStep &S, const TileNz &T,
-                                             int k, int64_t w) {
-  const int64_t off = w - T.woff[k];
-  if (S.kind == STEP_LIST) return gld(E.list + off);
-  const int64_t r = T.lo[k];
-  return gld(A.g.idx[ref_dir(r)] + ref_lo(r) + off);
+                                             int k, int p) {
+  const int32_t *src = S.kind == STEP_LIST ? E.list : A.g.idx[T.dg[k] & 1];
+  return gld(src + T.base[k] + p);
 }
 
 // gen: which bound segment the candidate was read from (see seg_ref); that
@@ -703,6 +668,8 @@ __device__ __forceinline__ bool test_candidate(const IterArgs &A, const EState &
   return true;
 }
 
+// Count pass over the tiles of tested levels: validity bits per tile, valid
+// entries per tile, per entry and per workgroup (contiguous tile ranges).
 __global__ __launch_bounds__(kBlock) void k_expand_count(const IterArgs A) {
   __shared__ TileNz T;
   __shared__ int64_t red4[kWaves][4];
@@ -710,55 +677,42 @@ __global__ __launch_bounds__(kBlock) void k_expand_count(const IterArgs A) {
   if (it->abort) return;
   EState *es = A.es;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  constexpr int R = kTileWork / kBlock;
+  if (threadIdx.x < kWaves) T.wscat[threadIdx.x] = 0;
+  for (int i = threadIdx.x; i < kTileWork; i += blockDim.x) T.kmap[i] = 0;
+  lds_sync();
   int64_t tb, te;
   block_share(it->work_tiles, tb, te);
   int64_t bsum = 0, b_pr = 0, b_ft = 0, b_ct = 0;
-  __shared__ TileCursor cur;
-  if (threadIdx.x == 0) cur.init();
   EntryAcc acc, qacc;                    // valid counts per entry, probes per query
   int64_t *p_cnt = &es[0].cnt, *p_probe = A.qstats + QS_PROBE;
   for (int64_t t = tb; t < te;) {
-    __shared__ int sh_e, sh_free;
-    __shared__ int64_t sh_end;
-    if (threadIdx.x == 0) {
-      const int e = last_le(A.E, t, [&](int i) { return es[i].w_tile0; });
-      sh_e = e;
-      sh_free = test_free(A.steps[A.ent[e].step]);
-      sh_end = es[e].w_tile0 + ceil_div(es[e].w, kTileWork);
-    }
-    lds_sync();
-    const int e0 = uniform(sh_e);
-    const bool free_e = sh_free;
-    const int64_t t_end = min(te, sh_end);
-    lds_sync();
-    if (free_e) {   // every candidate is a child: the entry's count was set by the node scan
-      const int64_t a = (t - es[e0].w_tile0) * kTileWork;
-      const int64_t b = min((t_end - es[e0].w_tile0) * kTileWork, es[e0].w);
-      bsum += b - a;
-      t = t_end;
-      continue;
-    }
-    const int64_t t_cur = t++;
-    load_tile(A, t_cur, T, cur);
-    const int e = uniform(T.e);
+    const int e = uniform(gld(&it->tiles[t].e));
     const EState E = es[e];
     const DEntry d = A.ent[e];
     const DStep S = A.steps[d.step];
+    if (test_free(S)) {   // every candidate is a child: the entry's count was set by the node scan
+      const int64_t t_end = min(te, E.w_tile0 + ceil_div(E.w, kTileWork));
+      bsum += min((t_end - E.w_tile0) * kTileWork, E.w) - (t - E.w_tile0) * kTileWork;
+      t = t_end;
+      continue;
+    }
+    load_tile(A, t, T);
     int64_t c_tile = 0;
     int probes = 0, ftests = 0, ctests = 0;
-    for (int r = 0; r < kTileWork / kBlock; ++r) {
-      const int64_t w = T.a + r * kBlock + threadIdx.x;
+    for (int r = 0; r < R; ++r) {
+      const int p = r * kBlock + threadIdx.x;
+      const int k = take_node(T, p);
       bool ok = false;
-      if (w < T.b) {
-        const int k = tile_find(T, w);
-        const int32_t c = candidate(A, E, S, T, k, w);
-        ok = test_candidate(A, E, S, T.node[k], ref_gen(T.lo[k]), c, probes, ftests, ctests);
+      if (p < T.n) {
+        const int32_t c = candidate(A, E, S, T, k, p);
+        ok = test_candidate(A, E, S, T.node[k], T.dg[k] >> 1, c, probes, ftests, ctests);
       }
       const uint64_t bal = __ballot(ok);
       if (lane == 0) {
-        uint32_t *vw = it->valid + t_cur * (kTileWork / 32) + (r * kBlock + wv * 64) / 32;
-        vw[0] = (uint32_t)bal;
-        vw[1] = (uint32_t)(bal >> 32);
+        uint32_t *vw = it->valid + t * (kTileWork / 32) + (r * kBlock + wv * 64) / 32;
+        gst(vw, (uint32_t)bal);
+        gst(vw + 1, (uint32_t)(bal >> 32));
       }
       c_tile += ok;
     }
@@ -769,16 +723,17 @@ __global__ __launch_bounds__(kBlock) void k_expand_count(const IterArgs A) {
     lds_sync();
     for (int i = 0; i < 4; ++i) { v4[i] = 0; for (int w2 = 0; w2 < kWaves; ++w2) v4[i] += red4[w2][i]; }
     c_tile = v4[0];
-    const int64_t pr = v4[1], ft = v4[2], ct = v4[3];
     if (threadIdx.x == 0) {
+      it->tiles[t].cnt = (int32_t)c_tile;
       acc.add(e, c_tile, 0, p_cnt, nullptr, kEsStride);
-      qacc.add(d.q, pr, 0, p_probe, nullptr, QS_N);
+      qacc.add(d.q, v4[1], 0, p_probe, nullptr, QS_N);
     }
-    b_pr += pr;
-    b_ft += ft;
-    b_ct += ct;
+    b_pr += v4[1];
+    b_ft += v4[2];
+    b_ct += v4[3];
     bsum += c_tile;
     lds_sync();
+    ++t;
   }
   if (threadIdx.x == 0) {
     acc.flush(p_cnt, nullptr, kEsStride);
@@ -823,10 +778,37 @@ __global__ __launch_bounds__(1024) void k_scan_expand(const IterArgs A) {
   }
 }
 
-// Children of the tiles: every item's output position is ranked first (its
-// offset in the tile for test-free levels, its rank among the valid items
-// otherwise); then each thread reads the nodes and candidates of all its items
-// before it issues their stores, so that its loads overlap.
+// Output position of every tile's first child, entry-local: the count pass's
+// contiguous tile ranges again, each scanned from its workgroup's offset.
+__global__ __launch_bounds__(kBlock) void k_tile_offsets(const IterArgs A) {
+  __shared__ int64_t lds[kWaves];
+  IterScalars *it = A.it;
+  if (it->abort) return;
+  EState *es = A.es;
+  int64_t tb, te;
+  block_share(it->work_tiles, tb, te);
+  int64_t run = A.blk_off_a[blockIdx.x];
+  for (int64_t c0 = tb; c0 < te; c0 += kBlock) {
+    const int64_t t = c0 + threadIdx.x;
+    int64_t v = 0;
+    int e = 0;
+    if (t < te) {
+      DTile *d = it->tiles + t;
+      e = d->e;
+      v = test_free(A.steps[A.ent[e].step]) ? d->n : d->cnt;
+    }
+    int64_t tot;
+    const int64_t x = block_excl_scan_i64(v, tot, lds);
+    if (t < te) it->tiles[t].out = run + x - es[e].out_base;
+    run += tot;
+  }
+}
+
+// Write pass: tiles dealt round-robin to a grid of resident workgroups (tiles
+// are independent; neighbours run side by side). Every item's output position is
+// ranked first (tile offset + item for test-free levels, + rank among the valid
+// items otherwise); then each thread reads the nodes and candidates of all its
+// items before it issues their stores, so that its loads overlap.
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_expand_write(const IterArgs A) {
   __shared__ TileNz T;
   __shared__ int wcnt[kTileWork / 64];   // valid items per (round, wave) of the tile
@@ -835,24 +817,24 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
   EState *es = A.es;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   constexpr int R = kTileWork / kBlock;
-  int64_t tb, te;
-  block_share(it->work_tiles, tb, te);
-  int64_t run = A.blk_off_a[blockIdx.x];
-  __shared__ TileCursor cur;
-  if (threadIdx.x == 0) cur.init();
-  for (int64_t t = tb; t < te; ++t) {
-    load_tile(A, t, T, cur);
+  if (threadIdx.x < kWaves) T.wscat[threadIdx.x] = 0;
+  for (int i = threadIdx.x; i < kTileWork; i += blockDim.x) T.kmap[i] = 0;
+  lds_sync();
+  const int64_t ntiles = it->work_tiles;
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    load_tile(A, t, T);
     const int e = uniform(T.e);
     const EState E = es[e];
     const DStep S = A.steps[A.ent[e].step];
+    const int64_t out0 = T.out;
+    int kk[R];
+    for (int r = 0; r < R; ++r) kk[r] = take_node(T, r * kBlock + threadIdx.x);
     int64_t li[R];   // output position of each item, -1: not a child
-    int total;
     if (test_free(S)) {
       for (int r = 0; r < R; ++r) {
-        const int64_t w = T.a + r * kBlock + threadIdx.x;
-        li[r] = w < T.b ? run + (w - T.a) - E.out_base : -1;
+        const int p = r * kBlock + threadIdx.x;
+        li[r] = p < T.n ? out0 + p : -1;
       }
-      total = (int)(T.b - T.a);
     } else {
       // rank the valid items of the whole tile with one barrier: per (round, wave) counts
       uint64_t bal[R];
@@ -863,12 +845,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
       }
       lds_sync();
       int before = 0;
-      total = 0;
-      for (int i = 0; i < R * kWaves; ++i) total += wcnt[i];
       for (int r = 0; r < R; ++r) {
         int pre = before;
         for (int w2 = 0; w2 < wv; ++w2) pre += wcnt[r * kWaves + w2];
-        li[r] = ((bal[r] >> lane) & 1ull) ? run + pre + __popcll(bal[r] & lanemask_lt()) - E.out_base : -1;
+        li[r] = ((bal[r] >> lane) & 1ull) ? out0 + pre + __popcll(bal[r] & lanemask_lt()) : -1;
         for (int w2 = 0; w2 < kWaves; ++w2) before += wcnt[r * kWaves + w2];
       }
     }
@@ -879,10 +859,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
         node[r] = 0;
         c[r] = 0;
         if (li[r] >= 0) {
-          const int64_t w = T.a + r * kBlock + threadIdx.x;
-          const int k = tile_find(T, w);
-          node[r] = T.node[k];
-          c[r] = candidate(A, E, S, T, k, w);
+          node[r] = T.node[kk[r]];
+          c[r] = candidate(A, E, S, T, kk[r], r * kBlock + threadIdx.x);
         }
       }
       for (int r = 0; r < R; ++r)
@@ -895,7 +873,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
           if (li[r] >= 0) gst(E.out + (int64_t)(2 + j) * cnt + li[r], v[r]);
       }
     }
-    run += total;
     lds_sync();
   }
 }
@@ -917,6 +894,14 @@ __global__ __launch_bounds__(kBlock) void k_enumerate(int32_t *const *lvl_ptr, c
 }
 
 // ---------------------------------------------------------------- launchers
+int expand_write_blocks_per_cu() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(k_expand_write), kBlock, 0) !=
+      hipSuccess || nb < 1)
+    nb = 4;
+  return nb;
+}
+
 hipError_t launch_iteration(const IterArgs &A, hipStream_t s, hipEvent_t *ev) {
   const dim3 G(A.grid), B(kBlock), W1(1024);
   auto mark = [&](int slot, int end) { if (ev) (void)hipEventRecord(ev[2 * slot + end], s); };
@@ -944,7 +929,8 @@ hipError_t launch_iteration(const IterArgs &A, hipStream_t s, hipEvent_t *ev) {
   GS_LAUNCH(KS_NZ_WRITE, k_nz_write, G, B);
   GS_LAUNCH(KS_EXPAND_COUNT, k_expand_count, G, B);
   GS_LAUNCH(KS_SCAN_EXPAND, k_scan_expand, dim3(1), W1);
-  GS_LAUNCH(KS_EXPAND_WRITE, k_expand_write, G, B);
+  GS_LAUNCH(KS_TILE_OFFSETS, k_tile_offsets, G, B);
+  GS_LAUNCH(KS_EXPAND_WRITE, k_expand_write, dim3((unsigned)A.wgrid), B);
 #undef GS_LAUNCH
   return hipGetLastError();
 }

@@ -16,6 +16,7 @@ struct IterArgs {
   int32_t nclear;          // bitmaps to zero
   int32_t has_list;        // any LIST step among the entries
   int32_t grid;            // workgroups of the fixed-grid kernels
+  int32_t wgrid;           // workgroups of the write pass (as many as are resident at once)
   const DStep *steps;
   const uint64_t *const *filt;
   const DCheck *checks;
@@ -36,6 +37,9 @@ struct IterArgs {
   char *tree_base;
   int64_t *blk_a, *blk_b, *blk_off_a, *blk_off_b;   // grid entries each
 };
+
+// Workgroups of the write pass one compute unit holds at once.
+int expand_write_blocks_per_cu();
 
 // ev: null, or 2 * KS_N events recorded around each launch (slot k: ev[2k], ev[2k+1]).
 hipError_t launch_iteration(const IterArgs &A, hipStream_t s, hipEvent_t *ev = nullptr);
