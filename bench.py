@@ -138,6 +138,125 @@ def serve_leg(gs, eng, qset, rates, seconds, seed=7):
     return out
 
 
+KERNEL_SOURCES = ["query.hip", "kernels_common.hpp", "gs_device.hpp", "query.hpp"]
+
+
+def kernel_source_hash():
+    """SHA-1 over the expansion kernels' sources: a traffic figure taken from
+    hardware counters holds only for the sources it was measured on."""
+    import hashlib
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2106_14038_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed counter summary of this
+    workload (FETCH_SIZE + WRITE_SIZE, each scaled by a plain copy's reading);
+    None when there is none or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith(" "):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source_sha1") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_probe(gib=1):
+    """A plain device copy of known size (read gib GiB, write gib GiB), five times:
+    the reference reading for the HBM byte counters."""
+    import torch
+    n = (gib << 30) // 4
+    src = torch.ones(n, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        torch.mul(src, 1, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "launches": 5}), flush=True)
+
+
+def _find(d, suffix):
+    out = []
+    for root, _, files in os.walk(d):
+        out += [os.path.join(root, f) for f in files if f.endswith(suffix)]
+    if not out:
+        raise SystemExit(f"no *{suffix} under {d}")
+    return sorted(out)
+
+
+def summarize_rocprof(args):
+    """Short text summaries of rocprofv3 output for profiles/ (kernel statistics,
+    or per-kernel HBM counters scaled by the copy probe's reading)."""
+    import csv
+    lines = [f"command: {args.command}"] if args.command else []
+    if args.summarize == "trace":
+        rows = []
+        for p in _find(args.dir, "kernel_stats.csv"):
+            with open(p) as f:
+                rows += list(csv.DictReader(f))
+        rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+        lines.append(f"{'kernel':60s} {'calls':>7s} {'total_ms':>10s} {'avg_us':>10s} {'pct':>6s}")
+        for r in rows[:24]:
+            name = r["Name"].split("(")[0][:60]
+            lines.append(f"{name:60s} {int(r['Calls']):7d} {float(r['TotalDurationNs']) / 1e6:10.3f} "
+                         f"{float(r['AverageNs']) / 1e3:10.2f} {float(r['Percentage']):6.2f}")
+    else:
+        def per_kernel(d):
+            acc = {}
+            for p in _find(d, "counter_collection.csv"):
+                with open(p) as f:
+                    for r in csv.DictReader(f):
+                        name = r["Kernel_Name"].split("(")[0]
+                        a = acc.setdefault((name, r["Counter_Name"]), {})
+                        a[r["Dispatch_Id"]] = a.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
+            return {k: (sum(v.values()) / len(v), len(v)) for k, v in acc.items()}
+        fetch, write = per_kernel(args.fetch_dir), per_kernel(args.write_dir)
+        cfetch, cwrite = per_kernel(args.copy_fetch_dir), per_kernel(args.copy_write_dir)
+        def pick(tab, counter, sub):
+            hits = [(k, v) for k, v in tab.items() if k[1] == counter and sub in k[0]]
+            if not hits:
+                raise SystemExit(f"no {counter} for a kernel named like {sub}")
+            return max(hits, key=lambda kv: kv[1][0])
+        copy_bytes = float(1 << 30)
+        (_, (cf, _)), (_, (cw, _)) = pick(cfetch, "FETCH_SIZE", ""), pick(cwrite, "WRITE_SIZE", "")
+        f_fetch, f_write = copy_bytes / (cf * 1024.0), copy_bytes / (cw * 1024.0)
+        (kn, (kf, nd)), (_, (kw, _)) = pick(fetch, "FETCH_SIZE", args.kernel), pick(write, "WRITE_SIZE", args.kernel)
+        hbm = kf * 1024.0 * f_fetch + kw * 1024.0 * f_write
+        lines += [f"kernel: {kn}",
+                  f"dispatches: {nd}",
+                  f"fetch_kib_per_launch: {kf:.1f}",
+                  f"write_kib_per_launch: {kw:.1f}",
+                  f"copy_probe_fetch_kib: {cf:.1f}",
+                  f"copy_probe_write_kib: {cw:.1f}",
+                  f"fetch_scale: {f_fetch:.4f}",
+                  f"write_scale: {f_write:.4f}",
+                  f"hbm_bytes_per_launch: {hbm:.0f}"]
+        if args.bench_json:
+            with open(args.bench_json) as f:
+                b = json.loads([ln for ln in f if ln.startswith("{")][-1])
+            alg = b["roofline"].get("alg_bytes_per_launch")
+            if alg:
+                lines.append(f"alg_bytes_per_launch: {alg:.0f}")
+                lines.append(f"hbm_over_alg: {hbm / alg:.3f}")
+        lines.append(f"source_sha1: {kernel_source_hash()}")
+    text = "\n".join(lines) + "\n"
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(text)
+    print(text, end="")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -150,11 +269,29 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--no-graphs", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true", help="run the HBM counter reference copy and exit")
+    ap.add_argument("--summarize", choices=["trace", "traffic"], help="summarise rocprofv3 output and exit")
+    ap.add_argument("--dir")
+    ap.add_argument("--fetch-dir")
+    ap.add_argument("--write-dir")
+    ap.add_argument("--copy-fetch-dir")
+    ap.add_argument("--copy-write-dir")
+    ap.add_argument("--kernel", default="k_expand_write")
+    ap.add_argument("--bench-json")
+    ap.add_argument("--command", default="")
+    ap.add_argument("--out")
     args = ap.parse_args()
+    if args.summarize:
+        summarize_rocprof(args)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for {args.gpus})",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_probe:
+        copy_probe()
+        return
 
     import torch
     import paper_2106_14038_amd as gs
@@ -205,7 +342,9 @@ def main():
     name, k = dom
     achieved = k["bytes_alg"] / (k["ms"] / 1e3) / 1e9 if k["ms"] > 0 and k["bytes_alg"] > 0 else None
     roofline = {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
+                "frac": achieved / HBM_PEAK_GBS if achieved else None,
+                "traffic": measured_traffic(name, args.workload),
+                "alg_bytes_per_launch": k["bytes_alg"] / max(k["launches"], 1),
                 "avg_launch_ms": k["ms"] / max(k["launches"], 1), "launches": k["launches"]}
     kernels = {n: {"ms_per_step": v["ms"] / args.steps, "launches_per_step": v["launches"] / args.steps,
                    "GBps": (v["bytes_alg"] / (v["ms"] / 1e3) / 1e9) if v["ms"] > 0 and v["bytes_alg"] > 0 else None}

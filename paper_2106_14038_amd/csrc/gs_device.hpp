@@ -9,7 +9,7 @@ namespace gs {
 constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
 constexpr int kWaves = kBlock / 64;
 constexpr int kTileNodes = 1024;     // tree nodes per tile (lookup, frontier, nz pass)
-constexpr int kTileWork = 1024;      // candidate entries per tile (expansion)
+constexpr int kTileWork = 256;       // candidate entries per tile (expansion; one wave's work)
 constexpr int kTileWords = 256;      // bitmap words per tile (lists, domains)
 constexpr int kMaxLevels = 64;
 
@@ -83,7 +83,11 @@ struct EState {
   int64_t list_tile0;
   int64_t list_n, list_base;
   int32_t *list;
+  const int32_t *copies; // write pass: previous-level columns copied into the new level
+  int32_t ncopy;
+  int32_t wflags;        // write pass: EW_FREE | EW_LIST
 };
+enum { EW_FREE = 1, EW_LIST = 2 };
 
 // One work tile of the expansion (kTileWork consecutive candidate entries of
 // one entry), written by the non-empty-node pass for the node its first entry

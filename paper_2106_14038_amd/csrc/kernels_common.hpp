@@ -21,6 +21,16 @@ template <class T>
 __device__ __forceinline__ T gld(const T *p) {
   return *(const __attribute__((address_space(1))) T *)p;
 }
+// Wave-uniform load through the scalar cache (constant address space): only for
+// data no wave writes while the kernel runs.
+template <class T>
+__device__ __forceinline__ T sld(const T *p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return *(const __attribute__((address_space(4))) T *)p;
+#else
+  return *p;   // host pass: never executed
+#endif
+}
 template <class T>
 __device__ __forceinline__ void gst(T *p, T v) {
   *(__attribute__((address_space(1))) T *)p = v;

@@ -519,6 +519,7 @@ __global__ __launch_bounds__(1024) void k_scan_nodes(const IterArgs A) {
 
 __global__ __launch_bounds__(kBlock) void k_nz_write(const IterArgs A) {
   __shared__ int64_t lds[kWaves];
+  __shared__ int64_t s_woff[kBlock];   // entry-local first entry of the round's non-empty nodes
   __shared__ int ldi[kWaves];
   __shared__ int sh_e;
   IterScalars *it = A.it;
@@ -548,19 +549,30 @@ __global__ __launch_bounds__(kBlock) void k_nz_write(const IterArgs A) {
         it->nz_node[k] = (int32_t)i;
         it->nz_lo[k] = lo;
         it->nz_woff[k] = woff;
-        // the tiles whose first entry falls in this node
-        for (int64_t j = ceil_div(woff, kTileWork); j * kTileWork < woff + len; ++j) {
-          DTile d;
-          d.k0 = k;
-          d.a = j * kTileWork;
-          d.out = 0;
-          d.e = e;
-          d.n = (int32_t)min((int64_t)kTileWork, ew - d.a);
-          d.cnt = 0;
-          d.pad = 0;
-          it->tiles[etile0 + j] = d;
-        }
+        s_woff[pos] = woff;
       }
+      __syncthreads();
+      // the tiles whose first entry lies among this round's entries [r0, r0 + wtot):
+      // each takes the last of the round's nodes starting at or before it
+      const int64_t r0 = run_w - es[e].w_base;
+      for (int64_t j = ceil_div(r0, kTileWork) + threadIdx.x; j * kTileWork < r0 + wtot; j += blockDim.x) {
+        const int64_t a = j * kTileWork;
+        int lo_k = 0, hi_k = ftot - 1;   // s_woff[0] == r0 <= a
+        while (lo_k < hi_k) {
+          const int mid = (lo_k + hi_k + 1) >> 1;
+          if (s_woff[mid] <= a) lo_k = mid; else hi_k = mid - 1;
+        }
+        DTile d;
+        d.k0 = run_nz + lo_k;
+        d.a = a;
+        d.out = 0;
+        d.e = e;
+        d.n = (int32_t)min((int64_t)kTileWork, ew - a);
+        d.cnt = 0;
+        d.pad = 0;
+        it->tiles[etile0 + j] = d;
+      }
+      __syncthreads();   // s_woff is refilled by the next round
       run_nz += ftot;
       run_w += wtot;
     }
@@ -568,76 +580,103 @@ __global__ __launch_bounds__(kBlock) void k_nz_write(const IterArgs A) {
 }
 
 // ------------------------------------------------------------------ expansion
+// Expansion tiles are taken by single waves: each wave stages its tile's nodes
+// in its own LDS region and maps items to nodes with wave-wide scans, so no
+// workgroup barrier couples the waves of a workgroup.
+constexpr int kItemsPerLane = kTileWork / 64;
+
+// Orders the calling wave's LDS accesses (LDS operations of one wave complete
+// in order; this keeps the compiler from moving them across).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
 // Staged nodes of one tile. Node i of the tile is non-empty node tiles[t].k0 + i;
 // item p (entry a + p) belongs to node kmap[p] and reads entry base[i] + p of
 // that node's segment (or list).
-struct TileNz {
+struct WaveTile {
   int64_t base[kTileWork + 2];  // segment start minus the node's first item position in the tile
   int32_t node[kTileWork + 2];  // local node index in the previous level
   uint8_t dg[kTileWork + 2];    // orientation | generator << 1 (see seg_ref)
   uint16_t kmap[kTileWork];     // item -> node; all zero between tiles
-  int32_t wmax[kWaves];
-  int32_t wscat[kWaves];
-  int32_t e, n;
-  int64_t a, out;
 };
 
-// Stage tile t: its nodes, and the item -> node map (a max-scan of node starts).
-// On return kmap holds the map; the item pass reads each entry once and clears it.
-__device__ __forceinline__ void load_tile(const IterArgs &A, int64_t t, TileNz &T) {
-  IterScalars *it = A.it;
-  const DTile d = it->tiles[t], dn = it->tiles[t + 1];
-  // nodes k0 .. the node holding the next tile's first entry (when it is the same entry's)
-  const int nwin = (int)(dn.k0 - d.k0 + (dn.e == d.e ? 1 : 0));
-  int scat = 0;
-  for (int i = threadIdx.x; i < nwin; i += blockDim.x) {
-    const int64_t k = d.k0 + i;
-    const int64_t s = gld(it->nz_woff + k) - d.a;   // first item of the node, relative to the tile
-    const int64_t r = gld(it->nz_lo + k);
-    T.base[i] = ref_lo(r) - s;
-    T.dg[i] = (uint8_t)(ref_dir(r) | (ref_gen(r) << 1));
-    T.node[i] = gld(it->nz_node + k);
-    if (i > 0 && s < d.n) { T.kmap[s] = (uint16_t)i; scat = 1; }
+// The first 64 nodes of a tile's window, one per lane (loaded ahead of staging).
+struct WinSlot {
+  int64_t woff = 0, lo = 0;
+  int32_t node = 0;
+};
+
+// Nodes k0 .. the node holding the next tile's first entry (when it is the same entry's).
+__device__ __forceinline__ int win_nodes(const DTile &d, const DTile &dn) {
+  return (int)(dn.k0 - d.k0 + (dn.e == d.e ? 1 : 0));
+}
+
+__device__ __forceinline__ WinSlot load_slot(const IterScalars *it, const DTile &d, int nwin) {
+  WinSlot w;
+  const int lane = threadIdx.x & 63;
+  if (lane < nwin) {
+    const int64_t k = d.k0 + lane;
+    w.woff = gld(it->nz_woff + k);
+    w.lo = gld(it->nz_lo + k);
+    w.node = gld(it->nz_node + k);
   }
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const uint64_t sb = __ballot(scat);
-  if (lane == 0) T.wscat[wv] = sb != 0;
-  if (threadIdx.x == 0) { T.e = d.e; T.n = d.n; T.a = d.a; T.out = d.out; }
-  lds_sync();
-  int any = 0;
-  for (int i = 0; i < kWaves; ++i) any |= T.wscat[i];
-  if (!any) return;   // one node covers the whole tile: the map stays zero
+  return w;
+}
+
+// Stage tile d (dn: the record after it; s0: its first window slot) into the
+// calling wave's region. On return kmap holds the item -> node map (a
+// max-scan of node starts); the item pass reads each entry once and clears it.
+__device__ __forceinline__ void stage_tile(const IterScalars *it, const DTile &d, int nwin, const WinSlot &s0,
+                                           WaveTile &W) {
+  const int lane = threadIdx.x & 63;
+  bool scat = false;
+  for (int i = lane; i < nwin; i += 64) {
+    const int64_t k = d.k0 + i;
+    int64_t woff, r;
+    int32_t nd;
+    if (i < 64) {
+      woff = s0.woff; r = s0.lo; nd = s0.node;
+    } else {
+      woff = gld(it->nz_woff + k); r = gld(it->nz_lo + k); nd = gld(it->nz_node + k);
+    }
+    const int64_t s = woff - d.a;   // first item of the node, relative to the tile
+    W.base[i] = ref_lo(r) - s;
+    W.dg[i] = (uint8_t)(ref_dir(r) | (ref_gen(r) << 1));
+    W.node[i] = nd;
+    if (i > 0 && s < d.n) { W.kmap[s] = (uint16_t)i; scat = true; }
+  }
+  wave_lds_sync();
+  if (__ballot(scat) == 0) return;   // one node covers the whole tile: the map stays zero
   // forward fill: each item takes the last node start at or before it (node starts ascend)
-  constexpr int per = kTileWork / kBlock;
-  int v[per];
+  int v[kItemsPerLane];
   int mx = 0;
-  for (int i = 0; i < per; ++i) { mx = max(mx, (int)T.kmap[threadIdx.x * per + i]); v[i] = mx; }
+  for (int i = 0; i < kItemsPerLane; ++i) { mx = max(mx, (int)W.kmap[lane * kItemsPerLane + i]); v[i] = mx; }
   int incl = mx;
   for (int off = 1; off < 64; off <<= 1) {
     const int u = __shfl_up(incl, off, 64);
     if (lane >= off) incl = max(incl, u);
   }
-  if (lane == 63) T.wmax[wv] = incl;
-  lds_sync();
   int pre = __shfl_up(incl, 1, 64);
   if (lane == 0) pre = 0;
-  for (int i = 0; i < wv; ++i) pre = max(pre, T.wmax[i]);
-  for (int i = 0; i < per; ++i) T.kmap[threadIdx.x * per + i] = (uint16_t)max(pre, v[i]);
-  lds_sync();
+  for (int i = 0; i < kItemsPerLane; ++i) W.kmap[lane * kItemsPerLane + i] = (uint16_t)max(pre, v[i]);
+  wave_lds_sync();
 }
 
 // Node of item p of the staged tile; clears the map entry for the next tile
-// (each entry is read by exactly one thread).
-__device__ __forceinline__ int take_node(TileNz &T, int p) {
-  const int k = T.kmap[p];
-  T.kmap[p] = 0;
+// (each entry is read by exactly one lane).
+__device__ __forceinline__ int take_node(WaveTile &W, int p) {
+  const int k = W.kmap[p];
+  W.kmap[p] = 0;
   return k;
 }
 
-__device__ __forceinline__ int32_t candidate(const IterArgs &A, const EState &E, const DStep &S, const TileNz &T,
+__device__ __forceinline__ int32_t candidate(const IterArgs &A, const EState &E, const DStep &S, const WaveTile &W,
                                              int k, int p) {
-  const int32_t *src = S.kind == STEP_LIST ? E.list : A.g.idx[T.dg[k] & 1];
-  return gld(src + T.base[k] + p);
+  const int32_t *src = S.kind == STEP_LIST ? E.list : A.g.idx[W.dg[k] & 1];
+  return gld(src + W.base[k] + p);
 }
 
 // gen: which bound segment the candidate was read from (see seg_ref); that
@@ -669,79 +708,81 @@ __device__ __forceinline__ bool test_candidate(const IterArgs &A, const EState &
 }
 
 // Count pass over the tiles of tested levels: validity bits per tile, valid
-// entries per tile, per entry and per workgroup (contiguous tile ranges).
+// entries per tile, per entry and per workgroup. A workgroup takes a
+// contiguous tile range; test-free entries in it are passed over whole, the
+// tiles of tested entries are dealt to its waves.
 __global__ __launch_bounds__(kBlock) void k_expand_count(const IterArgs A) {
-  __shared__ TileNz T;
+  __shared__ WaveTile Wt[kWaves];
   __shared__ int64_t red4[kWaves][4];
   IterScalars *it = A.it;
   if (it->abort) return;
   EState *es = A.es;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  constexpr int R = kTileWork / kBlock;
-  if (threadIdx.x < kWaves) T.wscat[threadIdx.x] = 0;
-  for (int i = threadIdx.x; i < kTileWork; i += blockDim.x) T.kmap[i] = 0;
-  lds_sync();
+  WaveTile &W = Wt[wv];
+  for (int i = lane; i < kTileWork; i += 64) W.kmap[i] = 0;
+  wave_lds_sync();
   int64_t tb, te;
   block_share(it->work_tiles, tb, te);
-  int64_t bsum = 0, b_pr = 0, b_ft = 0, b_ct = 0;
-  EntryAcc acc, qacc;                    // valid counts per entry, probes per query
-  int64_t *p_cnt = &es[0].cnt, *p_probe = A.qstats + QS_PROBE;
+  int64_t free_items = 0, w_cnt = 0, w_pr = 0, w_ft = 0, w_ct = 0;
   for (int64_t t = tb; t < te;) {
     const int e = uniform(gld(&it->tiles[t].e));
     const EState E = es[e];
     const DEntry d = A.ent[e];
     const DStep S = A.steps[d.step];
+    const int64_t t_end = min(te, E.w_tile0 + ceil_div(E.w, kTileWork));
     if (test_free(S)) {   // every candidate is a child: the entry's count was set by the node scan
-      const int64_t t_end = min(te, E.w_tile0 + ceil_div(E.w, kTileWork));
-      bsum += min((t_end - E.w_tile0) * kTileWork, E.w) - (t - E.w_tile0) * kTileWork;
+      free_items += min((t_end - E.w_tile0) * kTileWork, E.w) - (t - E.w_tile0) * kTileWork;
       t = t_end;
       continue;
     }
-    load_tile(A, t, T);
-    int64_t c_tile = 0;
-    int probes = 0, ftests = 0, ctests = 0;
-    for (int r = 0; r < R; ++r) {
-      const int p = r * kBlock + threadIdx.x;
-      const int k = take_node(T, p);
-      bool ok = false;
-      if (p < T.n) {
-        const int32_t c = candidate(A, E, S, T, k, p);
-        ok = test_candidate(A, E, S, T.node[k], T.dg[k] >> 1, c, probes, ftests, ctests);
+    int64_t e_cnt = 0;
+    int pr = 0, ft = 0, ct = 0;
+    for (int64_t u = t + wv; u < t_end; u += kWaves) {
+      const DTile dt = it->tiles[u], dn = it->tiles[u + 1];
+      const int nwin = win_nodes(dt, dn);
+      stage_tile(it, dt, nwin, load_slot(it, dt, nwin), W);
+      uint64_t bal[kItemsPerLane];
+      int c_tile = 0;
+      for (int r = 0; r < kItemsPerLane; ++r) {
+        const int p = r * 64 + lane;
+        const int k = take_node(W, p);
+        bool ok = false;
+        if (p < dt.n) {
+          const int32_t c = candidate(A, E, S, W, k, p);
+          ok = test_candidate(A, E, S, W.node[k], W.dg[k] >> 1, c, pr, ft, ct);
+        }
+        bal[r] = __ballot(ok);
+        c_tile += __popcll(bal[r]);
       }
-      const uint64_t bal = __ballot(ok);
+      wave_lds_sync();
       if (lane == 0) {
-        uint32_t *vw = it->valid + t * (kTileWork / 32) + (r * kBlock + wv * 64) / 32;
-        gst(vw, (uint32_t)bal);
-        gst(vw + 1, (uint32_t)(bal >> 32));
+        uint64_t *vw = (uint64_t *)(it->valid + u * (kTileWork / 32));
+        for (int r = 0; r < kItemsPerLane; ++r) gst(vw + r, bal[r]);
+        it->tiles[u].cnt = c_tile;
       }
-      c_tile += ok;
+      e_cnt += c_tile;
     }
-    // one reduction for the four tile counters
-    int64_t v4[4] = {c_tile, probes, ftests, ctests};
-    for (int i = 0; i < 4; ++i) v4[i] = wave_sum_i64(v4[i]);
-    if (lane == 0) for (int i = 0; i < 4; ++i) red4[wv][i] = v4[i];
-    lds_sync();
-    for (int i = 0; i < 4; ++i) { v4[i] = 0; for (int w2 = 0; w2 < kWaves; ++w2) v4[i] += red4[w2][i]; }
-    c_tile = v4[0];
-    if (threadIdx.x == 0) {
-      it->tiles[t].cnt = (int32_t)c_tile;
-      acc.add(e, c_tile, 0, p_cnt, nullptr, kEsStride);
-      qacc.add(d.q, v4[1], 0, p_probe, nullptr, QS_N);
+    // this wave's share of the entry and of its query's probes
+    const int64_t epr = wave_sum_i64(pr), eft = wave_sum_i64(ft), ect = wave_sum_i64(ct);
+    if (lane == 0) {
+      if (e_cnt) atomicAdd((unsigned long long *)&es[e].cnt, (unsigned long long)e_cnt);
+      if (epr) atomicAdd((unsigned long long *)&A.qstats[(int64_t)d.q * QS_N + QS_PROBE], (unsigned long long)epr);
     }
-    b_pr += v4[1];
-    b_ft += v4[2];
-    b_ct += v4[3];
-    bsum += c_tile;
-    lds_sync();
-    ++t;
+    w_cnt += e_cnt;
+    w_pr += epr;
+    w_ft += eft;
+    w_ct += ect;
+    t = t_end;
   }
+  if (lane == 0) { red4[wv][0] = w_cnt; red4[wv][1] = w_pr; red4[wv][2] = w_ft; red4[wv][3] = w_ct; }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    acc.flush(p_cnt, nullptr, kEsStride);
-    qacc.flush(p_probe, nullptr, QS_N);
-    if (b_pr) atomicAdd((unsigned long long *)&it->probes, (unsigned long long)b_pr);
-    if (b_ft) atomicAdd((unsigned long long *)&it->ftests, (unsigned long long)b_ft);
-    if (b_ct) atomicAdd((unsigned long long *)&it->ctests, (unsigned long long)b_ct);
-    A.blk_a[blockIdx.x] = bsum;
+    int64_t v4[4] = {0, 0, 0, 0};
+    for (int i = 0; i < 4; ++i) for (int w2 = 0; w2 < kWaves; ++w2) v4[i] += red4[w2][i];
+    if (v4[1]) atomicAdd((unsigned long long *)&it->probes, (unsigned long long)v4[1]);
+    if (v4[2]) atomicAdd((unsigned long long *)&it->ftests, (unsigned long long)v4[2]);
+    if (v4[3]) atomicAdd((unsigned long long *)&it->ctests, (unsigned long long)v4[3]);
+    A.blk_a[blockIdx.x] = v4[0] + free_items;
   }
 }
 
@@ -773,6 +814,9 @@ __global__ __launch_bounds__(1024) void k_scan_expand(const IterArgs A) {
       A.qstats[(int64_t)d.q * QS_N + QS_OVERFLOW] = 2;
     }
     es[e].out = out;
+    es[e].copies = A.ints + S.copy0;
+    es[e].ncopy = S.ncopy;
+    es[e].wflags = (test_free(S) ? EW_FREE : 0) | (S.kind == STEP_LIST ? EW_LIST : 0);
     A.lvl_ptr[(int64_t)d.q * kMaxLevels + d.level] = out;
     A.lvl_n[(int64_t)d.q * kMaxLevels + d.level] = n_rec;
   }
@@ -804,76 +848,95 @@ __global__ __launch_bounds__(kBlock) void k_tile_offsets(const IterArgs A) {
   }
 }
 
-// Write pass: tiles dealt round-robin to a grid of resident workgroups (tiles
-// are independent; neighbours run side by side). Every item's output position is
-// ranked first (tile offset + item for test-free levels, + rank among the valid
-// items otherwise); then each thread reads the nodes and candidates of all its
-// items before it issues their stores, so that its loads overlap.
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_expand_write(const IterArgs A) {
-  __shared__ TileNz T;
-  __shared__ int wcnt[kTileWork / 64];   // valid items per (round, wave) of the tile
-  IterScalars *it = A.it;
-  if (it->abort) return;
-  EState *es = A.es;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  constexpr int R = kTileWork / kBlock;
-  if (threadIdx.x < kWaves) T.wscat[threadIdx.x] = 0;
-  for (int i = threadIdx.x; i < kTileWork; i += blockDim.x) T.kmap[i] = 0;
-  lds_sync();
-  const int64_t ntiles = it->work_tiles;
-  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    load_tile(A, t, T);
-    const int e = uniform(T.e);
-    const EState E = es[e];
-    const DStep S = A.steps[A.ent[e].step];
-    const int64_t out0 = T.out;
+// Write pass: tiles dealt round-robin to the waves of a grid of resident
+// workgroups (tiles are independent; neighbours run side by side). A wave
+// loads its tile records two tiles ahead and the node window one tile ahead,
+// so that one round trip to memory (the candidates) remains per tile. Every
+// item's output position is ranked first (tile offset + item for test-free
+// levels, + rank among the valid items otherwise); then each lane reads the
+// nodes and candidates of all its items before it issues their stores.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_expand_write(const IterArgs A) {
+  __shared__ WaveTile Wt[kWaves];
+  const IterScalars *it = A.it;
+  if (sld(&it->abort)) return;
+  const EState *es = A.es;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  constexpr int R = kItemsPerLane;
+  WaveTile &W = Wt[wv];
+  for (int i = lane; i < kTileWork; i += 64) W.kmap[i] = 0;
+  wave_lds_sync();
+  const DTile *tiles = sld(&it->tiles);
+  const uint32_t *valid = sld(&it->valid);
+  const int64_t ntiles = sld(&it->work_tiles), stride = (int64_t)gridDim.x * kWaves;
+  int64_t t = (int64_t)blockIdx.x * kWaves + wv;
+  if (t >= ntiles) return;
+  DTile d1 = sld(tiles + t), d1n = sld(tiles + t + 1), d2{}, d2n{};
+  int nw1 = win_nodes(d1, d1n);
+  WinSlot s1 = load_slot(it, d1, nw1);
+  if (t + stride < ntiles) { d2 = sld(tiles + t + stride); d2n = sld(tiles + t + stride + 1); }
+  for (; t < ntiles; t += stride) {
+    stage_tile(it, d1, nw1, s1, W);
+    const int e = d1.e;
+    const int64_t out0 = d1.out;
+    const int n = d1.n;
+    // next tile: its window loads now (its records arrived during the previous tile), the one after: its records
+    const int64_t tn = t + stride;
+    if (tn < ntiles) {
+      d1 = d2; d1n = d2n;
+      nw1 = win_nodes(d1, d1n);
+      s1 = load_slot(it, d1, nw1);
+      if (tn + stride < ntiles) { d2 = sld(tiles + tn + stride); d2n = sld(tiles + tn + stride + 1); }
+    }
+    int32_t *out = sld(&es[e].out);
+    const int32_t wflags = sld(&es[e].wflags);
     int kk[R];
-    for (int r = 0; r < R; ++r) kk[r] = take_node(T, r * kBlock + threadIdx.x);
+    for (int r = 0; r < R; ++r) kk[r] = take_node(W, r * 64 + lane);
     int64_t li[R];   // output position of each item, -1: not a child
-    if (test_free(S)) {
+    if (wflags & EW_FREE) {
       for (int r = 0; r < R; ++r) {
-        const int p = r * kBlock + threadIdx.x;
-        li[r] = p < T.n ? out0 + p : -1;
+        const int p = r * 64 + lane;
+        li[r] = p < n ? out0 + p : -1;
       }
     } else {
-      // rank the valid items of the whole tile with one barrier: per (round, wave) counts
-      uint64_t bal[R];
+      const uint64_t *vw = (const uint64_t *)(valid + t * (kTileWork / 32));
+      int64_t before = out0;
       for (int r = 0; r < R; ++r) {
-        const uint32_t *vw = it->valid + t * (kTileWork / 32) + (r * kBlock + wv * 64) / 32;
-        bal[r] = (uint64_t)gld(vw) | ((uint64_t)gld(vw + 1) << 32);
-        if (lane == 0) wcnt[r * kWaves + wv] = __popcll(bal[r]);
-      }
-      lds_sync();
-      int before = 0;
-      for (int r = 0; r < R; ++r) {
-        int pre = before;
-        for (int w2 = 0; w2 < wv; ++w2) pre += wcnt[r * kWaves + w2];
-        li[r] = ((bal[r] >> lane) & 1ull) ? out0 + pre + __popcll(bal[r] & lanemask_lt()) : -1;
-        for (int w2 = 0; w2 < kWaves; ++w2) before += wcnt[r * kWaves + w2];
+        const uint64_t bal = gld(vw + r);
+        li[r] = ((bal >> lane) & 1ull) ? before + __popcll(bal & lanemask_lt()) : -1;
+        before += __popcll(bal);
       }
     }
-    if (E.out) {
-      const int64_t cnt = E.cnt;
+    if (out) {
+      const int64_t cnt = sld(&es[e].cnt);
+      const int32_t *list = sld(&es[e].list);
       int32_t node[R], c[R];
       for (int r = 0; r < R; ++r) {
         node[r] = 0;
         c[r] = 0;
         if (li[r] >= 0) {
-          node[r] = T.node[kk[r]];
-          c[r] = candidate(A, E, S, T, kk[r], r * kBlock + threadIdx.x);
+          const int k = kk[r];
+          node[r] = W.node[k];
+          const int32_t *src = (wflags & EW_LIST) ? list : A.g.idx[W.dg[k] & 1];
+          c[r] = gld(src + W.base[k] + r * 64 + lane);
         }
       }
       for (int r = 0; r < R; ++r)
-        if (li[r] >= 0) { gst(E.out + li[r], node[r]); gst(E.out + cnt + li[r], c[r]); }
-      for (int j = 0; j < S.ncopy; ++j) {
-        const int32_t *col = E.prev + (int64_t)A.ints[S.copy0 + j] * E.prev_n;
-        int32_t v[R];
-        for (int r = 0; r < R; ++r) v[r] = li[r] >= 0 ? gld(col + node[r]) : 0;
-        for (int r = 0; r < R; ++r)
-          if (li[r] >= 0) gst(E.out + (int64_t)(2 + j) * cnt + li[r], v[r]);
+        if (li[r] >= 0) { gst(out + li[r], node[r]); gst(out + cnt + li[r], c[r]); }
+      const int ncopy = sld(&es[e].ncopy);
+      if (ncopy) {
+        const int32_t *prev = sld(&es[e].prev), *copies = sld(&es[e].copies);
+        const int64_t prev_n = sld(&es[e].prev_n);
+        for (int j = 0; j < ncopy; ++j) {
+          const int32_t *col = prev + (int64_t)sld(copies + j) * prev_n;
+          int32_t v[R];
+          for (int r = 0; r < R; ++r) v[r] = li[r] >= 0 ? gld(col + node[r]) : 0;
+          for (int r = 0; r < R; ++r)
+            if (li[r] >= 0) gst(out + (int64_t)(2 + j) * cnt + li[r], v[r]);
+        }
       }
     }
-    lds_sync();
+    wave_lds_sync();
   }
 }
 
