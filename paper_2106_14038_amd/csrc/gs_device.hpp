@@ -9,7 +9,7 @@ namespace gs {
 constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
 constexpr int kWaves = kBlock / 64;
 constexpr int kTileNodes = 1024;     // tree nodes per tile (lookup, frontier, nz pass)
-constexpr int kTileWork = 256;       // candidate entries per tile (expansion; one wave's work)
+constexpr int kTileWork = 512;       // candidate entries per tile (expansion; one wave's work)
 constexpr int kTileWords = 256;      // bitmap words per tile (lists, domains)
 constexpr int kMaxLevels = 64;
 

@@ -157,8 +157,11 @@ __device__ __forceinline__ int64_t lower_bound_u16(const uint16_t *a, int64_t lo
 // Entries of vertex b with label `label` in orientation dir: [lo, hi).
 __device__ __forceinline__ void seg_find(const DevGraph &g, int dir, int32_t b, int32_t label, int64_t &lo,
                                          int64_t &hi, int &probes) {
-  const int64_t a = gld(g.ptr[dir] + b), e = gld(g.ptr[dir] + b + 1);
-  const uint16_t *lab = g.lab[dir];
+  // selects, not indexing: dir may differ between lanes, and indexing the
+  // pointer arrays by a per-lane value loads the pointers from memory
+  const int64_t *ptr = dir ? g.ptr[1] : g.ptr[0];
+  const int64_t a = gld(ptr + b), e = gld(ptr + b + 1);
+  const uint16_t *lab = dir ? g.lab[1] : g.lab[0];
   if (e - a <= 8) {          // short rows: one linear pass
     int64_t x = a;
     while (x < e && gld(lab + x) < (uint32_t)label) ++x;
@@ -177,7 +180,7 @@ __device__ __forceinline__ bool seg_has(const DevGraph &g, int dir, int32_t b, i
                                         int &probes) {
   int64_t lo, hi;
   seg_find(g, dir, b, label, lo, hi, probes);
-  const int32_t *idx = g.idx[dir];
+  const int32_t *idx = dir ? g.idx[1] : g.idx[0];
   int64_t x = lo, y = hi;
   while (x < y) {
     int64_t mid = (x + y) >> 1;
@@ -185,6 +188,13 @@ __device__ __forceinline__ bool seg_has(const DevGraph &g, int dir, int32_t b, i
     if (gld(idx + mid) < c) x = mid + 1; else y = mid;
   }
   return x < hi && gld(idx + x) == c;
+}
+
+// Store that is not kept in the caches (tree levels are written once and read
+// back by a later kernel, from HBM).
+template <class T>
+__device__ __forceinline__ void gst_stream(T *p, T v) {
+  __builtin_nontemporal_store(v, p);
 }
 
 __device__ __forceinline__ bool bit_test(const uint64_t *bm, int32_t c) {

@@ -673,9 +673,16 @@ __device__ __forceinline__ int take_node(WaveTile &W, int p) {
   return k;
 }
 
+// The orientation bit of a node selects between the two id arrays with a
+// select (indexing A.g.idx by a per-lane value would load the pointer from
+// memory for every item).
+__device__ __forceinline__ const int32_t *seg_ids(const IterArgs &A, int dg) {
+  return (dg & 1) ? A.g.idx[1] : A.g.idx[0];
+}
+
 __device__ __forceinline__ int32_t candidate(const IterArgs &A, const EState &E, const DStep &S, const WaveTile &W,
                                              int k, int p) {
-  const int32_t *src = S.kind == STEP_LIST ? E.list : A.g.idx[W.dg[k] & 1];
+  const int32_t *src = S.kind == STEP_LIST ? E.list : seg_ids(A, W.dg[k]);
   return gld(src + W.base[k] + p);
 }
 
@@ -917,12 +924,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
         if (li[r] >= 0) {
           const int k = kk[r];
           node[r] = W.node[k];
-          const int32_t *src = (wflags & EW_LIST) ? list : A.g.idx[W.dg[k] & 1];
+          const int32_t *src = (wflags & EW_LIST) ? list : seg_ids(A, W.dg[k]);
           c[r] = gld(src + W.base[k] + r * 64 + lane);
         }
       }
       for (int r = 0; r < R; ++r)
-        if (li[r] >= 0) { gst(out + li[r], node[r]); gst(out + cnt + li[r], c[r]); }
+        if (li[r] >= 0) { gst_stream(out + li[r], node[r]); gst_stream(out + cnt + li[r], c[r]); }
       const int ncopy = sld(&es[e].ncopy);
       if (ncopy) {
         const int32_t *prev = sld(&es[e].prev), *copies = sld(&es[e].copies);
@@ -932,7 +939,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
           int32_t v[R];
           for (int r = 0; r < R; ++r) v[r] = li[r] >= 0 ? gld(col + node[r]) : 0;
           for (int r = 0; r < R; ++r)
-            if (li[r] >= 0) gst(out + (int64_t)(2 + j) * cnt + li[r], v[r]);
+            if (li[r] >= 0) gst_stream(out + (int64_t)(2 + j) * cnt + li[r], v[r]);
         }
       }
     }
