@@ -403,7 +403,15 @@ gs_status gs_result_level(gs_result *result, int32_t level, int32_t *par, int32_
   std::lock_guard<std::mutex> lk(R.eng->mu);
   HIPRET(hipSetDevice(R.eng->device));
   const int64_t cnt = R.lvl_n[level];
-  if (par) HIPRET(hipMemcpy(par, R.lvl_ptr[level], 4 * cnt, hipMemcpyDeviceToHost));
+  if (par && R.lvl_cptr[level]) {   // a level stored as child offsets per parent: expand them
+    const int64_t pn = level ? R.lvl_n[level - 1] : 1;
+    std::vector<int32_t> off((size_t)pn + 1);
+    HIPRET(hipMemcpy(off.data(), R.lvl_cptr[level], 4 * (pn + 1), hipMemcpyDeviceToHost));
+    for (int64_t p = 0; p < pn; ++p)
+      for (int64_t i = off[p]; i < off[p + 1]; ++i) par[i] = (int32_t)p;
+  } else if (par) {
+    HIPRET(hipMemcpy(par, R.lvl_ptr[level], 4 * cnt, hipMemcpyDeviceToHost));
+  }
   if (vid) HIPRET(hipMemcpy(vid, R.lvl_ptr[level] + cnt, 4 * cnt, hipMemcpyDeviceToHost));
   return GS_OK;
 }

@@ -425,6 +425,7 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
   off = tab_off + align256(buf.size());
   // device-written tables
   const uint64_t o_lvlp = off; off += align256(sizeof(int32_t *) * kMaxLevels * (uint64_t)nq);
+  const uint64_t o_lvlc = off; off += align256(sizeof(int32_t *) * kMaxLevels * (uint64_t)nq);
   const uint64_t o_lvln = off; off += align256(sizeof(int64_t) * kMaxLevels * (uint64_t)nq);
   const uint64_t o_qs = off; off += align256(sizeof(int64_t) * QS_N * (uint64_t)nq);
   const uint64_t o_zero = off; off += align256(sizeof(int64_t) * (uint64_t)nq);
@@ -482,6 +483,7 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
     A.es = (EState *)dp(o_es);
     A.it = (IterScalars *)dp(o_it) + t;
     A.lvl_ptr = (int32_t **)dp(o_lvlp);
+    A.lvl_cptr = (int32_t **)dp(o_lvlc);
     A.lvl_n = (int64_t *)dp(o_lvln);
     A.qstats = (int64_t *)dp(o_qs);
     A.scratch = E.d_arenas + 1;
@@ -559,9 +561,10 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
 
   // 6. read back sizes and counters
   std::vector<int64_t> lvl_n((size_t)nq * kMaxLevels), qst((size_t)nq * QS_N), zero_res(nq);
-  std::vector<int32_t *> lvl_p((size_t)nq * kMaxLevels);
+  std::vector<int32_t *> lvl_p((size_t)nq * kMaxLevels), lvl_c((size_t)nq * kMaxLevels);
   HIPCHK(hipMemcpyAsync(lvl_n.data(), dp(o_lvln), 8 * lvl_n.size(), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(lvl_p.data(), dp(o_lvlp), 8 * lvl_p.size(), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(lvl_c.data(), dp(o_lvlc), 8 * lvl_c.size(), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(qst.data(), dp(o_qs), 8 * qst.size(), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(zero_res.data(), dp(o_zero), 8 * zero_res.size(), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(ar, E.d_arenas, sizeof(ar), hipMemcpyDeviceToHost, s));
@@ -580,7 +583,9 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
         if (Q[i].plan.n_vars <= t) continue;
         const DStep &d = T.steps[Q[i].step0 + t];
         const int64_t c = std::max<int64_t>(lvl_n[(size_t)i * kMaxLevels + t], 0);
-        if (d.ncols_out > 0) wbytes += (double)c * (4.0 * d.ncols_out + 4.0 * d.ncopy + 4.0);
+        // columns written + copies read + candidate read; CSR levels write no parent column
+        const int cols = d.ncols_out - (lvl_c[(size_t)i * kMaxLevels + t] ? 1 : 0);
+        if (d.ncols_out > 0) wbytes += (double)c * (4.0 * cols + 4.0 * d.ncopy + 4.0);
       }
       account_iteration(E, &E.events[(size_t)2 * KS_N * t], iv[t], its[t], wbytes);
     }
@@ -602,9 +607,10 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
     Result *R = new Result();
     R->eng = &E;
     R->run_id = run_id;
-    fill_result(*R, Q[i], count_only, &lvl_p[(size_t)i * kMaxLevels], &lvl_n[(size_t)i * kMaxLevels],
-                &qst[(size_t)i * QS_N], zero_res[i], ms);
+    fill_result(*R, Q[i], count_only, &lvl_p[(size_t)i * kMaxLevels], &lvl_c[(size_t)i * kMaxLevels],
+                &lvl_n[(size_t)i * kMaxLevels], &qst[(size_t)i * QS_N], zero_res[i], ms);
     R->d_lvl_ptr = (int32_t **)dp(o_lvlp) + (size_t)i * kMaxLevels;
+    R->d_lvl_cptr = (int32_t **)dp(o_lvlc) + (size_t)i * kMaxLevels;
     R->d_lvl_n = (int64_t *)dp(o_lvln) + (size_t)i * kMaxLevels;
     R->d_var_rank = (int32_t *)dp(tab_off + o_vr) + Q[i].vr0;
     out.push_back(R);
@@ -614,8 +620,8 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
   return GS_OK;
 }
 
-void fill_result(Result &R, const QInfo &qi, bool count_only, int32_t *const *lvl_p, const int64_t *lvl_n,
-                 const int64_t *c, int64_t zero_res, double ms) {
+void fill_result(Result &R, const QInfo &qi, bool count_only, int32_t *const *lvl_p, int32_t *const *lvl_c,
+                 const int64_t *lvl_n, const int64_t *c, int64_t zero_res, double ms) {
   const Plan &P = qi.plan;
   R.k = P.n_vars;
   R.n_vars = P.n_vars;
@@ -627,6 +633,7 @@ void fill_result(Result &R, const QInfo &qi, bool count_only, int32_t *const *lv
   } else {
     for (int j = 0; j < P.n_vars; ++j) {
       R.lvl_ptr.push_back(lvl_p[j]);
+      R.lvl_cptr.push_back(lvl_c[j]);
       R.lvl_n.push_back(lvl_n[j]);
       R.ncols_extra.push_back((int32_t)P.steps[j].carried.size());
     }
@@ -648,7 +655,11 @@ void fill_result(Result &R, const QInfo &qi, bool count_only, int32_t *const *lv
   st.domain_pull = (int32_t)c[QS_DOMPULL];
   int64_t nodes_written = 0, nodes_read = 0;
   for (int j = 0; j < R.k; ++j) {
-    const int64_t cols = (count_only && j == R.k - 1) ? 0 : 2 + (int64_t)P.steps[j].carried.size();
+    int64_t cols = (count_only && j == R.k - 1) ? 0 : 2 + (int64_t)P.steps[j].carried.size();
+    if (cols && R.lvl_cptr[j]) {   // child offsets per parent instead of a parent column
+      cols -= 1;
+      nodes_written += j ? R.lvl_n[j - 1] + 1 : 2;
+    }
     nodes_written += R.lvl_n[j] * cols;
     if (j + 1 < R.k) nodes_read += R.lvl_n[j];
   }
@@ -679,7 +690,7 @@ int result_rows(Result &R, int64_t first, int64_t n, void *dst, int mem_kind, in
   hipStream_t s = E.stream;
   const int k = R.k;
   if (mem_kind == GS_MEM_DEVICE) {
-    hipError_t e = launch_enumerate(R.d_lvl_ptr, R.d_lvl_n, k, R.d_var_rank, first, n, (int32_t *)dst, s);
+    hipError_t e = launch_enumerate(R.d_lvl_ptr, R.d_lvl_cptr, R.d_lvl_n, k, R.d_var_rank, first, n, (int32_t *)dst, s);
     if (e != hipSuccess) { set_error(hipGetErrorString(e)); return GS_EDEVICE; }
     HIPCHK(hipStreamSynchronize(s));
   } else {
@@ -688,7 +699,7 @@ int result_rows(Result &R, int64_t first, int64_t n, void *dst, int mem_kind, in
     if (!tmp) { set_error("out of device memory for rows"); return GS_ENOMEM; }
     for (int64_t r = 0; r < n; r += chunk) {
       const int64_t c = std::min(chunk, n - r);
-      hipError_t e = launch_enumerate(R.d_lvl_ptr, R.d_lvl_n, k, R.d_var_rank, first + r, c, tmp, s);
+      hipError_t e = launch_enumerate(R.d_lvl_ptr, R.d_lvl_cptr, R.d_lvl_n, k, R.d_var_rank, first + r, c, tmp, s);
       if (e == hipSuccess) e = hipMemcpyAsync((int32_t *)dst + r * k, tmp, sizeof(int32_t) * c * k, hipMemcpyDeviceToHost, s);
       if (e == hipSuccess) e = hipStreamSynchronize(s);
       if (e != hipSuccess) { E.dfree(tmp); set_error(hipGetErrorString(e)); return GS_EDEVICE; }
@@ -717,7 +728,8 @@ int result_prune(Result &R) {
   hipError_t e = hipMemsetAsync(alive, 0, (size_t)tot, s);
   if (e == hipSuccess) e = hipMemsetAsync(alive + off[k - 1], 1, (size_t)R.lvl_n[k - 1], s);
   for (int j = k - 1; j >= 1 && e == hipSuccess; --j)   // a node survives when one of its children does
-    e = launch_prune_mark(R.lvl_ptr[j], R.lvl_n[j], alive + off[j], alive + off[j - 1], s);
+    e = launch_prune_mark(R.lvl_ptr[j], R.lvl_cptr[j], R.lvl_n[j - 1], R.lvl_n[j], alive + off[j], alive + off[j - 1],
+                          s);
   std::vector<int32_t *> np(k);
   std::vector<int64_t> nn(k);
   for (int j = 0; j < k && e == hipSuccess; ++j) {
@@ -734,15 +746,19 @@ int result_prune(Result &R) {
     E.tree_top = at + bytes;
     np[j] = (int32_t *)(E.tree_base + at);
     nn[j] = cnt;
-    e = launch_prune_write(R.lvl_ptr[j], R.lvl_n[j], ncols, alive + off[j], blk + E.grid,
-                           j ? newidx + off[j - 1] : nullptr, newidx + off[j], np[j], cnt, E.grid, s);
+    e = launch_prune_write(R.lvl_ptr[j], R.lvl_cptr[j], j ? R.lvl_n[j - 1] : 1, R.lvl_n[j], ncols, alive + off[j],
+                           blk + E.grid, j ? newidx + off[j - 1] : nullptr, newidx + off[j], np[j], cnt, E.grid, s);
   }
+  // pruned levels always carry a parent column
+  const std::vector<int32_t *> nc(k, nullptr);
+  if (e == hipSuccess) e = hipMemcpyAsync(R.d_lvl_cptr, nc.data(), sizeof(void *) * k, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(R.d_lvl_ptr, np.data(), sizeof(void *) * k, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(R.d_lvl_n, nn.data(), sizeof(int64_t) * k, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   cleanup();
   if (e != hipSuccess) { set_error(hipGetErrorString(e)); return GS_EDEVICE; }
   R.lvl_ptr = np;
+  R.lvl_cptr = nc;
   R.lvl_n = nn;
   return GS_OK;
 }

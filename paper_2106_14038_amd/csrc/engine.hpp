@@ -26,10 +26,12 @@ struct Result {
   bool count_only = false;
   bool zero_vars = false;
   std::vector<int32_t *> lvl_ptr;  // device pointers per level
+  std::vector<int32_t *> lvl_cptr; // child offsets of CSR levels (device), else null
   std::vector<int64_t> lvl_n;
   std::vector<int32_t> var_rank;
   std::vector<int32_t> ncols_extra;  // carried columns per level
   int32_t **d_lvl_ptr = nullptr;   // device copies for enumeration (in the run's arena block)
+  int32_t **d_lvl_cptr = nullptr;
   int64_t *d_lvl_n = nullptr;
   int32_t *d_var_rank = nullptr;
   void *own = nullptr;             // device memory owned by this result, else arena
@@ -124,7 +126,8 @@ void compile_query(const Engine &E, QInfo &qi, bool count_only, int slot, Tables
 void build_iteration(const Tables &T, const std::vector<const QInfo *> &qs, const std::vector<int> &level,
                      IterLists &L);
 void account_iteration(Engine &E, const hipEvent_t *ev, const IterScalars &I, const IterLists &L, double write_bytes);
-void fill_result(Result &R, const QInfo &qi, bool count_only, int32_t *const *lvl_p, const int64_t *lvl_n,
+void fill_result(Result &R, const QInfo &qi, bool count_only, int32_t *const *lvl_p, int32_t *const *lvl_c,
+                 const int64_t *lvl_n,
                  const int64_t *qstats, int64_t zero_res, double ms);
 hipError_t zero_words(uint64_t *p, int64_t n, hipStream_t s);
 hipError_t launch_const_only(const DevGraph &g, const DConst *cc, int n, int64_t *out, hipStream_t s);

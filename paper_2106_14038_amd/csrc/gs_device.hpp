@@ -86,6 +86,7 @@ struct EState {
   const int32_t *copies; // write pass: previous-level columns copied into the new level
   int32_t ncopy;
   int32_t wflags;        // write pass: EW_FREE | EW_LIST
+  int32_t *cptr;         // levels without tests: child offsets per parent (prev_n + 1), no parent column
 };
 enum { EW_FREE = 1, EW_LIST = 2 };
 

@@ -469,6 +469,40 @@ __global__ __launch_bounds__(kBlock) void k_lookup(const IterArgs A) {
   if (threadIdx.x == 0) { acc.flush(p_nz, p_w, kEsStride); A.blk_a[blockIdx.x] = bnz; A.blk_b[blockIdx.x] = bw; }
 }
 
+// Allocate the tree level of entry e (es[e].cnt children) in the tree arena and
+// publish it. Levels without tests are stored with child offsets per parent
+// instead of a parent column. On overflow the level is recorded as -1 nodes.
+__device__ void alloc_level(const IterArgs &A, int e, const DEntry &d, const DStep &S) {
+  EState *es = A.es;
+  const int64_t cnt = es[e].cnt, pn = es[e].prev_n;
+  const bool csr = test_free(S);
+  int32_t *out = nullptr, *cptr = nullptr;
+  int64_t n_rec = cnt;
+  if (cnt > 2147483647LL && S.ncols_out > 0) {   // child positions and parent indices are int32
+    n_rec = -1;
+    A.qstats[(int64_t)d.q * QS_N + QS_OVERFLOW] = 2;
+  } else if (cnt > 0 && S.ncols_out > 0) {
+    const uint64_t cols = (uint64_t)cnt * (S.ncols_out - (csr ? 1 : 0));
+    const uint64_t offs = csr ? (uint64_t)(pn + 1) : 0;
+    int32_t *blk = (int32_t *)arena_alloc(A.tree, A.tree_base, sizeof(int32_t) * (cols + offs));
+    if (!blk) {
+      n_rec = -1;
+      A.qstats[(int64_t)d.q * QS_N + QS_OVERFLOW] = 1;
+    } else if (csr) {
+      cptr = blk;
+      cptr[pn] = (int32_t)cnt;
+      out = blk + (pn + 1) - cnt;   // column c >= 1 at out + c * cnt, inside the block
+    } else {
+      out = blk;
+    }
+  }
+  es[e].out = out;
+  es[e].cptr = cptr;
+  A.lvl_ptr[(int64_t)d.q * kMaxLevels + d.level] = out;
+  A.lvl_cptr[(int64_t)d.q * kMaxLevels + d.level] = cptr;
+  A.lvl_n[(int64_t)d.q * kMaxLevels + d.level] = n_rec;
+}
+
 __global__ __launch_bounds__(1024) void k_scan_nodes(const IterArgs A) {
   __shared__ int64_t lds[1024];
   IterScalars *it = A.it;
@@ -512,8 +546,10 @@ __global__ __launch_bounds__(1024) void k_scan_nodes(const IterArgs A) {
   }
   for (int e = threadIdx.x; e < A.E; e += blockDim.x) {
     const DEntry d = A.ent[e];
-    if (A.steps[d.step].kind != STEP_LIST && es[e].w)
+    const DStep S = A.steps[d.step];
+    if (S.kind != STEP_LIST && es[e].w)
       atomicAdd((unsigned long long *)&A.qstats[(int64_t)d.q * QS_N + QS_EXPAND], (unsigned long long)es[e].w);
+    if (test_free(S)) alloc_level(A, e, d, S);   // its size is known now: the node pass writes its offsets
   }
 }
 
@@ -535,6 +571,7 @@ __global__ __launch_bounds__(kBlock) void k_nz_write(const IterArgs A) {
     const int e = uniform(sh_e);
     const int64_t i0 = (t - es[e].node_tile0) * kTileNodes, pn = es[e].prev_n;
     const int64_t ew = es[e].w, etile0 = es[e].w_tile0;
+    int32_t *const cptr = es[e].cptr;
     for (int r = 0; r < kTileNodes / kBlock; ++r) {
       const int64_t i = i0 + r * kBlock + threadIdx.x;
       int64_t len = 0, lo = 0;
@@ -543,6 +580,7 @@ __global__ __launch_bounds__(kBlock) void k_nz_write(const IterArgs A) {
       const int pos = block_excl_flag(len > 0, ftot, ldi);
       int64_t wtot;
       const int64_t wpos = block_excl_scan_i64(len, wtot, lds);
+      if (cptr && i < pn) cptr[i] = (int32_t)(run_w + wpos - es[e].w_base);   // first child of node i
       if (len > 0) {
         const int64_t k = run_nz + pos;
         const int64_t woff = run_w + wpos - es[e].w_base;
@@ -805,27 +843,10 @@ __global__ __launch_bounds__(1024) void k_scan_expand(const IterArgs A) {
   for (int e = threadIdx.x; e < A.E; e += blockDim.x) {
     const DEntry d = A.ent[e];
     const DStep S = A.steps[d.step];
-    const int64_t cnt = es[e].cnt;
-    int32_t *out = nullptr;
-    int64_t n_rec = cnt;
-    if (cnt > 0 && S.ncols_out > 0) {
-      out = (int32_t *)arena_alloc(A.tree, A.tree_base, sizeof(int32_t) * (uint64_t)cnt * S.ncols_out);
-      if (!out) {
-        n_rec = -1;
-        A.qstats[(int64_t)d.q * QS_N + QS_OVERFLOW] = 1;
-      }
-    }
-    if (cnt > 2147483647LL && S.ncols_out > 0) {   // parent indices are int32
-      out = nullptr;
-      n_rec = -1;
-      A.qstats[(int64_t)d.q * QS_N + QS_OVERFLOW] = 2;
-    }
-    es[e].out = out;
+    if (!test_free(S)) alloc_level(A, e, d, S);   // levels without tests were allocated by the node scan
     es[e].copies = A.ints + S.copy0;
     es[e].ncopy = S.ncopy;
     es[e].wflags = (test_free(S) ? EW_FREE : 0) | (S.kind == STEP_LIST ? EW_LIST : 0);
-    A.lvl_ptr[(int64_t)d.q * kMaxLevels + d.level] = out;
-    A.lvl_n[(int64_t)d.q * kMaxLevels + d.level] = n_rec;
   }
 }
 
@@ -929,7 +950,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
         }
       }
       for (int r = 0; r < R; ++r)
-        if (li[r] >= 0) { gst_stream(out + li[r], node[r]); gst_stream(out + cnt + li[r], c[r]); }
+        if (li[r] >= 0) {
+          if (!(wflags & EW_FREE)) gst_stream(out + li[r], node[r]);   // levels without tests keep offsets instead
+          gst_stream(out + cnt + li[r], c[r]);
+        }
       const int ncopy = sld(&es[e].ncopy);
       if (ncopy) {
         const int32_t *prev = sld(&es[e].prev), *copies = sld(&es[e].copies);
@@ -949,16 +973,29 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
 
 // ------------------------------------------------------------------ results
 // Rows [first, first + n) of one query: walk each leaf's parents to the root.
-__global__ __launch_bounds__(kBlock) void k_enumerate(int32_t *const *lvl_ptr, const int64_t *lvl_n, int k,
-                                                      const int32_t *var_rank, int64_t first, int64_t n,
-                                                      int32_t *rows) {
+// Parent of node i of a level: its parent column, or the last parent whose
+// first child is at or before i (child offsets ascend).
+__device__ __forceinline__ int64_t parent_of(const int32_t *L, const int32_t *cptr, int64_t prev_n, int64_t i) {
+  if (!cptr) return L[i];
+  int64_t lo = 0, hi = prev_n - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (cptr[mid] <= i) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Rows [first, first + n) of one query: walk each leaf's parents to the root.
+__global__ __launch_bounds__(kBlock) void k_enumerate(int32_t *const *lvl_ptr, int32_t *const *lvl_cptr,
+                                                      const int64_t *lvl_n, int k, const int32_t *var_rank,
+                                                      int64_t first, int64_t n, int32_t *rows) {
   for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
     int64_t node = first + r;
     for (int j = k - 1; j >= 0; --j) {
       const int32_t *L = lvl_ptr[j];
       const int64_t nj = lvl_n[j];
       rows[r * k + var_rank[j]] = L[nj + node];
-      node = L[node];
+      if (j > 0) node = parent_of(L, lvl_cptr[j], lvl_n[j - 1], node);
     }
   }
 }
@@ -1005,13 +1042,13 @@ hipError_t launch_iteration(const IterArgs &A, hipStream_t s, hipEvent_t *ev) {
   return hipGetLastError();
 }
 
-hipError_t launch_enumerate(int32_t *const *lvl_ptr, const int64_t *lvl_n, int k, const int32_t *var_rank,
-                            int64_t first, int64_t n, int32_t *rows, hipStream_t s) {
+hipError_t launch_enumerate(int32_t *const *lvl_ptr, int32_t *const *lvl_cptr, const int64_t *lvl_n, int k,
+                            const int32_t *var_rank, int64_t first, int64_t n, int32_t *rows, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   int64_t g = (n + kBlock - 1) / kBlock;
   if (g > 8192) g = 8192;
-  hipLaunchKernelGGL(k_enumerate, dim3((unsigned)g), dim3(kBlock), 0, s, lvl_ptr, lvl_n, k, var_rank, first, n,
-                     rows);
+  hipLaunchKernelGGL(k_enumerate, dim3((unsigned)g), dim3(kBlock), 0, s, lvl_ptr, lvl_cptr, lvl_n, k, var_rank, first,
+                     n, rows);
   return hipGetLastError();
 }
 
@@ -1044,10 +1081,10 @@ hipError_t launch_domain_only(const IterArgs &A, hipStream_t s) {
 // down, remapping each child's parent index to its parent's new position.
 namespace gs {
 
-__global__ __launch_bounds__(kBlock) void k_prune_mark(const int32_t *par, int64_t n, const uint8_t *alive,
-                                                       uint8_t *alive_parent) {
+__global__ __launch_bounds__(kBlock) void k_prune_mark(const int32_t *par, const int32_t *cptr, int64_t prev_n,
+                                                       int64_t n, const uint8_t *alive, uint8_t *alive_parent) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    if (!alive || alive[i]) alive_parent[par[i]] = 1;
+    if (!alive || alive[i]) alive_parent[parent_of(par, cptr, prev_n, i)] = 1;
 }
 
 __global__ __launch_bounds__(kBlock) void k_prune_count(const uint8_t *alive, int64_t n, int64_t *blk) {
@@ -1060,7 +1097,8 @@ __global__ __launch_bounds__(kBlock) void k_prune_count(const uint8_t *alive, in
   if (threadIdx.x == 0) blk[blockIdx.x] = c;
 }
 
-__global__ __launch_bounds__(kBlock) void k_prune_write(const int32_t *L, int64_t n, int ncols, const uint8_t *alive,
+__global__ __launch_bounds__(kBlock) void k_prune_write(const int32_t *L, const int32_t *cptr, int64_t prev_n,
+                                                        int64_t n, int ncols, const uint8_t *alive,
                                                         const int64_t *blkoff, const int32_t *parent_newidx,
                                                         int32_t *newidx, int32_t *out, int64_t n_out) {
   __shared__ int lds[kWaves];
@@ -1075,17 +1113,19 @@ __global__ __launch_bounds__(kBlock) void k_prune_write(const int32_t *L, int64_
     if (f) {
       const int64_t k = run + pos;
       newidx[i] = (int32_t)k;
-      out[k] = parent_newidx ? parent_newidx[L[i]] : L[i];
+      const int64_t p = parent_of(L, cptr, prev_n, i);
+      out[k] = parent_newidx ? parent_newidx[p] : (int32_t)p;
       for (int c = 1; c < ncols; ++c) out[(int64_t)c * n_out + k] = L[(int64_t)c * n + i];
     }
     run += tot;
   }
 }
 
-hipError_t launch_prune_mark(const int32_t *par, int64_t n, const uint8_t *alive, uint8_t *alive_parent, hipStream_t s) {
+hipError_t launch_prune_mark(const int32_t *par, const int32_t *cptr, int64_t prev_n, int64_t n, const uint8_t *alive,
+                             uint8_t *alive_parent, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   int64_t g = std::min<int64_t>((n + kBlock - 1) / kBlock, 8192);
-  hipLaunchKernelGGL(k_prune_mark, dim3((unsigned)g), dim3(kBlock), 0, s, par, n, alive, alive_parent);
+  hipLaunchKernelGGL(k_prune_mark, dim3((unsigned)g), dim3(kBlock), 0, s, par, cptr, prev_n, n, alive, alive_parent);
   return hipGetLastError();
 }
 
@@ -1094,11 +1134,11 @@ hipError_t launch_prune_count(const uint8_t *alive, int64_t n, int64_t *blk, int
   return hipGetLastError();
 }
 
-hipError_t launch_prune_write(const int32_t *L, int64_t n, int ncols, const uint8_t *alive, const int64_t *blkoff,
-                              const int32_t *parent_newidx, int32_t *newidx, int32_t *out, int64_t n_out, int grid,
-                              hipStream_t s) {
-  hipLaunchKernelGGL(k_prune_write, dim3(grid), dim3(kBlock), 0, s, L, n, ncols, alive, blkoff, parent_newidx, newidx,
-                     out, n_out);
+hipError_t launch_prune_write(const int32_t *L, const int32_t *cptr, int64_t prev_n, int64_t n, int ncols,
+                              const uint8_t *alive, const int64_t *blkoff, const int32_t *parent_newidx,
+                              int32_t *newidx, int32_t *out, int64_t n_out, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_prune_write, dim3(grid), dim3(kBlock), 0, s, L, cptr, prev_n, n, ncols, alive, blkoff,
+                     parent_newidx, newidx, out, n_out);
   return hipGetLastError();
 }
 

@@ -28,7 +28,8 @@ struct IterArgs {
   uint64_t *const *clear;
   EState *es;
   IterScalars *it;
-  int32_t **lvl_ptr;       // [q * kMaxLevels + level]
+  int32_t **lvl_ptr;       // [q * kMaxLevels + level]: column c of a level at lvl_ptr + c * n (c >= 1 on CSR levels)
+  int32_t **lvl_cptr;      // [q * kMaxLevels + level]: child offsets of a CSR level, else null
   int64_t *lvl_n;          // [q * kMaxLevels + level], -1 = overflow
   int64_t *qstats;         // [q * QS_N + counter]
   DArena *scratch;
@@ -45,12 +46,19 @@ int expand_write_blocks_per_cu();
 hipError_t launch_iteration(const IterArgs &A, hipStream_t s, hipEvent_t *ev = nullptr);
 hipError_t launch_list_only(const IterArgs &A, hipStream_t s);
 hipError_t launch_domain_only(const IterArgs &A, hipStream_t s);
-hipError_t launch_prune_mark(const int32_t *par, int64_t n, const uint8_t *alive, uint8_t *alive_parent, hipStream_t s);
+// Tree levels come in two forms: a parent column (column 0, one entry per
+// node), or, for levels whose candidates face no test, child offsets per
+// parent (cptr, prev_n + 1 entries; the children of parent p are
+// [cptr[p], cptr[p + 1])) and no column 0. cptr = null selects the first form.
+hipError_t launch_prune_mark(const int32_t *par, const int32_t *cptr, int64_t prev_n, int64_t n, const uint8_t *alive,
+                             uint8_t *alive_parent, hipStream_t s);
 hipError_t launch_prune_count(const uint8_t *alive, int64_t n, int64_t *blk, int grid, hipStream_t s);
-hipError_t launch_prune_write(const int32_t *L, int64_t n, int ncols, const uint8_t *alive, const int64_t *blkoff,
+hipError_t launch_prune_write(const int32_t *L, const int32_t *cptr, int64_t prev_n, int64_t n, int ncols,
+                              const uint8_t *alive, const int64_t *blkoff,
                               const int32_t *parent_newidx, int32_t *newidx, int32_t *out, int64_t n_out, int grid,
                               hipStream_t s);
-hipError_t launch_enumerate(int32_t *const *lvl_ptr, const int64_t *lvl_n, int k, const int32_t *var_rank,
+hipError_t launch_enumerate(int32_t *const *lvl_ptr, int32_t *const *lvl_cptr, const int64_t *lvl_n, int k,
+                            const int32_t *var_rank,
                             int64_t first, int64_t n, int32_t *rows, hipStream_t s);
 
 }  // namespace gs

@@ -86,6 +86,7 @@ struct ServerImpl {
   DConst *d_cc = nullptr;
   int32_t *d_vr = nullptr;
   int32_t **d_lvlp = nullptr;
+  int32_t **d_lvlc = nullptr;
   int64_t *d_lvln = nullptr;
   int64_t *d_qs = nullptr;
   // per-iteration
@@ -252,6 +253,7 @@ hipError_t upload_slot(ServerImpl &S, Active *a, hipStream_t s) {
   cp(S.d_cc + (size_t)sl * kSlotCc, T.cconst.data(), sizeof(DConst) * T.cconst.size());
   cp(S.d_vr + (size_t)sl * kMaxLevels, T.var_rank.data(), sizeof(int32_t) * T.var_rank.size());
   if (e == hipSuccess) e = zero_words((uint64_t *)(S.d_lvlp + (size_t)sl * kMaxLevels), kMaxLevels, s);
+  if (e == hipSuccess) e = zero_words((uint64_t *)(S.d_lvlc + (size_t)sl * kMaxLevels), kMaxLevels, s);
   if (e == hipSuccess) e = zero_words((uint64_t *)(S.d_lvln + (size_t)sl * kMaxLevels), kMaxLevels, s);
   if (e == hipSuccess) e = zero_words((uint64_t *)(S.d_qs + (size_t)sl * QS_N), QS_N, s);
   return e;
@@ -262,15 +264,19 @@ int retire(ServerImpl &S, Active *a, const int64_t *lvl_n_all, hipStream_t s) {
   Engine &E = *S.E;
   Result *R = new Result();
   R->eng = &E;
-  std::vector<int32_t *> lp(kMaxLevels, nullptr);
+  std::vector<int32_t *> lp(kMaxLevels, nullptr), lc(kMaxLevels, nullptr);
   std::vector<int64_t> qs(QS_N);
   hipError_t e = hipMemcpyAsync(lp.data(), S.d_lvlp + (size_t)a->slot * kMaxLevels, sizeof(void *) * kMaxLevels,
                                 hipMemcpyDeviceToHost, s);
   if (e == hipSuccess)
+    e = hipMemcpyAsync(lc.data(), S.d_lvlc + (size_t)a->slot * kMaxLevels, sizeof(void *) * kMaxLevels,
+                       hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess)
     e = hipMemcpyAsync(qs.data(), S.d_qs + (size_t)a->slot * QS_N, 8 * QS_N, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) { delete R; return GS_EDEVICE; }
-  fill_result(*R, a->qi, a->count_only, lp.data(), lvl_n_all + (size_t)a->slot * kMaxLevels, qs.data(), 0, 0);
+  fill_result(*R, a->qi, a->count_only, lp.data(), lc.data(), lvl_n_all + (size_t)a->slot * kMaxLevels, qs.data(), 0,
+              0);
   R->host_owned = true;
   if (!a->count_only && R->count > 0 && R->k > 0) {
     const int k = R->k;
@@ -278,7 +284,8 @@ int retire(ServerImpl &S, Active *a, const int64_t *lvl_n_all, hipStream_t s) {
     const int64_t chunk = std::max<int64_t>(1, (int64_t)(S.rows_cap / (4 * (size_t)k)));
     for (int64_t r = 0; r < R->count && e == hipSuccess; r += chunk) {
       const int64_t c = std::min(chunk, R->count - r);
-      e = launch_enumerate(S.d_lvlp + (size_t)a->slot * kMaxLevels, S.d_lvln + (size_t)a->slot * kMaxLevels, k,
+      e = launch_enumerate(S.d_lvlp + (size_t)a->slot * kMaxLevels, S.d_lvlc + (size_t)a->slot * kMaxLevels,
+                           S.d_lvln + (size_t)a->slot * kMaxLevels, k,
                            S.d_vr + (size_t)a->slot * kMaxLevels, r, c, S.d_rows, s);
       if (e == hipSuccess)
         e = hipMemcpyAsync(R->host_rows.data() + (size_t)r * k, S.d_rows, sizeof(int32_t) * c * k,
@@ -288,6 +295,7 @@ int retire(ServerImpl &S, Active *a, const int64_t *lvl_n_all, hipStream_t s) {
     if (e != hipSuccess) { delete R; return GS_EDEVICE; }
   }
   R->lvl_ptr.assign(R->lvl_ptr.size(), nullptr);   // the ring space is released below
+  R->lvl_cptr.assign(R->lvl_cptr.size(), nullptr);
   const double t = now_ms();
   R->stats.latency_ms = t - a->req.t_arrive;
   finish(S, a->req.ticket, GS_OK, R);
@@ -336,7 +344,7 @@ void loop(ServerImpl &S) {
         Result *R = new Result();
         R->eng = &E;
         std::vector<int64_t> qs0(QS_N, 0);
-        fill_result(*R, a->qi, a->count_only, nullptr, nullptr, qs0.data(), ok, 0);
+        fill_result(*R, a->qi, a->count_only, nullptr, nullptr, nullptr, qs0.data(), ok, 0);
         R->host_owned = true;
         R->stats.latency_ms = now_ms() - a->req.t_arrive;
         release(S, a);
@@ -385,7 +393,7 @@ void loop(ServerImpl &S) {
     A.D = (int32_t)L.doms.size(); A.nclear = (int32_t)L.clears.size(); A.has_list = L.has_list; A.grid = E.grid; A.wgrid = E.wgrid;
     A.steps = S.d_steps; A.filt = S.d_filt; A.checks = S.d_checks; A.ints = S.d_ints; A.cconst = S.d_cc;
     A.seeds = S.d_seeds; A.doms = S.d_doms; A.fcount = S.d_fc; A.clear = S.d_clear; A.es = S.d_es; A.it = S.d_it;
-    A.lvl_ptr = S.d_lvlp; A.lvl_n = S.d_lvln; A.qstats = S.d_qs;
+    A.lvl_ptr = S.d_lvlp; A.lvl_cptr = S.d_lvlc; A.lvl_n = S.d_lvln; A.qstats = S.d_qs;
     A.scratch = E.d_arenas + 1; A.scratch_base = E.scratch_base; A.tree = E.d_arenas; A.tree_base = E.tree_base;
     A.blk_a = S.d_blk; A.blk_b = S.d_blk + E.grid; A.blk_off_a = S.d_blk + 2 * E.grid; A.blk_off_b = S.d_blk + 3 * E.grid;
     if (prof) {
@@ -466,6 +474,7 @@ int server_start(Engine *E, const gs_server_options *o, gs_server **out) {
   take((void **)&S.d_cc, sizeof(DConst) * cap * kSlotCc);
   take((void **)&S.d_vr, sizeof(int32_t) * cap * kMaxLevels);
   take((void **)&S.d_lvlp, sizeof(void *) * cap * kMaxLevels);
+  take((void **)&S.d_lvlc, sizeof(void *) * cap * kMaxLevels);
   take((void **)&S.d_lvln, sizeof(int64_t) * cap * kMaxLevels);
   take((void **)&S.d_qs, sizeof(int64_t) * cap * QS_N);
   take((void **)&S.d_ents, sizeof(DEntry) * cap);
@@ -561,7 +570,7 @@ int server_stop(gs_server *srv, gs_server_stats *st) {
   if (st) *st = S.stats;
   for (auto &d : S.done) if (d.second.second) result_free(d.second.second);
   Engine *E = S.E;
-  void *ps[] = {S.d_steps, S.d_filt, S.d_checks, S.d_ints, S.d_cc, S.d_vr, S.d_lvlp, S.d_lvln, S.d_qs, S.d_ents,
+  void *ps[] = {S.d_steps, S.d_filt, S.d_checks, S.d_ints, S.d_cc, S.d_vr, S.d_lvlp, S.d_lvlc, S.d_lvln, S.d_qs, S.d_ents,
                 S.d_doms, S.d_clear, S.d_seeds, S.d_fc, S.d_es, S.d_it, S.d_blk, S.d_zero, S.d_rows, S.pool};
   for (void *p : ps) E->dfree(p);
   delete srv;
