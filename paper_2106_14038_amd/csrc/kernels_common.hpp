@@ -154,14 +154,9 @@ __device__ __forceinline__ int64_t lower_bound_u16(const uint16_t *a, int64_t lo
   return lo;
 }
 
-// Entries of vertex b with label `label` in orientation dir: [lo, hi).
-__device__ __forceinline__ void seg_find(const DevGraph &g, int dir, int32_t b, int32_t label, int64_t &lo,
-                                         int64_t &hi, int &probes) {
-  // selects, not indexing: dir may differ between lanes, and indexing the
-  // pointer arrays by a per-lane value loads the pointers from memory
-  const int64_t *ptr = dir ? g.ptr[1] : g.ptr[0];
-  const int64_t a = gld(ptr + b), e = gld(ptr + b + 1);
-  const uint16_t *lab = dir ? g.lab[1] : g.lab[0];
+// Entries with label `label` among the row entries [a, e) (labels ascend): [lo, hi).
+__device__ __forceinline__ void label_range(const uint16_t *lab, int64_t a, int64_t e, int32_t label, int64_t &lo,
+                                            int64_t &hi, int &probes) {
   if (e - a <= 8) {          // short rows: one linear pass
     int64_t x = a;
     while (x < e && gld(lab + x) < (uint32_t)label) ++x;
@@ -173,6 +168,16 @@ __device__ __forceinline__ void seg_find(const DevGraph &g, int dir, int32_t b, 
   }
   lo = lower_bound_u16(lab, a, e, (uint32_t)label, probes);
   hi = lower_bound_u16(lab, lo, e, (uint32_t)label + 1, probes);
+}
+
+// Entries of vertex b with label `label` in orientation dir: [lo, hi).
+__device__ __forceinline__ void seg_find(const DevGraph &g, int dir, int32_t b, int32_t label, int64_t &lo,
+                                         int64_t &hi, int &probes) {
+  // selects, not indexing: dir may differ between lanes, and indexing the
+  // pointer arrays by a per-lane value loads the pointers from memory
+  const int64_t *ptr = dir ? g.ptr[1] : g.ptr[0];
+  const int64_t a = gld(ptr + b), e = gld(ptr + b + 1);
+  label_range(dir ? g.lab[1] : g.lab[0], a, e, label, lo, hi, probes);
 }
 
 // Is c among the entries of vertex b with label `label` (orientation dir)?

@@ -290,8 +290,11 @@ __global__ __launch_bounds__(kBlock) void k_dom_frontier(const IterArgs A) {
         if (i < pn) {
           const int32_t b = es[e].prev[(int64_t)dm.col * pn + i];
           const uint64_t bit = 1ull << (b & 63);
-          const uint64_t old = atomicOr((unsigned long long *)&dm.F[b >> 6], bit);
-          fresh += (old & bit) ? 0 : 1;
+          // bindings repeat (hubs): test before the atomic, which then runs once per distinct word bit
+          if (!(gld(dm.F + (b >> 6)) & bit)) {
+            const uint64_t old = atomicOr((unsigned long long *)&dm.F[b >> 6], bit);
+            fresh += (old & bit) ? 0 : 1;
+          }
         }
       }
       fresh = block_sum_i64(fresh, lds);
@@ -309,6 +312,13 @@ __device__ __forceinline__ int dom_mode(const IterArgs &A, int d) {
 }
 
 constexpr int64_t kCoopSeg = 32;   // push: segments longer than this are walked by a whole wave
+
+// Set bit c of a bitmap that other waves set concurrently; the atomic is
+// skipped when the bit is already visible (many segments share targets).
+__device__ __forceinline__ void set_bit_once(uint64_t *bm, int32_t c) {
+  const uint64_t bit = 1ull << (c & 63);
+  if (!(gld(bm + (c >> 6)) & bit)) atomicOr((unsigned long long *)&bm[c >> 6], bit);
+}
 
 // Push: for every b in F, OR the label-p segment of b into D (sparse-frontier product).
 __global__ __launch_bounds__(kBlock) void k_dom_push(const IterArgs A) {
@@ -339,18 +349,12 @@ __global__ __launch_bounds__(kBlock) void k_dom_push(const IterArgs A) {
         work += hi - lo;
         coop = hi - lo > kCoopSeg;
         if (!coop)
-          for (int64_t k = lo; k < hi; ++k) {
-            const int32_t c = idx[k];
-            atomicOr((unsigned long long *)&dm.D[c >> 6], 1ull << (c & 63));
-          }
+          for (int64_t k = lo; k < hi; ++k) set_bit_once(dm.D, idx[k]);
       }
       for (uint64_t m = __ballot(coop); m; m &= m - 1) {
         const int l = __ffsll((unsigned long long)m) - 1;
         const int64_t L = __shfl(lo, l, 64), H = __shfl(hi, l, 64);
-        for (int64_t k = L + lane; k < H; k += 64) {
-          const int32_t c = idx[k];
-          atomicOr((unsigned long long *)&dm.D[c >> 6], 1ull << (c & 63));
-        }
+        for (int64_t k = L + lane; k < H; k += 64) set_bit_once(dm.D, idx[k]);
       }
     }
     work = block_sum_i64(work, lds);
@@ -433,26 +437,37 @@ __global__ __launch_bounds__(kBlock) void k_lookup(const IterArgs A) {
     __syncthreads();
     const int64_t i0 = (t - es[e].node_tile0) * kTileNodes, pn = es[e].prev_n;
     int64_t cnz = 0, cw = 0;
-    for (int r = 0; r < kTileNodes / kBlock; ++r) {
+    constexpr int RN = kTileNodes / kBlock;
+    // the parent bindings, then their rows, of all of the thread's nodes first (independent loads)
+    const int32_t *src = es[e].prev + (int64_t)S.src * pn;
+    const int64_t *ptr = S.dir ? A.g.ptr[1] : A.g.ptr[0];
+    int64_t ra[RN], re[RN];
+    for (int r = 0; r < RN; ++r) {
+      const int64_t i = i0 + r * kBlock + threadIdx.x;
+      ra[r] = re[r] = 0;
+      if (i < pn && S.kind != STEP_LIST) {
+        const int32_t b = S.kind == STEP_SEG ? gld(src + i) : S.src;
+        ra[r] = gld(ptr + b);
+        re[r] = gld(ptr + b + 1);
+      }
+    }
+    for (int r = 0; r < RN; ++r) {
       const int64_t i = i0 + r * kBlock + threadIdx.x;
       if (i >= pn) break;
       int64_t lo = 0, hi = 0;
       int probes = 0;
       int dir = S.dir, gen = 0;
-      if (S.kind == STEP_SEG) {
-        seg_find(A.g, S.dir, es[e].prev[(int64_t)S.src * pn + i], S.label, lo, hi, probes);
-      } else if (S.kind == STEP_SEG_CONST) {
-        seg_find(A.g, S.dir, S.src, S.label, lo, hi, probes);
-      } else {
-        hi = es[e].list_n;
-      }
-      if (S.kind != STEP_LIST)   // read the shortest bound segment
-        for (int k = 0; k < min(S.nchk, kMaxGen) && hi > lo; ++k) {
+      if (S.kind != STEP_LIST) {
+        label_range(S.dir ? A.g.lab[1] : A.g.lab[0], ra[r], re[r], S.label, lo, hi, probes);
+        for (int k = 0; k < min(S.nchk, kMaxGen) && hi > lo; ++k) {   // read the shortest bound segment
           const DCheck ck = A.checks[S.chk0 + k];
           int64_t clo, chi;
           seg_find(A.g, ck.dir, es[e].prev[(int64_t)ck.col * pn + i], ck.label, clo, chi, probes);
           if (chi - clo < hi - lo) { lo = clo; hi = chi; dir = ck.dir; gen = k + 1; }
         }
+      } else {
+        hi = es[e].list_n;
+      }
       if (!sh_ok) hi = lo;
       const int64_t gn = es[e].node0 + i;
       it->lo[gn] = seg_ref(lo, dir, gen);

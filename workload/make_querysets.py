@@ -96,16 +96,17 @@ def batched_set(trip, n, pool, args, t0):
 
 
 def served_set(trip, n, pool, args, t0):
-    """Mixed walk shapes, 1-12 edges, 0-2 constants, counts in [1, 1e7]."""
+    """Mixed walk shapes, 1-12 edges, 0-2 constants, counts in [1, 1e7] (message passing for
+    acyclic queries, backtracking with the work cap for cyclic ones)."""
     got, first = [], 0
     while len(got) < args.total and first < args.max_candidates * 4:
         batch = workload.walk_queries(trip, n, 200, "mixed", 64, first=first, max_consts=2)
-        counts = pool.starmap(_count_bt, [(q, args.work_cap) for q in batch])
+        counts = pool.starmap(_count, [(q, args.work_cap) for q in batch])
         for i, (q, c) in enumerate(zip(batch, counts)):
             if 1 <= c <= 10_000_000 and len(got) < args.total:
                 got.append({"shape": "mixed", "candidate": first + i, "count": int(c), "query": q})
         first += 64
-    print(f"served: {len(got)} from {first} candidates ({time.time() - t0:.0f}s)", flush=True)
+        print(f"served: {len(got)} from {first} candidates ({time.time() - t0:.0f}s)", flush=True)
     return got
 
 
