@@ -233,7 +233,7 @@ def summarize_rocprof(args):
         f_fetch, f_write = copy_bytes / (cf * 1024.0), copy_bytes / (cw * 1024.0)
         (kn, (kf, nd)), (_, (kw, _)) = pick(fetch, "FETCH_SIZE", args.kernel), pick(write, "WRITE_SIZE", args.kernel)
         hbm = kf * 1024.0 * f_fetch + kw * 1024.0 * f_write
-        lines += [f"kernel: {kn}",
+        lines += [f"kernel: {kn[0]}",
                   f"dispatches: {nd}",
                   f"fetch_kib_per_launch: {kf:.1f}",
                   f"write_kib_per_launch: {kw:.1f}",
