@@ -5,7 +5,9 @@
 - for every query up to 2M rows, the rows whose root binding falls in a seeded
   sample of vertices equal the oracle's rows restricted to the same sample
   (the sample is drawn among vertices that meet the root's label filters,
-  computed by the oracle);
+  computed by the oracle), and so do the rows of a few root values drawn from
+  the result (8, else 2 when the oracle's search under 8 exceeds its work
+  bound, else a sample of 64 rows checked one by one);
 - for larger queries, a seeded sample of rows are each valid bindings (the
   oracle finds exactly one binding when every variable is fixed to the row).
 """
@@ -61,6 +63,34 @@ def m_distinct(eng):
     return gs.gs_graph_info(eng)[2]
 
 
+def bfs_order(q, root):
+    """Variables in breadth-first order from the root over the query's edges, so
+    that every variable after the first is adjacent to an earlier one or to a
+    constant (any order gives the oracle the same rows; a connected one keeps
+    its search local)."""
+    const = q["qv_const"]
+    var = [v for v, c in enumerate(const) if c < 0]
+    order, seen = [root], {root}
+    i = 0
+    while len(order) < len(var):
+        while i < len(order):
+            u = order[i]
+            i += 1
+            for s, _, o in q["edges"]:
+                for a, b in ((s, o), (o, s)):
+                    if a == u and const[b] < 0 and b not in seen:
+                        seen.add(b)
+                        order.append(b)
+        rest = [v for v in var if v not in seen]
+        if rest:   # next component: a variable next to a constant, else any
+            near = [v for v in rest if any((s == v and const[o] >= 0) or (o == v and const[s] >= 0)
+                                           for s, _, o in q["edges"])]
+            v = (near or rest)[0]
+            seen.add(v)
+            order.append(v)
+    return order
+
+
 def root_sample(G, q, root, n, rng, k=64):
     """Seeded vertices meeting the root's label-existence filters (computed by the oracle)."""
     ok = np.ones(n, np.uint8)
@@ -75,6 +105,27 @@ def root_sample(G, q, root, n, rng, k=64):
     return rng.choice(cand, size=min(k, len(cand)), replace=False)
 
 
+def restricted(G, q, order, root, n, roots, cap):
+    mask = np.zeros(n, np.uint8)
+    mask[roots] = 1
+    return mask, G.eval(q, order=order, restrict=(root, mask), rows_cap=cap, work_cap=ORACLE_WORK)
+
+
+def rows_valid(G, q, var_qv, rows):
+    """Each row is a binding: with every variable fixed to it the oracle finds exactly one."""
+    for row in rows:
+        fixed = list(q["qv_const"])
+        for v, val in zip(var_qv, row):
+            fixed[v] = int(val)
+        qc = {"n_qv": q["n_qv"], "qv_const": fixed, "edges": q["edges"]}
+        if G.eval(qc, rows=False)[0] != 1:
+            return False
+    return True
+
+
+ORACLE_WORK = 300_000_000   # per restricted oracle call (a few seconds on one core)
+
+
 @pytest.mark.timeout(1200)
 def test_c1_sampled_rows_match_oracle(c1):
     qs, trip, G, eng = c1
@@ -86,6 +137,7 @@ def test_c1_sampled_rows_match_oracle(c1):
         info = gs.gs_plan_query(q)
         root = info.order[0]
         col = var_qv.index(root)
+        order = bfs_order(q, root)   # the oracle binds the root first: the restriction prunes at the top
         print(f"[c1] query {i} {rec['shape']} count={rec['count']}", flush=True)
         r = gs.gs_query_run(eng, q)
         try:
@@ -93,30 +145,32 @@ def test_c1_sampled_rows_match_oracle(c1):
             assert cnt == rec["count"]
             if cnt <= 2_000_000:
                 rows = gs.gs_result_rows(r)
+                # seeded roots among the vertices meeting the root's label filters (mostly childless)
                 sample = root_sample(G, q, root, n, rng)
-                # the oracle binds the root first, so the restriction prunes its search at the top
-                order = [root] + [v for v in var_qv if v != root]
-                mask = np.zeros(n, np.uint8)
-                mask[sample] = 1
-                ocnt, orows = G.eval(q, order=order, restrict=(root, mask), rows_cap=cnt + 1)
+                print(f"[c1]   oracle: {len(sample)} sampled roots", flush=True)
+                mask, (ocnt, orows) = restricted(G, q, order, root, n, sample, cnt + 1)
                 mine = sort_rows(rows[mask[rows[:, col]] == 1])
                 assert ocnt == len(mine) and np.array_equal(mine, orows), i
-                # and a few root values that do appear in the result
+                # root values that occur in the result: all their rows, or (too much oracle work) a row sample
                 vals = np.unique(rows[:, col])
-                pick = rng.choice(vals, size=min(8, len(vals)), replace=False)
-                mask[:] = 0
-                mask[pick] = 1
-                ocnt, orows = G.eval(q, order=order, restrict=(root, mask), rows_cap=cnt + 1)
-                mine = sort_rows(rows[mask[rows[:, col]] == 1])
-                assert ocnt == len(mine) and np.array_equal(mine, orows), i
+                for k in (8, 2):
+                    pick = rng.choice(vals, size=min(k, len(vals)), replace=False)
+                    print(f"[c1]   oracle: {len(pick)} roots from the result", flush=True)
+                    try:
+                        mask, (ocnt, orows) = restricted(G, q, order, root, n, pick, cnt + 1)
+                    except oracle.OracleError:
+                        continue
+                    mine = sort_rows(rows[mask[rows[:, col]] == 1])
+                    assert ocnt == len(mine) and np.array_equal(mine, orows), i
+                    break
+                else:
+                    print("[c1]   oracle: row sample", flush=True)
+                    take = rng.choice(cnt, size=min(64, cnt), replace=False)
+                    assert rows_valid(G, q, var_qv, rows[np.sort(take)]), i
             else:
                 idx = np.sort(rng.choice(cnt, size=64, replace=False))
-                for j in idx[:64]:
-                    row = gs.gs_result_rows(r, int(j), 1)[0]
-                    fixed = list(q["qv_const"])
-                    for v, val in zip(var_qv, row):
-                        fixed[v] = int(val)
-                    qc = {"n_qv": q["n_qv"], "qv_const": fixed, "edges": q["edges"]}
-                    assert G.eval(qc, rows=False)[0] == 1, (i, j, row)
+                print("[c1]   oracle: row sample", flush=True)
+                sampled = np.stack([gs.gs_result_rows(r, int(j), 1)[0] for j in idx])
+                assert rows_valid(G, q, var_qv, sampled), i
         finally:
             gs.gs_result_free(r)
