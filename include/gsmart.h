@@ -199,10 +199,15 @@ typedef struct {
   int32_t roots[64];
 } gs_plan_info;
 
-/* Degree-driven traversal with the constants rule (Section 6.1.2): the order in
- * which query vertices are visited and their incident edges evaluated.
- * Errors: GS_EINVAL, GS_EUNSUPPORTED. */
-gs_status gs_plan_query(const gs_query *query, gs_plan_info *out);
+/* Degree-driven traversal with the constants rule (Section 6.1.2): the roots,
+ * the groups of edges evaluated at each visited vertex, and the tree level of
+ * each query vertex (order[]: a vertex follows the one that discovered it;
+ * among the vertices that may come next, the smallest estimated fan-out goes
+ * first, ties in pop order). engine: optional; with an engine that holds a
+ * matrix the plan is the one its evaluation uses (label statistics, id and
+ * label ranges checked); NULL plans without statistics (levels in pop order).
+ * Errors: GS_EINVAL, GS_ERANGE, GS_EUNSUPPORTED. */
+gs_status gs_plan_query(gs_engine *engine, const gs_query *query, gs_plan_info *out);
 
 /* ---- plain and batched evaluation ------------------------------------------- */
 

@@ -104,7 +104,7 @@ SIGNATURES = {
     "gs_label_exists": ([_vp, _i32, ctypes.c_int, _vp], ctypes.c_int),
     "gs_frontier_domain": ([_vp, _vp, _i32, ctypes.c_int, ctypes.c_int, _vp, _vp], ctypes.c_int),
     "gs_bitmap_and_compact": ([_vp, _vp, _i32, _vp, _P(_i64)], ctypes.c_int),
-    "gs_plan_query": ([_P(gs_query), _P(gs_plan_info)], ctypes.c_int),
+    "gs_plan_query": ([_vp, _P(gs_query), _P(gs_plan_info)], ctypes.c_int),
     "gs_query_run": ([_vp, _P(gs_query), _u32, _P(_vp)], ctypes.c_int),
     "gs_batch_run": ([_vp, _P(gs_query), _i32, _u32, _P(_vp)], ctypes.c_int),
     "gs_result_count": ([_vp, _P(_i64)], ctypes.c_int),
@@ -240,9 +240,10 @@ def gs_bitmap_and_compact(engine, bitmaps) -> np.ndarray:
     return out[:cnt.value].copy()
 
 
-def gs_plan_query(q: dict) -> gs_plan_info:
+def gs_plan_query(q: dict, engine=None) -> gs_plan_info:
+    """The plan of query q: the engine's (label statistics) when an engine is given."""
     info = gs_plan_info()
-    _check(lib().gs_plan_query(ctypes.byref(make_query(q)), ctypes.byref(info)))
+    _check(lib().gs_plan_query(engine, ctypes.byref(make_query(q)), ctypes.byref(info)))
     return info
 
 

@@ -251,19 +251,26 @@ gs_status gs_bitmap_and_compact(gs_engine *engine, const uint64_t *const *bitmap
   return GS_OK;
 }
 
-gs_status gs_plan_query(const gs_query *query, gs_plan_info *out) {
+gs_status gs_plan_query(gs_engine *engine, const gs_query *query, gs_plan_info *out) {
   if (!query || !out) { set_error("null argument"); return GS_EINVAL; }
   if (query->n_edges > 0 && !query->edges) { set_error("query edges missing"); return GS_EINVAL; }
   std::vector<int32_t> e3(3 * (size_t)std::max(query->n_edges, 0));
   for (int k = 0; k < query->n_edges; ++k) {
     e3[3 * k] = query->edges[k].src; e3[3 * k + 1] = query->edges[k].label; e3[3 * k + 2] = query->edges[k].dst;
   }
-  NormQuery q;
-  Plan P;
+  QInfo qi;
   std::string msg;
-  int rc = normalise_query(query->n_qv, query->qv_const, query->n_edges, e3.data(), -1, -1, q, msg);
-  if (rc == GS_OK) rc = build_plan(q, nullptr, false, P, msg);
+  int rc;
+  if (engine && engine->e.g.n > 0) {   // the plan the engine's evaluation uses
+    std::lock_guard<std::mutex> lk(engine->e.mu);
+    rc = plan_query(engine->e, *query, qi, msg);
+  } else {
+    rc = normalise_query(query->n_qv, query->qv_const, query->n_edges, e3.data(), -1, -1, qi.nq, msg);
+    if (rc == GS_OK) rc = build_plan(qi.nq, nullptr, false, qi.plan, msg);
+  }
   if (rc != GS_OK) { set_error(msg); return (gs_status)rc; }
+  const NormQuery &q = qi.nq;
+  const Plan &P = qi.plan;
   memset(out, 0, sizeof *out);
   out->n_vars = P.n_vars;
   std::vector<int32_t> first_input(q.edges.size(), -1);

@@ -151,18 +151,63 @@ int build_plan(const NormQuery &q, const LabelStats *st, bool want_domains, Plan
     }
   }
 
-  // Levels follow the pop order.
-  P.n_vars = (int)pop_order.size();
-  P.order = pop_order;
+  // Level order. The traversal above (roots, edge groups, pops) is the
+  // paper's; it keeps one binding tree per traversal path, where the single
+  // tree here interleaves the paths. Every vertex follows the vertex that
+  // discovered it; among the vertices that may come next, the one with the
+  // smallest estimated fan-out goes first, so that selective vertices
+  // (constant seeds, label filters, closed cycles) shrink the tree before
+  // wide ones grow it. Ties keep the pop order; a further root is placed
+  // when nothing else can be.
+  const double nvert = (st && st->n > 0) ? (double)st->n : 1.0;
+  std::vector<uint8_t> placed(nv, 0);
+  auto fanout = [&](int w) {
+    const int k0 = discovered_by_edge[w];
+    const QEdge &e0 = q.edges[k0];
+    const int u = (e0.s == w) ? e0.o : e0.s;
+    double f = est_seg(st, e0.p - 1, e0.s == u ? 0 : 1);
+    if (!st || st->nnz.empty()) return f;
+    for (int k = 0; k < ne; ++k) {
+      const QEdge &e = q.edges[k];
+      if (k == k0 || (e.s != w && e.o != w) || e.s == e.o) continue;
+      const int x = (e.s == w) ? e.o : e.s;
+      if (!is_var(x) || placed[x])   // seed bitmap, or exact check against a bound vertex
+        f *= std::min(1.0, est_seg(st, e.p - 1, e.s == x ? 0 : 1) / nvert);
+      else                           // label-existence filter (Eq. 4/5)
+        f *= (double)(e.s == w ? st->rows[e.p - 1] : st->cols[e.p - 1]) / nvert;
+    }
+    return f;
+  };
+  std::vector<int32_t> order;
+  size_t next_root = 0;
+  while (order.size() < pop_order.size()) {
+    int best = -1;
+    double bf = 0;
+    for (int w : pop_order) {
+      if (placed[w] || discovered_by_edge[w] < 0) continue;
+      const QEdge &e = q.edges[discovered_by_edge[w]];
+      if (!placed[(e.s == w) ? e.o : e.s]) continue;
+      const double f = fanout(w);
+      if (best < 0 || f < bf) { best = w; bf = f; }
+    }
+    if (best < 0) {
+      if (next_root >= P.roots.size()) { msg = "planner: no vertex can take the next level"; return GS_EINVAL; }
+      best = P.roots[next_root++];
+    }
+    placed[best] = 1;
+    order.push_back(best);
+  }
+  P.n_vars = (int)order.size();
+  P.order = order;
   std::vector<int32_t> level_of(nv, -1);
-  for (int j = 0; j < P.n_vars; ++j) level_of[pop_order[j]] = j;
+  for (int j = 0; j < P.n_vars; ++j) level_of[order[j]] = j;
   {
     std::vector<int32_t> vars;
     for (int v = 0; v < nv; ++v) if (is_var(v)) vars.push_back(v);
     if ((int)vars.size() != P.n_vars) { msg = "planner did not reach every variable"; return GS_EINVAL; }
     P.var_rank.assign(P.n_vars, 0);
     for (int j = 0; j < P.n_vars; ++j)
-      P.var_rank[j] = (int)(std::lower_bound(vars.begin(), vars.end(), pop_order[j]) - vars.begin());
+      P.var_rank[j] = (int)(std::lower_bound(vars.begin(), vars.end(), order[j]) - vars.begin());
   }
   for (int k = 0; k < ne; ++k) {
     const QEdge &e = q.edges[k];
@@ -174,7 +219,7 @@ int build_plan(const NormQuery &q, const LabelStats *st, bool want_domains, Plan
   std::vector<std::vector<int32_t>> refs(P.n_vars);   // levels referenced by each step
   for (int j = 0; j < P.n_vars; ++j) {
     PlanStep &S = P.steps[j];
-    int x = pop_order[j];
+    int x = order[j];
     S.qv = x;
     int pe = discovered_by_edge[x];
     if (pe >= 0 && level_of[(q.edges[pe].s == x) ? q.edges[pe].o : q.edges[pe].s] >= j) pe = -1;

@@ -134,7 +134,7 @@ def test_c1_sampled_rows_match_oracle(c1):
     for i, rec in enumerate(qs["queries"]):
         q = rec["query"]
         var_qv = [v for v, c in enumerate(q["qv_const"]) if c < 0]
-        info = gs.gs_plan_query(q)
+        info = gs.gs_plan_query(q, eng)
         root = info.order[0]
         col = var_qv.index(root)
         order = bfs_order(q, root)   # the oracle binds the root first: the restriction prunes at the top

@@ -58,11 +58,21 @@ def test_reconstructed_example_query():
             assert cnt == 2 and rows.tolist() == ex["expect_rows"], mode
             r = gs.gs_query_run(e, q)
             st = gs.gs_result_stats(r)
-            # Example 7.2: v2 = 0 and v2 = 4 die at level 0, v2 = 5 dies at level 1 (v0 in {6, 7} has no
-            # label-2 out-edge), v2 = 1 survives: level 0 holds {1, 5}, level 1 the single node v0 = 2
+            # Example 7.2: v2 = 0 and v2 = 4 die at level 0, v2 = 5 dies where v0 binds (v0 in {6, 7}
+            # has no label-2 out-edge), v2 = 1 survives: level 0 holds {1, 5}; v0's level holds only
+            # v0 = 2, below v2 = 1
             assert st.n_domains == (0 if mode == gs.GS_DOMAIN_OFF else 1)
-            assert st.level_nodes[0] == 2 and st.level_nodes[1] == 1
             assert sorted(gs.gs_result_level(r, 0)[1].tolist()) == [1, 5]
+            order = list(gs.gs_plan_query(q, e).order[:4])
+            assert order[0] == 2
+            lv = [gs.gs_result_level(r, j) for j in range(4)]
+            j0 = order.index(0)
+            assert set(lv[j0][1].tolist()) == {2}
+            for node in range(len(lv[j0][1])):
+                a = node
+                for j in range(j0, 0, -1):
+                    a = lv[j][0][a]
+                assert lv[0][1][a] == 1
             gs.gs_result_free(r)
         finally:
             gs.gs_engine_destroy(e)
@@ -184,7 +194,7 @@ def test_tree_levels_are_a_valid_binding_tree(c0):
     e = make_engine(trip, n, P)
     try:
         r = gs.gs_query_run(e, q)
-        info = gs.gs_plan_query(q)
+        info = gs.gs_plan_query(q, e)
         k = info.n_vars
         levels = [gs.gs_result_level(r, j) for j in range(k)]
         for j in range(1, k):
