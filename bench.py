@@ -86,6 +86,51 @@ def cpu_baseline(trip, qs, per_query_T, budget_s):
             "queries_per_s": done / secs if secs > 0 else None}
 
 
+def batched_set_leg(gs, eng, qset, wave=128):
+    """The batched query set (1024 queries of the four shapes, counts 1..1e7): batched in
+    waves of `wave` queries (count only, each wave's trees freed before the next) vs the
+    same queries one at a time; every count against the stored oracle count."""
+    import torch
+    queries = [q["query"] for q in qset["queries"]]
+    expect = [q["count"] for q in qset["queries"]]
+
+    def batched():
+        got, T = [], 0
+        for i in range(0, len(queries), wave):
+            rs = gs.gs_batch_run(eng, queries[i:i + wave], gs.GS_COUNT_ONLY)
+            got += [gs.gs_result_count(r) for r in rs]
+            T += sum(gs.gs_result_stats(r).t_total for r in rs)
+            for r in rs:
+                gs.gs_result_free(r)
+        return got, T
+
+    got, T = batched()   # warm-up (plans, graph keys, allocations) and parity
+    bad = [i for i, (c, e) in enumerate(zip(got, expect)) if c != e]
+    if bad:
+        raise SystemExit(f"batched set: count mismatch against the stored oracle counts: {bad[:10]}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    got, T = batched()
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    plain = []
+    for q in queries:
+        r = gs.gs_query_run(eng, q, gs.GS_COUNT_ONLY)
+        plain.append(gs.gs_result_count(r))
+        gs.gs_result_free(r)
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    if plain != expect:
+        raise SystemExit("batched set: plain counts differ from the stored oracle counts")
+    out = {"queries": len(queries), "wave": wave, "batched_queries_per_s": len(queries) / tb,
+           "plain_queries_per_s": len(queries) / tp, "speedup": tp / tb, "batched_ms": tb * 1e3,
+           "plain_ms": tp * 1e3, "traversed_triples": int(T), "batched_triples_per_s": T / tb,
+           "counts_match_oracle": True}
+    log(f"batched set: {out}")
+    return out
+
+
 def serve_leg(gs, eng, qset, rates, seconds, seed=7):
     """Open-loop Poisson arrivals at each rate, served with continuous batching; the same
     trace served one query at a time (FIFO) by the plain engine as the baseline."""
@@ -269,6 +314,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--no-graphs", action="store_true")
+    ap.add_argument("--no-batched-set", action="store_true")
     ap.add_argument("--copy-probe", action="store_true", help="run the HBM counter reference copy and exit")
     ap.add_argument("--summarize", choices=["trace", "traffic"], help="summarise rocprofv3 output and exit")
     ap.add_argument("--dir")
@@ -385,6 +431,11 @@ def main():
         log(f"batched with graphs: {gms:.2f} ms/step")
         gs.gs_engine_destroy(geng)
 
+    batched_set = None
+    c2 = os.path.join(ROOT, "workload", "data", "c2_queries.json")
+    if not args.no_batched_set and os.path.exists(c2) and args.workload == "c1":
+        batched_set = batched_set_leg(gs, eng, load_queryset("c2"))
+
     served = None
     c3 = os.path.join(ROOT, "workload", "data", "c3_queries.json")
     if not args.no_serve and os.path.exists(c3) and args.workload == "c1":
@@ -407,6 +458,7 @@ def main():
         "batched": {"queries_per_s": len(queries) / (ms_step / 1e3), "triples_per_s": value},
         "plain": plain,
         "batched_graphs": graphs,
+        "batched_set": batched_set,
         "served": served,
         "load_ms": load_ms,
         "roofline": roofline,

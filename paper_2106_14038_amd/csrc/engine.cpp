@@ -76,6 +76,8 @@ int load_triples(Engine &E, int64_t n, int32_t P, const gs_triple *t, int64_t m,
   if (n <= 0 || n > 2147483647LL) { set_error("vertex count must be in [1, 2^31-1]"); return GS_ERANGE; }
   if (P <= 0 || P > 65536) { set_error("label count must be in [1, 65536]"); return GS_ERANGE; }
   if (m < 0 || (m > 0 && !t)) { set_error("bad triple buffer"); return GS_EINVAL; }
+  // expansion tiles stage segment positions in 32 bits (see WaveTile)
+  if (m > (1ll << 32) - 4096) { set_error("more than 2^32 - 4096 triples"); return GS_EUNSUPPORTED; }
   HIPCHK(hipSetDevice(E.device));
   hipStream_t s = E.stream;
   const int64_t words = (n + 63) / 64;

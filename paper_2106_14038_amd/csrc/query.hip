@@ -650,7 +650,8 @@ __device__ __forceinline__ void wave_lds_sync() {
 // item p (entry a + p) belongs to node kmap[p] and reads entry base[i] + p of
 // that node's segment (or list).
 struct WaveTile {
-  int64_t base[kTileWork + 2];  // segment start minus the node's first item position in the tile
+  uint32_t base[kTileWork + 2]; // segment start minus the node's first item position in the tile, plus
+                                // kTileWork (>= 0; below 2^32 while the matrix has under 2^32 - 4096 entries)
   int32_t node[kTileWork + 2];  // local node index in the previous level
   uint8_t dg[kTileWork + 2];    // orientation | generator << 1 (see seg_ref)
   uint16_t kmap[kTileWork];     // item -> node; all zero between tiles
@@ -696,7 +697,7 @@ __device__ __forceinline__ void stage_tile(const IterScalars *it, const DTile &d
       woff = gld(it->nz_woff + k); r = gld(it->nz_lo + k); nd = gld(it->nz_node + k);
     }
     const int64_t s = woff - d.a;   // first item of the node, relative to the tile
-    W.base[i] = ref_lo(r) - s;
+    W.base[i] = (uint32_t)(ref_lo(r) - s + kTileWork);
     W.dg[i] = (uint8_t)(ref_dir(r) | (ref_gen(r) << 1));
     W.node[i] = nd;
     if (i > 0 && s < d.n) { W.kmap[s] = (uint16_t)i; scat = true; }
@@ -736,7 +737,7 @@ __device__ __forceinline__ const int32_t *seg_ids(const IterArgs &A, int dg) {
 __device__ __forceinline__ int32_t candidate(const IterArgs &A, const EState &E, const DStep &S, const WaveTile &W,
                                              int k, int p) {
   const int32_t *src = S.kind == STEP_LIST ? E.list : seg_ids(A, W.dg[k]);
-  return gld(src + W.base[k] + p);
+  return gld(src + ((int64_t)W.base[k] - kTileWork + p));
 }
 
 // gen: which bound segment the candidate was read from (see seg_ref); that
@@ -898,7 +899,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_offsets(const IterArgs A) {
 // item's output position is ranked first (tile offset + item for test-free
 // levels, + rank among the valid items otherwise); then each lane reads the
 // nodes and candidates of all its items before it issues their stores.
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_expand_write(const IterArgs A) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_expand_write(const IterArgs A) {
   __shared__ WaveTile Wt[kWaves];
   const IterScalars *it = A.it;
   if (sld(&it->abort)) return;
@@ -935,19 +936,19 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
     const int32_t wflags = sld(&es[e].wflags);
     int kk[R];
     for (int r = 0; r < R; ++r) kk[r] = take_node(W, r * 64 + lane);
-    int64_t li[R];   // output position of each item, -1: not a child
+    int32_t li[R];   // output position of each item, -1: not a child (levels stay below 2^31 nodes)
     if (wflags & EW_FREE) {
       for (int r = 0; r < R; ++r) {
         const int p = r * 64 + lane;
-        li[r] = p < n ? out0 + p : -1;
+        li[r] = p < n ? (int32_t)(out0 + p) : -1;
       }
     } else {
       const uint64_t *vw = (const uint64_t *)(valid + t * (kTileWork / 32));
-      int64_t before = out0;
+      int32_t before = (int32_t)out0;
       for (int r = 0; r < R; ++r) {
         const uint64_t bal = gld(vw + r);
-        li[r] = ((bal >> lane) & 1ull) ? before + __popcll(bal & lanemask_lt()) : -1;
-        before += __popcll(bal);
+        li[r] = ((bal >> lane) & 1ull) ? before + (int32_t)__popcll(bal & lanemask_lt()) : -1;
+        before += (int32_t)__popcll(bal);
       }
     }
     if (out) {
@@ -961,7 +962,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
           const int k = kk[r];
           node[r] = W.node[k];
           const int32_t *src = (wflags & EW_LIST) ? list : seg_ids(A, W.dg[k]);
-          c[r] = gld(src + W.base[k] + r * 64 + lane);
+          c[r] = gld(src + ((int64_t)W.base[k] - kTileWork + r * 64 + lane));
         }
       }
       for (int r = 0; r < R; ++r)

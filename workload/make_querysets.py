@@ -73,21 +73,22 @@ def _count_bt(q, work_cap):
 
 
 def batched_set(trip, n, pool, args, t0):
-    """Queries of the four shapes with random constants, spread over count decades [1,10) .. [1e6,1e7]."""
+    """Queries of the four shapes with random constants, spread over count decades [1,10) .. [1e6,1e7]
+    (exact counts: message passing for acyclic queries, backtracking with the work cap for cyclic ones)."""
     cells = {(sh, d): [] for sh in SHAPES for d in range(7)}
     per = -(-args.total // len(cells))
     for si, shape in enumerate(SHAPES):
         first = 0
         while first < args.max_candidates and any(len(cells[(shape, d)]) < per for d in range(7)):
             batch = workload.walk_queries(trip, n, 100 + si, shape, 64, const_prob=args.const_prob, first=first)
-            counts = pool.starmap(_count_bt, [(q, args.work_cap) for q in batch])
+            counts = pool.starmap(_count, [(q, args.work_cap) for q in batch])
             for i, (q, c) in enumerate(zip(batch, counts)):
                 if 1 <= c <= 10_000_000:
                     d = min(6, len(str(c)) - 1)
                     if len(cells[(shape, d)]) < per:
                         cells[(shape, d)].append({"shape": shape, "candidate": first + i, "count": int(c), "query": q})
             first += 64
-        print(shape, {d: len(cells[(shape, d)]) for d in range(7)}, f"({time.time() - t0:.0f}s)", flush=True)
+            print(shape, first, {d: len(cells[(shape, d)]) for d in range(7)}, f"({time.time() - t0:.0f}s)", flush=True)
     out = []
     for d in range(7):   # interleave so that a prefix covers every cell
         for sh in SHAPES:
