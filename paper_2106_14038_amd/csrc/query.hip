@@ -475,8 +475,11 @@ __global__ __launch_bounds__(kBlock) void k_lookup(const IterArgs A) {
       cnz += (hi > lo);
       cw += hi - lo;
     }
-    cnz = block_sum_i64(cnz, lds);
-    cw = block_sum_i64(cw, lds);
+    {   // one reduction for both: entries above bit 11, non-empty nodes (at most kTileNodes) below
+      const int64_t pk = block_sum_i64((cw << 11) | cnz, lds);
+      cnz = pk & 2047;
+      cw = pk >> 11;
+    }
     if (threadIdx.x == 0) acc.add(e, cnz, cw, p_nz, p_w, kEsStride);
     bnz += cnz;
     bw += cw;
@@ -569,9 +572,9 @@ __global__ __launch_bounds__(1024) void k_scan_nodes(const IterArgs A) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_nz_write(const IterArgs A) {
+  constexpr int NPT = kTileNodes / kBlock;   // consecutive nodes per thread
   __shared__ int64_t lds[kWaves];
-  __shared__ int64_t s_woff[kBlock];   // entry-local first entry of the round's non-empty nodes
-  __shared__ int ldi[kWaves];
+  __shared__ int64_t s_woff[kTileNodes];     // entry-local first entry of the tile's non-empty nodes
   __shared__ int sh_e;
   IterScalars *it = A.it;
   if (it->abort) return;
@@ -584,51 +587,62 @@ __global__ __launch_bounds__(kBlock) void k_nz_write(const IterArgs A) {
     if (threadIdx.x == 0) sh_e = ncur.at(A, t);
     __syncthreads();
     const int e = uniform(sh_e);
-    const int64_t i0 = (t - es[e].node_tile0) * kTileNodes, pn = es[e].prev_n;
-    const int64_t ew = es[e].w, etile0 = es[e].w_tile0;
+    const int64_t i0 = (t - es[e].node_tile0) * kTileNodes + (int64_t)NPT * threadIdx.x, pn = es[e].prev_n;
+    const int64_t ew = es[e].w, etile0 = es[e].w_tile0, wb = es[e].w_base, n0 = es[e].node0;
     int32_t *const cptr = es[e].cptr;
-    for (int r = 0; r < kTileNodes / kBlock; ++r) {
-      const int64_t i = i0 + r * kBlock + threadIdx.x;
-      int64_t len = 0, lo = 0;
-      if (i < pn) { const int64_t gn = es[e].node0 + i; len = it->len[gn]; lo = it->lo[gn]; }
-      int ftot;
-      const int pos = block_excl_flag(len > 0, ftot, ldi);
-      int64_t wtot;
-      const int64_t wpos = block_excl_scan_i64(len, wtot, lds);
-      if (cptr && i < pn) cptr[i] = (int32_t)(run_w + wpos - es[e].w_base);   // first child of node i
-      if (len > 0) {
-        const int64_t k = run_nz + pos;
-        const int64_t woff = run_w + wpos - es[e].w_base;
-        it->nz_node[k] = (int32_t)i;
-        it->nz_lo[k] = lo;
-        it->nz_woff[k] = woff;
-        s_woff[pos] = woff;
-      }
-      __syncthreads();
-      // the tiles whose first entry lies among this round's entries [r0, r0 + wtot):
-      // each takes the last of the round's nodes starting at or before it
-      const int64_t r0 = run_w - es[e].w_base;
-      for (int64_t j = ceil_div(r0, kTileWork) + threadIdx.x; j * kTileWork < r0 + wtot; j += blockDim.x) {
-        const int64_t a = j * kTileWork;
-        int lo_k = 0, hi_k = ftot - 1;   // s_woff[0] == r0 <= a
-        while (lo_k < hi_k) {
-          const int mid = (lo_k + hi_k + 1) >> 1;
-          if (s_woff[mid] <= a) lo_k = mid; else hi_k = mid - 1;
-        }
-        DTile d;
-        d.k0 = run_nz + lo_k;
-        d.a = a;
-        d.out = 0;
-        d.e = e;
-        d.n = (int32_t)min((int64_t)kTileWork, ew - a);
-        d.cnt = 0;
-        d.pad = 0;
-        it->tiles[etile0 + j] = d;
-      }
-      __syncthreads();   // s_woff is refilled by the next round
-      run_nz += ftot;
-      run_w += wtot;
+    int64_t len[NPT], lo[NPT], ws = 0;
+    int nzc = 0;
+    for (int k = 0; k < NPT; ++k) {
+      len[k] = lo[k] = 0;
+      if (i0 + k < pn) { len[k] = gld(it->len + n0 + i0 + k); lo[k] = gld(it->lo + n0 + i0 + k); }
+      nzc += len[k] > 0;
+      ws += len[k];
     }
+    // one scan for both counts: entries above bit 11, non-empty nodes (at most kTileNodes) below
+    int64_t tot;
+    const int64_t ex = block_excl_scan_i64((ws << 11) | nzc, tot, lds);
+    int pos = (int)(ex & 2047);
+    int64_t wpos = ex >> 11;
+    const int ftot = (int)(tot & 2047);
+    const int64_t wtot = tot >> 11;
+    for (int k = 0; k < NPT; ++k) {
+      const int64_t i = i0 + k;
+      const int64_t woff = run_w + wpos - wb;   // entry-local first entry of node i
+      if (cptr && i < pn) cptr[i] = (int32_t)woff;
+      if (len[k] > 0) {
+        const int64_t kk = run_nz + pos;
+        it->nz_node[kk] = (int32_t)i;
+        it->nz_lo[kk] = lo[k];
+        it->nz_woff[kk] = woff;
+        s_woff[pos] = woff;
+        ++pos;
+      }
+      wpos += len[k];
+    }
+    __syncthreads();
+    // the tiles whose first entry lies among this node tile's entries [r0, r0 + wtot):
+    // each takes the last of the tile's nodes starting at or before it
+    const int64_t r0 = run_w - wb;
+    for (int64_t j = ceil_div(r0, kTileWork) + threadIdx.x; j * kTileWork < r0 + wtot; j += blockDim.x) {
+      const int64_t a = j * kTileWork;
+      int lo_k = 0, hi_k = ftot - 1;   // s_woff[0] == r0 <= a
+      while (lo_k < hi_k) {
+        const int mid = (lo_k + hi_k + 1) >> 1;
+        if (s_woff[mid] <= a) lo_k = mid; else hi_k = mid - 1;
+      }
+      DTile d;
+      d.k0 = run_nz + lo_k;
+      d.a = a;
+      d.out = 0;
+      d.e = e;
+      d.n = (int32_t)min((int64_t)kTileWork, ew - a);
+      d.cnt = 0;
+      d.pad = 0;
+      it->tiles[etile0 + j] = d;
+    }
+    __syncthreads();   // s_woff is refilled by the next tile
+    run_nz += ftot;
+    run_w += wtot;
   }
 }
 
