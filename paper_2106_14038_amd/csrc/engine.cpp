@@ -309,7 +309,7 @@ void compile_query(const Engine &E, QInfo &qi, bool count_only, int slot, Tables
 // Work lists of one iteration: query qs[i] produces its level `level[i]`.
 void build_iteration(const Tables &T, const std::vector<const QInfo *> &qs, const std::vector<int> &level,
                      IterLists &L) {
-  L.ents.clear(); L.doms.clear(); L.clears.clear(); L.seeds.clear(); L.has_list = 0;
+  L.ents.clear(); L.doms.clear(); L.clears.clear(); L.seeds.clear(); L.has_list = 0; L.has_tested = 0;
   for (size_t i = 0; i < qs.size(); ++i) {
     const QInfo &qi = *qs[i];
     const int t = level[i];
@@ -324,6 +324,11 @@ void build_iteration(const Tables &T, const std::vector<const QInfo *> &qs, cons
       e.ndom++;
     }
     if (qi.plan.steps[t].kind == STEP_LIST) L.has_list = 1;
+    {   // the device's test-free rule (no filter beyond a list's own, no check, no self loop), from the plan
+      const PlanStep &ps = qi.plan.steps[t];
+      const bool filtered = ps.kind == STEP_LIST ? false : !ps.filters.empty();
+      if (filtered || !ps.checks.empty() || !ps.self_labels.empty()) L.has_tested = 1;
+    }
     L.ents.push_back(e);
   }
 }
@@ -336,6 +341,7 @@ void account_iteration(Engine &E, const hipEvent_t *ev, const IterScalars &I, co
   ran[KS_SEED] = !L.seeds.empty();
   ran[KS_LIST_COUNT] = ran[KS_LIST_SCAN] = ran[KS_LIST_WRITE] = L.has_list != 0;
   ran[KS_DOM_FRONTIER] = ran[KS_DOM_PUSH] = ran[KS_DOM_PULL] = !L.doms.empty();
+  ran[KS_EXPAND_COUNT] = ran[KS_TILE_OFFSETS] = L.has_tested != 0;
   for (int k = 0; k < KS_N; ++k) {
     if (!ran[k]) continue;
     float kms = 0;
@@ -471,6 +477,7 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
     A.D = dom_off[t + 1] - dom_off[t];
     A.nclear = clr_off[t + 1] - clr_off[t];
     A.has_list = its[t].has_list;
+    A.has_tested = its[t].has_tested;
     A.grid = E.grid;
     A.wgrid = E.wgrid;
     A.steps = (const DStep *)dp(tab_off + o_steps);

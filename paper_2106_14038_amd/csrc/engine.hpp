@@ -118,6 +118,7 @@ struct IterLists {                   // host work lists of one iteration
   std::vector<uint64_t *> clears;
   std::vector<DSeed> seeds;
   int32_t has_list = 0;
+  int32_t has_tested = 0;
 };
 
 int plan_query(const Engine &E, const gs_query &q, QInfo &qi, std::string &msg);

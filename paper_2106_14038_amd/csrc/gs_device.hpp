@@ -64,6 +64,11 @@ struct DDomain {
   int32_t pad;
 };
 
+// A step whose candidates face no test: every candidate entry becomes a child.
+__host__ __device__ inline bool step_test_free(const DStep &S) {
+  return S.nfilt == S.list_nfilt && S.nchk == 0 && S.nself == 0;
+}
+
 // Host-built per-iteration work list entry: query q produces level `level`
 // using step program `step`.
 struct DEntry { int32_t q, level, step, dom0, ndom, pad; };

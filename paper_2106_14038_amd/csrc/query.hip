@@ -71,9 +71,7 @@ struct EntryAcc {
   }
 };
 // A step whose candidates face no test: every candidate entry becomes a child.
-__device__ __forceinline__ bool test_free(const DStep &S) {
-  return S.nfilt == S.list_nfilt && S.nchk == 0 && S.nself == 0;
-}
+__device__ __forceinline__ bool test_free(const DStep &S) { return step_test_free(S); }
 
 // Per-node segment reference: the start of the segment the node's candidates
 // are read from, the orientation of that segment, and which of the step's
@@ -936,7 +934,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
   for (; t < ntiles; t += stride) {
     stage_tile(it, d1, nw1, s1, W);
     const int e = d1.e;
-    const int64_t out0 = d1.out;
+    const int64_t out0 = d1.out, a0 = d1.a;
     const int n = d1.n;
     // next tile: its window loads now (its records arrived during the previous tile), the one after: its records
     const int64_t tn = t + stride;
@@ -951,10 +949,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
     int kk[R];
     for (int r = 0; r < R; ++r) kk[r] = take_node(W, r * 64 + lane);
     int32_t li[R];   // output position of each item, -1: not a child (levels stay below 2^31 nodes)
-    if (wflags & EW_FREE) {
+    if (wflags & EW_FREE) {   // every entry is a child: a tile's children start at its first entry
       for (int r = 0; r < R; ++r) {
         const int p = r * 64 + lane;
-        li[r] = p < n ? (int32_t)(out0 + p) : -1;
+        li[r] = p < n ? (int32_t)(a0 + p) : -1;
       }
     } else {
       const uint64_t *vw = (const uint64_t *)(valid + t * (kTileWork / 32));
@@ -1064,9 +1062,9 @@ hipError_t launch_iteration(const IterArgs &A, hipStream_t s, hipEvent_t *ev) {
   GS_LAUNCH(KS_LOOKUP, k_lookup, G, B);
   GS_LAUNCH(KS_SCAN_NODES, k_scan_nodes, dim3(1), W1);
   GS_LAUNCH(KS_NZ_WRITE, k_nz_write, G, B);
-  GS_LAUNCH(KS_EXPAND_COUNT, k_expand_count, G, B);
+  if (A.has_tested) GS_LAUNCH(KS_EXPAND_COUNT, k_expand_count, G, B);
   GS_LAUNCH(KS_SCAN_EXPAND, k_scan_expand, dim3(1), W1);
-  GS_LAUNCH(KS_TILE_OFFSETS, k_tile_offsets, G, B);
+  if (A.has_tested) GS_LAUNCH(KS_TILE_OFFSETS, k_tile_offsets, G, B);
   GS_LAUNCH(KS_EXPAND_WRITE, k_expand_write, dim3((unsigned)A.wgrid), B);
 #undef GS_LAUNCH
   return hipGetLastError();

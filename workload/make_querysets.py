@@ -9,8 +9,8 @@ same stream is tried. Run from the repository root:
     python -m workload.make_querysets [--set c1|c2|c3] [--scale 1.0] [--per-shape 25] [--total 1024]
 
 c1: 25 queries per shape (chain-4, star-5, snowflake-8, triangle), counts in
-[1, 1e9]; c2: the batched set, the four shapes with random constants spread
-over count decades up to 1e7; c3: the served set, mixed walk shapes with 1-12
+[1, 1e9]; c2: the batched set, 256 queries per shape with random constants and
+counts in [1, 1e7] (they spread over the decades; the histogram is printed); c3: the served set, mixed walk shapes with 1-12
 edges and 0-2 constants, counts up to 1e7. Output:
 workload/data/<set>[s<scale>]_queries.json.
 """
@@ -73,27 +73,28 @@ def _count_bt(q, work_cap):
 
 
 def batched_set(trip, n, pool, args, t0):
-    """Queries of the four shapes with random constants, spread over count decades [1,10) .. [1e6,1e7]
-    (exact counts: message passing for acyclic queries, backtracking with the work cap for cyclic ones)."""
-    cells = {(sh, d): [] for sh in SHAPES for d in range(7)}
-    per = -(-args.total // len(cells))
+    """Queries of the four shapes with random constants: per shape the first total/4 walk
+    candidates whose exact count is in [1, 1e7] (message passing for acyclic queries,
+    backtracking with the work cap for cyclic ones); the count histogram by decade is
+    printed."""
+    per = args.total // len(SHAPES)
+    out = []
     for si, shape in enumerate(SHAPES):
-        first = 0
-        while first < args.max_candidates and any(len(cells[(shape, d)]) < per for d in range(7)):
+        got, first = [], 0
+        while len(got) < per and first < args.max_candidates:
             batch = workload.walk_queries(trip, n, 100 + si, shape, 64, const_prob=args.const_prob, first=first)
             counts = pool.starmap(_count, [(q, args.work_cap) for q in batch])
             for i, (q, c) in enumerate(zip(batch, counts)):
-                if 1 <= c <= 10_000_000:
-                    d = min(6, len(str(c)) - 1)
-                    if len(cells[(shape, d)]) < per:
-                        cells[(shape, d)].append({"shape": shape, "candidate": first + i, "count": int(c), "query": q})
+                if 1 <= c <= 10_000_000 and len(got) < per:
+                    got.append({"shape": shape, "candidate": first + i, "count": int(c), "query": q})
             first += 64
-            print(shape, first, {d: len(cells[(shape, d)]) for d in range(7)}, f"({time.time() - t0:.0f}s)", flush=True)
-    out = []
-    for d in range(7):   # interleave so that a prefix covers every cell
-        for sh in SHAPES:
-            out += cells[(sh, d)]
-    return out[:args.total]
+            print(shape, first, len(got), f"({time.time() - t0:.0f}s)", flush=True)
+        hist = [0] * 8
+        for g in got:
+            hist[min(7, len(str(g["count"])) - 1)] += 1
+        print(shape, "decades", hist, flush=True)
+        out += got
+    return out
 
 
 def served_set(trip, n, pool, args, t0):
