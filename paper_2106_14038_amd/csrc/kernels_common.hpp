@@ -106,29 +106,32 @@ __device__ __forceinline__ int64_t block_sum_i64(int64_t v, int64_t *lds) {
   return t;
 }
 
-// Exclusive scan over an index space [0, L) by one workgroup of any size.
-// get(i) returns the value, set(i, prefix) stores the exclusive prefix.
-// lds: blockDim.x int64 entries. Returns the total.
+// Exclusive scan over an index space [0, L) by one workgroup (size a multiple
+// of 64, at most 64 waves). get(i) returns the value, set(i, prefix) stores the
+// exclusive prefix. Each thread takes a contiguous chunk; the chunk sums are
+// scanned within waves by shuffles and across waves through lds (at least one
+// entry per wave). Returns the total.
 template <class Get, class Set>
 __device__ int64_t wg_scan(int64_t L, Get get, Set set, int64_t *lds) {
   const int t = threadIdx.x, T = blockDim.x;
+  const int lane = t & 63, w = t >> 6, nw = T >> 6;
   const int64_t per = (L + T - 1) / T;
   const int64_t b = min(L, (int64_t)t * per), e = min(L, b + per);
   int64_t s = 0;
   for (int64_t i = b; i < e; ++i) s += get(i);
-  lds[t] = s;
+  const int64_t inc = wave_incl_scan_i64(s);
+  if (lane == 63) lds[w] = inc;
   __syncthreads();
-  for (int off = 1; off < T; off <<= 1) {
-    int64_t v = (t >= off) ? lds[t - off] : 0;
-    __syncthreads();
-    lds[t] += v;
-    __syncthreads();
+  int64_t off = 0, total = 0;
+  for (int i = 0; i < nw; ++i) {
+    const int64_t c = lds[i];
+    if (i < w) off += c;
+    total += c;
   }
-  const int64_t total = lds[T - 1];
-  int64_t run = lds[t] - s;
   __syncthreads();
+  int64_t run = off + inc - s;
   for (int64_t i = b; i < e; ++i) {
-    int64_t v = get(i);
+    const int64_t v = get(i);
     set(i, run);
     run += v;
   }

@@ -34,6 +34,23 @@ __device__ __forceinline__ void *arena_alloc(DArena *a, char *base, uint64_t byt
   return base + at;
 }
 
+// Several arrays from one arena bump (one atomic instead of one per array).
+template <int K>
+__device__ __forceinline__ void arena_alloc_many(DArena *a, char *base, const uint64_t (&bytes)[K], void *(&out)[K]) {
+  uint64_t tot = 0, off[K];
+  for (int k = 0; k < K; ++k) { off[k] = tot; tot += (bytes[k] + 255ull) & ~255ull; }
+  uint64_t at = 0;
+  if (tot) {
+    at = atomicAdd((unsigned long long *)&a->top, (unsigned long long)tot);
+    if (at + tot > a->cap) {
+      atomicOr(&a->overflow, 1);
+      for (int k = 0; k < K; ++k) out[k] = nullptr;
+      return;
+    }
+  }
+  for (int k = 0; k < K; ++k) out[k] = base + at + off[k];
+}
+
 // last entry e with key(e) <= t (key non-decreasing)
 template <class Key>
 __device__ __forceinline__ int last_le(int E, int64_t t, Key key) {
@@ -132,8 +149,11 @@ __global__ __launch_bounds__(1024) void k_it_setup(const IterArgs A) {
     it->nodes_total = nodes;
     it->node_tiles = ntiles;
     it->list_tiles = ltiles;
-    it->lo = (int64_t *)arena_alloc(A.scratch, A.scratch_base, sizeof(int64_t) * nodes);
-    it->len = (int64_t *)arena_alloc(A.scratch, A.scratch_base, sizeof(int64_t) * nodes);
+    const uint64_t sz[2] = {sizeof(int64_t) * (uint64_t)nodes, sizeof(int64_t) * (uint64_t)nodes};
+    void *p[2];
+    arena_alloc_many(A.scratch, A.scratch_base, sz, p);
+    it->lo = (int64_t *)p[0];
+    it->len = (int64_t *)p[1];
     if (A.scratch->overflow) it->abort = 1;
   }
 }
@@ -546,11 +566,16 @@ __global__ __launch_bounds__(1024) void k_scan_nodes(const IterArgs A) {
     it->nz_total = nz;
     it->w_total = w;
     it->work_tiles = wt;
-    it->nz_node = (int32_t *)arena_alloc(A.scratch, A.scratch_base, sizeof(int32_t) * nz);
-    it->nz_lo = (int64_t *)arena_alloc(A.scratch, A.scratch_base, sizeof(int64_t) * nz);
-    it->nz_woff = (int64_t *)arena_alloc(A.scratch, A.scratch_base, sizeof(int64_t) * nz);
-    it->valid = (uint32_t *)arena_alloc(A.scratch, A.scratch_base, (uint64_t)wt * (kTileWork / 8));
-    it->tiles = (DTile *)arena_alloc(A.scratch, A.scratch_base, sizeof(DTile) * (uint64_t)(wt + 1));
+    const uint64_t sz[5] = {sizeof(int32_t) * (uint64_t)nz, sizeof(int64_t) * (uint64_t)nz,
+                            sizeof(int64_t) * (uint64_t)nz, (uint64_t)wt * (kTileWork / 8),
+                            sizeof(DTile) * (uint64_t)(wt + 1)};
+    void *p[5];
+    arena_alloc_many(A.scratch, A.scratch_base, sz, p);
+    it->nz_node = (int32_t *)p[0];
+    it->nz_lo = (int64_t *)p[1];
+    it->nz_woff = (int64_t *)p[2];
+    it->valid = (uint32_t *)p[3];
+    it->tiles = (DTile *)p[4];
     if (A.scratch->overflow) {
       it->abort = 1;
     } else {
