@@ -809,7 +809,7 @@ __device__ __forceinline__ bool test_candidate(const IterArgs &A, const EState &
 // entries per tile, per entry and per workgroup. A workgroup takes a
 // contiguous tile range; test-free entries in it are passed over whole, the
 // tiles of tested entries are dealt to its waves.
-__global__ __launch_bounds__(kBlock) void k_expand_count(const IterArgs A) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_expand_count(const IterArgs A) {
   __shared__ WaveTile Wt[kWaves];
   __shared__ int64_t red4[kWaves][4];
   IterScalars *it = A.it;
@@ -839,7 +839,7 @@ __global__ __launch_bounds__(kBlock) void k_expand_count(const IterArgs A) {
       const DTile dt = it->tiles[u], dn = it->tiles[u + 1];
       const int nwin = win_nodes(dt, dn);
       stage_tile(it, dt, nwin, load_slot(it, dt, nwin), W);
-      uint64_t bal[kItemsPerLane];
+      uint64_t *vw = (uint64_t *)(it->valid + u * (kTileWork / 32));
       int c_tile = 0;
       for (int r = 0; r < kItemsPerLane; ++r) {
         const int p = r * 64 + lane;
@@ -849,15 +849,12 @@ __global__ __launch_bounds__(kBlock) void k_expand_count(const IterArgs A) {
           const int32_t c = candidate(A, E, S, W, k, p);
           ok = test_candidate(A, E, S, W.node[k], W.dg[k] >> 1, c, pr, ft, ct);
         }
-        bal[r] = __ballot(ok);
-        c_tile += __popcll(bal[r]);
+        const uint64_t bal = __ballot(ok);
+        if (lane == 0) gst(vw + r, bal);
+        c_tile += __popcll(bal);
       }
       wave_lds_sync();
-      if (lane == 0) {
-        uint64_t *vw = (uint64_t *)(it->valid + u * (kTileWork / 32));
-        for (int r = 0; r < kItemsPerLane; ++r) gst(vw + r, bal[r]);
-        it->tiles[u].cnt = c_tile;
-      }
+      if (lane == 0) it->tiles[u].cnt = c_tile;
       e_cnt += c_tile;
     }
     // this wave's share of the entry and of its query's probes
