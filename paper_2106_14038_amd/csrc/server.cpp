@@ -260,22 +260,15 @@ hipError_t upload_slot(ServerImpl &S, Active *a, hipStream_t s) {
 }
 
 // Copy a finished query out of the ring into a result that owns host memory.
-int retire(ServerImpl &S, Active *a, const int64_t *lvl_n_all, hipStream_t s) {
+// lp_all, lc_all, qs_all, lvl_n_all: host copies of the slots' level pointers, counters and sizes.
+int retire(ServerImpl &S, Active *a, int32_t *const *lp_all, int32_t *const *lc_all, const int64_t *qs_all,
+           const int64_t *lvl_n_all, hipStream_t s) {
   Engine &E = *S.E;
   Result *R = new Result();
   R->eng = &E;
-  std::vector<int32_t *> lp(kMaxLevels, nullptr), lc(kMaxLevels, nullptr);
-  std::vector<int64_t> qs(QS_N);
-  hipError_t e = hipMemcpyAsync(lp.data(), S.d_lvlp + (size_t)a->slot * kMaxLevels, sizeof(void *) * kMaxLevels,
-                                hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(lc.data(), S.d_lvlc + (size_t)a->slot * kMaxLevels, sizeof(void *) * kMaxLevels,
-                       hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(qs.data(), S.d_qs + (size_t)a->slot * QS_N, 8 * QS_N, hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) { delete R; return GS_EDEVICE; }
-  fill_result(*R, a->qi, a->count_only, lp.data(), lc.data(), lvl_n_all + (size_t)a->slot * kMaxLevels, qs.data(), 0,
+  hipError_t e = hipSuccess;
+  const size_t lv = (size_t)a->slot * kMaxLevels;
+  fill_result(*R, a->qi, a->count_only, lp_all + lv, lc_all + lv, lvl_n_all + lv, qs_all + (size_t)a->slot * QS_N, 0,
               0);
   R->host_owned = true;
   if (!a->count_only && R->count > 0 && R->k > 0) {
@@ -311,7 +304,8 @@ void loop(ServerImpl &S) {
   Engine &E = *S.E;
   hipStream_t s = E.stream;
   (void)hipSetDevice(E.device);
-  std::vector<int64_t> lvl_n((size_t)S.cap * kMaxLevels);
+  std::vector<int64_t> lvl_n((size_t)S.cap * kMaxLevels), qs_all((size_t)S.cap * QS_N);
+  std::vector<int32_t *> lp_all((size_t)S.cap * kMaxLevels), lc_all((size_t)S.cap * kMaxLevels);
   const bool prof = E.opt.profile_kernels != 0;
   for (;;) {
     std::vector<Active *> fresh;
@@ -361,13 +355,13 @@ void loop(ServerImpl &S) {
 
     // this iteration's work lists
     IterLists L;
+    IterLists one;
+    std::vector<const QInfo *> qv(1);
+    std::vector<int> lv(1);
     for (Active *a : S.active) {
-      IterLists one;
-      std::vector<const QInfo *> qv{&a->qi};
-      std::vector<int> lv{a->level};
-      QInfo q2 = a->qi;   // tables of this query are local: seed0 = dom0 = 0
-      q2.seed0 = 0; q2.dom0 = 0;
-      qv[0] = &q2;
+      // tables of this query are local: seed0 = dom0 = 0 (set once at admission)
+      qv[0] = &a->qi;
+      lv[0] = a->level;
       build_iteration(a->T, qv, lv, one);
       for (DEntry e : one.ents) { e.dom0 += (int32_t)L.doms.size(); L.ents.push_back(e); }
       L.doms.insert(L.doms.end(), one.doms.begin(), one.doms.end());
@@ -410,6 +404,19 @@ void loop(ServerImpl &S) {
     if (e != hipSuccess) { set_error(hipGetErrorString(e)); fail_all(S, GS_EDEVICE); continue; }
     if (prof) account_iteration(E, E.events.data(), I, L, 0);
 
+    // level pointers and counters of every slot, once, when some query finishes now
+    bool finishing = false;
+    for (Active *a : S.active)
+      if (lvl_n[(size_t)a->slot * kMaxLevels + a->level] >= 0 && !ar[1].overflow && a->level + 1 == a->qi.plan.n_vars)
+        finishing = true;
+    if (finishing) {
+      e = hipMemcpyAsync(lp_all.data(), S.d_lvlp, sizeof(void *) * lp_all.size(), hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipMemcpyAsync(lc_all.data(), S.d_lvlc, sizeof(void *) * lc_all.size(), hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipMemcpyAsync(qs_all.data(), S.d_qs, 8 * qs_all.size(), hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) { set_error(hipGetErrorString(e)); fail_all(S, GS_EDEVICE); continue; }
+    }
+
     // the iteration's region of the ring
     const uint64_t rid = S.next_region++;
     const uint64_t used_end = std::min<uint64_t>(ar[0].top, whi);
@@ -435,7 +442,7 @@ void loop(ServerImpl &S) {
       }
       a->level++;
       if (a->level == a->qi.plan.n_vars) {   // rows leave the ring now: the new level needs no reference
-        const int rc = retire(S, a, lvl_n.data(), s);
+        const int rc = retire(S, a, lp_all.data(), lc_all.data(), qs_all.data(), lvl_n.data(), s);
         if (rc != GS_OK) finish(S, a->req.ticket, rc, nullptr);
         release(S, a);
         delete a;
