@@ -309,7 +309,7 @@ void compile_query(const Engine &E, QInfo &qi, bool count_only, int slot, Tables
 // Work lists of one iteration: query qs[i] produces its level `level[i]`.
 void build_iteration(const Tables &T, const std::vector<const QInfo *> &qs, const std::vector<int> &level,
                      IterLists &L) {
-  L.ents.clear(); L.doms.clear(); L.clears.clear(); L.seeds.clear(); L.has_list = 0; L.has_tested = 0;
+  L.ents.clear(); L.doms.clear(); L.clears.clear(); L.seeds.clear(); L.has_list = 0; L.has_tested = 0; L.has_checks = 0;
   for (size_t i = 0; i < qs.size(); ++i) {
     const QInfo &qi = *qs[i];
     const int t = level[i];
@@ -328,6 +328,7 @@ void build_iteration(const Tables &T, const std::vector<const QInfo *> &qs, cons
       const PlanStep &ps = qi.plan.steps[t];
       const bool filtered = ps.kind == STEP_LIST ? false : !ps.filters.empty();
       if (filtered || !ps.checks.empty() || !ps.self_labels.empty()) L.has_tested = 1;
+      if (!ps.checks.empty()) L.has_checks = 1;
     }
     L.ents.push_back(e);
   }
@@ -478,6 +479,7 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
     A.nclear = clr_off[t + 1] - clr_off[t];
     A.has_list = its[t].has_list;
     A.has_tested = its[t].has_tested;
+    A.has_checks = its[t].has_checks;
     A.grid = E.grid;
     A.wgrid = E.wgrid;
     A.steps = (const DStep *)dp(tab_off + o_steps);

@@ -119,6 +119,7 @@ struct IterLists {                   // host work lists of one iteration
   std::vector<DSeed> seeds;
   int32_t has_list = 0;
   int32_t has_tested = 0;
+  int32_t has_checks = 0;
 };
 
 int plan_query(const Engine &E, const gs_query &q, QInfo &qi, std::string &msg);

@@ -118,6 +118,9 @@ struct IterScalars {
   int64_t *len;            // per node: segment length
   int32_t *nz_node;        // compacted non-empty nodes: local node index
   int64_t *nz_lo, *nz_woff;// their segment start and entry-local work offset
+  // levels with exact checks: bounds of the first tested segment of each node (the
+  // check the count pass makes first), per node and per non-empty node
+  int64_t *chk_lo, *chk_hi, *nz_chk_lo, *nz_chk_hi;
   uint32_t *valid;         // expansion validity bits, kTileWork bits per work tile
   DTile *tiles;            // work_tiles + 1 records (the last one a sentinel)
   int32_t *list_buf;

@@ -149,11 +149,14 @@ __global__ __launch_bounds__(1024) void k_it_setup(const IterArgs A) {
     it->nodes_total = nodes;
     it->node_tiles = ntiles;
     it->list_tiles = ltiles;
-    const uint64_t sz[2] = {sizeof(int64_t) * (uint64_t)nodes, sizeof(int64_t) * (uint64_t)nodes};
-    void *p[2];
+    const uint64_t b8 = sizeof(int64_t) * (uint64_t)nodes;
+    const uint64_t sz[4] = {b8, b8, A.has_checks ? b8 : 0, A.has_checks ? b8 : 0};
+    void *p[4];
     arena_alloc_many(A.scratch, A.scratch_base, sz, p);
     it->lo = (int64_t *)p[0];
     it->len = (int64_t *)p[1];
+    it->chk_lo = (int64_t *)p[2];
+    it->chk_hi = (int64_t *)p[3];
     if (A.scratch->overflow) it->abort = 1;
   }
 }
@@ -477,11 +480,19 @@ __global__ __launch_bounds__(kBlock) void k_lookup(const IterArgs A) {
       int dir = S.dir, gen = 0;
       if (S.kind != STEP_LIST) {
         label_range(S.dir ? A.g.lab[1] : A.g.lab[0], ra[r], re[r], S.label, lo, hi, probes);
+        const int64_t plo = lo, phi = hi;
+        int64_t c0lo = 0, c0hi = 0;
         for (int k = 0; k < min(S.nchk, kMaxGen) && hi > lo; ++k) {   // read the shortest bound segment
           const DCheck ck = A.checks[S.chk0 + k];
           int64_t clo, chi;
           seg_find(A.g, ck.dir, es[e].prev[(int64_t)ck.col * pn + i], ck.label, clo, chi, probes);
+          if (k == 0) { c0lo = clo; c0hi = chi; }
           if (chi - clo < hi - lo) { lo = clo; hi = chi; dir = ck.dir; gen = k + 1; }
+        }
+        if (S.nchk > 0) {   // the first check the count pass makes: the parent's segment when check 0 generates
+          const int64_t gn = es[e].node0 + i;
+          it->chk_lo[gn] = gen == 1 ? plo : c0lo;
+          it->chk_hi[gn] = gen == 1 ? phi : c0hi;
         }
       } else {
         hi = es[e].list_n;
@@ -566,16 +577,18 @@ __global__ __launch_bounds__(1024) void k_scan_nodes(const IterArgs A) {
     it->nz_total = nz;
     it->w_total = w;
     it->work_tiles = wt;
-    const uint64_t sz[5] = {sizeof(int32_t) * (uint64_t)nz, sizeof(int64_t) * (uint64_t)nz,
-                            sizeof(int64_t) * (uint64_t)nz, (uint64_t)wt * (kTileWork / 8),
-                            sizeof(DTile) * (uint64_t)(wt + 1)};
-    void *p[5];
+    const uint64_t b8 = sizeof(int64_t) * (uint64_t)nz;
+    const uint64_t sz[7] = {sizeof(int32_t) * (uint64_t)nz, b8, b8, (uint64_t)wt * (kTileWork / 8),
+                            sizeof(DTile) * (uint64_t)(wt + 1), A.has_checks ? b8 : 0, A.has_checks ? b8 : 0};
+    void *p[7];
     arena_alloc_many(A.scratch, A.scratch_base, sz, p);
     it->nz_node = (int32_t *)p[0];
     it->nz_lo = (int64_t *)p[1];
     it->nz_woff = (int64_t *)p[2];
     it->valid = (uint32_t *)p[3];
     it->tiles = (DTile *)p[4];
+    it->nz_chk_lo = (int64_t *)p[5];
+    it->nz_chk_hi = (int64_t *)p[6];
     if (A.scratch->overflow) {
       it->abort = 1;
     } else {
@@ -613,6 +626,7 @@ __global__ __launch_bounds__(kBlock) void k_nz_write(const IterArgs A) {
     const int64_t i0 = (t - es[e].node_tile0) * kTileNodes + (int64_t)NPT * threadIdx.x, pn = es[e].prev_n;
     const int64_t ew = es[e].w, etile0 = es[e].w_tile0, wb = es[e].w_base, n0 = es[e].node0;
     int32_t *const cptr = es[e].cptr;
+    const bool checked = A.steps[A.ent[e].step].nchk > 0 && A.steps[A.ent[e].step].kind != STEP_LIST;
     int64_t len[NPT], lo[NPT], ws = 0;
     int nzc = 0;
     for (int k = 0; k < NPT; ++k) {
@@ -637,6 +651,10 @@ __global__ __launch_bounds__(kBlock) void k_nz_write(const IterArgs A) {
         it->nz_node[kk] = (int32_t)i;
         it->nz_lo[kk] = lo[k];
         it->nz_woff[kk] = woff;
+        if (checked) {
+          it->nz_chk_lo[kk] = gld(it->chk_lo + n0 + i);
+          it->nz_chk_hi[kk] = gld(it->chk_hi + n0 + i);
+        }
         s_woff[pos] = woff;
         ++pos;
       }
@@ -779,14 +797,29 @@ __device__ __forceinline__ int32_t candidate(const IterArgs &A, const EState &E,
 
 // gen: which bound segment the candidate was read from (see seg_ref); that
 // check is replaced by the parent edge's.
+// clo/chi: bounds of the first tested segment (found by the lookup), searched
+// directly; the others are located by row and label first.
 __device__ __forceinline__ bool test_candidate(const IterArgs &A, const EState &E, const DStep &S, int32_t node,
-                                               int gen, int32_t c, int &probes, int &ftests, int &ctests) {
+                                               int gen, int64_t clo, int64_t chi, int32_t c, int &probes, int &ftests,
+                                               int &ctests) {
   for (int f = S.list_nfilt; f < S.nfilt; ++f) {
     ++ftests;
     if (!bit_test(A.filt[S.filt0 + f], c)) return false;
   }
   for (int k = 0; k < S.nchk; ++k) {
     ++ctests;
+    if (k == 0) {
+      const int dir0 = gen == 1 ? S.dir : A.checks[S.chk0].dir;
+      const int32_t *ids = dir0 ? A.g.idx[1] : A.g.idx[0];
+      int64_t x = clo, y = chi;
+      while (x < y) {
+        const int64_t mid = (x + y) >> 1;
+        ++probes;
+        if (gld(ids + mid) < c) x = mid + 1; else y = mid;
+      }
+      if (!(x < chi && gld(ids + x) == c)) return false;
+      continue;
+    }
     int32_t b, label, dir;
     if (k + 1 == gen) {
       b = S.kind == STEP_SEG ? gld(E.prev + (int64_t)S.src * E.prev_n + node) : S.src;
@@ -847,7 +880,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
         bool ok = false;
         if (p < dt.n) {
           const int32_t c = candidate(A, E, S, W, k, p);
-          ok = test_candidate(A, E, S, W.node[k], W.dg[k] >> 1, c, pr, ft, ct);
+          int64_t clo = 0, chi = 0;
+          if (S.nchk > 0) { clo = gld(it->nz_chk_lo + dt.k0 + k); chi = gld(it->nz_chk_hi + dt.k0 + k); }
+          ok = test_candidate(A, E, S, W.node[k], W.dg[k] >> 1, clo, chi, c, pr, ft, ct);
         }
         const uint64_t bal = __ballot(ok);
         if (lane == 0) gst(vw + r, bal);
