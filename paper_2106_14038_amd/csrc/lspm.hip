@@ -43,10 +43,33 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(const uint64_t *hi, const
   hist[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
 }
 
-// One workgroup: exclusive scan of L uint32 counts into int64 offsets.
-__global__ __launch_bounds__(1024) void k_scan_u32(const uint32_t *in, int64_t L, int64_t *out) {
-  __shared__ int64_t lds[1024];
-  wg_scan(L, [&](int64_t i) { return (int64_t)in[i]; }, [&](int64_t i, int64_t v) { out[i] = v; }, lds);
+// Multi-workgroup exclusive scan of L uint32 counts into int64 offsets, in three
+// launches: chunk sums (one chunk per workgroup, coalesced), a one-workgroup scan
+// of the chunk sums, then each chunk rescanned from its offset.
+__global__ __launch_bounds__(kBlock) void k_scan_parts(const uint32_t *in, int64_t L, int64_t *parts) {
+  __shared__ int64_t lds[kWaves];
+  int64_t b, e;
+  block_share(L, b, e);
+  int64_t v = 0;
+  for (int64_t i = b + threadIdx.x; i < e; i += kBlock) v += in[i];
+  v = block_sum_i64(v, lds);
+  if (threadIdx.x == 0) parts[blockIdx.x] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_apply(const uint32_t *in, int64_t L, const int64_t *parts,
+                                                       int64_t *out) {
+  __shared__ int64_t lds[kWaves];
+  int64_t b, e;
+  block_share(L, b, e);
+  int64_t carry = parts[blockIdx.x];
+  for (int64_t c0 = b; c0 < e; c0 += kBlock) {
+    const int64_t i = c0 + threadIdx.x;
+    const int64_t v = i < e ? (int64_t)in[i] : 0;
+    int64_t tot;
+    const int64_t x = block_excl_scan_i64(v, tot, lds);
+    if (i < e) out[i] = carry + x;
+    carry += tot;
+  }
 }
 
 // One workgroup: exclusive scan of L int64 values (in place allowed); *total gets the sum.
@@ -220,8 +243,10 @@ hipError_t scan_i64(const int64_t *in, int64_t L, int64_t *out, int64_t *total, 
 
 // Sort (hi, lo) pairs of length m; the result ends in (hi0, lo0). Temporaries
 // hi1/lo1 of the same size; hist of 256 * G uint32 and off of 256 * G int64.
+// parts: at least min(G, 256) int64 of scratch for the offset scan.
 static hipError_t radix_sort(uint64_t *hi0, uint32_t *lo0, uint64_t *hi1, uint32_t *lo1, int64_t m, int lo_bits,
-                             int hi_bits, uint32_t *hist, int64_t *off, int G, hipStream_t s) {
+                             int hi_bits, uint32_t *hist, int64_t *off, int64_t *parts, int G, hipStream_t s) {
+  const int np = G < 256 ? G : 256;
   if (m <= 1) return hipSuccess;
   const int64_t chunk = (m + G - 1) / G;
   bool swapped = false;
@@ -231,7 +256,9 @@ static hipError_t radix_sort(uint64_t *hi0, uint32_t *lo0, uint64_t *hi1, uint32
       uint64_t *hs = swapped ? hi1 : hi0, *hd = swapped ? hi0 : hi1;
       uint32_t *ls = swapped ? lo1 : lo0, *ld = swapped ? lo0 : lo1;
       hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(kBlock), 0, s, hs, ls, m, shift, pass, chunk, hist);
-      hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, s, hist, (int64_t)256 * G, off);
+      hipLaunchKernelGGL(k_scan_parts, dim3(np), dim3(kBlock), 0, s, hist, (int64_t)256 * G, parts);
+      hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(1024), 0, s, parts, (int64_t)np, parts, nullptr);
+      hipLaunchKernelGGL(k_scan_apply, dim3(np), dim3(kBlock), 0, s, hist, (int64_t)256 * G, parts, off);
       hipLaunchKernelGGL(k_radix_scatter, dim3(G), dim3(kBlock), 0, s, hs, ls, hd, ld, m, shift, pass, chunk,
                          (const int64_t *)off);
       swapped = !swapped;
@@ -259,7 +286,7 @@ hipError_t lspm_build_orientation(const LspmBuildArgs &a, int orient, LspmOut &o
   const int abits = bits_for((uint64_t)(a.n - 1));
   hipLaunchKernelGGL(k_make_keys, dim3(grid_for(a.m, 4096)), dim3(kBlock), 0, s, a.triples, a.m, a.n, a.P, orient,
                      pbits, a.hi0, a.lo0, a.err);
-  hipError_t e = radix_sort(a.hi0, a.lo0, a.hi1, a.lo1, a.m, abits, abits + pbits, a.hist, a.off, G, s);
+  hipError_t e = radix_sort(a.hi0, a.lo0, a.hi1, a.lo1, a.m, abits, abits + pbits, a.hist, a.off, a.blk, G, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_uniq_count, dim3(G), dim3(kBlock), 0, s, a.hi0, a.lo0, a.m, a.blk);
   hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(1024), 0, s, a.blk, (int64_t)G, a.blk, a.total);
