@@ -372,10 +372,14 @@ def main():
     gs.gs_kernel_stats(eng, reset=True)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
+    step_ms = []
     for _ in range(args.steps):
+        ts = time.perf_counter()
         counts, st = batched_step()
+        step_ms.append((time.perf_counter() - ts) * 1e3)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t2
+    log(f"batched step times (ms): {[round(x, 2) for x in step_ms]}")
     ks = gs.gs_kernel_stats(eng, reset=True)
     ms_step = elapsed * 1e3 / args.steps
     T = sum(s.t_total for s in st)
