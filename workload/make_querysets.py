@@ -73,27 +73,43 @@ def _count_bt(q, work_cap):
 
 
 def batched_set(trip, n, pool, args, t0):
-    """Queries of the four shapes with random constants: per shape the first total/4 walk
-    candidates whose exact count is in [1, 1e7] (message passing for acyclic queries,
-    backtracking with the work cap for cyclic ones); the count histogram by decade is
-    printed."""
+    """Queries of the four shapes with random constants (0-2 per query; snowflakes
+    with 2, else almost all of them exceed the count bound): per shape the first
+    walk candidates whose exact count is in [1, 1e7], up to total/4 per shape or
+    the shape's time budget; the remaining quota is filled by the shapes in order.
+    Exact counts: message passing for acyclic queries, backtracking with the work
+    cap for cyclic ones. The count histogram by decade is printed."""
     per = args.total // len(SHAPES)
-    out = []
-    for si, shape in enumerate(SHAPES):
-        got, first = [], 0
-        while len(got) < per and first < args.max_candidates:
-            batch = workload.walk_queries(trip, n, 100 + si, shape, 64, const_prob=args.const_prob, first=first)
+    got = {sh: [] for sh in SHAPES}
+    first = {sh: 0 for sh in SHAPES}
+
+    def fill(shape, si, want, budget):
+        ts = time.time()
+        cp, mc = (1.0, 2) if shape == "snowflake8" else (args.const_prob, 2)
+        while len(got[shape]) < want and first[shape] < args.max_candidates and time.time() - ts < budget:
+            batch = workload.walk_queries(trip, n, 100 + si, shape, 64, const_prob=cp, first=first[shape],
+                                          max_consts=mc)
             counts = pool.starmap(_count, [(q, args.work_cap) for q in batch])
             for i, (q, c) in enumerate(zip(batch, counts)):
-                if 1 <= c <= 10_000_000 and len(got) < per:
-                    got.append({"shape": shape, "candidate": first + i, "count": int(c), "query": q})
-            first += 64
-            print(shape, first, len(got), f"({time.time() - t0:.0f}s)", flush=True)
+                if 1 <= c <= 10_000_000 and len(got[shape]) < want:
+                    got[shape].append({"shape": shape, "candidate": first[shape] + i, "count": int(c), "query": q})
+            first[shape] += 64
+            print(shape, first[shape], len(got[shape]), f"({time.time() - t0:.0f}s)", flush=True)
+
+    for si, shape in enumerate(SHAPES):
+        fill(shape, si, per, args.shape_budget)
+    for si, shape in enumerate(SHAPES):   # top up from the shapes that yield
+        short = args.total - sum(len(v) for v in got.values())
+        if short <= 0:
+            break
+        fill(shape, si, len(got[shape]) + short, args.shape_budget)
+    out = []
+    for shape in SHAPES:
         hist = [0] * 8
-        for g in got:
+        for g in got[shape]:
             hist[min(7, len(str(g["count"])) - 1)] += 1
-        print(shape, "decades", hist, flush=True)
-        out += got
+        print(shape, len(got[shape]), "decades", hist, flush=True)
+        out += got[shape]
     return out
 
 
@@ -124,6 +140,7 @@ def main():
     ap.add_argument("--cap", type=int, default=1_000_000_000)
     ap.add_argument("--work-cap", type=int, default=300_000_000)
     ap.add_argument("--procs", type=int, default=min(8, os.cpu_count() or 1))
+    ap.add_argument("--shape-budget", type=float, default=1200.0, help="seconds per shape (batched set)")
     args = ap.parse_args()
     t0 = time.time()
     trip = workload.c1_graph(args.scale)
