@@ -90,6 +90,12 @@ struct EntryAcc {
 // A step whose candidates face no test: every candidate entry becomes a child.
 __device__ __forceinline__ bool test_free(const DStep &S) { return step_test_free(S); }
 
+// The count-only last level of a query whose candidates face no test: its
+// count is the sum of its nodes' segment lengths, known after the node scan;
+// it has no tiles, no compacted nodes, no count or write pass, and its entries
+// are not read (nor counted as traversed).
+__device__ __forceinline__ bool counted_only(const DStep &S) { return test_free(S) && S.ncols_out == 0; }
+
 // Per-node segment reference: the start of the segment the node's candidates
 // are read from, the orientation of that segment, and which of the step's
 // bound segments it is (0: the parent edge's, k: exact check k - 1). A level
@@ -458,6 +464,7 @@ __global__ __launch_bounds__(kBlock) void k_lookup(const IterArgs A) {
     __syncthreads();
     const int64_t i0 = (t - es[e].node_tile0) * kTileNodes, pn = es[e].prev_n;
     int64_t cnz = 0, cw = 0;
+    const bool counted = counted_only(S);
     constexpr int RN = kTileNodes / kBlock;
     // the parent bindings, then their rows, of all of the thread's nodes first (independent loads)
     const int32_t *src = es[e].prev + (int64_t)S.src * pn;
@@ -500,8 +507,8 @@ __global__ __launch_bounds__(kBlock) void k_lookup(const IterArgs A) {
       if (!sh_ok) hi = lo;
       const int64_t gn = es[e].node0 + i;
       it->lo[gn] = seg_ref(lo, dir, gen);
-      it->len[gn] = hi - lo;
-      cnz += (hi > lo);
+      it->len[gn] = counted ? 0 : hi - lo;   // a counted level's nodes take no part in the passes after the scan
+      cnz += (hi > lo) && !counted;
       cw += hi - lo;
     }
     {   // one reduction for both: entries above bit 11, non-empty nodes (at most kTileNodes) below
@@ -511,7 +518,7 @@ __global__ __launch_bounds__(kBlock) void k_lookup(const IterArgs A) {
     }
     if (threadIdx.x == 0) acc.add(e, cnz, cw, p_nz, p_w, kEsStride);
     bnz += cnz;
-    bw += cw;
+    bw += counted ? 0 : cw;
   }
   if (threadIdx.x == 0) { acc.flush(p_nz, p_w, kEsStride); A.blk_a[blockIdx.x] = bnz; A.blk_b[blockIdx.x] = bw; }
 }
@@ -558,8 +565,12 @@ __global__ __launch_bounds__(1024) void k_scan_nodes(const IterArgs A) {
   wg_scan(A.grid, [&](int64_t i) { return A.blk_a[i]; }, [&](int64_t i, int64_t v) { A.blk_off_a[i] = v; }, lds);
   wg_scan(A.grid, [&](int64_t i) { return A.blk_b[i]; }, [&](int64_t i, int64_t v) { A.blk_off_b[i] = v; }, lds);
   const int64_t nz = wg_scan(A.E, [&](int64_t i) { return es[i].nz; }, [&](int64_t i, int64_t v) { es[i].nz_base = v; }, lds);
-  const int64_t w = wg_scan(A.E, [&](int64_t i) { return es[i].w; }, [&](int64_t i, int64_t v) { es[i].w_base = v; }, lds);
-  const int64_t wt = wg_scan(A.E, [&](int64_t i) { return ceil_div(es[i].w, kTileWork); },
+  // entry offsets and the block offsets above leave out counted levels, as the node lengths do
+  const int64_t w = wg_scan(A.E, [&](int64_t i) { return counted_only(A.steps[A.ent[i].step]) ? (int64_t)0 : es[i].w; },
+                            [&](int64_t i, int64_t v) { es[i].w_base = v; }, lds);
+  const int64_t wt = wg_scan(A.E, [&](int64_t i) {
+                               return counted_only(A.steps[A.ent[i].step]) ? (int64_t)0 : ceil_div(es[i].w, kTileWork);
+                             },
                              [&](int64_t i, int64_t v) { es[i].w_tile0 = v; }, lds);
   __shared__ int64_t wtest;
   if (threadIdx.x == 0) wtest = 0;
@@ -601,7 +612,7 @@ __global__ __launch_bounds__(1024) void k_scan_nodes(const IterArgs A) {
   for (int e = threadIdx.x; e < A.E; e += blockDim.x) {
     const DEntry d = A.ent[e];
     const DStep S = A.steps[d.step];
-    if (S.kind != STEP_LIST && es[e].w)
+    if (S.kind != STEP_LIST && es[e].w && !counted_only(S))
       atomicAdd((unsigned long long *)&A.qstats[(int64_t)d.q * QS_N + QS_EXPAND], (unsigned long long)es[e].w);
     if (test_free(S)) alloc_level(A, e, d, S);   // its size is known now: the node pass writes its offsets
   }
@@ -922,7 +933,8 @@ __global__ __launch_bounds__(1024) void k_scan_expand(const IterArgs A) {
   if (it->abort) return;
   EState *es = A.es;
   wg_scan(A.grid, [&](int64_t i) { return A.blk_a[i]; }, [&](int64_t i, int64_t v) { A.blk_off_a[i] = v; }, lds);
-  const int64_t tot = wg_scan(A.E, [&](int64_t i) { return es[i].cnt; },
+  // the same sums as the tiles carry (levels counted without tiles take no positions)
+  const int64_t tot = wg_scan(A.E, [&](int64_t i) { return counted_only(A.steps[A.ent[i].step]) ? (int64_t)0 : es[i].cnt; },
                               [&](int64_t i, int64_t v) { es[i].out_base = v; }, lds);
   if (threadIdx.x == 0) it->cnt_total = tot;
   for (int e = threadIdx.x; e < A.E; e += blockDim.x) {
@@ -1006,6 +1018,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
     int kk[R];
     for (int r = 0; r < R; ++r) kk[r] = take_node(W, r * 64 + lane);
     int32_t li[R];   // output position of each item, -1: not a child (levels stay below 2^31 nodes)
+    int64_t end = a0 + n;   // one past the tile's last output position
     if (wflags & EW_FREE) {   // every entry is a child: a tile's children start at its first entry
       for (int r = 0; r < R; ++r) {
         const int p = r * 64 + lane;
@@ -1019,9 +1032,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
         li[r] = ((bal >> lane) & 1ull) ? before + (int32_t)__popcll(bal & lanemask_lt()) : -1;
         before += (int32_t)__popcll(bal);
       }
+      end = __builtin_amdgcn_readfirstlane(before);
     }
-    if (out) {
-      const int64_t cnt = sld(&es[e].cnt);
+    const int64_t cnt = out ? sld(&es[e].cnt) : 0;
+    if (out && end <= cnt) {   // a tile whose positions would leave the level writes nothing
       const int32_t *list = sld(&es[e].list);
       int32_t node[R], c[R];
       for (int r = 0; r < R; ++r) {
