@@ -116,7 +116,9 @@ typedef struct {
   int32_t n_levels;           /* tree levels (= variables) */
   int32_t n_domains;          /* cycle-closing edges given a frontier domain */
   int64_t level_nodes[64];    /* nodes per tree level before pruning */
-  int64_t t_expand;           /* candidate entries read while growing the tree */
+  int64_t t_expand;           /* candidate entries read while growing the tree (a last level that is
+                                 only counted and faces no test is summed from segment lengths: its
+                                 entries are not read and not counted here) */
   int64_t t_seed;             /* entries read to seed constant filters */
   int64_t t_push;             /* entries read by push domain products */
   int64_t t_pull;             /* entries read by pull domain products */
