@@ -774,13 +774,16 @@ __device__ __forceinline__ void stage_tile(const IterScalars *it, const DTile &d
   int v[kItemsPerLane];
   int mx = 0;
   for (int i = 0; i < kItemsPerLane; ++i) { mx = max(mx, (int)W.kmap[lane * kItemsPerLane + i]); v[i] = mx; }
-  int incl = mx;
-  for (int off = 1; off < 64; off <<= 1) {
-    const int u = __shfl_up(incl, off, 64);
-    if (lane >= off) incl = max(incl, u);
-  }
-  int pre = __shfl_up(incl, 1, 64);
-  if (lane == 0) pre = 0;
+  // inclusive max-scan over the wave with DPP row shifts and row broadcasts
+  // (values are >= 0, so lanes without a source read 0)
+  int incl = max(mx, __builtin_amdgcn_update_dpp(0, mx, 0x111, 0xf, 0xf, true));   // row_shr:1
+  incl = max(incl, __builtin_amdgcn_update_dpp(0, mx, 0x112, 0xf, 0xf, true));     // row_shr:2
+  incl = max(incl, __builtin_amdgcn_update_dpp(0, mx, 0x113, 0xf, 0xf, true));     // row_shr:3
+  incl = max(incl, __builtin_amdgcn_update_dpp(0, incl, 0x114, 0xf, 0xe, true));   // row_shr:4, lanes 4-15 of a row
+  incl = max(incl, __builtin_amdgcn_update_dpp(0, incl, 0x118, 0xf, 0xc, true));   // row_shr:8, lanes 8-15 of a row
+  incl = max(incl, __builtin_amdgcn_update_dpp(0, incl, 0x142, 0xa, 0xf, false));  // row_bcast:15 into rows 1, 3
+  incl = max(incl, __builtin_amdgcn_update_dpp(0, incl, 0x143, 0xc, 0xf, false));  // row_bcast:31 into rows 2, 3
+  const int pre = __builtin_amdgcn_update_dpp(0, incl, 0x138, 0xf, 0xf, true);    // wave_shr:1 (lane 0 reads 0)
   for (int i = 0; i < kItemsPerLane; ++i) W.kmap[lane * kItemsPerLane + i] = (uint16_t)max(pre, v[i]);
   wave_lds_sync();
 }
