@@ -41,14 +41,28 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
   return (1ull << lane) - 1ull;
 }
 
+// v of the lane that DPP control `ctrl` names, as two 32-bit moves; 0 where the
+// control names no lane (bound_ctrl) or the lane is masked off.
+template <int ctrl, int row_mask, int bank_mask, bool bound>
+__device__ __forceinline__ int64_t dpp_i64(int64_t v) {
+  const uint64_t u = (uint64_t)v;
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, ctrl, row_mask, bank_mask, bound);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), ctrl, row_mask, bank_mask, bound);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Inclusive sum over the lanes of a full wave: row shifts by 1, 2, 3 (of the
+// input), 4 and 8 (of the partial sums, upper banks only), then the last lane
+// of rows 0 and 2 into rows 1 and 3, and lane 31 into rows 2 and 3.
 __device__ __forceinline__ int64_t wave_incl_scan_i64(int64_t v) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    int64_t u = __shfl_up(v, off, 64);
-    if (lane >= off) v += u;
-  }
-  return v;
+  int64_t s = v + dpp_i64<0x111, 0xf, 0xf, true>(v);
+  s += dpp_i64<0x112, 0xf, 0xf, true>(v);
+  s += dpp_i64<0x113, 0xf, 0xf, true>(v);
+  s += dpp_i64<0x114, 0xf, 0xe, true>(s);
+  s += dpp_i64<0x118, 0xf, 0xc, true>(s);
+  s += dpp_i64<0x142, 0xa, 0xf, false>(s);
+  s += dpp_i64<0x143, 0xc, 0xf, false>(s);
+  return s;
 }
 
 __device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
