@@ -7,8 +7,12 @@ A step evaluates the whole query set once in the batched form: each tree level
 of every query runs in the same launch sequence, the binding trees are built in
 HBM and the counts come back to the host. The matrix (both orientations) is
 built once from triples already resident in HBM and stays resident; its build
-time is reported as load_ms. The plain form (one query at a time) and the
-served form are measured beside it on the same GPU.
+time is reported as load_ms. The headline value times the step as the
+batched form runs it in production, its launch sequence replayed from a
+captured hipGraph; an instrumented run of the same step (HIP events around
+every kernel) gives the per-kernel table and the roofline of the dominant
+kernel. The plain form (one query at a time) and the served form are measured
+beside it on the same GPU.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c1]
 
@@ -450,16 +454,24 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(trip, qs, per_query_T, args.cpu_budget)
 
+    # the headline: the batched step as a production caller runs it, replayed from its hipGraph
+    # (same launches and results; the per-kernel events of the instrumented run above only
+    # feed the kernel table and the roofline)
+    head_ms, head_value, launch = ms_step, value, "eager launches with per-kernel events"
+    if graphs:
+        head_ms, head_value, launch = graphs["ms_per_step"], graphs["triples_per_s"], "hipGraph replay"
     out = {
-        "metric": METRIC, "value": value, "unit": "triples/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "metric": METRIC, "value": head_value, "unit": "triples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head_ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int32", "data": "synthetic",
         "config": {"workload": f"{args.workload}: Chung-Lu beta 2.1, N={qs['n']}, M={qs['m']}, "
                                f"{qs['n_labels']} Zipf(1.1) labels, typed 20% object domains; "
                                f"{len(queries)} walk queries (chain-4, star-5, snowflake-8, triangle), "
                                f"batched form",
-                   "queries": len(queries), "total_rows": int(sum(counts)), "parallelism": "single GPU"},
-        "batched": {"queries_per_s": len(queries) / (ms_step / 1e3), "triples_per_s": value},
+                   "queries": len(queries), "total_rows": int(sum(counts)), "parallelism": "single GPU",
+                   "launch": launch},
+        "batched": {"queries_per_s": len(queries) / (ms_step / 1e3), "triples_per_s": value, "ms_per_step": ms_step,
+                    "launch": "eager launches with per-kernel events"},
         "plain": plain,
         "batched_graphs": graphs,
         "batched_set": batched_set,
