@@ -104,7 +104,7 @@ typedef struct {
   void *alloc_ctx;
   int32_t domain_mode;        /* GS_DOMAIN_* */
   float push_pull_theta;      /* push when est. push work < theta * est. pull work; 0 = 1.0 */
-  int32_t grid_blocks;        /* workgroups of the fixed-grid kernels; 0 = 8 per compute unit */
+  int32_t grid_blocks;        /* workgroups of the fixed-grid kernels; 0 = 12 per compute unit */
   int32_t use_graphs;         /* batched form: capture each step's launches in a hipGraph (1) or not (0) */
   int32_t profile_kernels;    /* record HIP events around every kernel launch (gs_kernel_stats) */
 } gs_options;

@@ -138,6 +138,14 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: run paper_2106_14038_amd.build() (hipcc, gfx950) first")
+        # PyTorch ships its own HIP runtime under the same soname as the system one; whichever
+        # is loaded first serves the whole process. Load PyTorch's first, so that the library
+        # and any later torch.cuda use share one runtime (loaded the other way round, torch
+        # finds no device).
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         for name, (args, res) in SIGNATURES.items():
             f = getattr(L, name)

@@ -72,7 +72,7 @@ gs_status gs_engine_create(const gs_options *options, gs_engine **out) {
   if (hipSetDevice(E.device) != hipSuccess) { delete ge; set_error("hipSetDevice failed"); return GS_EDEVICE; }
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, E.device) == hipSuccess) E.cus = prop.multiProcessorCount;
-  E.grid = o.grid_blocks > 0 ? o.grid_blocks : 8 * E.cus;
+  E.grid = o.grid_blocks > 0 ? o.grid_blocks : 12 * E.cus;
   if (E.grid > 8192) E.grid = 8192;
   E.wgrid = expand_write_blocks_per_cu() * E.cus;
   if (o.hip_stream) {

@@ -458,16 +458,18 @@ __global__ __launch_bounds__(kBlock) void k_lookup(const IterArgs A) {
     if (threadIdx.x == 0) sh_e = ncur.at(A, t);
     __syncthreads();
     const int e = uniform(sh_e);
-    const DEntry d = A.ent[e];
-    const DStep S = A.steps[d.step];
+    const DEntry d = sld(A.ent + e);
+    const DStep S = sld(A.steps + d.step);
     if (threadIdx.x == 0) sh_ok = (d.level == 0 && S.ncc > 0) ? const_checks_hold(A, S) : 1;
     __syncthreads();
-    const int64_t i0 = (t - es[e].node_tile0) * kTileNodes, pn = es[e].prev_n;
+    const int64_t i0 = (t - sld(&es[e].node_tile0)) * kTileNodes, pn = sld(&es[e].prev_n);
+    const int32_t *const eprev = sld(&es[e].prev);
+    const int64_t enode0 = sld(&es[e].node0);
     int64_t cnz = 0, cw = 0;
     const bool counted = counted_only(S);
     constexpr int RN = kTileNodes / kBlock;
     // the parent bindings, then their rows, of all of the thread's nodes first (independent loads)
-    const int32_t *src = es[e].prev + (int64_t)S.src * pn;
+    const int32_t *src = eprev + (int64_t)S.src * pn;
     const int64_t *ptr = S.dir ? A.g.ptr[1] : A.g.ptr[0];
     int64_t ra[RN], re[RN];
     for (int r = 0; r < RN; ++r) {
@@ -492,12 +494,12 @@ __global__ __launch_bounds__(kBlock) void k_lookup(const IterArgs A) {
         for (int k = 0; k < min(S.nchk, kMaxGen) && hi > lo; ++k) {   // read the shortest bound segment
           const DCheck ck = A.checks[S.chk0 + k];
           int64_t clo, chi;
-          seg_find(A.g, ck.dir, es[e].prev[(int64_t)ck.col * pn + i], ck.label, clo, chi, probes);
+          seg_find(A.g, ck.dir, eprev[(int64_t)ck.col * pn + i], ck.label, clo, chi, probes);
           if (k == 0) { c0lo = clo; c0hi = chi; }
           if (chi - clo < hi - lo) { lo = clo; hi = chi; dir = ck.dir; gen = k + 1; }
         }
         if (S.nchk > 0) {   // the first check the count pass makes: the parent's segment when check 0 generates
-          const int64_t gn = es[e].node0 + i;
+          const int64_t gn = enode0 + i;
           it->chk_lo[gn] = gen == 1 ? plo : c0lo;
           it->chk_hi[gn] = gen == 1 ? phi : c0hi;
         }
@@ -505,7 +507,7 @@ __global__ __launch_bounds__(kBlock) void k_lookup(const IterArgs A) {
         hi = es[e].list_n;
       }
       if (!sh_ok) hi = lo;
-      const int64_t gn = es[e].node0 + i;
+      const int64_t gn = enode0 + i;
       it->lo[gn] = seg_ref(lo, dir, gen);
       it->len[gn] = counted ? 0 : hi - lo;   // a counted level's nodes take no part in the passes after the scan
       cnz += (hi > lo) && !counted;
