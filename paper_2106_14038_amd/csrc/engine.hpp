@@ -46,7 +46,7 @@ struct Engine {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   gs_options opt{};
-  int grid = 2048;
+  int grid = 3072;    // fixed-grid kernels: 12 workgroups per CU unless the options say otherwise
   int wgrid = 1024;   // write-pass workgroups: as many as the device holds at once
   int cus = 256;
 
