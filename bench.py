@@ -91,10 +91,11 @@ def cpu_baseline(trip, qs, per_query_T, budget_s):
             "queries_per_s": done / secs if secs > 0 else None}
 
 
-def batched_set_leg(gs, eng, qset, wave=256):
+def batched_set_leg(gs, eng, qset, wave=1024):
     """The batched query set (1024 queries of the four shapes, counts 1..1e7): batched in
-    waves of `wave` queries (count only, each wave's trees freed before the next) vs the
-    same queries one at a time; every count against the stored oracle count."""
+    waves of `wave` queries (count only, each wave's trees freed before the next; by default
+    the whole set in one batch) vs the same queries one at a time; every count against the
+    stored oracle count."""
     import torch
     queries = [q["query"] for q in qset["queries"]]
     expect = [q["count"] for q in qset["queries"]]

@@ -175,19 +175,40 @@ __global__ __launch_bounds__(kBlock) void k_clear(const IterArgs A) {
 }
 
 // Constant edges (c, p, x) / (x, p, c): the segment of c -> bitmap of x's candidates.
+// Each segment is cut into as many contiguous parts as the grid has workgroups per
+// constant edge (a hub constant's segment holds millions of entries). The ids of a
+// segment ascend, so lanes whose ids fall in one bitmap word are neighbours: the
+// wave ORs their bits together and the first of them sets the word, one atomic per
+// word instead of one per entry.
 __global__ __launch_bounds__(kBlock) void k_seed(const IterArgs A) {
-  for (int s = blockIdx.x; s < A.S; s += gridDim.x) {
+  const int lane = threadIdx.x & 63;
+  const int64_t parts = max((int64_t)1, (int64_t)gridDim.x / A.S);
+  for (int64_t b = blockIdx.x; b < (int64_t)A.S * parts; b += gridDim.x) {
+    const int s = (int)(b / parts);
+    const int64_t part = b % parts;
     const DSeed sd = A.seeds[s];
     int64_t lo, hi;
     int probes = 0;
     seg_find(A.g, sd.dir, sd.c, sd.label, lo, hi, probes);
-    const int32_t *idx = A.g.idx[sd.dir];
-    for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
-      const int32_t c = idx[k];
-      atomicOr((unsigned long long *)&sd.bm[c >> 6], 1ull << (c & 63));
+    const int32_t *idx = sd.dir ? A.g.idx[1] : A.g.idx[0];
+    const int64_t per = ceil_div(hi - lo, parts);
+    const int64_t a = lo + part * per, e = min(hi, a + per);
+    for (int64_t k0 = a + (threadIdx.x & ~63); k0 < e; k0 += blockDim.x) {   // whole waves
+      const int64_t k = k0 + lane;
+      const bool ok = k < e;
+      const int32_t c = ok ? gld(idx + k) : 0;
+      const int64_t w = ok ? (int64_t)(c >> 6) : -1;
+      uint64_t bits = ok ? (1ull << (c & 63)) : 0ull;
+      for (int off = 1; off < 64; off <<= 1) {   // OR over the following lanes of the same word
+        const uint64_t ob = __shfl_down(bits, off, 64);
+        const int64_t ow = __shfl_down(w, off, 64);
+        if (lane + off < 64 && ow == w) bits |= ob;
+      }
+      const int64_t pw = __shfl_up(w, 1, 64);
+      if (ok && (lane == 0 || pw != w)) atomicOr((unsigned long long *)&sd.bm[w], (unsigned long long)bits);
     }
-    if (threadIdx.x == 0) atomicAdd((unsigned long long *)&A.qstats[(int64_t)sd.q * QS_N + QS_SEED],
-                                    (unsigned long long)(hi - lo));
+    if (part == 0 && threadIdx.x == 0)
+      atomicAdd((unsigned long long *)&A.qstats[(int64_t)sd.q * QS_N + QS_SEED], (unsigned long long)(hi - lo));
   }
 }
 
