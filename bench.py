@@ -416,7 +416,11 @@ def main():
         return e
 
     # the baselines and the other forms run without per-kernel events
-    leng = fresh_engine()
+    c2 = os.path.join(ROOT, "workload", "data", "c2_queries.json")
+    c3 = os.path.join(ROOT, "workload", "data", "c3_queries.json")
+    want_set = not args.no_batched_set and os.path.exists(c2) and args.workload == "c1"
+    want_serve = not args.no_serve and os.path.exists(c3) and args.workload == "c1"
+    leng = fresh_engine() if (not args.no_plain or want_set or want_serve) else None
     plain = None
     if not args.no_plain:
         r = gs.gs_query_run(leng, queries[0])   # warm the plain path
@@ -450,17 +454,11 @@ def main():
         log(f"batched with graphs: {gms:.2f} ms/step")
         gs.gs_engine_destroy(geng)
 
-    batched_set = None
-    c2 = os.path.join(ROOT, "workload", "data", "c2_queries.json")
-    if not args.no_batched_set and os.path.exists(c2) and args.workload == "c1":
-        batched_set = batched_set_leg(gs, leng, load_queryset("c2"))
-
-    served = None
-    c3 = os.path.join(ROOT, "workload", "data", "c3_queries.json")
-    if not args.no_serve and os.path.exists(c3) and args.workload == "c1":
-        served = serve_leg(gs, leng, load_queryset("c3"), [1000.0, 5000.0, 20000.0], args.serve_seconds)
-
-    gs.gs_engine_destroy(leng)
+    batched_set = batched_set_leg(gs, leng, load_queryset("c2")) if want_set else None
+    served = (serve_leg(gs, leng, load_queryset("c3"), [1000.0, 5000.0, 20000.0], args.serve_seconds)
+              if want_serve else None)
+    if leng is not None:
+        gs.gs_engine_destroy(leng)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(trip, qs, per_query_T, args.cpu_budget)
