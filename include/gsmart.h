@@ -214,8 +214,11 @@ gs_status gs_plan_query(gs_engine *engine, const gs_query *query, gs_plan_info *
 /* ---- plain and batched evaluation ------------------------------------------- */
 
 /* Evaluate one query (one at a time). *out receives a result to be freed with
- * gs_result_free. Errors: GS_ESTATE (no data), GS_EINVAL, GS_ERANGE,
- * GS_EUNSUPPORTED, GS_ENOMEM (tree exceeds the arena). */
+ * gs_result_free. Errors: GS_ESTATE (no data, or a server running on the
+ * engine), GS_EINVAL, GS_ERANGE, GS_EUNSUPPORTED, GS_ENOMEM (tree exceeds the
+ * tree arena, or a level's temporaries exceed the scratch arena), GS_EDEVICE
+ * (HIP error, or an internal inconsistency between the count and write passes
+ * detected on the device). */
 gs_status gs_query_run(gs_engine *engine, const gs_query *query, uint32_t flags, gs_result **out);
 
 /* Evaluate nq queries together: each vertex step of every query runs in the
@@ -292,8 +295,12 @@ typedef struct {
   int64_t requeued;           /* requests re-run after an arena overflow */
 } gs_server_stats;
 
-/* Start the request loop on its own host thread. The engine must be loaded and
- * must not be used directly until gs_server_stop. */
+/* Start the request loop on its own host thread. The engine must be loaded, and
+ * every result of its direct evaluation freed (the loop uses the whole tree
+ * arena). Until gs_server_stop, direct evaluation on the engine (gs_query_run,
+ * gs_batch_run, gs_autotune, gs_frontier_domain, gs_bitmap_and_compact) returns
+ * GS_ESTATE. Errors: GS_ESTATE (no data, live results, a server already
+ * running), GS_ENOMEM. */
 gs_status gs_server_start(gs_engine *engine, const gs_server_options *options, gs_server **out);
 
 /* Enqueue a request; *ticket identifies it. Thread-safe. */

@@ -168,6 +168,7 @@ gs_status gs_frontier_domain(gs_engine *engine, const uint64_t *frontier_words, 
   if (!E.loaded) { set_error("no dataset loaded"); return GS_ESTATE; }
   if (label < 1 || label > E.g.P) { set_error("label out of range"); return GS_ERANGE; }
   std::lock_guard<std::mutex> lk(E.mu);
+  if (E.serving) { set_error("a server is running on this engine"); return GS_ESTATE; }
   HIPRET(hipSetDevice(E.device));
   hipStream_t s = E.stream;
   const size_t wb = 8 * (size_t)E.g.words;
@@ -207,6 +208,7 @@ gs_status gs_bitmap_and_compact(gs_engine *engine, const uint64_t *const *bitmap
   Engine &E = engine->e;
   if (!E.loaded) { set_error("no dataset loaded"); return GS_ESTATE; }
   std::lock_guard<std::mutex> lk(E.mu);
+  if (E.serving) { set_error("a server is running on this engine"); return GS_ESTATE; }
   HIPRET(hipSetDevice(E.device));
   hipStream_t s = E.stream;
   const size_t wb = 8 * (size_t)E.g.words;
@@ -324,6 +326,7 @@ gs_status gs_autotune(gs_engine *engine, const gs_query *queries, int32_t nq, gs
   if (!engine || !queries || nq <= 0 || !out) { set_error("bad argument"); return GS_EINVAL; }
   Engine &E = engine->e;
   std::lock_guard<std::mutex> lk(E.mu);
+  if (E.serving) { set_error("a server is running on this engine"); return GS_ESTATE; }
   const int grid0 = E.grid;
   const float theta0 = E.opt.push_pull_theta;
   const int prof0 = E.opt.profile_kernels;

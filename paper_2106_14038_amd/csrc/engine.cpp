@@ -372,6 +372,7 @@ void account_iteration(Engine &E, const hipEvent_t *ev, const IterScalars &I, co
 
 int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector<Result *> &out, double *ms_out) {
   if (!E.loaded) { set_error("no dataset loaded"); return GS_ESTATE; }
+  if (E.serving) { set_error("a server is running on this engine"); return GS_ESTATE; }
   if (nq <= 0 || !qs) { set_error("empty batch"); return GS_EINVAL; }
   HIPCHK(hipSetDevice(E.device));
   hipStream_t s = E.stream;
@@ -438,6 +439,7 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
   const uint64_t o_lvln = off; off += align256(sizeof(int64_t) * kMaxLevels * (uint64_t)nq);
   const uint64_t o_qs = off; off += align256(sizeof(int64_t) * QS_N * (uint64_t)nq);
   const uint64_t o_zero = off; off += align256(sizeof(int64_t) * (uint64_t)nq);
+  const uint64_t o_flags = off; off += align256(sizeof(int32_t) * RF_N);
   const uint64_t zero_end = off;
   const uint64_t o_fc = off; off += align256(sizeof(int64_t) * max_d);
   const uint64_t o_es = off; off += align256(sizeof(EState) * max_e);
@@ -503,6 +505,7 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
     A.tree_base = E.tree_base;
     int64_t *blk = (int64_t *)dp(o_blk);
     A.blk_a = blk; A.blk_b = blk + E.grid; A.blk_off_a = blk + 2 * E.grid; A.blk_off_b = blk + 3 * E.grid;
+    A.flags = (int32_t *)dp(o_flags);
   }
   uint64_t *zero_p = (uint64_t *)dp(o_lvlp);
   const int64_t zero_n = (int64_t)((zero_end - o_lvlp) / 8);
@@ -572,6 +575,7 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
 
   // 6. read back sizes and counters
   std::vector<int64_t> lvl_n((size_t)nq * kMaxLevels), qst((size_t)nq * QS_N), zero_res(nq);
+  int32_t rflags[RF_N] = {0, 0};
   std::vector<int32_t *> lvl_p((size_t)nq * kMaxLevels), lvl_c((size_t)nq * kMaxLevels);
   HIPCHK(hipMemcpyAsync(lvl_n.data(), dp(o_lvln), 8 * lvl_n.size(), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(lvl_p.data(), dp(o_lvlp), 8 * lvl_p.size(), hipMemcpyDeviceToHost, s));
@@ -579,6 +583,7 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
   HIPCHK(hipMemcpyAsync(qst.data(), dp(o_qs), 8 * qst.size(), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(zero_res.data(), dp(o_zero), 8 * zero_res.size(), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(ar, E.d_arenas, sizeof(ar), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(rflags, dp(o_flags), sizeof(rflags), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   float ms = 0;
   HIPCHK(hipEventElapsedTime(&ms, ev0, ev1));
@@ -601,7 +606,11 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
       account_iteration(E, &E.events[(size_t)2 * KS_N * t], iv[t], its[t], wbytes);
     }
   }
-  if (ar[1].overflow) {
+  if (rflags[RF_WRITE]) {
+    set_error("device inconsistency: the write pass met output positions beyond a level's count");
+    return GS_EDEVICE;
+  }
+  if (rflags[RF_SCRATCH] || ar[1].overflow) {
     set_error("scratch arena overflow: a level's temporaries exceed the scratch arena");
     return GS_ENOMEM;
   }
@@ -697,6 +706,7 @@ int result_rows(Result &R, int64_t first, int64_t n, void *dst, int mem_kind, in
     return GS_OK;
   }
   Engine &E = *R.eng;
+  if (E.serving) { set_error("a server is running on this engine"); return GS_ESTATE; }
   HIPCHK(hipSetDevice(E.device));
   hipStream_t s = E.stream;
   const int k = R.k;
@@ -724,6 +734,7 @@ int result_rows(Result &R, int64_t first, int64_t n, void *dst, int mem_kind, in
 int result_prune(Result &R) {
   if (R.count_only || R.zero_vars || R.host_owned || R.k <= 1) return GS_OK;
   Engine &E = *R.eng;
+  if (E.serving) { set_error("a server is running on this engine"); return GS_ESTATE; }
   HIPCHK(hipSetDevice(E.device));
   hipStream_t s = E.stream;
   const int k = R.k;

@@ -69,6 +69,7 @@ struct Engine {
   uint64_t tree_top = 0;           // host view of the tree arena's end
   int live_results = 0;
   int run_counter = 0;
+  bool serving = false;            // a server owns the tree arena: direct evaluation is refused
 
   // per-run workspaces (grown on demand)
   void *work = nullptr;

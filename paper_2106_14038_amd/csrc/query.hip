@@ -115,19 +115,28 @@ static_assert(sizeof(EState) % sizeof(int64_t) == 0, "EState must be a whole num
 constexpr int64_t kEsStride = sizeof(EState) / sizeof(int64_t);
 
 // ------------------------------------------------------------------ setup
+// A scratch overflow in any iteration of a run stops the run: the aborted
+// level is never published, so no later iteration may read it.
+__device__ __forceinline__ void run_abort(const IterArgs &A) {
+  A.it->abort = 1;
+  if (A.flags) atomicOr(&A.flags[RF_SCRATCH], 1);
+}
+
 __global__ __launch_bounds__(1024) void k_it_setup(const IterArgs A) {
   __shared__ int64_t lds[1024];
   IterScalars *it = A.it;
   EState *es = A.es;
+  const bool dead = A.flags && gld(&A.flags[RF_SCRATCH]) != 0;   // set by an earlier iteration's kernels only
   if (threadIdx.x == 0) {
     A.scratch->top = 0;
     A.scratch->overflow = 0;
     it->n_entries = A.E;
-    it->abort = 0;
+    it->abort = dead ? 1 : 0;
     it->ftests = 0;
     it->ctests = 0;
     it->probes = 0;
   }
+  if (dead) return;
   for (int e = threadIdx.x; e < A.E; e += blockDim.x) {
     const DEntry d = A.ent[e];
     const DStep S = A.steps[d.step];
@@ -163,7 +172,7 @@ __global__ __launch_bounds__(1024) void k_it_setup(const IterArgs A) {
     it->len = (int64_t *)p[1];
     it->chk_lo = (int64_t *)p[2];
     it->chk_hi = (int64_t *)p[3];
-    if (A.scratch->overflow) it->abort = 1;
+    if (A.scratch->overflow) run_abort(A);
   }
 }
 
@@ -259,7 +268,7 @@ __global__ __launch_bounds__(1024) void k_list_scan(const IterArgs A) {
     it->list_total = total;
     buf = (int32_t *)arena_alloc(A.scratch, A.scratch_base, sizeof(int32_t) * total);
     it->list_buf = buf;
-    if (A.scratch->overflow) it->abort = 1;
+    if (A.scratch->overflow) run_abort(A);
   }
   __syncthreads();
   for (int e = threadIdx.x; e < A.E; e += blockDim.x) es[e].list = buf ? buf + es[e].list_base : nullptr;
@@ -596,6 +605,7 @@ __global__ __launch_bounds__(1024) void k_scan_nodes(const IterArgs A) {
                              },
                              [&](int64_t i, int64_t v) { es[i].w_tile0 = v; }, lds);
   __shared__ int64_t wtest;
+  __shared__ int32_t sh_abort;
   if (threadIdx.x == 0) wtest = 0;
   __syncthreads();
   for (int e = threadIdx.x; e < A.E; e += blockDim.x) {
@@ -624,14 +634,17 @@ __global__ __launch_bounds__(1024) void k_scan_nodes(const IterArgs A) {
     it->nz_chk_lo = (int64_t *)p[5];
     it->nz_chk_hi = (int64_t *)p[6];
     if (A.scratch->overflow) {
-      it->abort = 1;
+      run_abort(A);
     } else {
       DTile z{};
       z.k0 = nz;
       z.e = -1;
       it->tiles[wt] = z;
     }
+    sh_abort = it->abort;
   }
+  __syncthreads();
+  if (sh_abort) return;   // no level of an aborted iteration is published
   for (int e = threadIdx.x; e < A.E; e += blockDim.x) {
     const DEntry d = A.ent[e];
     const DStep S = A.steps[d.step];
@@ -1061,7 +1074,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
       end = __builtin_amdgcn_readfirstlane(before);
     }
     const int64_t cnt = out ? sld(&es[e].cnt) : 0;
-    if (out && end <= cnt) {   // a tile whose positions would leave the level writes nothing
+    if (out && end > cnt) {   // count and write passes disagree: write nothing, report it
+      if (lane == 0 && A.flags) atomicOr(&A.flags[RF_WRITE], 1);
+    } else if (out) {
       const int32_t *list = sld(&es[e].list);
       int32_t node[R], c[R];
       for (int r = 0; r < R; ++r) {

@@ -39,7 +39,14 @@ struct IterArgs {
   DArena *tree;
   char *tree_base;
   int64_t *blk_a, *blk_b, *blk_off_a, *blk_off_b;   // grid entries each
+  // Run-wide flags, zeroed by the host before the first iteration of a run:
+  // [RF_SCRATCH] a level's temporaries overflowed the scratch arena (every later
+  // iteration of the run then does nothing); [RF_WRITE] the write pass met a tile
+  // whose output positions leave its level (count and write passes disagree).
+  // Null only for the standalone list and domain launches.
+  int32_t *flags;
 };
+enum RunFlag { RF_SCRATCH = 0, RF_WRITE = 1, RF_N = 2 };
 
 // Workgroups of the write pass one compute unit holds at once.
 int expand_write_blocks_per_cu();

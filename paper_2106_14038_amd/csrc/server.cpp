@@ -99,6 +99,7 @@ struct ServerImpl {
   IterScalars *d_it = nullptr;
   int64_t *d_blk = nullptr;
   int64_t *d_zero = nullptr;
+  int32_t *d_flags = nullptr;       // run flags (RF_*), cleared before every iteration
   int32_t *d_rows = nullptr;
   size_t rows_cap = 0;
   // bitmap pool
@@ -392,17 +393,27 @@ void loop(ServerImpl &S) {
     A.lvl_ptr = S.d_lvlp; A.lvl_cptr = S.d_lvlc; A.lvl_n = S.d_lvln; A.qstats = S.d_qs;
     A.scratch = E.d_arenas + 1; A.scratch_base = E.scratch_base; A.tree = E.d_arenas; A.tree_base = E.tree_base;
     A.blk_a = S.d_blk; A.blk_b = S.d_blk + E.grid; A.blk_off_a = S.d_blk + 2 * E.grid; A.blk_off_b = S.d_blk + 3 * E.grid;
+    A.flags = S.d_flags;
+    if (e == hipSuccess) e = zero_words((uint64_t *)S.d_flags, 1, s);
     if (prof) {
       while (E.events.size() < (size_t)2 * KS_N) { hipEvent_t ev; (void)hipEventCreate(&ev); E.events.push_back(ev); }
     }
     if (e == hipSuccess) e = launch_iteration(A, s, prof ? E.events.data() : nullptr);
     IterScalars I{};
+    int32_t rflags[RF_N] = {0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(rflags, S.d_flags, sizeof(rflags), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipMemcpyAsync(lvl_n.data(), S.d_lvln, 8 * lvl_n.size(), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipMemcpyAsync(ar, E.d_arenas, sizeof(ar), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipMemcpyAsync(&I, S.d_it, sizeof(I), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     S.stats.iterations++;
     if (e != hipSuccess) { set_error(hipGetErrorString(e)); fail_all(S, GS_EDEVICE); continue; }
+    if (rflags[RF_WRITE]) {
+      set_error("device inconsistency: the write pass met output positions beyond a level's count");
+      fail_all(S, GS_EDEVICE);
+      continue;
+    }
+    if (rflags[RF_SCRATCH]) ar[1].overflow = 1;   // the iteration was aborted: restart its queries
     if (prof) account_iteration(E, E.events.data(), I, L, 0);
 
     // level pointers and counters of every slot, once, when some query finishes now
@@ -467,6 +478,12 @@ void loop(ServerImpl &S) {
 int server_start(Engine *E, const gs_server_options *o, gs_server **out) {
   *out = nullptr;
   if (!E->loaded) { set_error("no dataset loaded"); return GS_ESTATE; }
+  {   // the server uses the whole tree arena as its ring: no direct result may live in it
+    std::lock_guard<std::mutex> lk(E->mu);
+    if (E->serving) { set_error("a server is already running on this engine"); return GS_ESTATE; }
+    if (E->live_results > 0) { set_error("results of direct evaluation are still live; free them first"); return GS_ESTATE; }
+    E->serving = true;
+  }
   gs_server *srv = new gs_server();
   ServerImpl &S = srv->s;
   S.E = E;
@@ -495,6 +512,7 @@ int server_start(Engine *E, const gs_server_options *o, gs_server **out) {
   take((void **)&S.d_it, sizeof(IterScalars));
   take((void **)&S.d_blk, sizeof(int64_t) * 4 * E->grid);
   take((void **)&S.d_zero, 256);
+  take((void **)&S.d_flags, 256);
   S.rows_cap = 64ull << 20;
   take((void **)&S.d_rows, S.rows_cap);
   // bitmap pool: up to 8 bitmaps per slot, bounded by a sixteenth of the tree arena
@@ -505,6 +523,7 @@ int server_start(Engine *E, const gs_server_options *o, gs_server **out) {
     if (!*p) {
       for (void **q : allocs) E->dfree(*q);
       delete srv;
+      { std::lock_guard<std::mutex> lk(E->mu); E->serving = false; }
       set_error("out of device memory for the server tables");
       return GS_ENOMEM;
     }
@@ -580,9 +599,10 @@ int server_stop(gs_server *srv, gs_server_stats *st) {
   for (auto &d : S.done) if (d.second.second) result_free(d.second.second);
   Engine *E = S.E;
   void *ps[] = {S.d_steps, S.d_filt, S.d_checks, S.d_ints, S.d_cc, S.d_vr, S.d_lvlp, S.d_lvlc, S.d_lvln, S.d_qs, S.d_ents,
-                S.d_doms, S.d_clear, S.d_seeds, S.d_fc, S.d_es, S.d_it, S.d_blk, S.d_zero, S.d_rows, S.pool};
+                S.d_doms, S.d_clear, S.d_seeds, S.d_fc, S.d_es, S.d_it, S.d_blk, S.d_zero, S.d_flags, S.d_rows, S.pool};
   for (void *p : ps) E->dfree(p);
   delete srv;
+  { std::lock_guard<std::mutex> lk(E->mu); E->serving = false; }
   return GS_OK;
 }
 

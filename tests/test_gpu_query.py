@@ -289,3 +289,33 @@ def test_prune_keeps_rows_and_removes_dead_nodes(c0):
         assert err.value.status == gs.GS_EINVAL
     finally:
         gs.gs_engine_destroy(e)
+
+
+@pytest.mark.parametrize("scratch_mb", [8, 24])
+def test_scratch_overflow_in_a_middle_level_is_a_clean_enomem(scratch_mb):
+    """A level whose temporaries exceed the scratch arena stops the whole run:
+    the call fails with GS_ENOMEM (no later level reads the unwritten one), and
+    the engine answers the next query normally. With 8 MB the overflow comes in
+    the iteration set-up of level 3 (16 B per parent node, 10^6 parents), with
+    24 MB in the node pass's allocation (20 B per non-empty parent more), after
+    which test-free levels would otherwise have been published unwritten."""
+    n, P = 10_000, 1
+    trip = workload.uniform_graph(3, n, P, 100_000)   # out-degree ~10: levels grow ~10x
+    chain = {"n_qv": 5, "qv_const": [-1] * 5, "edges": [(0, 1, 1), (1, 1, 2), (2, 1, 3), (3, 1, 4)]}
+    small = {"n_qv": 2, "qv_const": [-1, -1], "edges": [(0, 1, 1)]}
+    # levels 0-2 need a few MB of temporaries, level 3 (10^6 parents) tens of MB
+    e = make_engine(trip, n, P, scratch_bytes=scratch_mb << 20, tree_bytes=1 << 30)
+    try:
+        for flags in (gs.GS_COUNT_ONLY, 0):
+            with pytest.raises(gs.GsError) as ei:
+                gs.gs_query_run(e, chain, flags)
+            assert ei.value.status == gs.GS_ENOMEM, str(ei.value)
+            with pytest.raises(gs.GsError) as ei:
+                gs.gs_batch_run(e, [small, chain], flags)
+            assert ei.value.status == gs.GS_ENOMEM
+        G = oracle.Graph(trip, n, P)
+        cnt, rows = engine_rows(gs, e, small)
+        ocnt, orows = G.eval(small)
+        assert cnt == ocnt == len(trip) and np.array_equal(rows, orows)
+    finally:
+        gs.gs_engine_destroy(e)

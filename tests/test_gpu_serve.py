@@ -161,3 +161,40 @@ def test_poll_ready_drains_every_request_once(c0_mix):
             assert seen[tk] == ocount(G, qs[i], 0)
     finally:
         gs.gs_engine_destroy(eng)
+
+
+def test_server_and_direct_use_are_exclusive():
+    """The server uses the whole tree arena: it does not start while a direct
+    result is live, and direct evaluation is refused while it runs."""
+    n, P = 2000, 4
+    trip = workload.uniform_graph(4, n, P, 20_000)
+    q = {"n_qv": 2, "qv_const": [-1, -1], "edges": [(0, 1, 1)]}
+    e = gs.gs_engine_create(gs.options(tree_bytes=1 << 28, scratch_bytes=1 << 27))
+    try:
+        gs.gs_load_triples(e, n, P, trip)
+        r = gs.gs_query_run(e, q)
+        with pytest.raises(gs.GsError) as ei:
+            gs.gs_server_start(e)
+        assert ei.value.status == gs.GS_ESTATE
+        expect = gs.gs_result_count(r)
+        gs.gs_result_free(r)
+        srv = gs.gs_server_start(e)
+        with pytest.raises(gs.GsError) as ei:
+            gs.gs_query_run(e, q)
+        assert ei.value.status == gs.GS_ESTATE
+        with pytest.raises(gs.GsError) as ei:
+            gs.gs_server_start(e)
+        assert ei.value.status == gs.GS_ESTATE
+        t = gs.gs_submit(srv, q, gs.GS_COUNT_ONLY)
+        deadline = time.time() + 30
+        got = None
+        while got is None and time.time() < deadline:
+            got = gs.gs_poll(srv, t)
+        assert got is not None and gs.gs_result_count(got) == expect
+        gs.gs_result_free(got)
+        gs.gs_server_stop(srv)
+        r = gs.gs_query_run(e, q, gs.GS_COUNT_ONLY)   # direct use again after the stop
+        assert gs.gs_result_count(r) == expect
+        gs.gs_result_free(r)
+    finally:
+        gs.gs_engine_destroy(e)
