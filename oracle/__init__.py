@@ -32,7 +32,7 @@ class OracleError(RuntimeError):
 
 def build() -> str:
     src = os.path.join(_HERE, "oracle.c")
-    subprocess.run(["gcc", "-O2", "-std=c11", "-Wall", "-shared", "-fPIC", "-o", _SO + ".tmp", src],
+    subprocess.run(["gcc", "-O2", "-std=c11", "-Wall", "-shared", "-fPIC", "-pthread", "-o", _SO + ".tmp", src],
                    check=True)
     os.replace(_SO + ".tmp", _SO)
     return _SO
@@ -62,6 +62,10 @@ def _load():
                             ctypes.POINTER(ctypes.c_int64), vp, ctypes.c_int64, ctypes.c_int64,
                             ctypes.POINTER(ctypes.c_int32)]
     lib.or_eval.restype = ctypes.c_int
+    lib.or_eval_digest.argtypes = [vp, ctypes.c_int32, i32p, ctypes.c_int32, i32p, vp, ctypes.c_int32,
+                                   ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_uint64),
+                                   ctypes.POINTER(ctypes.c_uint64)]
+    lib.or_eval_digest.restype = ctypes.c_int
     lib.or_count_acyclic.argtypes = [vp, ctypes.c_int32, i32p, ctypes.c_int32, i32p,
                                      ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]
     lib.or_count_acyclic.restype = ctypes.c_int
@@ -159,6 +163,20 @@ class Graph:
         if cnt.value > cap:
             raise OracleError(-4)
         return cnt.value, buf[:cnt.value * nvars].reshape(cnt.value, nvars).copy()
+
+    def digest(self, q: dict, order=None, threads: int = 1, work_cap: int = 0):
+        """Backtracking evaluation keeping only (count, sum of row hashes mod 2^64, XOR of row
+        hashes): the order-independent digest of the result rows (the row hash is defined in
+        oracle.c). threads > 1 splits the first variable's candidates over that many threads."""
+        consts, edges = _qarrays(q)
+        cnt, hs, hx = ctypes.c_int64(0), ctypes.c_uint64(0), ctypes.c_uint64(0)
+        o = np.ascontiguousarray(order, dtype=np.int32) if order is not None else None
+        rc = _load().or_eval_digest(self._h, q["n_qv"], consts, len(q["edges"]), edges,
+                                    o.ctypes.data if o is not None else None, int(threads), int(work_cap),
+                                    ctypes.byref(cnt), ctypes.byref(hs), ctypes.byref(hx))
+        if rc != 0:
+            raise OracleError(rc)
+        return cnt.value, hs.value, hx.value
 
     def count_acyclic(self, q: dict) -> int:
         """Exact count by message passing over the query forest (acyclic queries only)."""

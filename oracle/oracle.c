@@ -34,6 +34,10 @@
  *    candidates are the label-p neighbours of an already-bound endpoint of
  *    its first such edge (else every vertex); every edge whose endpoints are
  *    all bound is checked by set membership.
+ *  - or_eval_digest: the same backtracking, keeping only the count and an
+ *    order-independent digest of the rows; optionally on several threads,
+ *    each taking chunks of the first variable's candidates (the timing mode
+ *    "on all host cores").
  *  - or_count_acyclic: exact counting by message passing over the query
  *    forest (parallel edges between two variables bundled into one pairwise
  *    constraint). Unsigned 128-bit arithmetic, saturating.
@@ -41,6 +45,8 @@
  * Parity pins for every function live in the CPU test suite (brute force,
  * closed forms, the paper's worked examples, invariants).
  */
+#include <pthread.h>
+#include <stdatomic.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -209,14 +215,35 @@ static int constant_edges_hold(const oracle_graph *g, const nq_t *q) {
 }
 
 /* ------------------------------------------------ backtracking evaluator */
+/* Row digest: an order-independent summary of a bag of rows, for comparing
+ * results too large to store. A row (v_0..v_{k-1}) of width k hashes to
+ *   h_0 = k,  h_{i+1} = mix64(h_i + 0x9E3779B97F4A7C15 + (uint32)v_i),  hash = h_k,
+ * where mix64 is the output function of the splitmix64 generator (Steele, Lea
+ * and Flood, "Fast splittable pseudorandom number generators", OOPSLA 2014).
+ * The digest of a bag is (count, sum of hashes mod 2^64, XOR of hashes). */
+static uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+/* State shared by the workers of one evaluation (several threads: timing mode). */
 typedef struct {
-  const oracle_graph *g; const nq_t *q;
+  atomic_llong work;              /* candidate visits, flushed in batches of 4096 */
+  atomic_int abort;
+  atomic_llong next;              /* next root-candidate chunk */
+  int64_t work_cap;               /* 0 = unlimited */
+} shared_t;
+
+typedef struct {
+  const oracle_graph *g; const nq_t *q; shared_t *sh;
   int32_t order[OR_MAXQV];        /* query vertices (variables) in binding order */
   int32_t val[OR_MAXQV];          /* current value per query vertex (constants preset) */
   uint8_t bound[OR_MAXQV];
   int32_t restrict_qv; const uint8_t *restrict_mask;
   int64_t count; int32_t *rows; int64_t rows_cap;
-  int64_t work, work_cap; int aborted;
+  int digest; uint64_t hsum, hxor;
+  int64_t work; int aborted;
 } bt_t;
 
 static int edges_hold_at(bt_t *B, int32_t x) {
@@ -231,44 +258,66 @@ static int edges_hold_at(bt_t *B, int32_t x) {
 }
 
 static void emit(bt_t *B) {
+  const nq_t *q = B->q;
   if (B->rows && B->count < B->rows_cap) {
-    int32_t *r = B->rows + (size_t)B->count * B->q->nvar;
-    for (int v = 0; v < B->q->nvar; ++v) r[v] = B->val[B->q->qv_of[v]];
+    int32_t *r = B->rows + (size_t)B->count * q->nvar;
+    for (int v = 0; v < q->nvar; ++v) r[v] = B->val[q->qv_of[v]];
+  }
+  if (B->digest) {
+    uint64_t h = (uint64_t)q->nvar;
+    for (int v = 0; v < q->nvar; ++v) h = mix64(h + 0x9E3779B97F4A7C15ull + (uint64_t)(uint32_t)B->val[q->qv_of[v]]);
+    B->hsum += h;
+    B->hxor ^= h;
   }
   B->count++;
 }
 
-static void assign(bt_t *B, int i) {
-  if (B->aborted) return;
+/* One candidate visit against the work cap; returns 1 when the evaluation must stop. */
+static int tick(bt_t *B) {
+  shared_t *sh = B->sh;
+  if (sh->work_cap && (++B->work & 4095) == 0 && atomic_fetch_add(&sh->work, 4096) + 4096 > sh->work_cap)
+    atomic_store(&sh->abort, 1);
+  if (atomic_load_explicit(&sh->abort, memory_order_relaxed)) { B->aborted = 1; return 1; }
+  return 0;
+}
+
+/* Candidates of variable x: the label-p neighbours of the bound endpoint of its
+ * first edge to a bound query vertex (a constant or an earlier variable); NULL
+ * with *cnt = N when no such edge exists (every vertex is a candidate). */
+static const otrip *candidates(const bt_t *B, int32_t x, int64_t *cnt) {
   const nq_t *q = B->q;
-  if (i == q->nvar) { emit(B); return; }
-  int32_t x = B->order[i];
-  /* candidates: first edge of x whose other endpoint is bound (a constant or an earlier variable) */
-  int cand_k = -1, cand_dir = 0; int32_t anchor = -1;
-  for (int k = 0; k < q->n_edges && cand_k < 0; ++k) {
+  for (int k = 0; k < q->n_edges; ++k) {
     int32_t s = q->e[k][0], o = q->e[k][2];
-    if (s == x && o != x && B->bound[o]) { cand_k = k; cand_dir = 1; anchor = B->val[o]; }
-    else if (o == x && s != x && B->bound[s]) { cand_k = k; cand_dir = 0; anchor = B->val[s]; }
+    if (s == x && o != x && B->bound[o]) return adj(B->g, B->val[o], q->e[k][1], 1, cnt);
+    if (o == x && s != x && B->bound[s]) return adj(B->g, B->val[s], q->e[k][1], 0, cnt);
   }
+  *cnt = B->g->n;
+  return NULL;
+}
+
+static void assign(bt_t *B, int i);
+
+/* Bind order[i] to candidates [lo, hi) of its candidate list in turn, check every
+ * edge that becomes fully bound, and go on with the next variable. */
+static void assign_range(bt_t *B, int i, const otrip *nb, int64_t lo, int64_t hi) {
+  int32_t x = B->order[i];
   B->bound[x] = 1;
-  if (cand_k >= 0) {
-    int64_t cnt; const otrip *nb = adj(B->g, anchor, q->e[cand_k][1], cand_dir, &cnt);
-    for (int64_t t = 0; t < cnt; ++t) {
-      if (B->work_cap && ++B->work > B->work_cap) { B->aborted = 1; break; }
-      int32_t c = nb[t].b;
-      if (x == B->restrict_qv && !B->restrict_mask[c]) continue;
-      B->val[x] = c;
-      if (edges_hold_at(B, x)) assign(B, i + 1);
-    }
-  } else {
-    for (int64_t c = 0; c < B->g->n; ++c) {
-      if (B->work_cap && ++B->work > B->work_cap) { B->aborted = 1; break; }
-      if (x == B->restrict_qv && !B->restrict_mask[c]) continue;
-      B->val[x] = (int32_t)c;
-      if (edges_hold_at(B, x)) assign(B, i + 1);
-    }
+  for (int64_t t = lo; t < hi; ++t) {
+    if (tick(B)) break;
+    int32_t c = nb ? nb[t].b : (int32_t)t;
+    if (x == B->restrict_qv && !B->restrict_mask[c]) continue;
+    B->val[x] = c;
+    if (edges_hold_at(B, x)) assign(B, i + 1);
   }
   B->bound[x] = 0;
+}
+
+static void assign(bt_t *B, int i) {
+  if (B->aborted) return;
+  if (i == B->q->nvar) { emit(B); return; }
+  int64_t cnt;
+  const otrip *nb = candidates(B, B->order[i], &cnt);
+  assign_range(B, i, nb, 0, cnt);
 }
 
 /* Default order: breadth-first over the undirected query graph, starting from
@@ -308,37 +357,46 @@ static int cmp_rows(const void *x, const void *y) {
   return 0;
 }
 
+/* Common set-up of an evaluation: normalised query, binding order, constants. */
+static int setup(const oracle_graph *g, int32_t n_qv, const int32_t *qv_const, int32_t n_edges, const int32_t *edges,
+                 const int32_t *order, nq_t *q, bt_t *B) {
+  int rc = normalise(g, n_qv, qv_const, n_edges, edges, q);
+  if (rc) return rc;
+  memset(B, 0, sizeof *B);
+  B->g = g; B->q = q; B->restrict_qv = -1;
+  if (order) {
+    uint8_t seen[OR_MAXQV] = {0};
+    for (int i = 0; i < q->nvar; ++i) {
+      int32_t v = order[i];
+      if (v < 0 || v >= n_qv || q->cst[v] >= 0 || seen[v]) return -3;
+      seen[v] = 1; B->order[i] = v;
+    }
+  } else {
+    default_order(q, B->order);
+  }
+  for (int v = 0; v < n_qv; ++v) if (q->cst[v] >= 0) { B->bound[v] = 1; B->val[v] = q->cst[v]; }
+  return 0;
+}
+
 /* Evaluate a query.
  *  order: binding order as query-vertex indices of every variable, or NULL for the default.
  *  restrict_qv / restrict_mask: optionally keep only rows whose query vertex restrict_qv takes
  *    a value c with restrict_mask[c] != 0 (restrict_qv < 0: no restriction).
  *  rows: if non-NULL, up to rows_cap rows of width nvar are written, sorted lexicographically.
- *  work_cap: 0 = unlimited; else abort after that many candidate visits (returns -4).
+ *  work_cap: 0 = unlimited; else abort after about that many candidate visits (returns -4).
  * Returns 0 ok, -1 malformed query, -2 out of range, -3 bad order, -4 aborted on work cap. */
 int or_eval(const oracle_graph *g, int32_t n_qv, const int32_t *qv_const, int32_t n_edges, const int32_t *edges,
             const int32_t *order, int32_t restrict_qv, const uint8_t *restrict_mask,
             int64_t *count, int32_t *rows, int64_t rows_cap, int64_t work_cap, int32_t *n_vars_out) {
-  nq_t q;
-  int rc = normalise(g, n_qv, qv_const, n_edges, edges, &q);
+  nq_t q; bt_t B; shared_t sh;
+  int rc = setup(g, n_qv, qv_const, n_edges, edges, order, &q, &B);
   if (rc) return rc;
   if (n_vars_out) *n_vars_out = q.nvar;
-  bt_t B; memset(&B, 0, sizeof B);
-  B.g = g; B.q = &q; B.rows = rows; B.rows_cap = rows_cap; B.work_cap = work_cap;
+  atomic_init(&sh.work, 0); atomic_init(&sh.abort, 0); atomic_init(&sh.next, 0); sh.work_cap = work_cap;
+  B.sh = &sh; B.rows = rows; B.rows_cap = rows_cap;
   B.restrict_qv = (restrict_qv >= 0 && restrict_mask) ? restrict_qv : -1; B.restrict_mask = restrict_mask;
-  if (order) {
-    uint8_t seen[OR_MAXQV] = {0};
-    for (int i = 0; i < q.nvar; ++i) {
-      int32_t v = order[i];
-      if (v < 0 || v >= n_qv || q.cst[v] >= 0 || seen[v]) return -3;
-      seen[v] = 1; B.order[i] = v;
-    }
-  } else {
-    default_order(&q, B.order);
-  }
-  for (int v = 0; v < n_qv; ++v) if (q.cst[v] >= 0) { B.bound[v] = 1; B.val[v] = q.cst[v]; }
   *count = 0;
   if (!constant_edges_hold(g, &q)) return 0;
-  /* constant self-loops and constant-constant edges are covered above; variables start unbound */
   assign(&B, 0);
   if (B.aborted) return -4;
   *count = B.count;
@@ -347,6 +405,68 @@ int or_eval(const oracle_graph *g, int32_t n_qv, const int32_t *qv_const, int32_
     cmp_rows_k = q.nvar;
     qsort(rows, (size_t)nr, sizeof(int32_t) * q.nvar, cmp_rows);
   }
+  return 0;
+}
+
+/* ------------------------------------------------ digest, on all host cores */
+typedef struct { bt_t B; const otrip *nb; int64_t ncand, chunk; } worker_t;
+
+static void *worker_main(void *arg) {
+  worker_t *w = (worker_t *)arg;
+  bt_t *B = &w->B;
+  for (;;) {
+    int64_t c = atomic_fetch_add(&B->sh->next, 1);
+    int64_t lo = c * w->chunk;
+    if (lo >= w->ncand || B->aborted) break;
+    int64_t hi = lo + w->chunk < w->ncand ? lo + w->chunk : w->ncand;
+    assign_range(B, 0, w->nb, lo, hi);
+  }
+  return NULL;
+}
+
+/* Count and row digest of a query without storing rows. The first variable's
+ * candidates are split into chunks that nthreads threads take in turn, each
+ * running the same backtracking below its chunk (nthreads <= 1: the calling
+ * thread alone, the plain evaluation). work_cap bounds the candidate visits of
+ * all threads together (0 = unlimited). Returns as or_eval. */
+int or_eval_digest(const oracle_graph *g, int32_t n_qv, const int32_t *qv_const, int32_t n_edges,
+                   const int32_t *edges, const int32_t *order, int32_t nthreads, int64_t work_cap,
+                   int64_t *count, uint64_t *hsum, uint64_t *hxor) {
+  nq_t q; bt_t B; shared_t sh;
+  int rc = setup(g, n_qv, qv_const, n_edges, edges, order, &q, &B);
+  if (rc) return rc;
+  atomic_init(&sh.work, 0); atomic_init(&sh.abort, 0); atomic_init(&sh.next, 0); sh.work_cap = work_cap;
+  B.sh = &sh; B.digest = 1;
+  *count = 0; *hsum = 0; *hxor = 0;
+  if (!constant_edges_hold(g, &q)) return 0;
+  if (q.nvar == 0 || nthreads <= 1) {
+    assign(&B, 0);
+    if (B.aborted) return -4;
+    *count = B.count; *hsum = B.hsum; *hxor = B.hxor;
+    return 0;
+  }
+  int64_t ncand;
+  const otrip *nb = candidates(&B, B.order[0], &ncand);
+  if (nthreads > 256) nthreads = 256;
+  worker_t *w = (worker_t *)calloc((size_t)nthreads, sizeof(worker_t));
+  pthread_t *th = (pthread_t *)calloc((size_t)nthreads, sizeof(pthread_t));
+  int64_t chunk = ncand / ((int64_t)nthreads * 64);
+  if (chunk < 1) chunk = 1;
+  int started = 0;
+  for (int t = 0; t < nthreads; ++t) {
+    w[t].B = B; w[t].nb = nb; w[t].ncand = ncand; w[t].chunk = chunk;
+    if (pthread_create(&th[t], NULL, worker_main, &w[t]) != 0) break;
+    started++;
+  }
+  if (started == 0) worker_main(&w[0]);   /* no thread could be started: run the chunks here */
+  for (int t = 0; t < started; ++t) pthread_join(th[t], NULL);
+  int aborted = atomic_load(&sh.abort);
+  for (int t = 0; t < (started ? started : 1); ++t) {
+    aborted |= w[t].B.aborted;
+    *count += w[t].B.count; *hsum += w[t].B.hsum; *hxor ^= w[t].B.hxor;
+  }
+  free(w); free(th);
+  if (aborted) { *count = 0; *hsum = 0; *hxor = 0; return -4; }
   return 0;
 }
 

@@ -103,3 +103,28 @@ def engine_rows(gs, engine, q, flags=0):
     finally:
         gs.gs_result_free(r)
     return cnt, (sort_rows(rows) if rows is not None else None)
+
+
+_M64 = (1 << 64) - 1
+
+
+def _mix64(z):
+    # output function of splitmix64 (Steele, Lea and Flood, OOPSLA 2014), on Python ints
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _M64
+    return z ^ (z >> 31)
+
+
+def row_digest(rows, width):
+    """(count, sum of row hashes mod 2^64, XOR of row hashes) of a bag of rows; a row
+    (v_0..v_{k-1}) hashes to h_k with h_0 = k, h_{i+1} = mix64(h_i + 0x9E3779B97F4A7C15 + v_i)."""
+    s = x = 0
+    n = 0
+    for r in np.asarray(rows, dtype=np.int64).reshape(-1, width).tolist() if width else [[]] * len(rows):
+        h = width
+        for v in r:
+            h = _mix64((h + 0x9E3779B97F4A7C15 + (v & 0xFFFFFFFF)) & _M64)
+        s = (s + h) & _M64
+        x ^= h
+        n += 1
+    return n, s, x

@@ -13,7 +13,7 @@ import pytest
 
 import oracle
 import workload
-from helpers import brute_force, dense_tensor, random_query, sort_rows
+from helpers import _mix64, brute_force, dense_tensor, random_query, row_digest, sort_rows
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -339,3 +339,98 @@ def test_c0_workload_star_nonempty():
         val = {v: r[i] for i, v in enumerate(var_qv)}
         val.update({i: c for i, c in enumerate(q["qv_const"]) if c >= 0})
         assert all((val[s], p, val[o]) in S for s, p, o in q["edges"])
+
+
+# ------------------------------------------------------------------ set semantics of the load
+def test_duplicate_and_permuted_triples_form_a_set():
+    # Section 2.2.1: a dataset is a set of triples. Repeated and reordered input triples must
+    # give the same index, the same distinct count and the same results as the distinct set.
+    rng = np.random.default_rng(21)
+    for case in range(20):
+        n, P = int(rng.integers(2, 12)), int(rng.integers(1, 4))
+        base = np.stack([rng.integers(0, n, 60), rng.integers(1, P + 1, 60), rng.integers(0, n, 60)], 1)
+        dup = np.concatenate([base, base[rng.integers(0, len(base), 80)]])
+        dup = dup[rng.permutation(len(dup))].astype(np.int32)
+        uniq = np.unique(base, axis=0)
+        G = oracle.Graph(dup, n, P)
+        assert G.m == len(uniq)
+        # row-wise arrays straight from the distinct set: rows by s, each row by (p, o)
+        order = np.lexsort((uniq[:, 2], uniq[:, 1], uniq[:, 0]))
+        u = uniq[order]
+        rp, col, lab = G.csr()
+        assert np.array_equal(rp, np.searchsorted(u[:, 0], np.arange(n + 1), side="left"))
+        assert np.array_equal(col, u[:, 2]) and np.array_equal(lab, u[:, 1])
+        order = np.lexsort((uniq[:, 0], uniq[:, 1], uniq[:, 2]))
+        u = uniq[order]
+        cp, row, labc = G.csc()
+        assert np.array_equal(cp, np.searchsorted(u[:, 2], np.arange(n + 1), side="left"))
+        assert np.array_equal(row, u[:, 0]) and np.array_equal(labc, u[:, 1])
+        r = random.Random(case)
+        for _ in range(5):
+            q = random_query(r, n, P, r.randint(1, 3), r.randint(0, 1))
+            cnt, rows = G.eval(q)
+            bf = brute_force(uniq, n, P, q)
+            assert cnt == len(bf) and (rows.shape[1] == 0 or np.array_equal(rows, bf)), q
+
+
+# ------------------------------------------------------------------ row digest and the timing mode
+def test_splitmix64_output_function_reference_values():
+    # the first outputs of splitmix64 started from state 0 (Steele, Lea and Flood 2014): its
+    # output function applied to 1, 2 and 3 times the golden-ratio increment
+    g = 0x9E3779B97F4A7C15
+    got = [_mix64((i * g) % (1 << 64)) for i in (1, 2, 3)]
+    assert got == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_digest_matches_brute_force_rows(seed):
+    rng = random.Random(500 + seed)
+    for case in range(40):
+        n, P = rng.randint(1, 8), rng.randint(1, 3)
+        m = rng.randint(0, n * n * P)
+        trip = workload.uniform_graph(rng.randrange(1 << 30), n, P, m) if m else np.zeros((0, 3), np.int32)
+        nv = rng.randint(0, 4)
+        q = random_query(rng, n, P, nv, rng.randint(0 if nv else 1, 2), connected=rng.random() < 0.8)
+        G = oracle.Graph(trip, n, P)
+        bf = brute_force(trip, n, P, q)
+        expect = row_digest(bf, nv)
+        assert G.digest(q) == expect, (case, q)
+        assert G.digest(q, threads=3) == expect, (case, q)
+
+
+def test_digest_detects_a_changed_row():
+    # a row with one value changed, dropped or repeated changes the digest
+    rows = np.array([[1, 2, 3], [4, 5, 6], [1, 2, 4]], np.int32)
+    d = row_digest(rows, 3)
+    assert row_digest(rows[[0, 1]], 3) != d
+    assert row_digest(np.array([[1, 2, 3], [4, 5, 6], [1, 2, 5]]), 3) != d
+    assert row_digest(np.array([[1, 2, 3], [4, 5, 6], [1, 2, 3]]), 3)[1:] != d[1:]
+    assert row_digest(rows[[2, 0, 1]], 3) == d
+
+
+def test_digest_on_all_cores_equals_one_thread():
+    # the timing mode: the first variable's candidates split over threads gives the same
+    # count and digest as the plain evaluation, with and without a constant anchoring them
+    n, P = 3000, 4
+    trip = workload.uniform_graph(3, n, P, 30000)
+    G = oracle.Graph(trip, n, P)
+    shapes = ["chain4", "star5", "snowflake8", "triangle"]
+    qs = []
+    for i, sh in enumerate(shapes):
+        qs += workload.walk_queries(trip, n, 40 + i, sh, 2)
+    qs.append({"n_qv": 3, "qv_const": [-1, -1, int(trip[0, 0])], "edges": [(2, int(trip[0, 1]), 0), (0, 1, 1)]})
+    for q in qs:
+        one = G.digest(q)
+        assert one[0] == G.eval(q, rows=False)[0]
+        for t in (2, 8):
+            assert G.digest(q, threads=t) == one, (q, t)
+
+
+def test_digest_work_cap_aborts():
+    n, P = 400, 2
+    trip = workload.uniform_graph(4, n, P, 20000)
+    G = oracle.Graph(trip, n, P)
+    q = {"n_qv": 4, "qv_const": [-1] * 4, "edges": [(0, 1, 1), (1, 1, 2), (2, 2, 3)]}
+    for t in (1, 4):
+        with pytest.raises(oracle.OracleError):
+            G.digest(q, threads=t, work_cap=100_000)
