@@ -51,6 +51,15 @@ def _load():
     u8p = np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")
     lib.or_graph_new.argtypes = [i32p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32]
     lib.or_graph_new.restype = vp
+    lib.or_graph_begin.argtypes = [ctypes.c_int64, ctypes.c_int32]
+    lib.or_graph_begin.restype = vp
+    lib.or_graph_count.argtypes = [vp, i32p, ctypes.c_int64]
+    lib.or_graph_count.restype = ctypes.c_int
+    lib.or_graph_alloc.argtypes = [vp]
+    lib.or_graph_alloc.restype = ctypes.c_int
+    lib.or_graph_fill.argtypes = [vp, i32p, ctypes.c_int64]
+    lib.or_graph_finish.argtypes = [vp, ctypes.c_int32]
+    lib.or_graph_finish.restype = ctypes.c_int
     lib.or_graph_free.argtypes = [vp]
     lib.or_graph_m.argtypes = [vp]
     lib.or_graph_m.restype = ctypes.c_int64
@@ -63,7 +72,7 @@ def _load():
                             ctypes.POINTER(ctypes.c_int32)]
     lib.or_eval.restype = ctypes.c_int
     lib.or_eval_digest.argtypes = [vp, ctypes.c_int32, i32p, ctypes.c_int32, i32p, vp, ctypes.c_int32,
-                                   ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_uint64),
+                                   ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_uint64),
                                    ctypes.POINTER(ctypes.c_uint64)]
     lib.or_eval_digest.restype = ctypes.c_int
     lib.or_count_acyclic.argtypes = [vp, ctypes.c_int32, i32p, ctypes.c_int32, i32p,
@@ -87,12 +96,36 @@ class Graph:
     def __init__(self, triples: np.ndarray, n: int, n_labels: int):
         lib = _load()
         t = np.ascontiguousarray(triples, dtype=np.int32).reshape(-1)
-        self._t = t
         self.n, self.n_labels = int(n), int(n_labels)
         self._h = lib.or_graph_new(t if len(t) else np.zeros(3, np.int32), len(t) // 3, n, n_labels)
         if not self._h:
             raise OracleError(-2)
         self.m = lib.or_graph_m(self._h)
+
+    @classmethod
+    def from_chunks(cls, chunks, n: int, n_labels: int, threads: int = 1):
+        """The triple set of a stream too large to hold at once: chunks() yields int32 arrays
+        of triples; it is called twice (count, then fill) and must yield the same triples."""
+        lib = _load()
+        self = cls.__new__(cls)
+        self.n, self.n_labels = int(n), int(n_labels)
+        self._h = lib.or_graph_begin(n, n_labels)
+        if not self._h:
+            raise MemoryError("oracle graph")
+        for c in chunks():
+            c = np.ascontiguousarray(c, dtype=np.int32).reshape(-1)
+            if len(c) and lib.or_graph_count(self._h, c, len(c) // 3) != 0:
+                raise OracleError(-2)
+        if lib.or_graph_alloc(self._h) != 0:
+            raise MemoryError("oracle graph")
+        for c in chunks():
+            c = np.ascontiguousarray(c, dtype=np.int32).reshape(-1)
+            if len(c):
+                lib.or_graph_fill(self._h, c, len(c) // 3)
+        if lib.or_graph_finish(self._h, int(threads)) != 0:
+            raise RuntimeError("oracle graph: the two orientations disagree")
+        self.m = lib.or_graph_m(self._h)
+        return self
 
     def __del__(self):
         if getattr(self, "_h", None):
@@ -164,15 +197,17 @@ class Graph:
             raise OracleError(-4)
         return cnt.value, buf[:cnt.value * nvars].reshape(cnt.value, nvars).copy()
 
-    def digest(self, q: dict, order=None, threads: int = 1, work_cap: int = 0):
+    def digest(self, q: dict, order=None, threads: int = 1, work_cap: int = 0, support_filter: bool = False):
         """Backtracking evaluation keeping only (count, sum of row hashes mod 2^64, XOR of row
         hashes): the order-independent digest of the result rows (the row hash is defined in
-        oracle.c). threads > 1 splits the first variable's candidates over that many threads."""
+        oracle.c). threads > 1 splits the first variable's candidates over that many threads;
+        support_filter narrows candidates by arc consistency first (same rows, less search)."""
         consts, edges = _qarrays(q)
         cnt, hs, hx = ctypes.c_int64(0), ctypes.c_uint64(0), ctypes.c_uint64(0)
         o = np.ascontiguousarray(order, dtype=np.int32) if order is not None else None
         rc = _load().or_eval_digest(self._h, q["n_qv"], consts, len(q["edges"]), edges,
-                                    o.ctypes.data if o is not None else None, int(threads), int(work_cap),
+                                    o.ctypes.data if o is not None else None, int(threads),
+                                    int(bool(support_filter)), int(work_cap),
                                     ctypes.byref(cnt), ctypes.byref(hs), ctypes.byref(hx))
         if rc != 0:
             raise OracleError(rc)

@@ -51,107 +51,196 @@
 #include <stdlib.h>
 #include <string.h>
 
-typedef struct { int32_t a, p, b; } otrip;   /* (a, p, b): spo order or ops order */
+/* The triple set in both orientations. Row v of orientation 0 lists the
+ * triples (v, p, o) as keys p << 32 | o, row v of orientation 1 the triples
+ * (s, p, v) as keys p << 32 | s; each row sorted ascending, without repeats.
+ * A key's neighbour is its low 32 bits, its label the high 32 bits. */
+typedef uint64_t okey;
+static inline okey mkkey(int32_t p, int32_t v) { return ((uint64_t)(uint32_t)p << 32) | (uint32_t)v; }
+static inline int32_t key_nbr(okey k) { return (int32_t)(uint32_t)k; }
+static inline int32_t key_lab(okey k) { return (int32_t)(k >> 32); }
 
 typedef struct {
   int64_t n; int32_t P; int64_t m;
-  otrip *spo;      /* (s, p, o) sorted lexicographically, unique */
-  otrip *ops;      /* (o, p, s) sorted lexicographically, unique */
+  int64_t *ptr[2];    /* n + 1 row offsets per orientation */
+  okey *key[2];       /* m keys per orientation */
+  int64_t *cur[2];    /* build only: fill cursors */
+  int64_t cap;        /* build only: triples counted (repeats included) */
 } oracle_graph;
 
-static int cmp_trip(const void *x, const void *y) {
-  const otrip *u = (const otrip *)x, *v = (const otrip *)y;
-  if (u->a != v->a) return u->a < v->a ? -1 : 1;
-  if (u->p != v->p) return u->p < v->p ? -1 : 1;
-  if (u->b != v->b) return u->b < v->b ? -1 : 1;
-  return 0;
-}
-
-static int64_t sort_unique(otrip *t, int64_t m) {
-  qsort(t, (size_t)m, sizeof(otrip), cmp_trip);
-  int64_t k = 0;
-  for (int64_t i = 0; i < m; ++i)
-    if (k == 0 || cmp_trip(&t[k - 1], &t[i]) != 0) t[k++] = t[i];
-  return k;
-}
-
-/* Build the triple set. Returns NULL on bad ids (s/o outside [0,n), p outside [1,P]). */
-oracle_graph *or_graph_new(const int32_t *triples, int64_t m, int64_t n, int32_t P) {
-  if (n < 0 || P < 0 || m < 0) return NULL;
-  for (int64_t i = 0; i < m; ++i) {
-    int32_t s = triples[3 * i], p = triples[3 * i + 1], o = triples[3 * i + 2];
-    if (s < 0 || s >= n || o < 0 || o >= n || p < 1 || p > P) return NULL;
-  }
+/* Streamed build: count every triple (validating ids), allocate, place every
+ * triple again, then sort and deduplicate each row. The same triples must be
+ * passed to the count and the fill step. */
+oracle_graph *or_graph_begin(int64_t n, int32_t P) {
+  if (n < 0 || P < 0) return NULL;
   oracle_graph *g = (oracle_graph *)calloc(1, sizeof *g);
+  if (!g) return NULL;
   g->n = n; g->P = P;
-  g->spo = (otrip *)malloc(sizeof(otrip) * (size_t)(m ? m : 1));
-  g->ops = (otrip *)malloc(sizeof(otrip) * (size_t)(m ? m : 1));
-  for (int64_t i = 0; i < m; ++i) {
-    g->spo[i].a = triples[3 * i]; g->spo[i].p = triples[3 * i + 1]; g->spo[i].b = triples[3 * i + 2];
-    g->ops[i].a = triples[3 * i + 2]; g->ops[i].p = triples[3 * i + 1]; g->ops[i].b = triples[3 * i];
+  for (int d = 0; d < 2; ++d) {
+    g->ptr[d] = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    if (!g->ptr[d]) return NULL;
   }
-  g->m = sort_unique(g->spo, m);
-  sort_unique(g->ops, m);
   return g;
 }
 
-void or_graph_free(oracle_graph *g) { if (g) { free(g->spo); free(g->ops); free(g); } }
+/* Returns 0, or -2 when a triple has s/o outside [0, n) or p outside [1, P]. */
+int or_graph_count(oracle_graph *g, const int32_t *triples, int64_t m) {
+  for (int64_t i = 0; i < m; ++i) {
+    int32_t s = triples[3 * i], p = triples[3 * i + 1], o = triples[3 * i + 2];
+    if (s < 0 || s >= g->n || o < 0 || o >= g->n || p < 1 || p > g->P) return -2;
+  }
+  for (int64_t i = 0; i < m; ++i) { g->ptr[0][triples[3 * i] + 1]++; g->ptr[1][triples[3 * i + 2] + 1]++; }
+  g->cap += m;
+  return 0;
+}
+
+int or_graph_alloc(oracle_graph *g) {
+  for (int d = 0; d < 2; ++d) {
+    for (int64_t v = 0; v < g->n; ++v) g->ptr[d][v + 1] += g->ptr[d][v];
+    g->key[d] = (okey *)malloc(sizeof(okey) * (size_t)(g->cap ? g->cap : 1));
+    g->cur[d] = (int64_t *)malloc(sizeof(int64_t) * ((size_t)g->n + 1));
+    if (!g->key[d] || !g->cur[d]) return -1;
+    memcpy(g->cur[d], g->ptr[d], sizeof(int64_t) * ((size_t)g->n + 1));
+  }
+  return 0;
+}
+
+void or_graph_fill(oracle_graph *g, const int32_t *triples, int64_t m) {
+  for (int64_t i = 0; i < m; ++i) {
+    int32_t s = triples[3 * i], p = triples[3 * i + 1], o = triples[3 * i + 2];
+    g->key[0][g->cur[0][s]++] = mkkey(p, o);
+    g->key[1][g->cur[1][o]++] = mkkey(p, s);
+  }
+}
+
+static int cmp_key(const void *x, const void *y) {
+  okey a = *(const okey *)x, b = *(const okey *)y;
+  return a < b ? -1 : a > b;
+}
+
+typedef struct { oracle_graph *g; int d; int64_t v0, v1; int64_t *kept; } sort_job;
+
+/* Sort rows [v0, v1) and drop repeats; each row's distinct keys stay at its start. */
+static void *sort_rows_job(void *arg) {
+  sort_job *j = (sort_job *)arg;
+  const int64_t *ptr = j->g->ptr[j->d];
+  okey *key = j->g->key[j->d];
+  for (int64_t v = j->v0; v < j->v1; ++v) {
+    int64_t a = ptr[v], e = ptr[v + 1], k = a;
+    qsort(key + a, (size_t)(e - a), sizeof(okey), cmp_key);
+    for (int64_t i = a; i < e; ++i)
+      if (k == a || key[k - 1] != key[i]) key[k++] = key[i];
+    j->kept[v] = k - a;
+  }
+  return NULL;
+}
+
+/* Returns 0, or -1 when the orientations disagree (cannot happen for equal inputs). */
+int or_graph_finish(oracle_graph *g, int32_t nthreads) {
+  if (nthreads < 1) nthreads = 1;
+  if (nthreads > 64) nthreads = 64;
+  int64_t *kept = (int64_t *)malloc(sizeof(int64_t) * ((size_t)g->n + 1));
+  int64_t mm[2] = {0, 0};
+  for (int d = 0; d < 2; ++d) {
+    free(g->cur[d]); g->cur[d] = NULL;
+    sort_job jobs[64];
+    pthread_t th[64];
+    int running[64] = {0};
+    for (int t = 0; t < nthreads; ++t) {
+      jobs[t].g = g; jobs[t].d = d; jobs[t].kept = kept;
+      jobs[t].v0 = g->n * t / nthreads; jobs[t].v1 = g->n * (t + 1) / nthreads;
+      running[t] = nthreads > 1 && pthread_create(&th[t], NULL, sort_rows_job, &jobs[t]) == 0;
+      if (!running[t]) sort_rows_job(&jobs[t]);   /* this thread takes the job itself */
+    }
+    for (int t = 0; t < nthreads; ++t) if (running[t]) pthread_join(th[t], NULL);
+    /* compact the rows to the front, in order */
+    int64_t w = 0;
+    for (int64_t v = 0; v < g->n; ++v) {
+      const int64_t a = g->ptr[d][v];
+      g->ptr[d][v] = w;
+      memmove(g->key[d] + w, g->key[d] + a, sizeof(okey) * (size_t)kept[v]);
+      w += kept[v];
+    }
+    g->ptr[d][g->n] = w;
+    mm[d] = w;
+    okey *shrunk = (okey *)realloc(g->key[d], sizeof(okey) * (size_t)(w ? w : 1));   /* return the repeats' room */
+    if (shrunk) g->key[d] = shrunk;
+  }
+  free(kept);
+  g->m = mm[0];
+  return mm[0] == mm[1] ? 0 : -1;
+}
+
+/* Build the triple set from one array. Returns NULL on bad ids (s/o outside [0,n), p outside [1,P]). */
+oracle_graph *or_graph_new(const int32_t *triples, int64_t m, int64_t n, int32_t P) {
+  if (m < 0) return NULL;
+  oracle_graph *g = or_graph_begin(n, P);
+  if (!g) return NULL;
+  if (or_graph_count(g, triples, m) != 0 || or_graph_alloc(g) != 0) {
+    for (int d = 0; d < 2; ++d) { free(g->ptr[d]); free(g->key[d]); free(g->cur[d]); }
+    free(g);
+    return NULL;
+  }
+  or_graph_fill(g, triples, m);
+  or_graph_finish(g, 1);
+  return g;
+}
+
+void or_graph_free(oracle_graph *g) {
+  if (!g) return;
+  for (int d = 0; d < 2; ++d) { free(g->ptr[d]); free(g->key[d]); free(g->cur[d]); }
+  free(g);
+}
 int64_t or_graph_m(const oracle_graph *g) { return g->m; }
 
-/* first index in t[0..m) not less than (a, p, b) */
-static int64_t lower(const otrip *t, int64_t m, int32_t a, int32_t p, int32_t b) {
-  int64_t lo = 0, hi = m;
-  otrip key = {a, p, b};
+/* first index in key[lo, hi) not less than k */
+static int64_t lower_key(const okey *key, int64_t lo, int64_t hi, okey k) {
   while (lo < hi) {
     int64_t mid = lo + (hi - lo) / 2;
-    if (cmp_trip(&t[mid], &key) < 0) lo = mid + 1; else hi = mid;
+    if (key[mid] < k) lo = mid + 1; else hi = mid;
   }
   return lo;
 }
 
 /* Is (s, p, o) in the set? */
 static int has_triple(const oracle_graph *g, int32_t s, int32_t p, int32_t o) {
-  int64_t i = lower(g->spo, g->m, s, p, o);
-  return i < g->m && g->spo[i].a == s && g->spo[i].p == p && g->spo[i].b == o;
+  const okey k = mkkey(p, o);
+  const int64_t a = g->ptr[0][s], e = g->ptr[0][s + 1];
+  const int64_t i = lower_key(g->key[0], a, e, k);
+  return i < e && g->key[0][i] == k;
 }
 
-/* Neighbours of v along label p: dir 0 = objects of (v, p, *), dir 1 = subjects of (*, p, v).
- * Returns the range [*lo, *hi) in spo (dir 0) or ops (dir 1); neighbour = .b */
-static const otrip *adj(const oracle_graph *g, int32_t v, int32_t p, int dir, int64_t *cnt) {
-  const otrip *t = dir ? g->ops : g->spo;
-  int64_t lo = lower(t, g->m, v, p, INT32_MIN), hi = lower(t, g->m, v, p + 1, INT32_MIN);
+/* Neighbours of v along label p: dir 0 = objects of (v, p, *), dir 1 = subjects of (*, p, v);
+ * *cnt keys, each neighbour = key_nbr(key). */
+static const okey *adj(const oracle_graph *g, int32_t v, int32_t p, int dir, int64_t *cnt) {
+  const int64_t a = g->ptr[dir][v], e = g->ptr[dir][v + 1];
+  const int64_t lo = lower_key(g->key[dir], a, e, mkkey(p, 0));
+  const int64_t hi = lower_key(g->key[dir], lo, e, mkkey(p + 1, 0));
   *cnt = hi - lo;
-  return t + lo;
+  return g->key[dir] + lo;
 }
 
 /* ---------------------------------------------------- LSpM (Section 6.2) */
 /* Row-wise storage of the whole matrix: row_ptr[n+1], col[m], lab[m] (1-based
  * labels), each row's entries in (label, column) order. */
 void or_csr(const oracle_graph *g, int64_t *row_ptr, int32_t *col, int32_t *lab) {
-  int64_t k = 0;
-  for (int64_t r = 0; r <= g->n; ++r) {
-    while (k < g->m && g->spo[k].a < r) ++k;
-    row_ptr[r] = k;
-  }
-  for (int64_t i = 0; i < g->m; ++i) { col[i] = g->spo[i].b; lab[i] = g->spo[i].p; }
+  memcpy(row_ptr, g->ptr[0], sizeof(int64_t) * ((size_t)g->n + 1));
+  for (int64_t i = 0; i < g->m; ++i) { col[i] = key_nbr(g->key[0][i]); lab[i] = key_lab(g->key[0][i]); }
 }
 /* Column-wise storage: col_ptr[n+1], row[m], lab[m], each column in (label, row) order. */
 void or_csc(const oracle_graph *g, int64_t *col_ptr, int32_t *row, int32_t *lab) {
-  int64_t k = 0;
-  for (int64_t c = 0; c <= g->n; ++c) {
-    while (k < g->m && g->ops[k].a < c) ++k;
-    col_ptr[c] = k;
-  }
-  for (int64_t i = 0; i < g->m; ++i) { row[i] = g->ops[i].b; lab[i] = g->ops[i].p; }
+  memcpy(col_ptr, g->ptr[1], sizeof(int64_t) * ((size_t)g->n + 1));
+  for (int64_t i = 0; i < g->m; ++i) { row[i] = key_nbr(g->key[1][i]); lab[i] = key_lab(g->key[1][i]); }
 }
 
 /* ---------------------------------------------- algebra (Section 2.1) */
 /* Eq. (4) (dir 0): y(i) = OR_j [A(i,j) == p]; Eq. (5) (dir 1): y(j) = OR_i [A(i,j) == p].
- * Written as the definition: one pass over every nonzero. */
+ * Written as the definition: one pass over every nonzero (i, j) of the row-wise storage. */
 void or_label_exists(const oracle_graph *g, int32_t p, int dir, uint8_t *y) {
   memset(y, 0, (size_t)g->n);
-  for (int64_t k = 0; k < g->m; ++k)
-    if (g->spo[k].p == p) y[dir ? g->spo[k].b : g->spo[k].a] = 1;
+  for (int64_t i = 0; i < g->n; ++i)
+    for (int64_t k = g->ptr[0][i]; k < g->ptr[0][i + 1]; ++k)
+      if (key_lab(g->key[0][k]) == p) y[dir ? key_nbr(g->key[0][k]) : i] = 1;
 }
 
 /* Eq. (14)-(16): the binding vector reachable from the selected rows F along label p.
@@ -159,12 +248,13 @@ void or_label_exists(const oracle_graph *g, int32_t p, int dir, uint8_t *y) {
  * dir 1: y(i) = OR_j F(j) and A(i,j) == p   (columns of A diag(F)) */
 void or_frontier_domain(const oracle_graph *g, const uint8_t *F, int32_t p, int dir, uint8_t *y) {
   memset(y, 0, (size_t)g->n);
-  for (int64_t k = 0; k < g->m; ++k) {
-    const otrip *t = &g->spo[k];
-    if (t->p != p) continue;
-    if (dir == 0 && F[t->a]) y[t->b] = 1;
-    if (dir == 1 && F[t->b]) y[t->a] = 1;
-  }
+  for (int64_t i = 0; i < g->n; ++i)
+    for (int64_t k = g->ptr[0][i]; k < g->ptr[0][i + 1]; ++k) {
+      if (key_lab(g->key[0][k]) != p) continue;
+      const int32_t j = key_nbr(g->key[0][k]);
+      if (dir == 0 && F[i]) y[j] = 1;
+      if (dir == 1 && F[j]) y[i] = 1;
+    }
 }
 
 /* ------------------------------------------------ query normalisation */
@@ -243,6 +333,7 @@ typedef struct {
   int32_t restrict_qv; const uint8_t *restrict_mask;
   int64_t count; int32_t *rows; int64_t rows_cap;
   int digest; uint64_t hsum, hxor;
+  const uint8_t *dom;             /* support-filter domains (NULL: none) */
   int64_t work; int aborted;
 } bt_t;
 
@@ -284,7 +375,7 @@ static int tick(bt_t *B) {
 /* Candidates of variable x: the label-p neighbours of the bound endpoint of its
  * first edge to a bound query vertex (a constant or an earlier variable); NULL
  * with *cnt = N when no such edge exists (every vertex is a candidate). */
-static const otrip *candidates(const bt_t *B, int32_t x, int64_t *cnt) {
+static const okey *candidates(const bt_t *B, int32_t x, int64_t *cnt) {
   const nq_t *q = B->q;
   for (int k = 0; k < q->n_edges; ++k) {
     int32_t s = q->e[k][0], o = q->e[k][2];
@@ -299,13 +390,14 @@ static void assign(bt_t *B, int i);
 
 /* Bind order[i] to candidates [lo, hi) of its candidate list in turn, check every
  * edge that becomes fully bound, and go on with the next variable. */
-static void assign_range(bt_t *B, int i, const otrip *nb, int64_t lo, int64_t hi) {
+static void assign_range(bt_t *B, int i, const okey *nb, int64_t lo, int64_t hi) {
   int32_t x = B->order[i];
   B->bound[x] = 1;
   for (int64_t t = lo; t < hi; ++t) {
     if (tick(B)) break;
-    int32_t c = nb ? nb[t].b : (int32_t)t;
+    int32_t c = nb ? key_nbr(nb[t]) : (int32_t)t;
     if (x == B->restrict_qv && !B->restrict_mask[c]) continue;
+    if (B->dom && !B->dom[(size_t)B->q->var_of[x] * (size_t)B->g->n + (size_t)c]) continue;
     B->val[x] = c;
     if (edges_hold_at(B, x)) assign(B, i + 1);
   }
@@ -316,7 +408,7 @@ static void assign(bt_t *B, int i) {
   if (B->aborted) return;
   if (i == B->q->nvar) { emit(B); return; }
   int64_t cnt;
-  const otrip *nb = candidates(B, B->order[i], &cnt);
+  const okey *nb = candidates(B, B->order[i], &cnt);
   assign_range(B, i, nb, 0, cnt);
 }
 
@@ -408,8 +500,53 @@ int or_eval(const oracle_graph *g, int32_t n_qv, const int32_t *qv_const, int32_
   return 0;
 }
 
+/* ------------------------------------------------ support filter */
+/* Arc consistency (Mackworth, "Consistency in networks of relations", 1977):
+ * every variable x gets a domain D(x), initially every vertex; for each edge
+ * (a, p, b) a value v stays in D(a) only if some triple (v, p, u) has u in D(b)
+ * (u = the constant when b is one; u = v for a self loop), and symmetrically
+ * for D(b); the edges are swept until no domain changes. A row is an
+ * assignment under which every edge is a triple, so each of its values has
+ * that support in every sweep: no row is lost, and none is added (the domains
+ * only restrict candidates that the backtracking still checks edge by edge).
+ * The filter saves search work only: on acyclic queries nearly every partial
+ * assignment then extends to a row. */
+/* dom[var * n + v]: 1 while v may still take variable rank var. */
+static uint8_t *support_filter(const oracle_graph *g, const nq_t *q) {
+  const int64_t n = g->n;
+  uint8_t *dom = (uint8_t *)malloc((size_t)(q->nvar ? q->nvar : 1) * (size_t)(n ? n : 1));
+  memset(dom, 1, (size_t)q->nvar * (size_t)n);
+  int changed = 1;
+  while (changed) {
+    changed = 0;
+    for (int k = 0; k < q->n_edges; ++k) {
+      const int32_t a = q->e[k][0], p = q->e[k][1], b = q->e[k][2];
+      for (int side = 0; side < 2; ++side) {
+        /* side 0 narrows D(a) along the out-rows (a, p, .), side 1 D(b) along the in-rows (., p, b) */
+        const int32_t mine = side ? b : a, other = side ? a : b;
+        if (q->cst[mine] >= 0 || (side && a == b)) continue;
+        uint8_t *d = dom + (size_t)q->var_of[mine] * n;
+        const uint8_t *dother = q->cst[other] >= 0 ? NULL : dom + (size_t)q->var_of[other] * n;
+        for (int64_t v = 0; v < n; ++v) {
+          if (!d[v]) continue;
+          int64_t cnt;
+          const okey *nb = adj(g, (int32_t)v, p, side, &cnt);
+          int ok = 0;
+          for (int64_t t = 0; t < cnt && !ok; ++t) {
+            const int32_t u = key_nbr(nb[t]);
+            if (a == b) ok = (u == v);
+            else ok = dother ? dother[u] : (u == q->cst[other]);
+          }
+          if (!ok) { d[v] = 0; changed = 1; }
+        }
+      }
+    }
+  }
+  return dom;
+}
+
 /* ------------------------------------------------ digest, on all host cores */
-typedef struct { bt_t B; const otrip *nb; int64_t ncand, chunk; } worker_t;
+typedef struct { bt_t B; const okey *nb; int64_t ncand, chunk; } worker_t;
 
 static void *worker_main(void *arg) {
   worker_t *w = (worker_t *)arg;
@@ -427,10 +564,11 @@ static void *worker_main(void *arg) {
 /* Count and row digest of a query without storing rows. The first variable's
  * candidates are split into chunks that nthreads threads take in turn, each
  * running the same backtracking below its chunk (nthreads <= 1: the calling
- * thread alone, the plain evaluation). work_cap bounds the candidate visits of
- * all threads together (0 = unlimited). Returns as or_eval. */
-int or_eval_digest(const oracle_graph *g, int32_t n_qv, const int32_t *qv_const, int32_t n_edges,
-                   const int32_t *edges, const int32_t *order, int32_t nthreads, int64_t work_cap,
+ * thread alone, the plain evaluation). filter != 0 first narrows every
+ * variable's candidates by the support filter above. work_cap bounds the
+ * candidate visits of all threads together (0 = unlimited). Returns as or_eval. */
+int or_eval_digest(oracle_graph *g, int32_t n_qv, const int32_t *qv_const, int32_t n_edges,
+                   const int32_t *edges, const int32_t *order, int32_t nthreads, int32_t filter, int64_t work_cap,
                    int64_t *count, uint64_t *hsum, uint64_t *hxor) {
   nq_t q; bt_t B; shared_t sh;
   int rc = setup(g, n_qv, qv_const, n_edges, edges, order, &q, &B);
@@ -439,14 +577,17 @@ int or_eval_digest(const oracle_graph *g, int32_t n_qv, const int32_t *qv_const,
   B.sh = &sh; B.digest = 1;
   *count = 0; *hsum = 0; *hxor = 0;
   if (!constant_edges_hold(g, &q)) return 0;
+  uint8_t *dom = (filter && q.nvar > 0) ? support_filter(g, &q) : NULL;
+  B.dom = dom;
   if (q.nvar == 0 || nthreads <= 1) {
     assign(&B, 0);
+    free(dom);
     if (B.aborted) return -4;
     *count = B.count; *hsum = B.hsum; *hxor = B.hxor;
     return 0;
   }
   int64_t ncand;
-  const otrip *nb = candidates(&B, B.order[0], &ncand);
+  const okey *nb = candidates(&B, B.order[0], &ncand);
   if (nthreads > 256) nthreads = 256;
   worker_t *w = (worker_t *)calloc((size_t)nthreads, sizeof(worker_t));
   pthread_t *th = (pthread_t *)calloc((size_t)nthreads, sizeof(pthread_t));
@@ -465,7 +606,7 @@ int or_eval_digest(const oracle_graph *g, int32_t n_qv, const int32_t *qv_const,
     aborted |= w[t].B.aborted;
     *count += w[t].B.count; *hsum += w[t].B.hsum; *hxor ^= w[t].B.hxor;
   }
-  free(w); free(th);
+  free(w); free(th); free(dom);
   if (aborted) { *count = 0; *hsum = 0; *hxor = 0; return -4; }
   return 0;
 }
@@ -522,15 +663,14 @@ static u128 *dp_message(dp_t *D, int32_t x, int pb) {
     /* first edge, oriented from x: dir 0 with x == u means (x, p, w): neighbours of c along out-edges */
     int d0 = b->dir[0];
     int out_from_x = x_is_u ? (d0 == 0) : (d0 == 1);
-    const otrip *tt = out_from_x ? g->spo : g->ops;
     const int32_t p0 = b->lab[0];
-    int64_t k = 0;   /* cursor into the sorted triples: c ascends, so (c, p0) ranges come in order */
     for (int64_t c = 0; c < g->n; ++c) {
-      while (k < g->m && (tt[k].a < c || (tt[k].a == c && tt[k].p < p0))) ++k;
       if (!msg[c]) continue;
       u128 s = 0;
-      for (int64_t t = k; t < g->m && tt[t].a == c && tt[t].p == p0; ++t) {
-        int32_t d = tt[t].b;
+      int64_t cnt;
+      const okey *nb = adj(g, (int32_t)c, p0, out_from_x ? 0 : 1, &cnt);
+      for (int64_t t = 0; t < cnt; ++t) {
+        int32_t d = key_nbr(nb[t]);
         if (!cm[d]) continue;
         int ok = x_is_u ? bundle_holds(g, b, (int32_t)c, d) : bundle_holds(g, b, d, (int32_t)c);
         if (ok) s = sat_add(s, cm[d]);

@@ -373,6 +373,27 @@ def test_duplicate_and_permuted_triples_form_a_set():
             assert cnt == len(bf) and (rows.shape[1] == 0 or np.array_equal(rows, bf)), q
 
 
+def test_streamed_build_equals_one_array():
+    # the set built from chunks (repeats across chunks, rows sorted on several threads) is the
+    # set built from one array: same distinct count, same row-wise and column-wise arrays
+    rng = np.random.default_rng(22)
+    n, P = 300, 5
+    base = np.stack([rng.integers(0, n, 4000), rng.integers(1, P + 1, 4000), rng.integers(0, n, 4000)], 1)
+    dup = np.concatenate([base, base[rng.integers(0, len(base), 3000)]]).astype(np.int32)
+    dup = dup[rng.permutation(len(dup))]
+    chunks = np.array_split(dup, 7)
+    one = oracle.Graph(dup, n, P)
+    for threads in (1, 3):
+        st = oracle.Graph.from_chunks(lambda: iter(chunks), n, P, threads=threads)
+        assert st.m == one.m == len(np.unique(base, axis=0))
+        for a, b in zip(st.csr() + st.csc(), one.csr() + one.csc()):
+            assert np.array_equal(a, b)
+    with pytest.raises(oracle.OracleError):
+        bad = dup.copy()
+        bad[5, 1] = P + 1
+        oracle.Graph.from_chunks(lambda: iter([bad]), n, P)
+
+
 # ------------------------------------------------------------------ row digest and the timing mode
 def test_splitmix64_output_function_reference_values():
     # the first outputs of splitmix64 started from state 0 (Steele, Lea and Flood 2014): its
@@ -396,6 +417,43 @@ def test_digest_matches_brute_force_rows(seed):
         expect = row_digest(bf, nv)
         assert G.digest(q) == expect, (case, q)
         assert G.digest(q, threads=3) == expect, (case, q)
+        assert G.digest(q, support_filter=True) == expect, (case, q)
+        assert G.digest(q, threads=3, support_filter=True) == expect, (case, q)
+
+
+@pytest.mark.parametrize("seed", range(2))
+def test_support_filter_keeps_every_row(seed):
+    # denser graphs, longer and cyclic patterns, parallel and antiparallel edges, self loops,
+    # constants: the arc-consistency domains never drop a value of a row (brute force)
+    rng = random.Random(900 + seed)
+    for case in range(30):
+        n, P = rng.randint(2, 7), rng.randint(1, 2)
+        trip = workload.uniform_graph(rng.randrange(1 << 30), n, P, rng.randint(n, n * n * P))
+        nv = rng.randint(2, 4)
+        q = random_query(rng, n, P, nv, rng.randint(0, 1), n_edges=rng.randint(nv, nv + 3),
+                         connected=rng.random() < 0.9)
+        G = oracle.Graph(trip, n, P)
+        expect = row_digest(brute_force(trip, n, P, q), nv)
+        assert G.digest(q, support_filter=True) == expect, (case, q)
+
+
+def test_support_filter_cuts_the_search():
+    # a branch that can never be completed (no vertex has an out-edge of label 2 and an
+    # in-edge of label 1 at once): without the filter the search walks every partial row of
+    # the first branch before finding that out; with it the domains are empty at once
+    n = 200
+    a = np.arange(n, dtype=np.int32)
+    trip = np.concatenate([np.stack([a, np.ones(n, np.int32), (a + 1) % n], 1),
+                           np.stack([a[: n // 2], np.full(n // 2, 2, np.int32), a[n // 2:]], 1),
+                           np.stack([np.zeros(n, np.int32), np.full(n, 3, np.int32), a], 1)]).astype(np.int32)
+    keep = ~((trip[:, 1] == 1) & (trip[:, 2] < n // 2))   # label-1 edges only into the upper half
+    trip = trip[keep]
+    G = oracle.Graph(trip, n, 3)
+    q = {"n_qv": 4, "qv_const": [-1] * 4, "edges": [(0, 3, 1), (0, 3, 2), (2, 1, 3), (3, 2, 1)]}
+    assert G.eval(q, rows=False)[0] == 0
+    with pytest.raises(oracle.OracleError):
+        G.digest(q, work_cap=2000)
+    assert G.digest(q, support_filter=True, work_cap=2000) == (0, 0, 0)
 
 
 def test_digest_detects_a_changed_row():
@@ -424,6 +482,7 @@ def test_digest_on_all_cores_equals_one_thread():
         assert one[0] == G.eval(q, rows=False)[0]
         for t in (2, 8):
             assert G.digest(q, threads=t) == one, (q, t)
+            assert G.digest(q, threads=t, support_filter=True) == one, (q, t)
 
 
 def test_digest_work_cap_aborts():
