@@ -52,6 +52,12 @@ def _load():
     lib.gsw_chunglu_graph.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64,
                                       ctypes.c_double, ctypes.c_double, ctypes.c_int32, i32p]
     lib.gsw_chunglu_graph.restype = ctypes.c_int
+    lib.gsw_cl_new.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                               ctypes.c_int32]
+    lib.gsw_cl_new.restype = ctypes.c_void_p
+    lib.gsw_cl_free.argtypes = [ctypes.c_void_p]
+    lib.gsw_cl_draws.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int64, i32p]
+    lib.gsw_cl_draws.restype = ctypes.c_int64
     lib.gsw_query_record_words.restype = ctypes.c_int
     lib.gsw_walk_queries.argtypes = [i32p, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64, ctypes.c_int32,
                                      ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, i32p]
@@ -85,6 +91,35 @@ def chunglu_graph(seed: int, n: int, n_labels: int, m: int, beta: float = 2.1, z
     if rc != 0:
         raise ValueError(f"gsw_chunglu_graph failed ({rc})")
     return out
+
+
+class ChungLuStream:
+    """The Chung-Lu draws of chunglu_graph as a stream (draw i is a pure function of
+    (seed, i)), for graphs defined as the distinct triples among the first `draws` draws."""
+
+    def __init__(self, seed: int, n: int, n_labels: int, beta: float, zipf_s: float, domain_mod: int):
+        self.n, self.n_labels = int(n), int(n_labels)
+        self._h = _load().gsw_cl_new(seed, n, n_labels, beta, zipf_s, domain_mod)
+        if not self._h:
+            raise MemoryError("Chung-Lu generator tables")
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            _load().gsw_cl_free(self._h)
+            self._h = None
+
+    def draws(self, first: int, count: int, out: np.ndarray = None) -> np.ndarray:
+        """Draws [first, first + count) as (k, 3) int32, draws whose object rejection failed
+        left out (k <= count); `out` (count * 3 int32) is used as the buffer when given."""
+        buf = out if out is not None else np.empty(count * 3, np.int32)
+        k = _load().gsw_cl_draws(self._h, first, count, buf)
+        return buf[:3 * k].reshape(k, 3)
+
+    def chunks(self, total: int, chunk: int = 100_000_000):
+        """Draws [0, total) in chunks (one buffer reused: consume each chunk before the next)."""
+        buf = np.empty(min(chunk, total) * 3, np.int32)
+        for a in range(0, total, chunk):
+            yield self.draws(a, min(chunk, total - a), buf)
 
 
 def _decode(rec: np.ndarray) -> dict:
@@ -123,6 +158,24 @@ def poisson_arrivals(seed: int, rate: float, duration: float) -> np.ndarray:
 # Workload recipes (sizes of the configurations the tests and the benchmark use).
 C0 = dict(seed=0, n=10_000, n_labels=16, m=100_000)
 C1 = dict(seed=1, n=10_000_000, n_labels=256, m=100_000_000, beta=2.1, zipf_s=1.1, domain_mod=5)
+
+
+# The 2B-triple graph: the distinct triples among the first `draws` Chung-Lu draws (the draws
+# are counted before duplicates are removed); its query walks run on the first `walk_draws`.
+C4 = dict(seed=4, n=200_000_000, n_labels=1024, draws=2_000_000_000, walk_draws=200_000_000, beta=2.0,
+          zipf_s=1.1, domain_mod=5)
+
+
+def c4_stream(scale: float = 1.0) -> ChungLuStream:
+    """The 2B-triple graph's draw stream; `scale` < 1 shrinks n and the draws together."""
+    return ChungLuStream(C4["seed"], max(16, int(C4["n"] * scale)), C4["n_labels"], C4["beta"], C4["zipf_s"],
+                         C4["domain_mod"])
+
+
+def c4_sizes(scale: float = 1.0):
+    """(n, draws, walk draws) of the 2B-triple graph at a scale."""
+    return (max(16, int(C4["n"] * scale)), max(16, int(C4["draws"] * scale)),
+            max(16, int(C4["walk_draws"] * scale)))
 
 
 def c0_graph() -> np.ndarray:

@@ -230,33 +230,69 @@ static void cl_draw(const void *c, uint64_t idx, int32_t out[3]) {
   out[0] = -1; out[1] = -1; out[2] = -1;
 }
 
-/* Chung-Lu: vertex weight w_i = (i+1)^(-1/(beta-1)); subject and object drawn
- * proportional to weight; vertex ids then shuffled (Fisher-Yates) so that the
- * heavy vertices are spread over the id range. Predicates Zipf(zipf_s) over
- * [1, P]. Each predicate's objects are restricted to the typed domain
- * {v : mix(seed, p, v) mod dom_mod == 0} by rejection (dom_mod = 5 keeps 20%). */
-int gsw_chunglu_graph(uint64_t seed, int64_t n, int32_t P, int64_t m, double beta, double zipf_s,
-                      int32_t dom_mod, int32_t *out) {
-  if (n <= 1 || n > 2147483647LL || P <= 0 || m < 0 || beta <= 1.0) return -2;
+/* Tables of a Chung-Lu generator: vertex weight w_i = (i+1)^(-1/(beta-1)),
+ * subject and object drawn proportional to weight, vertex ids then shuffled
+ * (Fisher-Yates) so that the heavy vertices are spread over the id range.
+ * Predicates Zipf(zipf_s) over [1, P]. Each predicate's objects are restricted
+ * to the typed domain {v : mix(seed, p, v) mod dom_mod == 0} by rejection
+ * (dom_mod = 5 keeps 20%). */
+static int cl_init(cl_ctx *c, uint64_t seed, int64_t n, int32_t P, double beta, double zipf_s, int32_t dom_mod) {
+  memset(c, 0, sizeof *c);
   double *w = (double *)malloc(sizeof(double) * (size_t)(n > P ? n : P));
   int32_t *perm = (int32_t *)malloc(sizeof(int32_t) * n);
-  if (!w || !perm) return -1;
-  cl_ctx c; memset(&c, 0, sizeof c);
-  c.seed = seed; c.n = n; c.P = P; c.dom_mod = dom_mod;
+  if (!w || !perm) { free(w); free(perm); return -1; }
+  c->seed = seed; c->n = n; c->P = P; c->dom_mod = dom_mod;
+#pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) w[i] = pow((double)(i + 1), -1.0 / (beta - 1.0));
-  if (alias_build(&c.vw, w, n)) return -1;
+  if (alias_build(&c->vw, w, n)) { free(w); free(perm); return -1; }
   for (int32_t k = 0; k < P; ++k) w[k] = pow((double)(k + 1), -zipf_s);
-  if (alias_build(&c.lab, w, P)) return -1;
+  if (alias_build(&c->lab, w, P)) { free(w); free(perm); return -1; }
   for (int64_t i = 0; i < n; ++i) perm[i] = (int32_t)i;
   for (int64_t i = n - 1; i > 0; --i) {
     uint32_t r[4]; ph_block(seed, TAG_PERM, (uint64_t)i, 0, r);
     int64_t j = (int64_t)((((uint64_t)r[0] << 32) | r[1]) % (uint64_t)(i + 1));
     int32_t t = perm[i]; perm[i] = perm[j]; perm[j] = t;
   }
-  c.perm = perm;
+  c->perm = perm;
+  free(w);
+  return 0;
+}
+static void cl_free(cl_ctx *c) { alias_free(&c->vw); alias_free(&c->lab); free((void *)c->perm); }
+
+/* m distinct Chung-Lu triples: the first distinct ones in draw order. */
+int gsw_chunglu_graph(uint64_t seed, int64_t n, int32_t P, int64_t m, double beta, double zipf_s,
+                      int32_t dom_mod, int32_t *out) {
+  if (n <= 1 || n > 2147483647LL || P <= 0 || m < 0 || beta <= 1.0) return -2;
+  cl_ctx c;
+  if (cl_init(&c, seed, n, P, beta, zipf_s, dom_mod)) return -1;
   int rc = draw_distinct(&c, cl_draw, m, out);
-  alias_free(&c.vw); alias_free(&c.lab); free(w); free(perm);
+  cl_free(&c);
   return rc;
+}
+
+/* The same draws as a stream, for graphs defined as the distinct triples among
+ * a fixed number of draws (too many to deduplicate on the host): a generator
+ * holds the tables, gsw_cl_draws writes draws [idx0, idx0 + count) in draw
+ * order, leaving out the (rare) draws whose object rejection failed, and
+ * returns how many it wrote. */
+void *gsw_cl_new(uint64_t seed, int64_t n, int32_t P, double beta, double zipf_s, int32_t dom_mod) {
+  if (n <= 1 || n > 2147483647LL || P <= 0 || beta <= 1.0) return NULL;
+  cl_ctx *c = (cl_ctx *)malloc(sizeof(cl_ctx));
+  if (!c || cl_init(c, seed, n, P, beta, zipf_s, dom_mod)) { free(c); return NULL; }
+  return c;
+}
+void gsw_cl_free(void *h) { if (h) { cl_free((cl_ctx *)h); free(h); } }
+int64_t gsw_cl_draws(const void *h, uint64_t idx0, int64_t count, int32_t *out) {
+  const cl_ctx *c = (const cl_ctx *)h;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < count; ++i) cl_draw(c, idx0 + (uint64_t)i, out + 3 * i);
+  int64_t k = 0;
+  for (int64_t i = 0; i < count; ++i)
+    if (out[3 * i] >= 0) {
+      if (k != i) memcpy(out + 3 * k, out + 3 * i, 12);
+      ++k;
+    }
+  return k;
 }
 
 /* --------------------------------------------------------- query graphs */
