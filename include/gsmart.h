@@ -124,11 +124,18 @@ typedef struct {
   int64_t t_pull;             /* entries read by pull domain products */
   int64_t t_probe;            /* entries touched by binary-search membership checks */
   int64_t t_total;            /* sum of the above */
-  int64_t bytes_alg;          /* algorithmic HBM bytes of the evaluation */
+  int64_t bytes_alg;          /* algorithmic bytes: 4 * t_total (int32 ids) + label width * t_label
+                                 + 2 * offset width * seg_lookups + 8 * nodes_written + 8 * nodes_read
+                                 + 8 * bitmap_words */
   int32_t domain_push;        /* domains evaluated by push */
   int32_t domain_pull;        /* domains evaluated by pull */
   double gpu_ms;              /* device time of the evaluation (events around its launches) */
   double latency_ms;          /* served form: submission to rows on the host; else 0 */
+  int64_t t_label;            /* label entries read while locating label sub-segments (not in t_total) */
+  int64_t seg_lookups;        /* segment lookups: row or column offset pairs read */
+  int64_t bitmap_words;       /* 64-bit bitmap words read or written (filters, lists, seeds, domains) */
+  int64_t nodes_written;      /* binding-tree nodes written (a count-only last level is not) */
+  int64_t nodes_read;         /* binding-tree nodes read by a later step */
 } gs_query_stats;
 
 /* ---- engine ---------------------------------------------------------------- */
@@ -241,6 +248,17 @@ gs_status gs_result_width(const gs_result *result, int32_t *n_vars);
 gs_status gs_result_rows(gs_result *result, int64_t first, int64_t n, void *dst, int mem_kind,
                          int64_t *n_written);
 
+/* Order-independent digest of the result rows, computed on the device without
+ * copying rows out: each row (v_0..v_{k-1}, the variables in ascending
+ * query-vertex order) hashes to h_k, where h_0 = k and
+ * h_{i+1} = mix64(h_i + 0x9E3779B97F4A7C15 + (uint32_t)v_i), mix64 being the
+ * output function of the splitmix64 generator (Steele, Lea and Flood, OOPSLA
+ * 2014); *hash_sum = sum of the row hashes mod 2^64, *hash_xor = their XOR,
+ * *count = rows. Equal results have equal digests; a differing digest proves
+ * the row multisets differ (the converse holds only with high probability).
+ * Errors: GS_EUNSUPPORTED for count-only results. */
+gs_status gs_result_digest(gs_result *result, int64_t *count, uint64_t *hash_sum, uint64_t *hash_xor);
+
 /* Counters of the evaluation (size = sizeof(gs_query_stats)). */
 gs_status gs_result_stats(const gs_result *result, gs_query_stats *stats);
 
@@ -251,15 +269,18 @@ gs_status gs_result_level(gs_result *result, int32_t level, int32_t *par, int32_
 
 /* Kernel timing, available when gs_options.profile_kernels was set: per
  * kernel of the evaluation, launches, device milliseconds (HIP events on the
- * engine's stream around each launch) and algorithmic bytes moved (ids and
- * bitmap words read, tree columns written, as counted by the kernels). Fills
- * up to cap entries, *n = kernels with at least one launch; reset != 0 clears
- * the counters after reading. */
+ * engine's stream around each launch) and bytes moved by two models: the
+ * method's own (expansion write pass: a candidate id read per entry and a tree
+ * node of parent and vertex written per child) and the implementation's (ids,
+ * carried columns, staged node records, validity bits, offsets, as the kernels
+ * touch them). Fills up to cap entries, *n = kernels with at least one launch;
+ * reset != 0 clears the counters after reading. */
 typedef struct {
   const char *name;           /* static string */
   int64_t launches;
   double ms;
-  double bytes_alg;           /* 0 where no byte model is kept */
+  double bytes_alg;           /* the method's bytes; 0 where the kernel has no such model */
+  double bytes_impl;          /* the implementation's bytes; 0 where no model is kept */
 } gs_kernel_stat;
 gs_status gs_kernel_stats(gs_engine *engine, gs_kernel_stat *out, int32_t cap, int32_t *n, int reset);
 

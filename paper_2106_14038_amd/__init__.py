@@ -63,7 +63,9 @@ class gs_query_stats(ctypes.Structure):
                 ("level_nodes", ctypes.c_int64 * 64), ("t_expand", ctypes.c_int64), ("t_seed", ctypes.c_int64),
                 ("t_push", ctypes.c_int64), ("t_pull", ctypes.c_int64), ("t_probe", ctypes.c_int64),
                 ("t_total", ctypes.c_int64), ("bytes_alg", ctypes.c_int64), ("domain_push", ctypes.c_int32),
-                ("domain_pull", ctypes.c_int32), ("gpu_ms", ctypes.c_double), ("latency_ms", ctypes.c_double)]
+                ("domain_pull", ctypes.c_int32), ("gpu_ms", ctypes.c_double), ("latency_ms", ctypes.c_double),
+                ("t_label", ctypes.c_int64), ("seg_lookups", ctypes.c_int64), ("bitmap_words", ctypes.c_int64),
+                ("nodes_written", ctypes.c_int64), ("nodes_read", ctypes.c_int64)]
 
 
 class gs_plan_info(ctypes.Structure):
@@ -74,7 +76,7 @@ class gs_plan_info(ctypes.Structure):
 
 class gs_kernel_stat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char_p), ("launches", ctypes.c_int64), ("ms", ctypes.c_double),
-                ("bytes_alg", ctypes.c_double)]
+                ("bytes_alg", ctypes.c_double), ("bytes_impl", ctypes.c_double)]
 
 
 class gs_tune_result(ctypes.Structure):
@@ -111,6 +113,7 @@ SIGNATURES = {
     "gs_result_width": ([_vp, _P(_i32)], ctypes.c_int),
     "gs_result_rows": ([_vp, _i64, _i64, _vp, ctypes.c_int, _P(_i64)], ctypes.c_int),
     "gs_result_stats": ([_vp, _P(gs_query_stats)], ctypes.c_int),
+    "gs_result_digest": ([_vp, _P(_i64), _P(_u64), _P(_u64)], ctypes.c_int),
     "gs_result_level": ([_vp, _i32, _vp, _vp, _P(_i64)], ctypes.c_int),
     "gs_result_free": ([_vp], None),
     "gs_server_start": ([_vp, _P(gs_server_options), _P(_vp)], ctypes.c_int),
@@ -303,6 +306,13 @@ def gs_result_stats(result) -> gs_query_stats:
     return s
 
 
+def gs_result_digest(result):
+    """(count, sum of row hashes mod 2^64, XOR of row hashes), computed on the device."""
+    c, hs, hx = ctypes.c_int64(), ctypes.c_uint64(), ctypes.c_uint64()
+    _check(lib().gs_result_digest(result, ctypes.byref(c), ctypes.byref(hs), ctypes.byref(hx)))
+    return c.value, hs.value, hx.value
+
+
 def gs_result_level(result, level: int):
     n = ctypes.c_int64()
     _check(lib().gs_result_level(result, level, None, None, ctypes.byref(n)))
@@ -316,7 +326,8 @@ def gs_kernel_stats(engine, reset: bool = False) -> dict:
     arr = (gs_kernel_stat * 32)()
     n = ctypes.c_int32()
     _check(lib().gs_kernel_stats(engine, arr, 32, ctypes.byref(n), int(reset)))
-    return {arr[i].name.decode(): {"launches": arr[i].launches, "ms": arr[i].ms, "bytes_alg": arr[i].bytes_alg}
+    return {arr[i].name.decode(): {"launches": arr[i].launches, "ms": arr[i].ms, "bytes_alg": arr[i].bytes_alg,
+                                   "bytes_impl": arr[i].bytes_impl}
             for i in range(min(n.value, 32))}
 
 

@@ -1,6 +1,8 @@
 // The C ABI (include/gsmart.h) over the host engine.
 #include <algorithm>
 #include <cstring>
+#include <mutex>
+#include <string>
 #include <new>
 #include <vector>
 
@@ -393,6 +395,15 @@ gs_status gs_result_rows(gs_result *result, int64_t first, int64_t n, void *dst,
   return (gs_status)result_rows(R, first, n, dst, mem_kind, n_written);
 }
 
+gs_status gs_result_digest(gs_result *result, int64_t *count, uint64_t *hash_sum, uint64_t *hash_xor) {
+  if (!result || !count || !hash_sum || !hash_xor) { set_error("null argument"); return GS_EINVAL; }
+  Result &R = *unwrap(result);
+  *count = R.count;
+  if (R.host_owned || !R.eng) return (gs_status)result_digest(R, hash_sum, hash_xor);
+  std::lock_guard<std::mutex> lk(R.eng->mu);
+  return (gs_status)result_digest(R, hash_sum, hash_xor);
+}
+
 gs_status gs_result_stats(const gs_result *result, gs_query_stats *stats) {
   if (!result || !stats) { set_error("null argument"); return GS_EINVAL; }
   *stats = unwrap(result)->stats;
@@ -454,7 +465,8 @@ gs_status gs_kernel_stats(gs_engine *engine, gs_kernel_stat *out, int32_t cap, i
       out[k].name = kSlotNames[i];
       out[k].launches = E.kstat[i].launches;
       out[k].ms = E.kstat[i].ms;
-      out[k].bytes_alg = E.kstat[i].bytes;
+      out[k].bytes_alg = E.kstat[i].alg;
+      out[k].bytes_impl = E.kstat[i].bytes;
     }
     ++k;
   }

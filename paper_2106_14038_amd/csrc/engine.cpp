@@ -335,7 +335,8 @@ void build_iteration(const Tables &T, const std::vector<const QInfo *> &qs, cons
 }
 
 // Accumulate per-kernel times and algorithmic bytes of one iteration (profiling).
-void account_iteration(Engine &E, const hipEvent_t *ev, const IterScalars &I, const IterLists &L, double write_bytes) {
+void account_iteration(Engine &E, const hipEvent_t *ev, const IterScalars &I, const IterLists &L, double write_bytes,
+                       double children) {
   bool ran[KS_N];
   for (int k = 0; k < KS_N; ++k) ran[k] = true;
   ran[KS_CLEAR] = !L.clears.empty();
@@ -347,7 +348,7 @@ void account_iteration(Engine &E, const hipEvent_t *ev, const IterScalars &I, co
     if (!ran[k]) continue;
     float kms = 0;
     if (hipEventElapsedTime(&kms, ev[2 * k], ev[2 * k + 1]) != hipSuccess) continue;
-    double b = 0;
+    double b = 0, alg = 0;
     const double W = (double)I.w_total, nz = (double)I.nz_total;
     switch (k) {
       case KS_EXPAND_COUNT: {  // tested levels only: ids, staged node records, filter words, parent bindings,
@@ -355,8 +356,12 @@ void account_iteration(Engine &E, const hipEvent_t *ev, const IterScalars &I, co
         b = 4 * Wt + 20 * nz * (W > 0 ? Wt / W : 0) + 8.0 * I.ftests + 4.0 * I.ctests + 4.0 * I.probes + Wt / 8;
         break;
       }
-      case KS_EXPAND_WRITE:   // valid bits, staged node records, candidate ids + copies read + columns written
-        b = W / 8 + 20 * nz + write_bytes; break;
+      case KS_EXPAND_WRITE:   // valid bits, staged node records, candidate ids + copies read + columns written;
+                              // the method's own bytes: a candidate id read per entry, a tree node (parent,
+                              // vertex) written per child
+        b = W / 8 + 20 * nz + write_bytes;
+        alg = 4 * W + 8 * children;
+        break;
       case KS_LOOKUP:         // parent binding, offset pair, segment written (the lookups of cycle-closing
                               // segments at cyclic levels are not counted)
         b = 36.0 * I.nodes_total; break;
@@ -367,6 +372,7 @@ void account_iteration(Engine &E, const hipEvent_t *ev, const IterScalars &I, co
     E.kstat[k].launches += 1;
     E.kstat[k].ms += kms;
     E.kstat[k].bytes += b;
+    E.kstat[k].alg += alg;
   }
 }
 
@@ -594,16 +600,19 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
     std::vector<IterScalars> iv(std::max(maxk, 1));
     HIPCHK(hipMemcpy(iv.data(), dp(o_it), sizeof(IterScalars) * iv.size(), hipMemcpyDeviceToHost));
     for (int t = 0; t < maxk; ++t) {
-      double wbytes = 0;   // rows written this iteration, weighted by the columns each query writes
+      double wbytes = 0, children = 0;   // rows written this iteration, weighted by the columns each query writes
       for (int i = 0; i < nq; ++i) {
         if (Q[i].plan.n_vars <= t) continue;
         const DStep &d = T.steps[Q[i].step0 + t];
         const int64_t c = std::max<int64_t>(lvl_n[(size_t)i * kMaxLevels + t], 0);
         // columns written + copies read + candidate read; CSR levels write no parent column
         const int cols = d.ncols_out - (lvl_c[(size_t)i * kMaxLevels + t] ? 1 : 0);
-        if (d.ncols_out > 0) wbytes += (double)c * (4.0 * cols + 4.0 * d.ncopy + 4.0);
+        if (d.ncols_out > 0) {
+          wbytes += (double)c * (4.0 * cols + 4.0 * d.ncopy + 4.0);
+          children += (double)c;
+        }
       }
-      account_iteration(E, &E.events[(size_t)2 * KS_N * t], iv[t], its[t], wbytes);
+      account_iteration(E, &E.events[(size_t)2 * KS_N * t], iv[t], its[t], wbytes, children);
     }
   }
   if (rflags[RF_WRITE]) {
@@ -673,20 +682,32 @@ void fill_result(Result &R, const QInfo &qi, bool count_only, int32_t *const *lv
   st.t_total = st.t_expand + st.t_seed + st.t_push + st.t_pull + st.t_probe;
   st.domain_push = (int32_t)c[QS_DOMPUSH];
   st.domain_pull = (int32_t)c[QS_DOMPULL];
-  int64_t nodes_written = 0, nodes_read = 0;
+  // Algorithmic bytes, the method's own traffic: 4 B per traversed entry (int32 id), the label
+  // entries read to locate label sub-segments, an offset pair per segment lookup, 8 B per tree
+  // node written (parent, vertex) and per node read by a later step, 8 B per bitmap word.
+  const int64_t W = R.eng ? R.eng->g.words : 0;
+  int64_t nodes_written = 0, nodes_read = 0, bm_words = c[QS_BMWORDS];
   for (int j = 0; j < R.k; ++j) {
-    int64_t cols = (count_only && j == R.k - 1) ? 0 : 2 + (int64_t)P.steps[j].carried.size();
-    if (cols && R.lvl_cptr[j]) {   // child offsets per parent instead of a parent column
-      cols -= 1;
-      nodes_written += j ? R.lvl_n[j - 1] + 1 : 2;
-    }
-    nodes_written += R.lvl_n[j] * cols;
+    const PlanStep &ps = P.steps[j];
+    const int64_t prev = j ? R.lvl_n[j - 1] : 1;
+    if (!(count_only && j == R.k - 1)) nodes_written += R.lvl_n[j];
     if (j + 1 < R.k) nodes_read += R.lvl_n[j];
+    if (ps.kind == STEP_LIST && prev > 0) bm_words += W * (int64_t)ps.filters.size();   // the AND of the filters
   }
-  // id reads (4 B) for every traversed entry, labels and ids touched by probes (6 B), offset pairs per
-  // segment lookup (16 B), tree columns written (4 B each) and parent bindings read (4 B)
-  st.bytes_alg = 4 * (st.t_expand + st.t_seed + st.t_push + st.t_pull) + 6 * st.t_probe + 16 * nodes_read +
-                 4 * nodes_written + 4 * nodes_read;
+  for (const DomainSpec &d : P.domains) {   // frontier and result bitmaps cleared, one frontier bit set per node
+    const int64_t prev = d.step > 0 && d.step <= R.k ? R.lvl_n[d.step - 1] : (d.step == 0 ? 1 : 0);
+    bm_words += 2 * W + prev;
+    nodes_read += prev;
+  }
+  bm_words += W * (int64_t)P.seeds.size();   // seed bitmaps cleared
+  const int64_t lab_bytes = R.eng ? R.eng->lab_bytes : 2, off_bytes = R.eng ? R.eng->off_bytes : 8;
+  st.t_label = c[QS_LABEL];
+  st.seg_lookups = c[QS_LOOKUP];
+  st.bitmap_words = bm_words;
+  st.nodes_written = nodes_written;
+  st.nodes_read = nodes_read;
+  st.bytes_alg = 4 * st.t_total + lab_bytes * st.t_label + 2 * off_bytes * st.seg_lookups + 8 * nodes_written +
+                 8 * nodes_read + 8 * bm_words;
   st.gpu_ms = ms;
 }
 
@@ -728,6 +749,51 @@ int result_rows(Result &R, int64_t first, int64_t n, void *dst, int mem_kind, in
     E.dfree(tmp);
   }
   if (written) *written = n;
+  return GS_OK;
+}
+
+static uint64_t host_row_hash(const int32_t *row, int k) {
+  uint64_t h = (uint64_t)k;
+  for (int i = 0; i < k; ++i) {
+    uint64_t z = h + 0x9E3779B97F4A7C15ull + (uint64_t)(uint32_t)row[i];
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    h = z ^ (z >> 31);
+  }
+  return h;
+}
+
+int result_digest(Result &R, uint64_t *hsum, uint64_t *hxor) {
+  *hsum = 0;
+  *hxor = 0;
+  if (R.count_only && !R.zero_vars) { set_error("digest of a count-only result"); return GS_EUNSUPPORTED; }
+  if (R.count == 0) return GS_OK;
+  if (R.n_vars == 0) {   // rows of width 0 all hash to 0
+    return GS_OK;
+  }
+  if (R.host_owned) {
+    for (int64_t r = 0; r < R.count; ++r) {
+      const uint64_t h = host_row_hash(R.host_rows.data() + (size_t)r * R.k, R.k);
+      *hsum += h;
+      *hxor ^= h;
+    }
+    return GS_OK;
+  }
+  Engine &E = *R.eng;
+  if (E.serving) { set_error("a server is running on this engine"); return GS_ESTATE; }
+  HIPCHK(hipSetDevice(E.device));
+  hipStream_t s = E.stream;
+  uint64_t *d = (uint64_t *)E.dmalloc(2 * sizeof(uint64_t));
+  if (!d) { set_error("out of device memory for the digest"); return GS_ENOMEM; }
+  uint64_t h[2] = {0, 0};
+  hipError_t e = hipMemcpyAsync(d, h, sizeof h, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = launch_row_digest(R.d_lvl_ptr, R.d_lvl_cptr, R.d_lvl_n, R.k, R.d_var_rank, R.count, d, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(h, d, sizeof h, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  E.dfree(d);
+  if (e != hipSuccess) { set_error(hipGetErrorString(e)); return GS_EDEVICE; }
+  *hsum = h[0];
+  *hxor = h[1];
   return GS_OK;
 }
 

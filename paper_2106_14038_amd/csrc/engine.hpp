@@ -59,6 +59,8 @@ struct Engine {
   uint64_t *d_bm[2] = {nullptr, nullptr};
   LabelStats stats;
   uint64_t graph_bytes = 0;
+  int32_t lab_bytes = 2;           // stored widths of a label and of a row offset
+  int32_t off_bytes = 8;
 
   // arenas: binding trees (+ per-run tables) and per-iteration scratch
   char *tree_base = nullptr;
@@ -76,7 +78,7 @@ struct Engine {
   size_t work_bytes = 0;
 
   // optional kernel timing (gs_options.profile_kernels)
-  struct KStat { int64_t launches = 0; double ms = 0, bytes = 0; };
+  struct KStat { int64_t launches = 0; double ms = 0, bytes = 0, alg = 0; };
   KStat kstat[KS_N];
   std::vector<hipEvent_t> events;  // pool, 2 * KS_N per iteration
 
@@ -128,7 +130,8 @@ void compile_query(const Engine &E, QInfo &qi, bool count_only, int slot, Tables
                    const std::function<uint64_t *()> &next_bitmap);
 void build_iteration(const Tables &T, const std::vector<const QInfo *> &qs, const std::vector<int> &level,
                      IterLists &L);
-void account_iteration(Engine &E, const hipEvent_t *ev, const IterScalars &I, const IterLists &L, double write_bytes);
+void account_iteration(Engine &E, const hipEvent_t *ev, const IterScalars &I, const IterLists &L, double write_bytes,
+                       double children);
 void fill_result(Result &R, const QInfo &qi, bool count_only, int32_t *const *lvl_p, int32_t *const *lvl_c,
                  const int64_t *lvl_n,
                  const int64_t *qstats, int64_t zero_res, double ms);
@@ -140,6 +143,7 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
 int load_triples(Engine &E, int64_t n, int32_t P, const gs_triple *t, int64_t m, int mem_kind);
 int result_rows(Result &R, int64_t first, int64_t n, void *dst, int mem_kind, int64_t *written);
 int result_prune(Result &R);
+int result_digest(Result &R, uint64_t *hsum, uint64_t *hxor);
 void result_free(Result *R);
 
 }  // namespace gs

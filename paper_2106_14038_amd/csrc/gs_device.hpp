@@ -142,7 +142,10 @@ struct DArena {
   int32_t overflow, pad;
 };
 
-// Per-query counters (int64 each).
-enum QStat { QS_EXPAND = 0, QS_SEED, QS_PUSH, QS_PULL, QS_PROBE, QS_DOMPUSH, QS_DOMPULL, QS_OVERFLOW, QS_N };
+// Per-query counters (int64 each). QS_LABEL: label entries read while locating
+// label sub-segments; QS_LOOKUP: segment lookups (offset pairs read); QS_BMWORDS:
+// bitmap words read or written by the candidate filters, seeds and domains.
+enum QStat { QS_EXPAND = 0, QS_SEED, QS_PUSH, QS_PULL, QS_PROBE, QS_DOMPUSH, QS_DOMPULL, QS_OVERFLOW, QS_LABEL,
+             QS_LOOKUP, QS_BMWORDS, QS_N };
 
 }  // namespace gs

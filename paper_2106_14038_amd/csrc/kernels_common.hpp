@@ -120,6 +120,20 @@ __device__ __forceinline__ int64_t block_sum_i64(int64_t v, int64_t *lds) {
   return t;
 }
 
+// Two sums over a kBlock workgroup with one pair of barriers. lds holds 2 * kWaves entries.
+__device__ __forceinline__ void block_sum2_i64(int64_t &a, int64_t &b, int64_t *lds) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  a = wave_sum_i64(a);
+  b = wave_sum_i64(b);
+  if (lane == 0) { lds[w] = a; lds[kWaves + w] = b; }
+  __syncthreads();
+  a = 0;
+  b = 0;
+#pragma unroll
+  for (int i = 0; i < kWaves; ++i) { a += lds[i]; b += lds[kWaves + i]; }
+  __syncthreads();
+}
+
 // Exclusive scan over an index space [0, L) by one workgroup (size a multiple
 // of 64, at most 64 waves). get(i) returns the value, set(i, prefix) stores the
 // exclusive prefix. Each thread takes a contiguous chunk; the chunk sums are

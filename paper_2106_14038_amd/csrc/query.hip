@@ -199,6 +199,7 @@ __global__ __launch_bounds__(kBlock) void k_seed(const IterArgs A) {
     int64_t lo, hi;
     int probes = 0;
     seg_find(A.g, sd.dir, sd.c, sd.label, lo, hi, probes);
+    int64_t words_set = 0;
     const int32_t *idx = sd.dir ? A.g.idx[1] : A.g.idx[0];
     const int64_t per = ceil_div(hi - lo, parts);
     const int64_t a = lo + part * per, e = min(hi, a + per);
@@ -214,10 +215,17 @@ __global__ __launch_bounds__(kBlock) void k_seed(const IterArgs A) {
         if (lane + off < 64 && ow == w) bits |= ob;
       }
       const int64_t pw = __shfl_up(w, 1, 64);
-      if (ok && (lane == 0 || pw != w)) atomicOr((unsigned long long *)&sd.bm[w], (unsigned long long)bits);
+      const bool first = ok && (lane == 0 || pw != w);
+      if (first) atomicOr((unsigned long long *)&sd.bm[w], (unsigned long long)bits);
+      words_set += __popcll(__ballot(first));
     }
-    if (part == 0 && threadIdx.x == 0)
-      atomicAdd((unsigned long long *)&A.qstats[(int64_t)sd.q * QS_N + QS_SEED], (unsigned long long)(hi - lo));
+    int64_t *qs = A.qstats + (int64_t)sd.q * QS_N;
+    if ((threadIdx.x & 63) == 0 && words_set) atomicAdd((unsigned long long *)&qs[QS_BMWORDS], (unsigned long long)words_set);
+    if (part == 0 && threadIdx.x == 0) {
+      atomicAdd((unsigned long long *)&qs[QS_SEED], (unsigned long long)(hi - lo));
+      atomicAdd((unsigned long long *)&qs[QS_LABEL], (unsigned long long)probes);
+      atomicAdd((unsigned long long *)&qs[QS_LOOKUP], 1ull);
+    }
   }
 }
 
@@ -379,7 +387,7 @@ __device__ __forceinline__ void set_bit_once(uint64_t *bm, int32_t c) {
 
 // Push: for every b in F, OR the label-p segment of b into D (sparse-frontier product).
 __global__ __launch_bounds__(kBlock) void k_dom_push(const IterArgs A) {
-  __shared__ int64_t lds[kWaves];
+  __shared__ int64_t lds[2 * kWaves];
   if (A.it->abort || A.D == 0) return;
   const int64_t W = A.g.words, tpd = ceil_div(W, kTileWords);
   const int64_t NT = (int64_t)A.D * tpd;
@@ -389,7 +397,7 @@ __global__ __launch_bounds__(kBlock) void k_dom_push(const IterArgs A) {
     const DDomain dm = A.doms[d];
     const int64_t w = (t % tpd) * kTileWords + threadIdx.x;
     const int lane = threadIdx.x & 63;
-    int64_t work = 0;
+    int64_t work = 0, lk = 0, lp = 0, bw = w < W ? 1 : 0;   // bw: frontier words read
     uint64_t x = w < W ? dm.F[w] : 0;
     if (w == W - 1 && (A.g.n & 63)) x &= (1ull << (A.g.n & 63)) - 1ull;   // no vertex ids >= n
     const int32_t *idx = A.g.idx[dm.dir];
@@ -404,6 +412,8 @@ __global__ __launch_bounds__(kBlock) void k_dom_push(const IterArgs A) {
         int probes = 0;
         seg_find(A.g, dm.dir, (int32_t)(w * 64 + b), dm.label, lo, hi, probes);
         work += hi - lo;
+        ++lk;
+        lp += probes;
         coop = hi - lo > kCoopSeg;
         if (!coop)
           for (int64_t k = lo; k < hi; ++k) set_bit_once(dm.D, idx[k]);
@@ -414,17 +424,23 @@ __global__ __launch_bounds__(kBlock) void k_dom_push(const IterArgs A) {
         for (int64_t k = L + lane; k < H; k += 64) set_bit_once(dm.D, idx[k]);
       }
     }
-    work = block_sum_i64(work, lds);
+    bw += work;   // one result-bitmap word read per entry
+    block_sum2_i64(work, bw, lds);
+    block_sum2_i64(lk, lp, lds);
     if (threadIdx.x == 0) {
-      if (work) atomicAdd((unsigned long long *)&A.qstats[(int64_t)dm.q * QS_N + QS_PUSH], (unsigned long long)work);
-      if (t % tpd == 0) atomicAdd((unsigned long long *)&A.qstats[(int64_t)dm.q * QS_N + QS_DOMPUSH], 1ull);
+      int64_t *qs = A.qstats + (int64_t)dm.q * QS_N;
+      if (work) atomicAdd((unsigned long long *)&qs[QS_PUSH], (unsigned long long)work);
+      if (lk) atomicAdd((unsigned long long *)&qs[QS_LOOKUP], (unsigned long long)lk);
+      if (lp) atomicAdd((unsigned long long *)&qs[QS_LABEL], (unsigned long long)lp);
+      if (bw) atomicAdd((unsigned long long *)&qs[QS_BMWORDS], (unsigned long long)bw);
+      if (t % tpd == 0) atomicAdd((unsigned long long *)&qs[QS_DOMPUSH], 1ull);
     }
   }
 }
 
 // Pull: for every candidate c of the mask, D(c) = OR over b in seg(c, p, opposite) of F(b).
 __global__ __launch_bounds__(kBlock) void k_dom_pull(const IterArgs A) {
-  __shared__ int64_t lds[kWaves];
+  __shared__ int64_t lds[2 * kWaves];
   if (A.it->abort || A.D == 0) return;
   const int64_t W = A.g.words, tpd = ceil_div(W, kTileWords);
   const int64_t NT = (int64_t)A.D * tpd;
@@ -433,8 +449,9 @@ __global__ __launch_bounds__(kBlock) void k_dom_pull(const IterArgs A) {
     if (dom_mode(A, d) != 2) continue;
     const DDomain dm = A.doms[d];
     const int64_t w = (t % tpd) * kTileWords + threadIdx.x;
-    int64_t work = 0;
+    int64_t work = 0, lk = 0, lp = 0, bw = 0;
     if (w < W) {
+      bw = dm.nfilt + 1;   // mask words read, result word written
       uint64_t x = ~0ull;
       for (int f = 0; f < dm.nfilt; ++f) x &= A.filt[dm.filt0 + f][w];
       if (w == W - 1 && (A.g.n & 63)) x &= (1ull << (A.g.n & 63)) - 1ull;
@@ -447,6 +464,8 @@ __global__ __launch_bounds__(kBlock) void k_dom_pull(const IterArgs A) {
         int64_t lo, hi;
         int probes = 0;
         seg_find(A.g, od, (int32_t)(w * 64 + b), dm.label, lo, hi, probes);
+        ++lk;
+        lp += probes;
         int64_t k = lo;
         for (; k < hi; ++k)
           if (bit_test(dm.F, idx[k])) { out |= 1ull << b; ++k; break; }
@@ -454,10 +473,16 @@ __global__ __launch_bounds__(kBlock) void k_dom_pull(const IterArgs A) {
       }
       dm.D[w] = out;
     }
-    work = block_sum_i64(work, lds);
+    bw += work;   // one frontier word read per entry tested
+    block_sum2_i64(work, bw, lds);
+    block_sum2_i64(lk, lp, lds);
     if (threadIdx.x == 0) {
-      if (work) atomicAdd((unsigned long long *)&A.qstats[(int64_t)dm.q * QS_N + QS_PULL], (unsigned long long)work);
-      if (t % tpd == 0) atomicAdd((unsigned long long *)&A.qstats[(int64_t)dm.q * QS_N + QS_DOMPULL], 1ull);
+      int64_t *qs = A.qstats + (int64_t)dm.q * QS_N;
+      if (work) atomicAdd((unsigned long long *)&qs[QS_PULL], (unsigned long long)work);
+      if (lk) atomicAdd((unsigned long long *)&qs[QS_LOOKUP], (unsigned long long)lk);
+      if (lp) atomicAdd((unsigned long long *)&qs[QS_LABEL], (unsigned long long)lp);
+      if (bw) atomicAdd((unsigned long long *)&qs[QS_BMWORDS], (unsigned long long)bw);
+      if (t % tpd == 0) atomicAdd((unsigned long long *)&qs[QS_DOMPULL], 1ull);
     }
   }
 }
@@ -473,7 +498,7 @@ __device__ __forceinline__ bool const_checks_hold(const IterArgs &A, const DStep
 }
 
 __global__ __launch_bounds__(kBlock) void k_lookup(const IterArgs A) {
-  __shared__ int64_t lds[kWaves];
+  __shared__ int64_t lds[2 * kWaves];
   __shared__ int sh_e, sh_ok;
   IterScalars *it = A.it;
   if (it->abort) return;
@@ -482,8 +507,9 @@ __global__ __launch_bounds__(kBlock) void k_lookup(const IterArgs A) {
   block_share(it->node_tiles, tb, te);
   NodeCursor ncur;
   int64_t bnz = 0, bw = 0;
-  EntryAcc acc;
+  EntryAcc acc, qacc;
   int64_t *p_nz = &es[0].nz, *p_w = &es[0].w;
+  int64_t *p_lab = A.qstats + QS_LABEL, *p_lk = A.qstats + QS_LOOKUP;
   for (int64_t t = tb; t < te; ++t) {
     if (threadIdx.x == 0) sh_e = ncur.at(A, t);
     __syncthreads();
@@ -495,7 +521,7 @@ __global__ __launch_bounds__(kBlock) void k_lookup(const IterArgs A) {
     const int64_t i0 = (t - sld(&es[e].node_tile0)) * kTileNodes, pn = sld(&es[e].prev_n);
     const int32_t *const eprev = sld(&es[e].prev);
     const int64_t enode0 = sld(&es[e].node0);
-    int64_t cnz = 0, cw = 0;
+    int64_t cnz = 0, cw = 0, clab = 0, clk = 0;
     const bool counted = counted_only(S);
     constexpr int RN = kTileNodes / kBlock;
     // the parent bindings, then their rows, of all of the thread's nodes first (independent loads)
@@ -521,9 +547,11 @@ __global__ __launch_bounds__(kBlock) void k_lookup(const IterArgs A) {
         label_range(S.dir ? A.g.lab[1] : A.g.lab[0], ra[r], re[r], S.label, lo, hi, probes);
         const int64_t plo = lo, phi = hi;
         int64_t c0lo = 0, c0hi = 0;
+        ++clk;
         for (int k = 0; k < min(S.nchk, kMaxGen) && hi > lo; ++k) {   // read the shortest bound segment
           const DCheck ck = A.checks[S.chk0 + k];
           int64_t clo, chi;
+          ++clk;
           seg_find(A.g, ck.dir, eprev[(int64_t)ck.col * pn + i], ck.label, clo, chi, probes);
           if (k == 0) { c0lo = clo; c0hi = chi; }
           if (chi - clo < hi - lo) { lo = clo; hi = chi; dir = ck.dir; gen = k + 1; }
@@ -533,6 +561,7 @@ __global__ __launch_bounds__(kBlock) void k_lookup(const IterArgs A) {
           it->chk_lo[gn] = gen == 1 ? plo : c0lo;
           it->chk_hi[gn] = gen == 1 ? phi : c0hi;
         }
+        clab += probes;
       } else {
         hi = es[e].list_n;
       }
@@ -543,16 +572,28 @@ __global__ __launch_bounds__(kBlock) void k_lookup(const IterArgs A) {
       cnz += (hi > lo) && !counted;
       cw += hi - lo;
     }
-    {   // one reduction for both: entries above bit 11, non-empty nodes (at most kTileNodes) below
-      const int64_t pk = block_sum_i64((cw << 11) | cnz, lds);
+    {   // two reductions for four sums: entries above bit 11, non-empty nodes (at most kTileNodes)
+        // below; label entries read above bit 24, segment lookups (at most 64 per node) below
+      int64_t pk = (cw << 11) | cnz, pl = (clab << 24) | clk;
+      block_sum2_i64(pk, pl, lds);
       cnz = pk & 2047;
       cw = pk >> 11;
+      clk = pl & ((1 << 24) - 1);
+      clab = pl >> 24;
     }
-    if (threadIdx.x == 0) acc.add(e, cnz, cw, p_nz, p_w, kEsStride);
+    if (threadIdx.x == 0) {
+      acc.add(e, cnz, cw, p_nz, p_w, kEsStride);
+      qacc.add(d.q, clab, clk, p_lab, p_lk, QS_N);
+    }
     bnz += cnz;
     bw += counted ? 0 : cw;
   }
-  if (threadIdx.x == 0) { acc.flush(p_nz, p_w, kEsStride); A.blk_a[blockIdx.x] = bnz; A.blk_b[blockIdx.x] = bw; }
+  if (threadIdx.x == 0) {
+    acc.flush(p_nz, p_w, kEsStride);
+    qacc.flush(p_lab, p_lk, QS_N);
+    A.blk_a[blockIdx.x] = bnz;
+    A.blk_b[blockIdx.x] = bw;
+  }
 }
 
 // Allocate the tree level of entry e (es[e].cnt children) in the tree arena and
@@ -947,6 +988,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
     if (lane == 0) {
       if (e_cnt) atomicAdd((unsigned long long *)&es[e].cnt, (unsigned long long)e_cnt);
       if (epr) atomicAdd((unsigned long long *)&A.qstats[(int64_t)d.q * QS_N + QS_PROBE], (unsigned long long)epr);
+      if (eft) atomicAdd((unsigned long long *)&A.qstats[(int64_t)d.q * QS_N + QS_BMWORDS], (unsigned long long)eft);
     }
     w_cnt += e_cnt;
     w_pr += epr;
@@ -1140,6 +1182,46 @@ __global__ __launch_bounds__(kBlock) void k_enumerate(int32_t *const *lvl_ptr, i
   }
 }
 
+// Order-independent digest of the rows: each leaf's row (variables in ascending
+// query-vertex order, k values) hashes to h_k with h_0 = k and
+// h_{i+1} = mix64(h_i + 0x9E3779B97F4A7C15 + (uint32)v_i), mix64 being the output
+// function of the splitmix64 generator (Steele, Lea and Flood, OOPSLA 2014);
+// the digest is the sum (mod 2^64) and the XOR of the row hashes.
+__device__ __forceinline__ uint64_t splitmix_out(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(kBlock) void k_row_digest(int32_t *const *lvl_ptr, int32_t *const *lvl_cptr,
+                                                       const int64_t *lvl_n, int k, const int32_t *var_rank,
+                                                       int64_t n, unsigned long long *out) {
+  uint64_t hs = 0, hx = 0;
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+    int32_t row[kMaxLevels];
+    int64_t node = r;
+    for (int j = k - 1; j >= 0; --j) {
+      const int32_t *L = lvl_ptr[j];
+      const int64_t nj = lvl_n[j];
+      row[var_rank[j]] = L[nj + node];
+      if (j > 0) node = parent_of(L, lvl_cptr[j], lvl_n[j - 1], node);
+    }
+    uint64_t h = (uint64_t)k;
+    for (int i = 0; i < k; ++i) h = splitmix_out(h + 0x9E3779B97F4A7C15ull + (uint64_t)(uint32_t)row[i]);
+    hs += h;
+    hx ^= h;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    hs += __shfl_xor(hs, off, 64);
+    hx ^= __shfl_xor(hx, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0 && (hs | hx)) {
+    atomicAdd(&out[0], (unsigned long long)hs);
+    atomicXor(&out[1], (unsigned long long)hx);
+  }
+}
+
 // ---------------------------------------------------------------- launchers
 int expand_write_blocks_per_cu() {
   int nb = 0;
@@ -1189,6 +1271,16 @@ hipError_t launch_enumerate(int32_t *const *lvl_ptr, int32_t *const *lvl_cptr, c
   if (g > 8192) g = 8192;
   hipLaunchKernelGGL(k_enumerate, dim3((unsigned)g), dim3(kBlock), 0, s, lvl_ptr, lvl_cptr, lvl_n, k, var_rank, first,
                      n, rows);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_digest(int32_t *const *lvl_ptr, int32_t *const *lvl_cptr, const int64_t *lvl_n, int k,
+                             const int32_t *var_rank, int64_t n, uint64_t *out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t g = (n + kBlock - 1) / kBlock;
+  if (g > 8192) g = 8192;
+  hipLaunchKernelGGL(k_row_digest, dim3((unsigned)g), dim3(kBlock), 0, s, lvl_ptr, lvl_cptr, lvl_n, k, var_rank, n,
+                     (unsigned long long *)out);
   return hipGetLastError();
 }
 

@@ -66,6 +66,10 @@ hipError_t launch_prune_write(const int32_t *L, const int32_t *cptr, int64_t pre
                               const uint8_t *alive, const int64_t *blkoff,
                               const int32_t *parent_newidx, int32_t *newidx, int32_t *out, int64_t n_out, int grid,
                               hipStream_t s);
+// Sum (mod 2^64) and XOR of the row hashes of every leaf into out[0], out[1]
+// (which the caller zeroes).
+hipError_t launch_row_digest(int32_t *const *lvl_ptr, int32_t *const *lvl_cptr, const int64_t *lvl_n, int k,
+                             const int32_t *var_rank, int64_t n, uint64_t *out, hipStream_t s);
 hipError_t launch_enumerate(int32_t *const *lvl_ptr, int32_t *const *lvl_cptr, const int64_t *lvl_n, int k,
                             const int32_t *var_rank,
                             int64_t first, int64_t n, int32_t *rows, hipStream_t s);

@@ -414,7 +414,7 @@ void loop(ServerImpl &S) {
       continue;
     }
     if (rflags[RF_SCRATCH]) ar[1].overflow = 1;   // the iteration was aborted: restart its queries
-    if (prof) account_iteration(E, E.events.data(), I, L, 0);
+    if (prof) account_iteration(E, E.events.data(), I, L, 0, 0);
 
     // level pointers and counters of every slot, once, when some query finishes now
     bool finishing = false;

@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import workload
-from helpers import brute_force, engine_rows, random_query, sort_rows
+from helpers import brute_force, engine_rows, random_query, row_digest, sort_rows
 
 gs = pytest.importorskip("paper_2106_14038_amd")
 pytestmark = pytest.mark.gpu
@@ -97,6 +97,11 @@ def test_random_tiny_graphs_vs_brute_force(seed):
                 cnt, rows = engine_rows(gs, e, q)
                 assert cnt == len(bf), q
                 assert np.array_equal(rows.reshape(-1, nv), bf.reshape(-1, nv)), q
+                r = gs.gs_query_run(e, q)
+                try:
+                    assert gs.gs_result_digest(r) == row_digest(bf, nv), q   # the device digest
+                finally:
+                    gs.gs_result_free(r)
         finally:
             gs.gs_engine_destroy(e)
 
@@ -276,6 +281,15 @@ def test_prune_keeps_rows_and_removes_dead_nodes(c0):
                 lv = [gs.gs_result_level(r1, j) for j in range(k)]
                 for j in range(k):
                     assert len(lv[j][0]) <= st.level_nodes[j]
+                # the pruned tree (Section 8.1): a level-j node is a binding of the first j + 1
+                # plan vertices that extends to a row, so level j holds one node per distinct
+                # projection of the oracle's rows onto those vertices
+                orows = G.eval(q)[1]
+                var_qv = [v for v, c in enumerate(q["qv_const"]) if c < 0]
+                cols = [var_qv.index(v) for v in gs.gs_plan_query(q, e).order[:k]]
+                for j in range(k):
+                    want = len(np.unique(orows[:, cols[:j + 1]], axis=0)) if len(orows) else 0
+                    assert len(lv[j][0]) == want, (q, j)
                 for j in range(k - 1):
                     par_next = lv[j + 1][0]
                     # every kept node has a child, children stay grouped in parent order
