@@ -64,31 +64,61 @@ def graph_for(qs):
     return workload.c1_graph(scale)
 
 
-def cpu_baseline(trip, qs, per_query_T, budget_s):
-    """The oracle, single-threaded, on a bounded sample of the same queries."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(trip, qs, per_query_T, budget_s, threads_all=None):
+    """The oracle (backtracking, count and row digest, no rows stored) on a bounded sample
+    of the same queries: once on one thread, once with the first variable's candidates
+    split over every host core. Queries are taken in set order until the budget is spent;
+    a query that reaches the oracle's work cap counts with its time and without its
+    traversed triples."""
     import oracle
+    nproc = threads_all or os.cpu_count() or 1
     t0 = time.time()
     G = oracle.Graph(trip, qs["n"], qs["n_labels"])
     index_s = time.time() - t0
-    done, T, secs = 0, 0, 0.0
-    for q, tq in zip(qs["queries"], per_query_T):
-        t1 = time.perf_counter()
-        try:
-            cnt, _ = G.eval(q["query"], rows=False, work_cap=200_000_000)
-        except oracle.OracleError:
-            continue
-        dt = time.perf_counter() - t1
-        assert cnt == q["count"], "oracle count differs from the stored count"
-        secs += dt
-        T += tq
-        done += 1
-        if secs > budget_s:
-            break
-    return {"value": T / secs if secs > 0 else None, "unit": "triples/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} of {len(qs['queries'])} queries in set order, count only, single thread, "
-                      f"{secs:.1f}s of evaluation (index build {index_s:.1f}s not timed); value = the engine's "
-                      f"traversed-triple count of those queries / oracle seconds",
-            "queries_per_s": done / secs if secs > 0 else None}
+
+    def run(threads):
+        done, aborted, T, secs = 0, 0, 0, 0.0
+        for q, tq in zip(qs["queries"], per_query_T):
+            t1 = time.perf_counter()
+            try:
+                cnt = G.digest(q["query"], threads=threads, work_cap=200_000_000)[0]
+                ok = True
+            except oracle.OracleError:
+                ok = False
+            secs += time.perf_counter() - t1
+            if ok:
+                assert cnt == q["count"], "oracle count differs from the stored count"
+                T += tq
+                done += 1
+            else:
+                aborted += 1
+            if secs > budget_s:
+                break
+        return {"value": T / secs if secs > 0 else None, "queries": done, "aborted": aborted, "seconds": secs,
+                "queries_per_s": (done + aborted) / secs if secs > 0 else None}
+
+    one = run(1)
+    allc = run(nproc)
+    log(f"cpu baseline: one thread {one}, {nproc} threads {allc}")
+    return {"value": allc["value"], "unit": "triples/s", "cores": nproc, "kind": "oracle",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "sample": f"queries in set order until {budget_s:.0f}s of oracle time per run (one thread: "
+                      f"{one['queries']} done + {one['aborted']} at the work cap; {nproc} threads: "
+                      f"{allc['queries']} + {allc['aborted']}); count and row digest, no rows stored; value = "
+                      f"the engine's traversed-triple count of the queries finished / oracle seconds including "
+                      f"the queries stopped at the work cap; index build {index_s:.1f}s not timed",
+            "one_core": one, "all_cores": allc}
 
 
 def batched_set_leg(gs, eng, qset, wave=1024):
@@ -390,10 +420,25 @@ def main():
     ms_step = elapsed * 1e3 / args.steps
     T = sum(s.t_total for s in st)
     per_query_T = [s.t_total for s in st]
+    B_alg = sum(s.bytes_alg for s in st)
     value = T / (ms_step / 1e3)
     log(f"batched: {ms_step:.2f} ms/step, {T} traversed triples/step, {value:.3e} triples/s")
 
-    # dominant kernel over the timed region
+    def step_roofline(kstats, steps, wall_ms):
+        """The whole step against HBM: the method's algorithmic bytes of every query (ids,
+        label entries, offset pairs, tree nodes written and read, bitmap words) over the summed
+        kernel time of the step, and over its wall time."""
+        kms = sum(v["ms"] for v in kstats.values()) / steps
+        impl = sum(v["bytes_impl"] for v in kstats.values()) / steps
+        return {"bytes_alg_per_step": B_alg, "kernel_ms_per_step": kms, "wall_ms_per_step": wall_ms,
+                "achieved_GBps": B_alg / (kms / 1e3) / 1e9, "frac": B_alg / (kms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                "wall_frac": B_alg / (wall_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                "bytes_impl_per_step": impl, "impl_GBps": impl / (kms / 1e3) / 1e9}
+
+    step_batched = step_roofline(ks, args.steps, ms_step)
+    log(f"batched step roofline: {step_batched}")
+
+    # dominant kernel over the timed region (the method's bytes of that kernel)
     dom = max(ks.items(), key=lambda kv: kv[1]["ms"])
     name, k = dom
     achieved = k["bytes_alg"] / (k["ms"] / 1e3) / 1e9 if k["ms"] > 0 and k["bytes_alg"] > 0 else None
@@ -401,10 +446,28 @@ def main():
                 "frac": achieved / HBM_PEAK_GBS if achieved else None,
                 "traffic": measured_traffic(name, args.workload),
                 "alg_bytes_per_launch": k["bytes_alg"] / max(k["launches"], 1),
+                "impl_bytes_per_launch": k["bytes_impl"] / max(k["launches"], 1),
                 "avg_launch_ms": k["ms"] / max(k["launches"], 1), "launches": k["launches"]}
     kernels = {n: {"ms_per_step": v["ms"] / args.steps, "launches_per_step": v["launches"] / args.steps,
-                   "GBps": (v["bytes_alg"] / (v["ms"] / 1e3) / 1e9) if v["ms"] > 0 and v["bytes_alg"] > 0 else None}
+                   "alg_GBps": (v["bytes_alg"] / (v["ms"] / 1e3) / 1e9) if v["ms"] > 0 and v["bytes_alg"] > 0 else None,
+                   "impl_GBps": (v["bytes_impl"] / (v["ms"] / 1e3) / 1e9) if v["ms"] > 0 and v["bytes_impl"] > 0
+                   else None}
                for n, v in ks.items()}
+
+    step_plain = None
+    if not args.no_plain:   # the plain form's kernel time: the same queries one at a time, with events
+        torch.cuda.synchronize()
+        tp0 = time.perf_counter()
+        for q in queries:
+            r = gs.gs_query_run(eng, q)
+            gs.gs_result_free(r)
+        torch.cuda.synchronize()
+        pwall = (time.perf_counter() - tp0) * 1e3
+        kp = gs.gs_kernel_stats(eng, reset=True)
+        step_plain = step_roofline(kp, 1, pwall)
+        step_plain["launches_per_pass"] = sum(v["launches"] for v in kp.values())
+        step_batched["launches_per_step"] = sum(v["launches"] for v in ks.values()) / args.steps
+        log(f"plain step roofline: {step_plain}")
 
     gs.gs_engine_destroy(eng)   # the instrumented engine has served its purpose
 
@@ -483,10 +546,13 @@ def main():
                     "launch": "eager launches with per-kernel events"},
         "plain": plain,
         "batched_graphs": graphs,
+        "batched_over_plain_queries_per_s": ((graphs or {}).get("queries_per_s", len(queries) / (ms_step / 1e3))
+                                             / plain["queries_per_s"]) if plain else None,
         "batched_set": batched_set,
         "served": served,
         "load_ms": load_ms,
         "roofline": roofline,
+        "step_roofline": {"batched": step_batched, "plain": step_plain},
         "kernels": kernels,
         "cpu_baseline": cpu,
     }

@@ -7,6 +7,7 @@ oracle cannot count within its work cap, are skipped; the next candidate of the
 same stream is tried. Run from the repository root:
 
     python -m workload.make_querysets [--set c1|c2|c3] [--scale 1.0] [--per-shape 25] [--total 1024]
+    python -m workload.make_querysets --set c1 --digests   (add row digests to an existing set)
 
 c1: 25 queries per shape (chain-4, star-5, snowflake-8, triangle), counts in
 [1, 1e9]; c2: the batched set, 256 queries per shape with random constants and
@@ -128,6 +129,29 @@ def served_set(trip, n, pool, args, t0):
     return got
 
 
+def add_digests(path, threads, t0):
+    """Add the oracle's order-independent row digest (count, sum and XOR of the row
+    hashes) to every query of an existing set file, evaluated by backtracking on
+    `threads` host threads; the digest's count must equal the stored count."""
+    with open(path) as f:
+        out = json.load(f)
+    for i, rec in enumerate(out["queries"]):
+        q = dict(rec["query"])
+        q["edges"] = [tuple(e) for e in q["edges"]]
+        ts = time.time()
+        cnt, hs, hx = _G.digest(q, threads=threads, support_filter=True)
+        if cnt != rec["count"]:
+            raise SystemExit(f"query {i}: backtracking count {cnt} != stored count {rec['count']}")
+        rec["digest_sum"], rec["digest_xor"] = str(hs), str(hx)
+        print(f"digest {i} {rec['shape']} count={cnt} {time.time() - ts:.1f}s ({time.time() - t0:.0f}s)", flush=True)
+    out["digest"] = ("row digest: count, sum mod 2^64 and XOR of per-row hashes (oracle.c), rows listing the "
+                     "variables in ascending query-vertex index")
+    with open(path + ".tmp", "w") as f:
+        json.dump(out, f)
+    os.replace(path + ".tmp", path)
+    print("wrote", path)
+
+
 def main():
     global _G
     ap = argparse.ArgumentParser()
@@ -141,6 +165,7 @@ def main():
     ap.add_argument("--work-cap", type=int, default=300_000_000)
     ap.add_argument("--procs", type=int, default=min(8, os.cpu_count() or 1))
     ap.add_argument("--shape-budget", type=float, default=1200.0, help="seconds per shape (batched set)")
+    ap.add_argument("--digests", action="store_true", help="add row digests to the existing set file")
     args = ap.parse_args()
     t0 = time.time()
     trip = workload.c1_graph(args.scale)
@@ -151,6 +176,10 @@ def main():
     out = {"workload": "c1", "scale": args.scale, "n": n, "m": int(len(trip)), "n_labels": workload.C1["n_labels"],
            "seed": workload.C1["seed"], "count_cap": args.cap,
            "note": "counts written by the oracle (workload/make_querysets.py)", "queries": []}
+    sc = "" if args.scale == 1.0 else f"s{args.scale:g}"
+    if args.digests:
+        add_digests(os.path.join(ROOT, "workload", "data", f"{args.set}{sc}_queries.json"), args.procs, t0)
+        return
     ctx = mp.get_context("fork")
     if args.set != "c1":
         with ctx.Pool(args.procs) as pool:
