@@ -194,6 +194,23 @@ gs_status gs_frontier_domain(gs_engine *engine, const uint64_t *frontier_words, 
 gs_status gs_bitmap_and_compact(gs_engine *engine, const uint64_t *const *bitmaps, int32_t k, int32_t *out,
                                 int64_t *count);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): gs_bitmap_and_compact
+ * over device memory, allocating nothing and copying nothing from the host.
+ * dev_bitmaps: host array of k device pointers, each to ceil(n/64) words;
+ * k <= 64 (GS_EINVAL above). dev_out: device buffer of capacity n int32
+ * (n = the loaded vertex count) that receives the ascending ids; dev_count: a
+ * device int64 that receives their number. Stream-ordered on the engine's
+ * stream and not synchronised: read the outputs after that stream. Temporaries
+ * live in one fixed device workspace per GPU (about 272 KiB, a static device
+ * array held until the process ends, located when an engine is created on
+ * that GPU); every call on a GPU uses the same workspace, so calls that overlap
+ * on one GPU (other streams, other engines, other threads) race. Each call
+ * clears what it accumulates. Errors: GS_EINVAL, GS_ESTATE (no data, or a
+ * server running), GS_EDEVICE (launch failure). */
+gs_status gs_bitmap_and_compact_noalloc(gs_engine *engine, const uint64_t *const *dev_bitmaps, int32_t k,
+                                        int32_t *dev_out, int64_t *dev_count);
+
 /* ---- planner (Section 6.1.2, host only, no device needed) -------------------- */
 
 typedef struct {

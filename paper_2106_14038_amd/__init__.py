@@ -106,6 +106,7 @@ SIGNATURES = {
     "gs_label_exists": ([_vp, _i32, ctypes.c_int, _vp], ctypes.c_int),
     "gs_frontier_domain": ([_vp, _vp, _i32, ctypes.c_int, ctypes.c_int, _vp, _vp], ctypes.c_int),
     "gs_bitmap_and_compact": ([_vp, _vp, _i32, _vp, _P(_i64)], ctypes.c_int),
+    "gs_bitmap_and_compact_noalloc": ([_vp, _vp, _i32, _vp, _vp], ctypes.c_int),
     "gs_plan_query": ([_vp, _P(gs_query), _P(gs_plan_info)], ctypes.c_int),
     "gs_query_run": ([_vp, _P(gs_query), _u32, _P(_vp)], ctypes.c_int),
     "gs_batch_run": ([_vp, _P(gs_query), _i32, _u32, _P(_vp)], ctypes.c_int),
@@ -249,6 +250,14 @@ def gs_bitmap_and_compact(engine, bitmaps) -> np.ndarray:
     cnt = ctypes.c_int64()
     _check(lib().gs_bitmap_and_compact(engine, ptrs, len(bms), out.ctypes.data, ctypes.byref(cnt)))
     return out[:cnt.value].copy()
+
+
+def gs_bitmap_and_compact_noalloc(engine, dev_bitmaps, dev_out, dev_count) -> None:
+    """dev_bitmaps: device addresses (ints) of k bitmaps; dev_out, dev_count: device
+    addresses of the id buffer (n int32) and of one int64. Stream-ordered, no sync."""
+    ptrs = (ctypes.c_void_p * max(len(dev_bitmaps), 1))(*[int(p) for p in dev_bitmaps])
+    _check(lib().gs_bitmap_and_compact_noalloc(engine, ptrs, len(dev_bitmaps), ctypes.c_void_p(int(dev_out)),
+                                               ctypes.c_void_p(int(dev_count))))
 
 
 def gs_plan_query(q: dict, engine=None) -> gs_plan_info:

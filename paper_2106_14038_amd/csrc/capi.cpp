@@ -45,6 +45,34 @@ struct Temps {
   ~Temps() { for (void *p : v) E.dfree(p); }
 };
 
+// Workspace of gs_bitmap_and_compact_noalloc: one fixed-size device array per
+// GPU, held until the process ends. Its host-side name is not a device address:
+// host code only ever uses the per-device address that hipGetSymbolAddress
+// returned, taken once per device when an engine is created on it.
+static __device__ __align__(256) char scratch[NoAllocLayout::bytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// With `device` current: the device address of its copy of the workspace.
+hipError_t scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void *ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!ptr) return hipErrorInvalidSymbol;
+  g_scratch_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+void *scratch_ptr(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
+
 gs_result *wrap(Result *r) {
   // gs_result is an opaque handle for a Result
   return reinterpret_cast<gs_result *>(r);
@@ -72,6 +100,11 @@ gs_status gs_engine_create(const gs_options *options, gs_engine **out) {
   E.opt = o;
   E.device = o.device;
   if (hipSetDevice(E.device) != hipSuccess) { delete ge; set_error("hipSetDevice failed"); return GS_EDEVICE; }
+  if (hipError_t se = scratch_setup(E.device); se != hipSuccess) {
+    delete ge;
+    set_error(std::string("cannot locate the device workspace: ") + hipGetErrorString(se));
+    return GS_EDEVICE;
+  }
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, E.device) == hipSuccess) E.cus = prop.multiProcessorCount;
   E.grid = o.grid_blocks > 0 ? o.grid_blocks : 12 * E.cus;
@@ -252,6 +285,33 @@ gs_status gs_bitmap_and_compact(gs_engine *engine, const uint64_t *const *bitmap
   if (h.abort) { set_error("scratch arena overflow"); return GS_ENOMEM; }
   *count = h.list_total;
   if (out && h.list_total) HIPRET(hipMemcpy(out, h.list_buf, 4 * h.list_total, hipMemcpyDeviceToHost));
+  return GS_OK;
+}
+
+gs_status gs_bitmap_and_compact_noalloc(gs_engine *engine, const uint64_t *const *dev_bitmaps, int32_t k,
+                                        int32_t *dev_out, int64_t *dev_count) {
+  if (!engine || k < 0 || (k > 0 && !dev_bitmaps) || !dev_out || !dev_count) {
+    set_error("bad argument");
+    return GS_EINVAL;
+  }
+  if (k > kNoAllocMaxBitmaps) {
+    set_error("gs_bitmap_and_compact_noalloc takes at most " + std::to_string(kNoAllocMaxBitmaps) + " bitmaps");
+    return GS_EINVAL;
+  }
+  Engine &E = engine->e;
+  if (!E.loaded) { set_error("no dataset loaded"); return GS_ESTATE; }
+  std::lock_guard<std::mutex> lk(E.mu);
+  if (E.serving) { set_error("a server is running on this engine"); return GS_ESTATE; }
+  for (int i = 0; i < k; ++i)
+    if (!dev_bitmaps[i]) { set_error("null bitmap"); return GS_EINVAL; }
+  char *ws = (char *)scratch_ptr(E.device);
+  if (!ws) { set_error("device workspace not set up"); return GS_ESTATE; }
+  const int grid = std::min(E.grid, kNoAllocMaxGrid);
+  HIPRET(hipSetDevice(E.device));
+  NoAllocInit init{};
+  init.k = k;
+  for (int i = 0; i < k; ++i) init.bm[i] = dev_bitmaps[i];
+  HIPRET(launch_list_noalloc(E.g, init, ws, grid, dev_out, dev_count, E.stream));
   return GS_OK;
 }
 

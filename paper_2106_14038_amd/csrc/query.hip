@@ -274,7 +274,7 @@ __global__ __launch_bounds__(1024) void k_list_scan(const IterArgs A) {
   __shared__ int32_t *buf;
   if (threadIdx.x == 0) {
     it->list_total = total;
-    buf = (int32_t *)arena_alloc(A.scratch, A.scratch_base, sizeof(int32_t) * total);
+    buf = A.list_out ? A.list_out : (int32_t *)arena_alloc(A.scratch, A.scratch_base, sizeof(int32_t) * total);
     it->list_buf = buf;
     if (A.scratch->overflow) run_abort(A);
   }
@@ -1295,6 +1295,75 @@ hipError_t launch_list_only(const IterArgs &A, hipStream_t s) {
   hipLaunchKernelGGL(k_list_count, G, B, 0, s, A);
   hipLaunchKernelGGL(k_list_scan, dim3(1), W1, 0, s, A);
   hipLaunchKernelGGL(k_list_write, G, B, 0, s, A);
+  return hipGetLastError();
+}
+
+static_assert(sizeof(DArena) <= NoAllocLayout::it - NoAllocLayout::arena, "workspace layout");
+static_assert(sizeof(IterScalars) <= NoAllocLayout::es - NoAllocLayout::it, "workspace layout");
+static_assert(sizeof(EState) <= NoAllocLayout::step - NoAllocLayout::es, "workspace layout");
+static_assert(sizeof(DStep) <= NoAllocLayout::ent - NoAllocLayout::step, "workspace layout");
+static_assert(sizeof(DEntry) <= NoAllocLayout::filt - NoAllocLayout::ent, "workspace layout");
+static_assert(8 * kNoAllocMaxBitmaps <= NoAllocLayout::lvl_ptr - NoAllocLayout::filt, "workspace layout");
+static_assert(8 * kMaxLevels <= NoAllocLayout::lvl_n - NoAllocLayout::lvl_ptr, "workspace layout");
+static_assert(8 * kMaxLevels <= NoAllocLayout::qstats - NoAllocLayout::lvl_n, "workspace layout");
+static_assert(8 * QS_N <= NoAllocLayout::heap - NoAllocLayout::qstats, "workspace layout");
+static_assert(NoAllocLayout::heap + NoAllocLayout::heap_bytes <= NoAllocLayout::blk, "workspace layout");
+
+// Writes the tables of a one-entry list iteration into the workspace and zeroes
+// what the list kernels accumulate into (the workspace keeps an earlier call's
+// contents). One wave.
+__global__ __launch_bounds__(64) void k_noalloc_setup(char *ws, const NoAllocInit init) {
+  using L = NoAllocLayout;
+  const int t = threadIdx.x;
+  for (size_t i = t; i < L::heap / 8; i += 64) {   // arena, scalars, entry state, tables, counters
+    if (i * 8 >= L::filt && i * 8 < L::lvl_ptr) continue;
+    ((int64_t *)ws)[i] = 0;
+  }
+  if (t < kNoAllocMaxBitmaps) ((const uint64_t **)(ws + L::filt))[t] = t < init.k ? init.bm[t] : nullptr;
+  if (t == 0) {
+    DArena *a = (DArena *)(ws + L::arena);
+    a->top = 0;
+    a->cap = L::heap_bytes;
+    DStep *st = (DStep *)(ws + L::step);
+    st->kind = STEP_LIST;
+    st->nfilt = init.k;
+    st->list_nfilt = init.k;
+  }
+}
+
+__global__ __launch_bounds__(64) void k_noalloc_finish(const IterScalars *it, int64_t *count) {
+  if (threadIdx.x == 0) *count = it->abort ? -1 : it->list_total;
+}
+
+hipError_t launch_list_noalloc(const DevGraph &g, const NoAllocInit &init, char *ws, int grid, int32_t *out,
+                               int64_t *count, hipStream_t s) {
+  using L = NoAllocLayout;
+  if (grid < 1 || grid > kNoAllocMaxGrid || init.k < 0 || init.k > kNoAllocMaxBitmaps) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_noalloc_setup, dim3(1), dim3(64), 0, s, ws, init);
+  IterArgs A{};
+  A.g = g;
+  A.ent = (const DEntry *)(ws + L::ent);
+  A.E = 1;
+  A.grid = grid;
+  A.has_list = 1;
+  A.steps = (const DStep *)(ws + L::step);
+  A.filt = (const uint64_t *const *)(ws + L::filt);
+  A.es = (EState *)(ws + L::es);
+  A.it = (IterScalars *)(ws + L::it);
+  A.lvl_ptr = (int32_t **)(ws + L::lvl_ptr);
+  A.lvl_n = (int64_t *)(ws + L::lvl_n);
+  A.qstats = (int64_t *)(ws + L::qstats);
+  A.scratch = (DArena *)(ws + L::arena);
+  A.scratch_base = ws + L::heap;
+  int64_t *blk = (int64_t *)(ws + L::blk);
+  A.blk_a = blk;
+  A.blk_b = blk + kNoAllocMaxGrid;
+  A.blk_off_a = blk + 2 * kNoAllocMaxGrid;
+  A.blk_off_b = blk + 3 * kNoAllocMaxGrid;
+  A.list_out = out;
+  hipError_t e = launch_list_only(A, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_noalloc_finish, dim3(1), dim3(64), 0, s, (const IterScalars *)A.it, count);
   return hipGetLastError();
 }
 

@@ -45,6 +45,9 @@ struct IterArgs {
   // whose output positions leave its level (count and write passes disagree).
   // Null only for the standalone list and domain launches.
   int32_t *flags;
+  // Standalone list launch only: the caller's output for the compacted ids (null:
+  // the ids go to a scratch-arena buffer, it->list_buf).
+  int32_t *list_out;
 };
 enum RunFlag { RF_SCRATCH = 0, RF_WRITE = 1, RF_N = 2 };
 
@@ -55,6 +58,25 @@ int expand_write_blocks_per_cu();
 hipError_t launch_iteration(const IterArgs &A, hipStream_t s, hipEvent_t *ev = nullptr);
 hipError_t launch_list_only(const IterArgs &A, hipStream_t s);
 hipError_t launch_domain_only(const IterArgs &A, hipStream_t s);
+
+// The standalone list launch over caller memory: every table it reads sits in one
+// caller-provided workspace (NoAllocLayout), written by a set-up kernel from the
+// by-value argument block, so the sequence allocates nothing and copies nothing
+// from the host. The count (or -1 when the workspace's arena overflowed) goes to
+// a device int64.
+constexpr int kNoAllocMaxBitmaps = 64;
+constexpr int kNoAllocMaxGrid = 8192;
+struct NoAllocInit {
+  const uint64_t *bm[kNoAllocMaxBitmaps];
+  int32_t k;
+};
+struct NoAllocLayout {   // byte offsets inside the workspace
+  static constexpr size_t arena = 0, it = 256, es = 1024, step = 2048, ent = 2304, filt = 2560,
+                          lvl_ptr = 3584, lvl_n = 4096, qstats = 4608, heap = 8192, heap_bytes = 8192,
+                          blk = 16384, bytes = blk + 4 * 8 * (size_t)kNoAllocMaxGrid;
+};
+hipError_t launch_list_noalloc(const DevGraph &g, const NoAllocInit &init, char *ws, int grid, int32_t *out,
+                               int64_t *count, hipStream_t s);
 // Tree levels come in two forms: a parent column (column 0, one entry per
 // node), or, for levels whose candidates face no test, child offsets per
 // parent (cptr, prev_n + 1 entries; the children of parent p are
