@@ -75,7 +75,7 @@ def _load():
                                    ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_uint64),
                                    ctypes.POINTER(ctypes.c_uint64)]
     lib.or_eval_digest.restype = ctypes.c_int
-    lib.or_count_acyclic.argtypes = [vp, ctypes.c_int32, i32p, ctypes.c_int32, i32p,
+    lib.or_count_acyclic.argtypes = [vp, ctypes.c_int32, i32p, ctypes.c_int32, i32p, ctypes.c_int32,
                                      ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]
     lib.or_count_acyclic.restype = ctypes.c_int
     _lib = lib
@@ -213,12 +213,13 @@ class Graph:
             raise OracleError(rc)
         return cnt.value, hs.value, hx.value
 
-    def count_acyclic(self, q: dict) -> int:
-        """Exact count by message passing over the query forest (acyclic queries only)."""
+    def count_acyclic(self, q: dict, threads: int = 1) -> int:
+        """Exact count by message passing over the query forest (acyclic queries only); the
+        per-vertex loops split over `threads` threads."""
         consts, edges = _qarrays(q)
         cnt = ctypes.c_int64(0)
         sat = ctypes.c_int32(0)
-        rc = _load().or_count_acyclic(self._h, q["n_qv"], consts, len(q["edges"]), edges,
+        rc = _load().or_count_acyclic(self._h, q["n_qv"], consts, len(q["edges"]), edges, int(threads),
                                       ctypes.byref(cnt), ctypes.byref(sat))
         if rc != 0:
             raise OracleError(rc)

@@ -501,6 +501,7 @@ int or_eval(const oracle_graph *g, int32_t n_qv, const int32_t *qv_const, int32_
 }
 
 /* ------------------------------------------------ support filter */
+static void par_for(int64_t n, int nthreads, void (*fn)(void *, int64_t, int64_t), void *ctx);
 /* Arc consistency (Mackworth, "Consistency in networks of relations", 1977):
  * every variable x gets a domain D(x), initially every vertex; for each edge
  * (a, p, b) a value v stays in D(a) only if some triple (v, p, u) has u in D(b)
@@ -511,8 +512,35 @@ int or_eval(const oracle_graph *g, int32_t n_qv, const int32_t *qv_const, int32_
  * only restrict candidates that the backtracking still checks edge by edge).
  * The filter saves search work only: on acyclic queries nearly every partial
  * assignment then extends to a row. */
+/* One narrowing pass of D(mine) by the edge (a, p, b); side 0 along the out-rows
+ * (a, p, .), side 1 along the in-rows (., p, b). Each v is decided alone (the
+ * other end's domain is not written in the pass), so the vertices may be split
+ * over threads. */
+typedef struct {
+  const oracle_graph *g; const nq_t *q; int32_t a, p, b, side;
+  uint8_t *d; const uint8_t *dother; int32_t other_const; atomic_int changed;
+} sf_pass;
+
+static void sf_run(void *arg, int64_t lo, int64_t hi) {
+  sf_pass *S = (sf_pass *)arg;
+  int changed = 0;
+  for (int64_t v = lo; v < hi; ++v) {
+    if (!S->d[v]) continue;
+    int64_t cnt;
+    const okey *nb = adj(S->g, (int32_t)v, S->p, S->side, &cnt);
+    int ok = 0;
+    for (int64_t t = 0; t < cnt && !ok; ++t) {
+      const int32_t u = key_nbr(nb[t]);
+      if (S->a == S->b) ok = (u == v);
+      else ok = S->dother ? S->dother[u] : (u == S->other_const);
+    }
+    if (!ok) { S->d[v] = 0; changed = 1; }
+  }
+  if (changed) atomic_store(&S->changed, 1);
+}
+
 /* dom[var * n + v]: 1 while v may still take variable rank var. */
-static uint8_t *support_filter(const oracle_graph *g, const nq_t *q) {
+static uint8_t *support_filter(const oracle_graph *g, const nq_t *q, int nthreads) {
   const int64_t n = g->n;
   uint8_t *dom = (uint8_t *)malloc((size_t)(q->nvar ? q->nvar : 1) * (size_t)(n ? n : 1));
   memset(dom, 1, (size_t)q->nvar * (size_t)n);
@@ -522,23 +550,16 @@ static uint8_t *support_filter(const oracle_graph *g, const nq_t *q) {
     for (int k = 0; k < q->n_edges; ++k) {
       const int32_t a = q->e[k][0], p = q->e[k][1], b = q->e[k][2];
       for (int side = 0; side < 2; ++side) {
-        /* side 0 narrows D(a) along the out-rows (a, p, .), side 1 D(b) along the in-rows (., p, b) */
         const int32_t mine = side ? b : a, other = side ? a : b;
         if (q->cst[mine] >= 0 || (side && a == b)) continue;
-        uint8_t *d = dom + (size_t)q->var_of[mine] * n;
-        const uint8_t *dother = q->cst[other] >= 0 ? NULL : dom + (size_t)q->var_of[other] * n;
-        for (int64_t v = 0; v < n; ++v) {
-          if (!d[v]) continue;
-          int64_t cnt;
-          const okey *nb = adj(g, (int32_t)v, p, side, &cnt);
-          int ok = 0;
-          for (int64_t t = 0; t < cnt && !ok; ++t) {
-            const int32_t u = key_nbr(nb[t]);
-            if (a == b) ok = (u == v);
-            else ok = dother ? dother[u] : (u == q->cst[other]);
-          }
-          if (!ok) { d[v] = 0; changed = 1; }
-        }
+        sf_pass S;
+        S.g = g; S.q = q; S.a = a; S.p = p; S.b = b; S.side = side;
+        S.d = dom + (size_t)q->var_of[mine] * n;
+        S.dother = (q->cst[other] >= 0 || mine == other) ? NULL : dom + (size_t)q->var_of[other] * n;
+        S.other_const = q->cst[other];
+        atomic_init(&S.changed, 0);
+        par_for(n, nthreads, sf_run, &S);
+        changed |= atomic_load(&S.changed);
       }
     }
   }
@@ -577,7 +598,7 @@ int or_eval_digest(oracle_graph *g, int32_t n_qv, const int32_t *qv_const, int32
   B.sh = &sh; B.digest = 1;
   *count = 0; *hsum = 0; *hxor = 0;
   if (!constant_edges_hold(g, &q)) return 0;
-  uint8_t *dom = (filter && q.nvar > 0) ? support_filter(g, &q) : NULL;
+  uint8_t *dom = (filter && q.nvar > 0) ? support_filter(g, &q, nthreads) : NULL;
   B.dom = dom;
   if (q.nvar == 0 || nthreads <= 1) {
     assign(&B, 0);
@@ -644,13 +665,61 @@ static int unary_holds(const oracle_graph *g, const nq_t *q, int32_t x, int32_t 
   return 1;
 }
 
-typedef struct { const oracle_graph *g; const nq_t *q; bundle_t *B; int nb; uint8_t *done; } dp_t;
+typedef struct { const oracle_graph *g; const nq_t *q; bundle_t *B; int nb; uint8_t *done; int nthreads; } dp_t;
+
+/* The vertex loops below are independent per vertex c; with several threads
+ * each takes a contiguous range of c (same values, any thread count). */
+typedef struct { void (*fn)(void *, int64_t, int64_t); void *ctx; int64_t lo, hi; } par_job;
+static void *par_main(void *a) { par_job *j = (par_job *)a; j->fn(j->ctx, j->lo, j->hi); return NULL; }
+static void par_for(int64_t n, int nthreads, void (*fn)(void *, int64_t, int64_t), void *ctx) {
+  if (nthreads < 1) nthreads = 1;
+  if (nthreads > 64) nthreads = 64;
+  par_job jobs[64];
+  pthread_t th[64];
+  int running[64] = {0};
+  for (int t = 0; t < nthreads; ++t) {
+    jobs[t].fn = fn; jobs[t].ctx = ctx; jobs[t].lo = n * t / nthreads; jobs[t].hi = n * (t + 1) / nthreads;
+    running[t] = nthreads > 1 && pthread_create(&th[t], NULL, par_main, &jobs[t]) == 0;
+    if (!running[t]) par_main(&jobs[t]);
+  }
+  for (int t = 0; t < nthreads; ++t) if (running[t]) pthread_join(th[t], NULL);
+}
+
+typedef struct { dp_t *D; int32_t x; u128 *msg; const u128 *cm; const bundle_t *b; int x_is_u, out_from_x; } dp_step;
+
+static void dp_unary(void *a, int64_t lo, int64_t hi) {
+  dp_step *S = (dp_step *)a;
+  for (int64_t c = lo; c < hi; ++c) S->msg[c] = unary_holds(S->D->g, S->D->q, S->x, (int32_t)c) ? 1 : 0;
+}
+
+/* msg[c] *= sum over values d of the child w adjacent to c through the bundle's first
+ * edge (oriented from x) that satisfy the bundle's other edges, of cm[d] */
+static void dp_combine(void *a, int64_t lo, int64_t hi) {
+  dp_step *S = (dp_step *)a;
+  const oracle_graph *g = S->D->g;
+  const bundle_t *b = S->b;
+  const int32_t p0 = b->lab[0];
+  for (int64_t c = lo; c < hi; ++c) {
+    if (!S->msg[c]) continue;
+    u128 s = 0;
+    int64_t cnt;
+    const okey *nb = adj(g, (int32_t)c, p0, S->out_from_x ? 0 : 1, &cnt);
+    for (int64_t t = 0; t < cnt; ++t) {
+      int32_t d = key_nbr(nb[t]);
+      if (!S->cm[d]) continue;
+      int ok = S->x_is_u ? bundle_holds(g, b, (int32_t)c, d) : bundle_holds(g, b, d, (int32_t)c);
+      if (ok) s = sat_add(s, S->cm[d]);
+    }
+    S->msg[c] = sat_mul(S->msg[c], s);
+  }
+}
 
 /* message of subtree rooted at x (entered from parent bundle pb, -1 for root): msg[c] for all c */
 static u128 *dp_message(dp_t *D, int32_t x, int pb) {
   const oracle_graph *g = D->g;
   u128 *msg = (u128 *)malloc(sizeof(u128) * (size_t)g->n);
-  for (int64_t c = 0; c < g->n; ++c) msg[c] = unary_holds(g, D->q, x, (int32_t)c) ? 1 : 0;
+  dp_step S = {D, x, msg, NULL, NULL, 0, 0};
+  par_for(g->n, D->nthreads, dp_unary, &S);
   D->done[x] = 1;
   for (int bi = 0; bi < D->nb; ++bi) {
     if (bi == pb) continue;
@@ -658,25 +727,12 @@ static u128 *dp_message(dp_t *D, int32_t x, int pb) {
     int32_t w;
     if (b->u == x) w = b->v; else if (b->v == x) w = b->u; else continue;
     u128 *cm = dp_message(D, w, bi);
-    /* sum over values d of w adjacent to c through the bundle's first edge, then check the rest */
-    int x_is_u = (b->u == x);
     /* first edge, oriented from x: dir 0 with x == u means (x, p, w): neighbours of c along out-edges */
-    int d0 = b->dir[0];
-    int out_from_x = x_is_u ? (d0 == 0) : (d0 == 1);
-    const int32_t p0 = b->lab[0];
-    for (int64_t c = 0; c < g->n; ++c) {
-      if (!msg[c]) continue;
-      u128 s = 0;
-      int64_t cnt;
-      const okey *nb = adj(g, (int32_t)c, p0, out_from_x ? 0 : 1, &cnt);
-      for (int64_t t = 0; t < cnt; ++t) {
-        int32_t d = key_nbr(nb[t]);
-        if (!cm[d]) continue;
-        int ok = x_is_u ? bundle_holds(g, b, (int32_t)c, d) : bundle_holds(g, b, d, (int32_t)c);
-        if (ok) s = sat_add(s, cm[d]);
-      }
-      msg[c] = sat_mul(msg[c], s);
-    }
+    S.cm = cm;
+    S.b = b;
+    S.x_is_u = (b->u == x);
+    S.out_from_x = S.x_is_u ? (b->dir[0] == 0) : (b->dir[0] == 1);
+    par_for(g->n, D->nthreads, dp_combine, &S);
     free(cm);
   }
   return msg;
@@ -686,7 +742,7 @@ static u128 *dp_message(dp_t *D, int32_t x, int pb) {
  * edges, is a forest). Returns 0 ok, -1 malformed, -2 out of range, -5 cyclic.
  * *saturated is set when the count exceeds 2^63-1 (then *count = INT64_MAX). */
 int or_count_acyclic(const oracle_graph *g, int32_t n_qv, const int32_t *qv_const, int32_t n_edges,
-                     const int32_t *edges, int64_t *count, int32_t *saturated) {
+                     const int32_t *edges, int32_t nthreads, int64_t *count, int32_t *saturated) {
   nq_t q;
   int rc = normalise(g, n_qv, qv_const, n_edges, edges, &q);
   if (rc) return rc;
@@ -715,7 +771,7 @@ int or_count_acyclic(const oracle_graph *g, int32_t n_qv, const int32_t *qv_cons
     parent[a] = b;
   }
   uint8_t done[OR_MAXQV] = {0};
-  dp_t D = {g, &q, B, nb, done};
+  dp_t D = {g, &q, B, nb, done, nthreads};
   u128 total = 1;
   for (int x = 0; x < n_qv; ++x) {
     if (q.cst[x] >= 0 || done[x]) continue;

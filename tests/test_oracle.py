@@ -244,7 +244,9 @@ def test_count_dp_matches_eval_on_acyclic(seed):
             e.append((v, rng.randint(1, P), v))
         q["edges"] = e
         G = oracle.Graph(trip, n, P)
-        assert G.count_acyclic(q) == G.eval(q, rows=False)[0], q
+        expect = G.eval(q, rows=False)[0]
+        assert G.count_acyclic(q) == expect, q
+        assert G.count_acyclic(q, threads=3) == expect, q   # vertex loops split over threads
 
 
 # ------------------------------------------------------------------ invariants
