@@ -15,6 +15,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import shutil
 import subprocess
 
 import numpy as np
@@ -26,14 +27,41 @@ _lib = None
 SHAPES = {"chain4": 0, "star5": 1, "snowflake8": 2, "triangle": 3, "c0star": 4, "mixed": 5}
 
 
+_DEV_SO = os.path.join(_HERE, "libgswork_dev.so")
+_dev_lib = None
+
+
 def build() -> str:
-    """Compile gen.c into libgswork.so (gcc, OpenMP)."""
+    """Compile gen.c into libgswork.so (gcc, OpenMP) and its device twin gen_dev.hip into
+    libgswork_dev.so (hipcc, gfx950)."""
     src = os.path.join(_HERE, "gen.c")
     cmd = ["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c11", "-Wall", "-Wno-unused-function",
            "-o", _SO + ".tmp", src, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(_SO + ".tmp", _SO)
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    arch = os.environ.get("GS_OFFLOAD_ARCH", "gfx950")
+    cmd = [hipcc, "-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={arch}", "-Xclang", "-target-feature",
+           "-Xclang", "-packed-fp32-ops", "-o", _DEV_SO + ".tmp", os.path.join(_HERE, "gen_dev.hip")]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("gen_dev.hip: " + r.stderr)
+    os.replace(_DEV_SO + ".tmp", _DEV_SO)
     return _SO
+
+
+def _load_dev():
+    """The device twin of the draw function (needs PyTorch's HIP runtime loaded first)."""
+    global _dev_lib
+    if _dev_lib is None:
+        import torch  # noqa: F401  (one HIP runtime for both)
+        lib = ctypes.CDLL(_DEV_SO)
+        vp = ctypes.c_void_p
+        lib.gsw_dev_cl_draws.argtypes = [vp, vp, ctypes.c_int64, vp, vp, ctypes.c_int32, vp, ctypes.c_uint64,
+                                         ctypes.c_int32, ctypes.c_uint64, ctypes.c_int64, vp, vp]
+        lib.gsw_dev_cl_draws.restype = ctypes.c_int
+        _dev_lib = lib
+    return _dev_lib
 
 
 def _load():
@@ -58,10 +86,16 @@ def _load():
     lib.gsw_cl_free.argtypes = [ctypes.c_void_p]
     lib.gsw_cl_draws.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int64, i32p]
     lib.gsw_cl_draws.restype = ctypes.c_int64
+    vpp = ctypes.POINTER(ctypes.c_void_p)
+    lib.gsw_cl_tables.argtypes = [ctypes.c_void_p, vpp, vpp, vpp, vpp, vpp]
     lib.gsw_query_record_words.restype = ctypes.c_int
     lib.gsw_walk_queries.argtypes = [i32p, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64, ctypes.c_int32,
                                      ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, i32p]
     lib.gsw_walk_queries.restype = ctypes.c_int
+    lib.gsw_walk_queries_ex.argtypes = [i32p, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64, ctypes.c_int32,
+                                        ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                        ctypes.c_int32, ctypes.c_int64, i32p]
+    lib.gsw_walk_queries_ex.restype = ctypes.c_int
     lib.gsw_poisson_arrivals.argtypes = [ctypes.c_uint64, ctypes.c_double, ctypes.c_double, ctypes.c_int64, f64p]
     lib.gsw_poisson_arrivals.restype = ctypes.c_int64
     _lib = lib
@@ -99,13 +133,54 @@ class ChungLuStream:
 
     def __init__(self, seed: int, n: int, n_labels: int, beta: float, zipf_s: float, domain_mod: int):
         self.n, self.n_labels = int(n), int(n_labels)
+        self.seed, self.domain_mod = int(seed), int(domain_mod)
         self._h = _load().gsw_cl_new(seed, n, n_labels, beta, zipf_s, domain_mod)
         if not self._h:
             raise MemoryError("Chung-Lu generator tables")
+        self._dev = None
+
+    def _device_tables(self):
+        """Device copies (torch tensors) of the generator's tables."""
+        if self._dev is None:
+            import torch
+            p = [ctypes.c_void_p() for _ in range(5)]
+            _load().gsw_cl_tables(self._h, *[ctypes.byref(x) for x in p])
+            sizes = [self.n, self.n, self.n_labels, self.n_labels, self.n]
+            types = [ctypes.c_uint32, ctypes.c_int32, ctypes.c_uint32, ctypes.c_int32, ctypes.c_int32]
+            self._dev = [torch.from_numpy(np.ctypeslib.as_array(ctypes.cast(x, ctypes.POINTER(t)), (k,))
+                                          .view(np.int32)).cuda()
+                         for x, t, k in zip(p, types, sizes)]
+        return self._dev
+
+    def device_draws(self, first: int, count: int, out, stream=None) -> int:
+        """Draws [first, first + count) into `out` (a device int32 tensor of count * 3 values,
+        in draw order), computed on the device by the twin of the host draw; a draw whose object
+        rejection failed is (-1, -1, -1). Returns the number of such failed draws."""
+        import torch
+        vthr, valias, lthr, lalias, perm = self._device_tables()
+        st = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+        rc = _load_dev().gsw_dev_cl_draws(vthr.data_ptr(), valias.data_ptr(), self.n, lthr.data_ptr(),
+                                          lalias.data_ptr(), self.n_labels, perm.data_ptr(), self.seed,
+                                          self.domain_mod, first, count, out.data_ptr(), st)
+        if rc != 0:
+            raise RuntimeError(f"gsw_dev_cl_draws: HIP error {rc}")
+        return int((out.view(-1, 3)[:, 0] < 0).sum().item())
+
+    def device_graph(self, total: int):
+        """Draws [0, total) as a device (k, 3) int32 tensor, failed draws left out."""
+        import torch
+        out = torch.empty(total * 3, dtype=torch.int32, device="cuda")
+        chunk = 1 << 28
+        bad = 0
+        for a in range(0, total, chunk):
+            k = min(chunk, total - a)
+            bad += self.device_draws(a, k, out[3 * a:3 * (a + k)])
+        t = out.view(-1, 3)
+        return t[t[:, 0] >= 0] if bad else t
 
     def __del__(self):
-        if getattr(self, "_h", None):
-            _load().gsw_cl_free(self._h)
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.gsw_cl_free(self._h)
             self._h = None
 
     def draws(self, first: int, count: int, out: np.ndarray = None) -> np.ndarray:
@@ -131,13 +206,16 @@ def _decode(rec: np.ndarray) -> dict:
 
 
 def walk_queries(triples: np.ndarray, n: int, seed: int, shape: str, nq: int, const_prob: float = 0.5,
-                 first: int = 0, max_consts: int = 2) -> list:
-    """nq query graphs of the given shape from seeded walks (candidates first .. first+nq-1)."""
+                 first: int = 0, max_consts: int = 2, n_consts: int = -1, const_max_deg: int = 0) -> list:
+    """nq query graphs of the given shape from seeded walks (candidates first .. first+nq-1).
+    n_consts >= 0: exactly that many non-centre constants (shapes chain4..triangle), chosen among
+    walk vertices with at most const_max_deg incident triples when const_max_deg > 0."""
     lib = _load()
     w = lib.gsw_query_record_words()
     out = np.zeros(max(nq, 1) * w, np.int32)
     t = np.ascontiguousarray(triples, dtype=np.int32).reshape(-1)
-    got = lib.gsw_walk_queries(t, len(triples), n, seed, SHAPES[shape], first, nq, const_prob, max_consts, out)
+    got = lib.gsw_walk_queries_ex(t, len(triples), n, seed, SHAPES[shape], first, nq, const_prob, max_consts,
+                                  n_consts, const_max_deg, out)
     if got < 0:
         raise ValueError(f"gsw_walk_queries failed ({got})")
     return [_decode(out[i * w:(i + 1) * w]) for i in range(got)]

@@ -282,6 +282,14 @@ void *gsw_cl_new(uint64_t seed, int64_t n, int32_t P, double beta, double zipf_s
   return c;
 }
 void gsw_cl_free(void *h) { if (h) { cl_free((cl_ctx *)h); free(h); } }
+/* The generator's tables, for a device twin of cl_draw (gen_dev.hip) that reads
+ * copies of them: vertex alias (n thresholds, n aliases), label alias (P, P),
+ * vertex permutation (n). */
+void gsw_cl_tables(const void *h, const uint32_t **vthr, const int32_t **valias, const uint32_t **lthr,
+                   const int32_t **lalias, const int32_t **perm) {
+  const cl_ctx *c = (const cl_ctx *)h;
+  *vthr = c->vw.thr; *valias = c->vw.alias; *lthr = c->lab.thr; *lalias = c->lab.alias; *perm = c->perm;
+}
 int64_t gsw_cl_draws(const void *h, uint64_t idx0, int64_t count, int32_t *out) {
   const cl_ctx *c = (const cl_ctx *)h;
 #pragma omp parallel for schedule(static)
@@ -473,19 +481,48 @@ static void qb_emit(const qb_t *q, const int32_t *is_const, int32_t *rec) {
  * Candidate i is drawn from counter stream (seed, TAG_QUERY + shape, first + i);
  * the walk is retried within that stream until it succeeds. Returns the number
  * of records written (nq unless a stream failed 10000 times). */
-int gsw_walk_queries(const int32_t *triples, int64_t m, int64_t n, uint64_t seed, int32_t shape,
-                     int64_t first, int32_t nq, double const_prob, int32_t max_consts, int32_t *out) {
+/* Non-centre walk positions whose vertex has at most max_deg incident triples
+ * (max_deg <= 0: every non-centre position). */
+static int light_positions(const inc_t *I, const qb_t *q, int64_t max_deg, int *pos) {
+  int k = 0;
+  for (int i = 1; i < q->nqv; ++i)
+    if (max_deg <= 0 || I->off[q->dv[i] + 1] - I->off[q->dv[i]] <= max_deg) pos[k++] = i;
+  return k;
+}
+
+/* As gsw_walk_queries, with two more knobs for shapes 0-3: n_consts >= 0 makes
+ * exactly that many distinct non-centre positions constants (instead of one
+ * with probability const_prob), chosen among the positions whose vertex has at
+ * most const_max_deg incident triples when const_max_deg > 0 (a walk with too
+ * few such positions is retried): constants of low degree make selective queries. */
+int gsw_walk_queries_ex(const int32_t *triples, int64_t m, int64_t n, uint64_t seed, int32_t shape, int64_t first,
+                        int32_t nq, double const_prob, int32_t max_consts, int32_t n_consts, int64_t const_max_deg,
+                        int32_t *out) {
   if (m <= 0 || n <= 0 || nq < 0) return -2;
   inc_t I;
   if (inc_build(&I, triples, m, n)) return -1;
   int written = 0;
   for (int i = 0; i < nq; ++i) {
     ph_stream rs; ps_init(&rs, seed, (uint32_t)(TAG_QUERY + shape), (uint64_t)(first + i));
-    qb_t q; int ok = 0;
-    for (int tries = 0; tries < 10000 && !ok; ++tries) ok = (gen_shape(&rs, &I, shape, &q) == 0);
+    const int exact = n_consts >= 0 && shape != SHAPE_C0STAR && shape != SHAPE_MIXED;
+    qb_t q; int ok = 0, pos[GSW_MAXQV], npos = 0;
+    for (int tries = 0; tries < 10000 && !ok; ++tries) {
+      ok = gen_shape(&rs, &I, shape, &q) == 0;
+      if (ok && exact) {
+        npos = light_positions(&I, &q, const_max_deg, pos);
+        ok = npos >= (n_consts < q.nqv - 1 ? n_consts : q.nqv - 1);
+      }
+    }
     if (!ok) break;
     int32_t isc[GSW_MAXQV] = {0};
-    if (shape == SHAPE_C0STAR) {
+    if (exact) {   /* n_consts distinct positions drawn from the light ones */
+      int nc = n_consts < npos ? n_consts : npos;
+      for (int k = 0; k < nc; ++k) {
+        int z = k + (int)ps_below(&rs, (uint64_t)(npos - k));
+        int t = pos[k]; pos[k] = pos[z]; pos[z] = t;
+        isc[pos[k]] = 1;
+      }
+    } else if (shape == SHAPE_C0STAR) {
       isc[q.e[2][2]] = 1;
     } else if (shape == SHAPE_MIXED) {
       int nc = (int)ps_below(&rs, (uint64_t)max_consts + 1);
@@ -503,6 +540,11 @@ int gsw_walk_queries(const int32_t *triples, int64_t m, int64_t n, uint64_t seed
   }
   inc_free(&I);
   return written;
+}
+
+int gsw_walk_queries(const int32_t *triples, int64_t m, int64_t n, uint64_t seed, int32_t shape,
+                     int64_t first, int32_t nq, double const_prob, int32_t max_consts, int32_t *out) {
+  return gsw_walk_queries_ex(triples, m, n, seed, shape, first, nq, const_prob, max_consts, -1, 0, out);
 }
 
 /* Open-loop Poisson arrival times (seconds from 0) at `rate` per second:
