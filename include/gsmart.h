@@ -107,7 +107,18 @@ typedef struct {
   int32_t grid_blocks;        /* workgroups of the fixed-grid kernels; 0 = 12 per compute unit */
   int32_t use_graphs;         /* batched form: capture each step's launches in a hipGraph (1) or not (0) */
   int32_t profile_kernels;    /* record HIP events around every kernel launch (gs_kernel_stats) */
+  int32_t offset_bytes;       /* stored row offsets: 0 = by size (4 bytes when M < 2^31, else 8), 8 = always 8 */
+  const char *autotune_cache; /* optional text file of tuned settings: gs_autotune records its choice for
+                                 the loaded graph's sizes there, gs_load_triples applies a recorded one */
+  int32_t traversal;          /* GS_TRAVERSAL_*: the planner's traversal for queries without constants */
 } gs_options;
+
+/* Query-graph traversal that orders the evaluation (Section 6.1): degree-driven
+ * (6.1.2, every incident edge of a visited vertex together) or direction-driven
+ * (6.1.1, DFS along edge directions from vertices without incoming edges, every
+ * outgoing edge of a visited vertex together, several roots). Queries with
+ * constants always take the degree-driven traversal with the constants rule. */
+enum { GS_TRAVERSAL_DEGREE = 0, GS_TRAVERSAL_DIRECTION = 1, GS_TRAVERSAL_ENGINE = -1 };
 
 /* Per-query counters, filled by gs_result_stats. T counts LSpM nonzeros read
  * by the kernels ("traversed triples"); bytes are algorithmic bytes. */
@@ -235,6 +246,10 @@ typedef struct {
  * Errors: GS_EINVAL, GS_ERANGE, GS_EUNSUPPORTED. */
 gs_status gs_plan_query(gs_engine *engine, const gs_query *query, gs_plan_info *out);
 
+/* As gs_plan_query with the traversal chosen explicitly (GS_TRAVERSAL_ENGINE:
+ * the engine's option; degree-driven without an engine). */
+gs_status gs_plan_query_ex(gs_engine *engine, const gs_query *query, int32_t traversal, gs_plan_info *out);
+
 /* ---- plain and batched evaluation ------------------------------------------- */
 
 /* Evaluate one query (one at a time). *out receives a result to be freed with
@@ -302,10 +317,12 @@ typedef struct {
 gs_status gs_kernel_stats(gs_engine *engine, gs_kernel_stat *out, int32_t cap, int32_t *n, int reset);
 
 /* Autotuner: evaluates the given queries (count only, batched) under every
- * candidate workgroup count of the fixed-grid kernels (2, 4, 8 and 16 per
+ * candidate workgroup count of the fixed-grid kernels (2, 4, 8, 12 and 16 per
  * compute unit) and push/pull threshold (0.25, 1, 4), keeps the fastest pair
- * for this engine's later calls, and reports it. Results are unchanged by the
- * choice. Errors as gs_batch_run. */
+ * for this engine's later calls, and reports it; with gs_options.autotune_cache
+ * set, the pair is also recorded there for the loaded graph's sizes (n, m, P),
+ * and a later engine loading a graph of those sizes starts from it. Results
+ * are unchanged by the choice. Errors as gs_batch_run. */
 typedef struct {
   int32_t grid_blocks;
   float push_pull_theta;

@@ -22,6 +22,7 @@ GS_OK, GS_EINVAL, GS_ERANGE, GS_ENOMEM, GS_EDEVICE, GS_ESTATE, GS_EUNSUPPORTED, 
 GS_MEM_HOST, GS_MEM_DEVICE = 0, 1
 GS_COUNT_ONLY, GS_PRUNE = 1, 2
 GS_DOMAIN_AUTO, GS_DOMAIN_PUSH, GS_DOMAIN_PULL, GS_DOMAIN_OFF = 0, 1, 2, 3
+GS_TRAVERSAL_DEGREE, GS_TRAVERSAL_DIRECTION, GS_TRAVERSAL_ENGINE = 0, 1, -1
 STATUS_NAMES = ["GS_OK", "GS_EINVAL", "GS_ERANGE", "GS_ENOMEM", "GS_EDEVICE", "GS_ESTATE", "GS_EUNSUPPORTED",
                 "GS_EAGAIN"]
 
@@ -55,7 +56,9 @@ class gs_options(ctypes.Structure):
                 ("scratch_bytes", ctypes.c_uint64), ("alloc", ALLOC_FN), ("free", FREE_FN),
                 ("alloc_ctx", ctypes.c_void_p), ("domain_mode", ctypes.c_int32),
                 ("push_pull_theta", ctypes.c_float), ("grid_blocks", ctypes.c_int32),
-                ("use_graphs", ctypes.c_int32), ("profile_kernels", ctypes.c_int32)]
+                ("use_graphs", ctypes.c_int32), ("profile_kernels", ctypes.c_int32),
+                ("offset_bytes", ctypes.c_int32), ("autotune_cache", ctypes.c_char_p),
+                ("traversal", ctypes.c_int32)]
 
 
 class gs_query_stats(ctypes.Structure):
@@ -108,6 +111,7 @@ SIGNATURES = {
     "gs_bitmap_and_compact": ([_vp, _vp, _i32, _vp, _P(_i64)], ctypes.c_int),
     "gs_bitmap_and_compact_noalloc": ([_vp, _vp, _i32, _vp, _vp], ctypes.c_int),
     "gs_plan_query": ([_vp, _P(gs_query), _P(gs_plan_info)], ctypes.c_int),
+    "gs_plan_query_ex": ([_vp, _P(gs_query), _i32, _P(gs_plan_info)], ctypes.c_int),
     "gs_query_run": ([_vp, _P(gs_query), _u32, _P(_vp)], ctypes.c_int),
     "gs_batch_run": ([_vp, _P(gs_query), _i32, _u32, _P(_vp)], ctypes.c_int),
     "gs_result_count": ([_vp, _P(_i64)], ctypes.c_int),
@@ -260,10 +264,14 @@ def gs_bitmap_and_compact_noalloc(engine, dev_bitmaps, dev_out, dev_count) -> No
                                                ctypes.c_void_p(int(dev_count))))
 
 
-def gs_plan_query(q: dict, engine=None) -> gs_plan_info:
-    """The plan of query q: the engine's (label statistics) when an engine is given."""
+def gs_plan_query(q: dict, engine=None, traversal: int | None = None) -> gs_plan_info:
+    """The plan of query q: the engine's (label statistics) when an engine is given; traversal
+    GS_TRAVERSAL_DEGREE / GS_TRAVERSAL_DIRECTION overrides the engine's choice."""
     info = gs_plan_info()
-    _check(lib().gs_plan_query(engine, ctypes.byref(make_query(q)), ctypes.byref(info)))
+    if traversal is None:
+        _check(lib().gs_plan_query(engine, ctypes.byref(make_query(q)), ctypes.byref(info)))
+    else:
+        _check(lib().gs_plan_query_ex(engine, ctypes.byref(make_query(q)), traversal, ctypes.byref(info)))
     return info
 
 

@@ -1,5 +1,6 @@
 // The C ABI (include/gsmart.h) over the host engine.
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -73,6 +74,41 @@ void *scratch_ptr(int device) {
   return g_scratch_ptr[device];
 }
 
+// Autotune cache: one line per graph, "n m P grid theta".
+bool tune_cache_lookup(const Engine &E, const char *path, int *grid, float *theta) {
+  FILE *f = fopen(path, "r");
+  if (!f) return false;
+  long long n, m;
+  int P, g;
+  float th;
+  bool hit = false;
+  while (fscanf(f, "%lld %lld %d %d %f", &n, &m, &P, &g, &th) == 5)
+    if (n == E.g.n && m == E.g.m && P == E.g.P && g > 0) { *grid = g; *theta = th; hit = true; }
+  fclose(f);
+  return hit;
+}
+
+bool tune_cache_store(const Engine &E, const char *path, int grid, float theta) {
+  std::vector<std::string> keep;
+  if (FILE *f = fopen(path, "r")) {
+    long long n, m;
+    int P, g;
+    float th;
+    while (fscanf(f, "%lld %lld %d %d %f", &n, &m, &P, &g, &th) == 5) {
+      if (n == E.g.n && m == E.g.m && P == E.g.P) continue;
+      char line[128];
+      snprintf(line, sizeof line, "%lld %lld %d %d %g\n", n, m, P, g, th);
+      keep.push_back(line);
+    }
+    fclose(f);
+  }
+  FILE *f = fopen(path, "w");
+  if (!f) return false;
+  for (const std::string &l : keep) fputs(l.c_str(), f);
+  fprintf(f, "%lld %lld %d %d %g\n", (long long)E.g.n, (long long)E.g.m, E.g.P, grid, theta);
+  return fclose(f) == 0;
+}
+
 gs_result *wrap(Result *r) {
   // gs_result is an opaque handle for a Result
   return reinterpret_cast<gs_result *>(r);
@@ -98,6 +134,10 @@ gs_status gs_engine_create(const gs_options *options, gs_engine **out) {
   if (!ge) return GS_ENOMEM;
   Engine &E = ge->e;
   E.opt = o;
+  if (o.autotune_cache) {   // the caller's string need not outlive the call
+    E.tune_path = o.autotune_cache;
+    E.opt.autotune_cache = E.tune_path.c_str();
+  }
   E.device = o.device;
   if (hipSetDevice(E.device) != hipSuccess) { delete ge; set_error("hipSetDevice failed"); return GS_EDEVICE; }
   if (hipError_t se = scratch_setup(E.device); se != hipSuccess) {
@@ -143,7 +183,17 @@ gs_status gs_load_triples(gs_engine *engine, int64_t n_vertices, int32_t n_label
   if (!engine) { set_error("null engine"); return GS_EINVAL; }
   if (mem_kind != GS_MEM_HOST && mem_kind != GS_MEM_DEVICE) { set_error("bad mem_kind"); return GS_EINVAL; }
   std::lock_guard<std::mutex> lk(engine->e.mu);
-  return (gs_status)load_triples(engine->e, n_vertices, n_labels, triples, m, mem_kind);
+  Engine &E = engine->e;
+  const int rc = load_triples(E, n_vertices, n_labels, triples, m, mem_kind);
+  if (rc == GS_OK && E.opt.autotune_cache) {   // a recorded tuning for a graph of these sizes
+    int grid = 0;
+    float theta = 0;
+    if (tune_cache_lookup(E, E.opt.autotune_cache, &grid, &theta)) {
+      E.grid = std::min(grid, 8192);
+      E.opt.push_pull_theta = theta;
+    }
+  }
+  return (gs_status)rc;
 }
 
 gs_status gs_graph_info(const gs_engine *engine, int64_t *n, int32_t *n_labels, int64_t *m_distinct,
@@ -163,12 +213,26 @@ gs_status gs_lspm_export(gs_engine *engine, int orientation, int64_t *ptr, int32
   Engine &E = engine->e;
   if (!E.loaded) { set_error("no dataset loaded"); return GS_ESTATE; }
   HIPRET(hipSetDevice(E.device));
-  if (ptr) HIPRET(hipMemcpy(ptr, E.d_ptr[orientation], sizeof(int64_t) * (E.g.n + 1), hipMemcpyDeviceToHost));
+  if (ptr) {
+    if (E.off_bytes == 8) {
+      HIPRET(hipMemcpy(ptr, E.d_ptr[orientation], sizeof(int64_t) * (E.g.n + 1), hipMemcpyDeviceToHost));
+    } else {
+      std::vector<int32_t> p((size_t)E.g.n + 1);
+      HIPRET(hipMemcpy(p.data(), E.d_ptr[orientation], sizeof(int32_t) * (E.g.n + 1), hipMemcpyDeviceToHost));
+      for (int64_t i = 0; i <= E.g.n; ++i) ptr[i] = p[i];
+    }
+  }
   if (idx && E.g.m) HIPRET(hipMemcpy(idx, E.d_idx[orientation], sizeof(int32_t) * E.g.m, hipMemcpyDeviceToHost));
   if (label && E.g.m) {
-    std::vector<uint16_t> l(E.g.m);
-    HIPRET(hipMemcpy(l.data(), E.d_lab[orientation], sizeof(uint16_t) * E.g.m, hipMemcpyDeviceToHost));
-    for (int64_t i = 0; i < E.g.m; ++i) label[i] = (int32_t)l[i] + 1;
+    if (E.lab_bytes == 2) {
+      std::vector<uint16_t> l(E.g.m);
+      HIPRET(hipMemcpy(l.data(), E.d_lab[orientation], sizeof(uint16_t) * E.g.m, hipMemcpyDeviceToHost));
+      for (int64_t i = 0; i < E.g.m; ++i) label[i] = (int32_t)l[i] + 1;
+    } else {
+      std::vector<uint8_t> l(E.g.m);
+      HIPRET(hipMemcpy(l.data(), E.d_lab[orientation], E.g.m, hipMemcpyDeviceToHost));
+      for (int64_t i = 0; i < E.g.m; ++i) label[i] = (int32_t)l[i] + 1;
+    }
   }
   return GS_OK;
 }
@@ -316,6 +380,10 @@ gs_status gs_bitmap_and_compact_noalloc(gs_engine *engine, const uint64_t *const
 }
 
 gs_status gs_plan_query(gs_engine *engine, const gs_query *query, gs_plan_info *out) {
+  return gs_plan_query_ex(engine, query, GS_TRAVERSAL_ENGINE, out);
+}
+
+gs_status gs_plan_query_ex(gs_engine *engine, const gs_query *query, int32_t traversal, gs_plan_info *out) {
   if (!query || !out) { set_error("null argument"); return GS_EINVAL; }
   if (query->n_edges > 0 && !query->edges) { set_error("query edges missing"); return GS_EINVAL; }
   std::vector<int32_t> e3(3 * (size_t)std::max(query->n_edges, 0));
@@ -325,12 +393,19 @@ gs_status gs_plan_query(gs_engine *engine, const gs_query *query, gs_plan_info *
   QInfo qi;
   std::string msg;
   int rc;
+  if (traversal != GS_TRAVERSAL_ENGINE && traversal != GS_TRAVERSAL_DEGREE && traversal != GS_TRAVERSAL_DIRECTION) {
+    set_error("unknown traversal");
+    return GS_EINVAL;
+  }
   if (engine && engine->e.g.n > 0) {   // the plan the engine's evaluation uses
     std::lock_guard<std::mutex> lk(engine->e.mu);
+    const int32_t keep = engine->e.opt.traversal;
+    if (traversal != GS_TRAVERSAL_ENGINE) engine->e.opt.traversal = traversal;
     rc = plan_query(engine->e, *query, qi, msg);
+    engine->e.opt.traversal = keep;
   } else {
     rc = normalise_query(query->n_qv, query->qv_const, query->n_edges, e3.data(), -1, -1, qi.nq, msg);
-    if (rc == GS_OK) rc = build_plan(qi.nq, nullptr, false, qi.plan, msg);
+    if (rc == GS_OK) rc = build_plan(qi.nq, nullptr, false, qi.plan, msg, traversal == GS_TRAVERSAL_DIRECTION);
   }
   if (rc != GS_OK) { set_error(msg); return (gs_status)rc; }
   const NormQuery &q = qi.nq;
@@ -415,7 +490,7 @@ gs_status gs_autotune(gs_engine *engine, const gs_query *queries, int32_t nq, gs
   out->push_pull_theta = theta0 > 0 ? theta0 : 1.0f;
   out->best_ms = ms0;
   out->default_ms = ms0;
-  const int mults[] = {2, 4, 8, 16};
+  const int mults[] = {2, 4, 8, 12, 16};
   const float thetas[] = {0.25f, 1.0f, 4.0f};
   for (int m : mults) {
     for (float th : thetas) {
@@ -431,6 +506,10 @@ gs_status gs_autotune(gs_engine *engine, const gs_query *queries, int32_t nq, gs
   if (rc != GS_OK) { E.grid = grid0; E.opt.push_pull_theta = theta0; return (gs_status)rc; }
   E.grid = out->grid_blocks;
   E.opt.push_pull_theta = out->push_pull_theta;
+  if (E.opt.autotune_cache && !tune_cache_store(E, E.opt.autotune_cache, out->grid_blocks, out->push_pull_theta)) {
+    set_error(std::string("cannot write the autotune cache ") + E.opt.autotune_cache);
+    return GS_EINVAL;
+  }
   return GS_OK;
 }
 

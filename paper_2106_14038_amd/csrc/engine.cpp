@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cstring>
 
+#include "kernels_common.hpp"
 #include "lspm.hpp"
 #include "query.hpp"
 
@@ -40,9 +41,24 @@ void Engine::dfree(void *p) {
   else (void)hipFree(p);
 }
 
+void *Engine::pinned(void *&buf, size_t &cap, size_t bytes) {
+  if (bytes <= cap && buf) return buf;
+  if (buf) (void)hipHostFree(buf);
+  buf = nullptr;
+  cap = 0;
+  size_t want = 1 << 16;
+  while (want < bytes) want <<= 1;
+  if (hipHostMalloc(&buf, want, hipHostMallocDefault) != hipSuccess) { buf = nullptr; return nullptr; }
+  cap = want;
+  return buf;
+}
+
 Engine::~Engine() {
   (void)hipSetDevice(device);
   if (stream) (void)hipStreamSynchronize(stream);
+  if (pin_up) (void)hipHostFree(pin_up);
+  if (pin_down) (void)hipHostFree(pin_down);
+  for (hipEvent_t e : run_ev) if (e) (void)hipEventDestroy(e);
   for (int o = 0; o < 2; ++o) { dfree(d_ptr[o]); dfree(d_idx[o]); dfree(d_lab[o]); dfree(d_bm[o]); }
   dfree(tree_base);
   dfree(scratch_base);
@@ -53,20 +69,24 @@ Engine::~Engine() {
 }
 
 // ------------------------------------------------------------------ loading
+// Bytes allocated after the last label: the short-row label search reads the aligned words
+// around a row's first eight entries, up to 32 bytes past the row's start.
+constexpr size_t kLabelPad = 32;
+
 struct LoadCtx { Engine *E; int64_t n; int32_t P; int64_t words; };
 
 static hipError_t alloc_orientation(void *vctx, int orient, int64_t m2, LspmOut &out) {
   LoadCtx *c = (LoadCtx *)vctx;
   Engine &E = *c->E;
   out.words = c->words;
-  E.d_ptr[orient] = (int64_t *)E.dmalloc(sizeof(int64_t) * (c->n + 1));
+  E.d_ptr[orient] = E.dmalloc(sizeof(int64_t) * (c->n + 1));
   E.d_idx[orient] = (int32_t *)E.dmalloc(sizeof(int32_t) * std::max<int64_t>(m2, 1));
-  E.d_lab[orient] = (uint16_t *)E.dmalloc(sizeof(uint16_t) * std::max<int64_t>(m2, 1));
+  E.d_lab[orient] = E.dmalloc(sizeof(uint16_t) * std::max<int64_t>(m2, 1) + kLabelPad);
   E.d_bm[orient] = (uint64_t *)E.dmalloc(sizeof(uint64_t) * c->words * c->P);
   if (!E.d_ptr[orient] || !E.d_idx[orient] || !E.d_lab[orient] || !E.d_bm[orient]) return hipErrorOutOfMemory;
-  out.ptr = E.d_ptr[orient];
+  out.ptr = (int64_t *)E.d_ptr[orient];
   out.idx = E.d_idx[orient];
-  out.lab = E.d_lab[orient];
+  out.lab = (uint16_t *)E.d_lab[orient];
   out.bm = E.d_bm[orient];
   return hipSuccess;
 }
@@ -148,11 +168,38 @@ int load_triples(Engine &E, int64_t n, int32_t P, const gs_triple *t, int64_t m,
   HIPCHK(hipStreamSynchronize(s));
   release();
   if (m2[0] != m2[1]) { set_error("orientations disagree on the distinct count"); return GS_EDEVICE; }
+  // stored widths: labels in one byte when P <= 256, offsets in four when M < 2^31 (unless wide offsets
+  // are asked for); the arrays were built wide and are copied down
+  const bool lab8 = P <= 256;
+  const bool off32 = m2[0] < (1ll << 31) && E.opt.offset_bytes != 8;
+  for (int o = 0; o < 2; ++o) {
+    if (off32) {
+      int32_t *p32 = (int32_t *)E.dmalloc(sizeof(int32_t) * (n + 1));
+      if (!p32) { set_error("out of device memory for the row offsets"); return GS_ENOMEM; }
+      HIPCHK(narrow_offsets((const int64_t *)E.d_ptr[o], p32, n + 1, s));
+      HIPCHK(hipStreamSynchronize(s));
+      E.dfree(E.d_ptr[o]);
+      E.d_ptr[o] = p32;
+    }
+    if (lab8) {
+      uint8_t *l8 = (uint8_t *)E.dmalloc(std::max<int64_t>(m2[o], 1) + kLabelPad);
+      if (!l8) { set_error("out of device memory for the labels"); return GS_ENOMEM; }
+      HIPCHK(narrow_labels((const uint16_t *)E.d_lab[o], l8, m2[o], s));
+      HIPCHK(hipStreamSynchronize(s));
+      E.dfree(E.d_lab[o]);
+      E.d_lab[o] = l8;
+    }
+  }
+  E.lab_bytes = lab8 ? 1 : 2;
+  E.off_bytes = off32 ? 4 : 8;
   DevGraph g;
   g.n = n; g.m = m2[0]; g.words = words; g.P = P;
+  g.lab8 = lab8 ? 1 : 0;
+  g.off32 = off32 ? 1 : 0;
   for (int o = 0; o < 2; ++o) { g.ptr[o] = E.d_ptr[o]; g.idx[o] = E.d_idx[o]; g.lab[o] = E.d_lab[o]; g.bm[o] = E.d_bm[o]; }
   E.g = g;
-  E.graph_bytes = 2 * ((uint64_t)(n + 1) * 8 + (uint64_t)g.m * 6 + (uint64_t)words * 8 * P);
+  E.graph_bytes = 2 * ((uint64_t)(n + 1) * E.off_bytes + (uint64_t)g.m * (4 + E.lab_bytes) +
+                       (uint64_t)words * 8 * P);
   E.loaded = true;
   return GS_OK;
 }
@@ -174,10 +221,8 @@ __global__ void k_const_only(DevGraph g, const DConst *cc, int n, int64_t *out) 
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     int64_t ok = 1;
     for (int k = 0; k < n && ok; ++k) {
-      int64_t a = g.ptr[0][cc[k].a], e = g.ptr[0][cc[k].a + 1];
-      int64_t x = a;
-      while (x < e && (g.lab[0][x] < (uint32_t)cc[k].label || (g.lab[0][x] == (uint32_t)cc[k].label && g.idx[0][x] < cc[k].b))) ++x;
-      ok = (x < e && g.lab[0][x] == (uint32_t)cc[k].label && g.idx[0][x] == cc[k].b);
+      int probes = 0;
+      ok = seg_has(g, 0, cc[k].a, cc[k].label, cc[k].b, probes);
     }
     *out = ok;
   }
@@ -218,7 +263,9 @@ int plan_query(const Engine &E, const gs_query &q, QInfo &qi, std::string &msg) 
     e3[3 * k] = q.edges[k].src; e3[3 * k + 1] = q.edges[k].label; e3[3 * k + 2] = q.edges[k].dst;
   }
   int rc = normalise_query(q.n_qv, q.qv_const, q.n_edges, e3.data(), E.g.n, E.g.P, qi.nq, msg);
-  if (rc == GS_OK) rc = build_plan(qi.nq, &E.stats, E.opt.domain_mode != GS_DOMAIN_OFF, qi.plan, msg);
+  if (rc == GS_OK)
+    rc = build_plan(qi.nq, &E.stats, E.opt.domain_mode != GS_DOMAIN_OFF, qi.plan, msg,
+                    E.opt.traversal == GS_TRAVERSAL_DIRECTION);
   qi.zero = rc == GS_OK && qi.plan.n_vars == 0;
   return rc;
 }
@@ -256,7 +303,27 @@ void compile_query(const Engine &E, QInfo &qi, bool count_only, int slot, Tables
     const std::vector<int32_t> &c = P.steps[at].carried;
     return 2 + (int)(std::find(c.begin(), c.end(), level) - c.begin());
   };
-  for (int j = 0; j < P.n_vars; ++j) {
+  // Factorised count (the per-path trees of Section 7.1, Example 7.1, in counting form): when
+  // only the count is asked for, trailing levels that are independent leaves (each generated
+  // from the segment of an earlier, non-trailing binding and facing no test) are not built:
+  // every node of the level before them contributes the product of their segment lengths.
+  int j0 = P.n_vars;
+  if (count_only) {
+    auto leaf = [&](int j, int first) {
+      const PlanStep &ps = P.steps[j];
+      return ps.kind == STEP_SEG && ps.filters.empty() && ps.checks.empty() && ps.self_labels.empty() &&
+             ps.src_level < first;
+    };
+    for (int f = P.n_vars - 1; f >= 1; --f) {   // the longest suffix [f, n_vars) of such leaves
+      bool ok = true;
+      for (int j = f; j < P.n_vars && ok; ++j) ok = leaf(j, f);
+      if (ok) j0 = f;
+    }
+    if (P.n_vars - j0 < 2) j0 = P.n_vars;      // one trailing leaf: the last level's own counted form
+  }
+  qi.nlev = j0 < P.n_vars ? j0 + 1 : P.n_vars;
+  qi.factor_lvl = j0 < P.n_vars ? j0 : -1;
+  for (int j = 0; j < qi.nlev; ++j) {
     const PlanStep &ps = P.steps[j];
     DStep d{};
     d.kind = ps.kind;
@@ -276,7 +343,16 @@ void compile_query(const Engine &E, QInfo &qi, bool count_only, int slot, Tables
     d.copy0 = (int32_t)T.ints.size();
     for (int32_t l : ps.carried) T.ints.push_back(col_of(l, j - 1));
     d.ncopy = (int32_t)ps.carried.size();
-    d.ncols_out = (count_only && j == P.n_vars - 1) ? 0 : 2 + d.ncopy;
+    d.ncols_out = (count_only && j == qi.nlev - 1) ? 0 : 2 + d.ncopy;
+    if (j == j0 && j0 < P.n_vars) {   // the factor level: this leaf and the ones after it
+      d.chk0 = (int32_t)T.checks.size();
+      for (int l = j0 + 1; l < P.n_vars; ++l) {
+        const PlanStep &pl = P.steps[l];
+        T.checks.push_back({col_of(pl.src_level, j0 - 1), pl.label, pl.dir, 0});
+      }
+      d.nfactor = P.n_vars - 1 - j0;
+      d.ncopy = 0;
+    }
     d.ncols_prev = j == 0 ? 0 : 2 + (int32_t)P.steps[j - 1].carried.size();
     if (j == 0) {
       d.cc0 = (int32_t)T.cconst.size();
@@ -309,7 +385,7 @@ void compile_query(const Engine &E, QInfo &qi, bool count_only, int slot, Tables
 // Work lists of one iteration: query qs[i] produces its level `level[i]`.
 void build_iteration(const Tables &T, const std::vector<const QInfo *> &qs, const std::vector<int> &level,
                      IterLists &L) {
-  L.ents.clear(); L.doms.clear(); L.clears.clear(); L.seeds.clear(); L.has_list = 0; L.has_tested = 0; L.has_checks = 0;
+  L.ents.clear(); L.doms.clear(); L.clears.clear(); L.seeds.clear(); L.has_list = 0; L.has_tested = 0; L.has_checks = 0; L.has_factor = 0;
   for (size_t i = 0; i < qs.size(); ++i) {
     const QInfo &qi = *qs[i];
     const int t = level[i];
@@ -324,6 +400,7 @@ void build_iteration(const Tables &T, const std::vector<const QInfo *> &qs, cons
       e.ndom++;
     }
     if (qi.plan.steps[t].kind == STEP_LIST) L.has_list = 1;
+    if (t == qi.factor_lvl) L.has_factor = 1;
     {   // the device's test-free rule (no filter beyond a list's own, no check, no self loop), from the plan
       const PlanStep &ps = qi.plan.steps[t];
       const bool filtered = ps.kind == STEP_LIST ? false : !ps.filters.empty();
@@ -392,7 +469,6 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
     std::string msg;
     int rc = plan_query(E, qs[i], Q[i], msg);
     if (rc != GS_OK) { set_error("query " + std::to_string(i) + ": " + msg); return rc; }
-    maxk = std::max(maxk, Q[i].plan.n_vars);
   }
 
   // 2. compile step programs; bitmaps at the front of this run's arena block
@@ -404,7 +480,10 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
   int64_t next_bm = 0;
   auto next_bitmap = [&]() { return (uint64_t *)(E.tree_base + bm_off + (uint64_t)(next_bm++) * words * 8); };
   Tables T;
-  for (int i = 0; i < nq; ++i) compile_query(E, Q[i], count_only, i, T, next_bitmap);
+  for (int i = 0; i < nq; ++i) {
+    compile_query(E, Q[i], count_only, i, T, next_bitmap);
+    maxk = std::max(maxk, Q[i].nlev);
+  }
 
   // 3. per-iteration work lists (every query advances one level per iteration)
   std::vector<IterLists> its(maxk);
@@ -417,7 +496,7 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
   for (int t = 0; t < maxk; ++t) {
     std::vector<const QInfo *> act;
     std::vector<int> lev;
-    for (int i = 0; i < nq; ++i) if (Q[i].plan.n_vars > t) { act.push_back(&Q[i]); lev.push_back(t); }
+    for (int i = 0; i < nq; ++i) if (Q[i].nlev > t) { act.push_back(&Q[i]); lev.push_back(t); }
     build_iteration(T, act, lev, its[t]);
     ent_off[t] = (int32_t)ents.size(); dom_off[t] = (int32_t)doms.size();
     clr_off[t] = (int32_t)clears.size(); seed_off[t] = (int32_t)seeds.size();
@@ -454,15 +533,19 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
   if (off > E.tree_cap) { set_error("tree arena too small for the batch tables"); return GS_ENOMEM; }
   char *base = E.tree_base;
   auto dp = [&](uint64_t o) { return (void *)(base + o); };
-  HIPCHK(hipMemcpyAsync(base + tab_off, buf.data(), buf.size(), hipMemcpyHostToDevice, s));
+  // the tables and the arena tops go up in one copy each from pinned staging
   DArena ar[2];
   ar[0] = {off, E.tree_cap, 0, 0};
   ar[1] = {0, E.scratch_cap, 0, 0};
-  HIPCHK(hipMemcpyAsync(E.d_arenas, ar, sizeof(ar), hipMemcpyHostToDevice, s));
+  char *up = (char *)E.pinned(E.pin_up, E.pin_up_bytes, align256(buf.size()) + sizeof ar);
+  if (!up) { set_error("cannot allocate pinned host staging"); return GS_ENOMEM; }
+  memcpy(up, buf.data(), buf.size());
+  memcpy(up + align256(buf.size()), ar, sizeof ar);
+  HIPCHK(hipMemcpyAsync(base + tab_off, up, buf.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(E.d_arenas, up + align256(buf.size()), sizeof(ar), hipMemcpyHostToDevice, s));
 
-  hipEvent_t ev0, ev1;
-  HIPCHK(hipEventCreate(&ev0));
-  HIPCHK(hipEventCreate(&ev1));
+  for (hipEvent_t &e : E.run_ev) if (!e) HIPCHK(hipEventCreate(&e));
+  hipEvent_t ev0 = E.run_ev[0], ev1 = E.run_ev[1];
 
   // 5. iterations
   const bool prof = E.opt.profile_kernels != 0;
@@ -488,6 +571,7 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
     A.has_list = its[t].has_list;
     A.has_tested = its[t].has_tested;
     A.has_checks = its[t].has_checks;
+    A.has_factor = its[t].has_factor;
     A.grid = E.grid;
     A.wgrid = E.wgrid;
     A.steps = (const DStep *)dp(tab_off + o_steps);
@@ -579,22 +663,27 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
   }
   HIPCHK(hipEventRecord(ev1, s));
 
-  // 6. read back sizes and counters
+  // 6. read back sizes and counters: the device-written tables are one contiguous block, copied
+  // with the arena tops into pinned staging
+  const size_t blk_bytes = zero_end - o_lvlp;
+  char *down = (char *)E.pinned(E.pin_down, E.pin_down_bytes, blk_bytes + sizeof ar);
+  if (!down) { set_error("cannot allocate pinned host staging"); return GS_ENOMEM; }
+  HIPCHK(hipMemcpyAsync(down, dp(o_lvlp), blk_bytes, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(down + blk_bytes, E.d_arenas, sizeof(ar), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  auto hp = [&](uint64_t o) { return (const void *)(down + (o - o_lvlp)); };
   std::vector<int64_t> lvl_n((size_t)nq * kMaxLevels), qst((size_t)nq * QS_N), zero_res(nq);
   int32_t rflags[RF_N] = {0, 0};
   std::vector<int32_t *> lvl_p((size_t)nq * kMaxLevels), lvl_c((size_t)nq * kMaxLevels);
-  HIPCHK(hipMemcpyAsync(lvl_n.data(), dp(o_lvln), 8 * lvl_n.size(), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(lvl_p.data(), dp(o_lvlp), 8 * lvl_p.size(), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(lvl_c.data(), dp(o_lvlc), 8 * lvl_c.size(), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(qst.data(), dp(o_qs), 8 * qst.size(), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(zero_res.data(), dp(o_zero), 8 * zero_res.size(), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(ar, E.d_arenas, sizeof(ar), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(rflags, dp(o_flags), sizeof(rflags), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
+  memcpy(lvl_n.data(), hp(o_lvln), 8 * lvl_n.size());
+  memcpy(lvl_p.data(), hp(o_lvlp), 8 * lvl_p.size());
+  memcpy(lvl_c.data(), hp(o_lvlc), 8 * lvl_c.size());
+  memcpy(qst.data(), hp(o_qs), 8 * qst.size());
+  memcpy(zero_res.data(), hp(o_zero), 8 * zero_res.size());
+  memcpy(rflags, hp(o_flags), sizeof(rflags));
+  memcpy(ar, down + blk_bytes, sizeof(ar));
   float ms = 0;
   HIPCHK(hipEventElapsedTime(&ms, ev0, ev1));
-  (void)hipEventDestroy(ev0);
-  (void)hipEventDestroy(ev1);
   if (ms_out) *ms_out = ms;
   if (prof) {
     std::vector<IterScalars> iv(std::max(maxk, 1));
@@ -602,7 +691,7 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
     for (int t = 0; t < maxk; ++t) {
       double wbytes = 0, children = 0;   // rows written this iteration, weighted by the columns each query writes
       for (int i = 0; i < nq; ++i) {
-        if (Q[i].plan.n_vars <= t) continue;
+        if (Q[i].nlev <= t) continue;
         const DStep &d = T.steps[Q[i].step0 + t];
         const int64_t c = std::max<int64_t>(lvl_n[(size_t)i * kMaxLevels + t], 0);
         // columns written + copies read + candidate read; CSR levels write no parent column
@@ -624,7 +713,12 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
     return GS_ENOMEM;
   }
   for (int i = 0; i < nq; ++i)
-    for (int j = 0; j < Q[i].plan.n_vars; ++j)
+    if (qst[(size_t)i * QS_N + QS_OVERFLOW] == 3) {
+      set_error("query " + std::to_string(i) + ": a node's product of leaf segments exceeds 2^50 (count-only factor)");
+      return GS_ERANGE;
+    }
+  for (int i = 0; i < nq; ++i)
+    for (int j = 0; j < Q[i].nlev; ++j)
       if (lvl_n[(size_t)i * kMaxLevels + j] < 0) {
         set_error("query " + std::to_string(i) + ": binding tree exceeds the tree arena (level " + std::to_string(j) + ")");
         return GS_ENOMEM;
@@ -652,7 +746,7 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
 void fill_result(Result &R, const QInfo &qi, bool count_only, int32_t *const *lvl_p, int32_t *const *lvl_c,
                  const int64_t *lvl_n, const int64_t *c, int64_t zero_res, double ms) {
   const Plan &P = qi.plan;
-  R.k = P.n_vars;
+  R.k = qi.nlev;
   R.n_vars = P.n_vars;
   R.count_only = count_only;
   R.zero_vars = qi.zero;
@@ -660,7 +754,7 @@ void fill_result(Result &R, const QInfo &qi, bool count_only, int32_t *const *lv
   if (qi.zero) {
     R.count = zero_res;
   } else {
-    for (int j = 0; j < P.n_vars; ++j) {
+    for (int j = 0; j < qi.nlev; ++j) {
       R.lvl_ptr.push_back(lvl_p[j]);
       R.lvl_cptr.push_back(lvl_c[j]);
       R.lvl_n.push_back(lvl_n[j]);

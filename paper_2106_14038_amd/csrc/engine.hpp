@@ -53,12 +53,13 @@ struct Engine {
   // matrix
   bool loaded = false;
   DevGraph g{};
-  int64_t *d_ptr[2] = {nullptr, nullptr};
+  void *d_ptr[2] = {nullptr, nullptr};    // int32 or int64 row offsets (off_bytes)
   int32_t *d_idx[2] = {nullptr, nullptr};
-  uint16_t *d_lab[2] = {nullptr, nullptr};
+  void *d_lab[2] = {nullptr, nullptr};    // uint8 or uint16 labels (lab_bytes)
   uint64_t *d_bm[2] = {nullptr, nullptr};
   LabelStats stats;
   uint64_t graph_bytes = 0;
+  std::string tune_path;           // copy of gs_options.autotune_cache (the option then points here)
   int32_t lab_bytes = 2;           // stored widths of a label and of a row offset
   int32_t off_bytes = 8;
 
@@ -76,6 +77,12 @@ struct Engine {
   // per-run workspaces (grown on demand)
   void *work = nullptr;
   size_t work_bytes = 0;
+  // pinned host staging of a run's table upload and result readback (grown on demand), and the
+  // run's two timing events (created once)
+  void *pin_up = nullptr, *pin_down = nullptr;
+  size_t pin_up_bytes = 0, pin_down_bytes = 0;
+  hipEvent_t run_ev[2] = {nullptr, nullptr};
+  void *pinned(void *&buf, size_t &cap, size_t bytes);
 
   // optional kernel timing (gs_options.profile_kernels)
   struct KStat { int64_t launches = 0; double ms = 0, bytes = 0, alg = 0; };
@@ -100,6 +107,9 @@ struct QInfo {                      // one planned query and where its tables si
   Plan plan;
   int32_t slot = 0;                  // index of its level / counter tables
   int32_t step0 = 0, seed0 = 0, nseed = 0, dom0 = 0, ndom = 0, vr0 = 0;
+  int32_t nlev = 0;                  // tree levels evaluated (fewer than the variables when trailing
+                                     // independent leaves of a count-only query are counted as a product)
+  int32_t factor_lvl = -1;           // the level that counts those leaves' product (-1: none)
   bool zero = false;                 // no variable: constant patterns only
 };
 
@@ -123,6 +133,7 @@ struct IterLists {                   // host work lists of one iteration
   int32_t has_list = 0;
   int32_t has_tested = 0;
   int32_t has_checks = 0;
+  int32_t has_factor = 0;
 };
 
 int plan_query(const Engine &E, const gs_query &q, QInfo &qi, std::string &msg);

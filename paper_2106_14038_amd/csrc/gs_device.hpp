@@ -20,12 +20,16 @@ constexpr int kMaxLevels = 64;
 // (s, p, b), sorted by (p, s). Labels are stored 0-based (p - 1).
 // bm[d] + p * words: label-existence vector of Eq. (4) (d = 0: rows holding p)
 // or Eq. (5) (d = 1: columns holding p), one bit per vertex.
+// Storage widths follow the sizes: labels are uint8 when P <= 256 (lab8) and
+// uint16 otherwise; row offsets are int32 when M < 2^31 (off32) and int64
+// otherwise (or when wide offsets are asked for).
 struct DevGraph {
   int64_t n = 0, m = 0, words = 0;
-  int32_t P = 0, pad = 0;
-  const int64_t *ptr[2] = {nullptr, nullptr};
+  int32_t P = 0;
+  int8_t lab8 = 0, off32 = 0, pad0 = 0, pad1 = 0;
+  const void *ptr[2] = {nullptr, nullptr};
   const int32_t *idx[2] = {nullptr, nullptr};
-  const uint16_t *lab[2] = {nullptr, nullptr};
+  const void *lab[2] = {nullptr, nullptr};
   const uint64_t *bm[2] = {nullptr, nullptr};
 };
 
@@ -43,7 +47,8 @@ struct DStep {
   int32_t cc0, ncc;    // constant-constant checks (level 0 only)
   int32_t dom0, ndom;  // domains computed before this level
   int32_t list_nfilt;  // LIST: filters ANDed into the list (the first list_nfilt of filt0..)
-  int32_t pad;
+  int32_t nfactor;     // count-only factor level: further independent leaves, as DCheck records at
+                       // chk0.. (column, label, dir), whose segment lengths multiply this one's
 };
 
 struct DCheck { int32_t col, label, dir, pad; };   // exact check: c in seg(prev[col], label, dir)

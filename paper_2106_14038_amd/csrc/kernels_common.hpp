@@ -2,6 +2,7 @@
 // reductions, segment lookup in the light-weight sparse matrix).
 #pragma once
 #include "gs_device.hpp"
+#include <type_traits>
 
 namespace gs {
 
@@ -175,55 +176,171 @@ __device__ __forceinline__ void block_share(int64_t total, int64_t &lo, int64_t 
   hi = total * (g + 1) / G;
 }
 
-__device__ __forceinline__ int64_t lower_bound_u16(const uint16_t *a, int64_t lo, int64_t hi, uint32_t key,
-                                                   int &probes) {
-  while (lo < hi) {
-    int64_t mid = (lo + hi) >> 1;
-    ++probes;
-    if (gld(a + mid) < key) lo = mid + 1; else hi = mid;
+// Workgroups that take part in a pass over `units` tiles on a grid of `grid`: all of
+// them, or one per tile when there are fewer tiles (a small level then costs a
+// small partial-sum scan). The pass's count, scan and write kernels agree on it.
+__device__ __forceinline__ int64_t active_groups(int64_t units, int64_t grid) {
+  return units < 1 ? 1 : (units < grid ? units : grid);
+}
+// Block g of G takes the contiguous share [lo, hi) of [0, total).
+__device__ __forceinline__ void block_share_g(int64_t total, int64_t G, int64_t &lo, int64_t &hi) {
+  const int64_t g = blockIdx.x;
+  lo = total * g / G;
+  hi = total * (g + 1) / G;
+}
+
+// Reads of the stored matrix at its widths: LB bytes per label (1 or 2), OB
+// bytes per row offset (4 or 8). The hot kernels are instantiated for the
+// loaded widths; the others dispatch once per segment lookup.
+template <int LB>
+__device__ __forceinline__ uint32_t lab_w(const void *lab, int64_t x) {
+  if constexpr (LB == 1) return (uint32_t)gld((const uint8_t *)lab + x);
+  else return (uint32_t)gld((const uint16_t *)lab + x);
+}
+// Positions in the entry arrays at the offsets' width: 32-bit when the offsets are (M < 2^31),
+// so that searches keep half the registers.
+template <int OB>
+using OffT = std::conditional_t<OB == 4, int32_t, int64_t>;
+template <int OB>
+__device__ __forceinline__ OffT<OB> off_w(const void *ptr, int64_t b) {
+  if constexpr (OB == 4) return gld((const int32_t *)ptr + b);
+  else return gld((const int64_t *)ptr + b);
+}
+
+// Iterations of the halving search over m entries (the label entries it reads).
+__device__ __forceinline__ int search_steps(int64_t m) { return m > 0 ? 64 - __clzll((unsigned long long)m) : 0; }
+
+// Short rows (e - a <= 8): the labels of entries [a, a + 8) come from aligned 8-byte loads
+// of the words around them (one or two cache lines, no dependent load; the label arrays
+// are allocated with 32 bytes to spare after their last entry), and the entries below and
+// equal to `label` among the first e - a of them are counted in registers.
+template <int LB, class I>
+__device__ __forceinline__ void label_range_short(const void *lab, I a, I e, uint32_t label, I &lo, I &hi) {
+  const int n = (int)(e - a);
+  int less = 0, eq = 0;
+  if (n > 0) {
+    const I base = a & ~(I)7;   // 8 entries: 8-byte aligned (LB 1), 16-byte aligned (LB 2)
+    const int sh = (int)(a - base);
+    uint64_t x0, x1 = 0;
+    if constexpr (LB == 1) {
+      const uint64_t *p = (const uint64_t *)((const uint8_t *)lab + base);
+      const uint64_t w0 = gld(p), w1 = gld(p + 1);
+      x0 = sh ? (w0 >> (8 * sh)) | (w1 << (64 - 8 * sh)) : w0;   // entries a .. a+7, one byte each
+    } else {
+      const uint64_t *p = (const uint64_t *)((const uint16_t *)lab + base);
+      const uint64_t w0 = gld(p), w1 = gld(p + 1), w2 = gld(p + 2), w3 = gld(p + 3);
+      const bool q = sh >= 4;
+      const int r = sh & 3;
+      uint64_t y0 = q ? w1 : w0, y1 = q ? w2 : w1, y2 = q ? w3 : w2;
+      if (r) {
+        y0 = (y0 >> (16 * r)) | (y1 << (64 - 16 * r));
+        y1 = (y1 >> (16 * r)) | (y2 << (64 - 16 * r));
+      }
+      x0 = y0;   // entries a .. a+3
+      x1 = y1;   // entries a+4 .. a+7
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      uint32_t v;
+      if constexpr (LB == 1) v = (uint32_t)(x0 >> (8 * k)) & 0xffu;
+      else v = (uint32_t)((k < 4 ? x0 : x1) >> (16 * (k & 3))) & 0xffffu;
+      if (k < n) {
+        less += v < label;
+        eq += v == label;
+      }
+    }
   }
-  return lo;
+  lo = a + less;
+  hi = lo + eq;
 }
 
 // Entries with label `label` among the row entries [a, e) (labels ascend): [lo, hi).
-__device__ __forceinline__ void label_range(const uint16_t *lab, int64_t a, int64_t e, int32_t label, int64_t &lo,
-                                            int64_t &hi, int &probes) {
-  if (e - a <= 8) {          // short rows: one linear pass
-    int64_t x = a;
-    while (x < e && gld(lab + x) < (uint32_t)label) ++x;
-    int64_t y = x;
-    while (y < e && gld(lab + y) == (uint32_t)label) ++y;
-    probes += (int)(y - a + (y < e));
-    lo = x; hi = y;
+template <int LB, class I>
+__device__ __forceinline__ void label_range_w(const void *lab, I a, I e, int32_t label, I &lo, I &hi, int &probes) {
+  if (e - a <= 8) {          // short rows: the labels of [a, a + 8) at once, counted in registers
+    label_range_short<LB>(lab, a, e, (uint32_t)label, lo, hi);
+    probes += (int)(hi - a + (hi < e));   // the entries a linear pass would read
     return;
   }
-  lo = lower_bound_u16(lab, a, e, (uint32_t)label, probes);
-  hi = lower_bound_u16(lab, lo, e, (uint32_t)label + 1, probes);
+  // both bounds (first entry >= label, first entry > label) halve the row in lockstep: two
+  // independent loads per step instead of one search after the other; positions are
+  // 32-bit, relative to the row's first entry (a row holds fewer than 2^31 entries)
+  const uint32_t key = (uint32_t)label;
+  const void *row = (const char *)lab + (int64_t)a * LB;
+  const int32_t n = (int32_t)(e - a);
+  int32_t l1 = 0, h1 = n, l2 = 0, h2 = n;
+  while (l1 < h1 || l2 < h2) {
+    const bool s1 = l1 < h1, s2 = l2 < h2;
+    const int32_t m1 = (l1 + h1) >> 1, m2 = (l2 + h2) >> 1;
+    const uint32_t v1 = s1 ? lab_w<LB>(row, m1) : 0u, v2 = s2 ? lab_w<LB>(row, m2) : 0u;
+    if (s1) { if (v1 < key) l1 = m1 + 1; else h1 = m1; }
+    if (s2) { if (v2 <= key) l2 = m2 + 1; else h2 = m2; }
+  }
+  lo = a + l1;
+  hi = a + l2;
+  probes += search_steps(e - a) + search_steps(e - lo);   // as the search of [lo, e) after [a, e) reads
+}
+
+// Label entries label_range_w reads to find [lo, hi) in [a, e), counted from the bounds
+// (so that the search itself keeps no counter).
+__device__ __forceinline__ int label_reads(int64_t a, int64_t e, int64_t lo, int64_t hi) {
+  if (e - a <= 8) return (int)(hi - a + (hi < e));
+  return search_steps(e - a) + search_steps(e - lo);
 }
 
 // Entries of vertex b with label `label` in orientation dir: [lo, hi).
-__device__ __forceinline__ void seg_find(const DevGraph &g, int dir, int32_t b, int32_t label, int64_t &lo,
-                                         int64_t &hi, int &probes) {
+template <int LB, int OB, class I>
+__device__ __forceinline__ void seg_find_w(const DevGraph &g, int dir, int32_t b, int32_t label, I &lo, I &hi,
+                                           int &probes) {
   // selects, not indexing: dir may differ between lanes, and indexing the
   // pointer arrays by a per-lane value loads the pointers from memory
-  const int64_t *ptr = dir ? g.ptr[1] : g.ptr[0];
-  const int64_t a = gld(ptr + b), e = gld(ptr + b + 1);
-  label_range(dir ? g.lab[1] : g.lab[0], a, e, label, lo, hi, probes);
+  const void *ptr = dir ? g.ptr[1] : g.ptr[0];
+  const OffT<OB> a = off_w<OB>(ptr, b), e = off_w<OB>(ptr, (int64_t)b + 1);
+  OffT<OB> l, h;
+  label_range_w<LB>(dir ? g.lab[1] : g.lab[0], a, e, label, l, h, probes);
+  lo = (I)l;
+  hi = (I)h;
+}
+
+template <int LB, int OB>
+__device__ __forceinline__ bool seg_has_w(const DevGraph &g, int dir, int32_t b, int32_t label, int32_t c,
+                                          int &probes) {
+  using I = OffT<OB>;
+  I lo, hi;
+  seg_find_w<LB, OB>(g, dir, b, label, lo, hi, probes);
+  const int32_t *idx = dir ? g.idx[1] : g.idx[0];
+  I x = lo, y = hi;
+  while (x < y) {
+    const I mid = x + ((y - x) >> 1);
+    ++probes;
+    if (gld(idx + mid) < c) x = mid + 1; else y = mid;
+  }
+  return x < hi && gld(idx + x) == c;
+}
+
+// Runs CALL with constexpr LB and OB set to the loaded widths (one uniform branch).
+#define GS_WITH_WIDTHS(g, CALL)                                  \
+  do {                                                           \
+    if ((g).lab8) {                                              \
+      if ((g).off32) { constexpr int LB = 1, OB = 4; CALL; }     \
+      else { constexpr int LB = 1, OB = 8; CALL; }               \
+    } else {                                                     \
+      if ((g).off32) { constexpr int LB = 2, OB = 4; CALL; }     \
+      else { constexpr int LB = 2, OB = 8; CALL; }               \
+    }                                                            \
+  } while (0)
+
+__device__ __forceinline__ void seg_find(const DevGraph &g, int dir, int32_t b, int32_t label, int64_t &lo,
+                                         int64_t &hi, int &probes) {
+  GS_WITH_WIDTHS(g, (seg_find_w<LB, OB>(g, dir, b, label, lo, hi, probes)));
 }
 
 // Is c among the entries of vertex b with label `label` (orientation dir)?
 __device__ __forceinline__ bool seg_has(const DevGraph &g, int dir, int32_t b, int32_t label, int32_t c,
                                         int &probes) {
-  int64_t lo, hi;
-  seg_find(g, dir, b, label, lo, hi, probes);
-  const int32_t *idx = dir ? g.idx[1] : g.idx[0];
-  int64_t x = lo, y = hi;
-  while (x < y) {
-    int64_t mid = (x + y) >> 1;
-    ++probes;
-    if (gld(idx + mid) < c) x = mid + 1; else y = mid;
-  }
-  return x < hi && gld(idx + x) == c;
+  bool r = false;
+  GS_WITH_WIDTHS(g, (r = seg_has_w<LB, OB>(g, dir, b, label, c, probes)));
+  return r;
 }
 
 // Store that is not kept in the caches (tree levels are written once and read

@@ -279,6 +279,25 @@ static int bits_for(uint64_t maxval) {   // bits to hold values in [0, maxval]
   return b;
 }
 
+__global__ __launch_bounds__(kBlock) void k_narrow_offsets(const int64_t *in, int32_t *out, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (int32_t)in[i];
+}
+__global__ __launch_bounds__(kBlock) void k_narrow_labels(const uint16_t *in, uint8_t *out, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (uint8_t)in[i];
+}
+hipError_t narrow_offsets(const int64_t *in, int32_t *out, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_narrow_offsets, dim3(grid_for(n, 8192)), dim3(kBlock), 0, s, in, out, n);
+  return hipGetLastError();
+}
+hipError_t narrow_labels(const uint16_t *in, uint8_t *out, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_narrow_labels, dim3(grid_for(n, 8192)), dim3(kBlock), 0, s, in, out, n);
+  return hipGetLastError();
+}
+
 hipError_t lspm_build_orientation(const LspmBuildArgs &a, int orient, LspmOut &out, int64_t *m_out) {
   hipStream_t s = a.stream;
   const int G = a.grid;

@@ -36,6 +36,10 @@ struct LspmBuildArgs {
 
 hipError_t lspm_build_orientation(const LspmBuildArgs &a, int orient, LspmOut &out, int64_t *m_out);
 hipError_t fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s);
+// Copies into the narrower stored widths (values known to fit): row offsets
+// int64 -> int32, labels uint16 -> uint8.
+hipError_t narrow_offsets(const int64_t *in, int32_t *out, int64_t n, hipStream_t s);
+hipError_t narrow_labels(const uint16_t *in, uint8_t *out, int64_t n, hipStream_t s);
 hipError_t scan_i64(const int64_t *in, int64_t L, int64_t *out, int64_t *total, hipStream_t s);
 
 }  // namespace gs

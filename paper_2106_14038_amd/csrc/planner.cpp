@@ -3,6 +3,7 @@
 #include "planner.hpp"
 
 #include <algorithm>
+#include <array>
 #include <cstdio>
 
 #include "gsmart.h"
@@ -54,7 +55,8 @@ double est_seg(const LabelStats *st, int32_t label0, int dir) {
 
 }  // namespace
 
-int build_plan(const NormQuery &q, const LabelStats *st, bool want_domains, Plan &P, std::string &msg) {
+int build_plan(const NormQuery &q, const LabelStats *st, bool want_domains, Plan &P, std::string &msg,
+               bool direction) {
   P = Plan();
   const int nv = q.n_qv, ne = (int)q.edges.size();
   std::vector<uint8_t> evaluated(ne, 0), visited(nv, 0);
@@ -103,7 +105,56 @@ int build_plan(const NormQuery &q, const LabelStats *st, bool want_domains, Plan
   };
 
   std::vector<int32_t> pop_order;
+  if (direction && !has_const) {
+    // Direction-driven traversal (Section 6.1.1): DFS along edge directions. A root is an
+    // unvisited vertex without unevaluated incoming edges (for cyclic queries, if none has,
+    // any unvisited vertex), the one with the most unevaluated outgoing edges; a popped vertex
+    // evaluates its unevaluated outgoing edges and pushes the newly reached vertices in
+    // ascending order of unevaluated outgoing edges (ties: the lower index pops first).
+    auto unev_in = [&](int v) {
+      int n = 0;
+      for (int k = 0; k < ne; ++k) if (!evaluated[k] && q.edges[k].o == v && q.edges[k].s != v) ++n;
+      return n;
+    };
+    for (;;) {
+      bool all_eval = true;
+      for (int k = 0; k < ne; ++k) if (!evaluated[k]) all_eval = false;
+      bool all_visited = true;
+      for (int v = 0; v < nv; ++v) if (!visited[v]) all_visited = false;
+      if (all_eval && all_visited) break;
+      int root = -1, bo = -1;
+      for (int pass = 0; pass < 2 && root < 0; ++pass)
+        for (int v = 0; v < nv; ++v) {
+          if (visited[v] || (pass == 0 && unev_in(v) > 0)) continue;
+          int t, o; unev(v, t, o);
+          if (root < 0 || o > bo) { root = v; bo = o; }
+        }
+      if (root < 0) break;
+      P.roots.push_back(root);
+      visited[root] = 1;
+      std::vector<int32_t> stack{root};
+      while (!stack.empty()) {
+        int v = stack.back(); stack.pop_back();
+        pop_order.push_back(v);
+        std::vector<int32_t> found;
+        int g = -1;
+        for (int k = 0; k < ne; ++k) {
+          if (evaluated[k] || q.edges[k].s != v) continue;
+          if (g < 0) { g = (int)P.group_vertex.size(); P.group_vertex.push_back(v); }
+          evaluated[k] = 1; P.edge_group[k] = g;
+          const int w = q.edges[k].o;
+          if (w != v && !visited[w]) { visited[w] = 1; discovered_by_edge[w] = k; found.push_back(w); }
+        }
+        std::vector<std::array<int, 2>> keyed;
+        for (int w : found) { int t, o; unev(w, t, o); keyed.push_back({o, -w}); }
+        std::sort(keyed.begin(), keyed.end());
+        for (auto &kk : keyed) stack.push_back(-kk[1]);
+      }
+      // edges into vertices that were visited already wait for the next root (Step 5)
+    }
+  }
   for (;;) {
+    if (direction && !has_const) break;
     bool all_visited = true;
     for (int v = 0; v < nv; ++v) if (is_var(v) && !visited[v]) all_visited = false;
     bool all_eval = true;
@@ -193,6 +244,18 @@ int build_plan(const NormQuery &q, const LabelStats *st, bool want_domains, Plan
     if (best < 0) {
       if (next_root >= P.roots.size()) { msg = "planner: no vertex can take the next level"; return GS_EINVAL; }
       best = P.roots[next_root++];
+      // A further root of the direction-driven traversal can have edges to vertices already
+      // placed (v3 -> v2 in Example 6.1); the single binding tree binds it through the one
+      // with the smallest estimated segment, read against its direction.
+      double bs = 0;
+      for (int k = 0; k < ne; ++k) {
+        const QEdge &e = q.edges[k];
+        if (e.s == e.o || (e.s != best && e.o != best)) continue;
+        const int u = (e.s == best) ? e.o : e.s;
+        if (!is_var(u) || !placed[u]) continue;
+        const double s = est_seg(st, e.p - 1, e.s == u ? 0 : 1);
+        if (discovered_by_edge[best] < 0 || s < bs) { discovered_by_edge[best] = k; bs = s; }
+      }
     }
     placed[best] = 1;
     order.push_back(best);
@@ -248,6 +311,15 @@ int build_plan(const NormQuery &q, const LabelStats *st, bool want_domains, Plan
         S.kind = STEP_LIST;
       }
     }
+    if (S.kind == STEP_LIST)
+      for (int k = 0; k < ne; ++k) {   // a list level is bound by nothing earlier, so tests nothing earlier
+        const QEdge &e = q.edges[k];
+        const int w = (e.s == x) ? e.o : (e.o == x ? e.s : -1);
+        if (w >= 0 && w != x && is_var(w) && level_of[w] < j) {
+          msg = "planner: a list level with an edge to an earlier level";
+          return GS_EINVAL;
+        }
+      }
     for (int k = 0; k < ne; ++k) {
       if (k == S.parent_edge) continue;
       const QEdge &e = q.edges[k];

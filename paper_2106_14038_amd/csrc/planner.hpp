@@ -71,8 +71,11 @@ struct LabelStats {
 int normalise_query(int32_t n_qv, const int32_t *qv_const, int32_t n_edges, const int32_t *edges3,
                     int64_t n_vertices, int32_t n_labels, NormQuery &q, std::string &msg);
 
-// Degree-driven traversal + step programs. domains: whether cycle-closing
-// edges get a frontier-domain filter. stats may be null.
-int build_plan(const NormQuery &q, const LabelStats *stats, bool domains, Plan &plan, std::string &msg);
+// Traversal + step programs. domains: whether cycle-closing edges get a
+// frontier-domain filter. stats may be null. direction: the direction-driven
+// traversal of Section 6.1.1 for queries without constants (with constants the
+// degree-driven traversal of Section 6.1.2 applies, as the paper prescribes).
+int build_plan(const NormQuery &q, const LabelStats *stats, bool domains, Plan &plan, std::string &msg,
+               bool direction = false);
 
 }  // namespace gs

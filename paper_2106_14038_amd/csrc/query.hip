@@ -87,6 +87,7 @@ struct EntryAcc {
     v0 = v1 = 0;
   }
 };
+
 // A step whose candidates face no test: every candidate entry becomes a child.
 __device__ __forceinline__ bool test_free(const DStep &S) { return step_test_free(S); }
 
@@ -102,6 +103,10 @@ __device__ __forceinline__ bool counted_only(const DStep &S) { return test_free(
 // whose new variable is bound by several edges reads its candidates from the
 // shortest of their segments and tests the others; all of them are sorted by
 // id, so the children and their order are the same whichever is read.
+// A factor level's per-node product of segment lengths is capped here (a tile of 1024
+// such products stays far below 2^63); a capped product fails the query with GS_ERANGE.
+constexpr int64_t kFactorCap = 1ll << 50;
+
 constexpr int kLoBits = 40;
 constexpr int kMaxGen = 63;
 __device__ __forceinline__ int64_t seg_ref(int64_t lo, int dir, int gen) {
@@ -109,7 +114,7 @@ __device__ __forceinline__ int64_t seg_ref(int64_t lo, int dir, int gen) {
 }
 __device__ __forceinline__ int64_t ref_lo(int64_t r) { return r & ((1ll << kLoBits) - 1); }
 __device__ __forceinline__ int ref_dir(int64_t r) { return (int)((r >> kLoBits) & 1); }
-__device__ __forceinline__ int ref_gen(int64_t r) { return (int)(r >> (kLoBits + 1)); }
+__device__ __forceinline__ int ref_gen(int64_t r) { return (int)((r >> (kLoBits + 1)) & kMaxGen); }
 
 static_assert(sizeof(EState) % sizeof(int64_t) == 0, "EState must be a whole number of int64");
 constexpr int64_t kEsStride = sizeof(EState) / sizeof(int64_t);
@@ -243,8 +248,10 @@ __global__ __launch_bounds__(kBlock) void k_list_count(const IterArgs A) {
   IterScalars *it = A.it;
   if (it->abort) return;
   EState *es = A.es;
+  const int64_t G = active_groups(it->list_tiles, gridDim.x);
+  if (blockIdx.x >= G) return;
   int64_t tb, te;
-  block_share(it->list_tiles, tb, te);
+  block_share_g(it->list_tiles, G, tb, te);
   int64_t bsum = 0;
   EntryAcc acc;
   int64_t *p_list_n = &es[0].list_n;
@@ -268,7 +275,8 @@ __global__ __launch_bounds__(1024) void k_list_scan(const IterArgs A) {
   IterScalars *it = A.it;
   if (it->abort) return;
   EState *es = A.es;
-  wg_scan(A.grid, [&](int64_t i) { return A.blk_a[i]; }, [&](int64_t i, int64_t v) { A.blk_off_a[i] = v; }, lds);
+  wg_scan(active_groups(it->list_tiles, A.grid), [&](int64_t i) { return A.blk_a[i]; },
+          [&](int64_t i, int64_t v) { A.blk_off_a[i] = v; }, lds);
   const int64_t total = wg_scan(A.E, [&](int64_t i) { return es[i].list_n; },
                                 [&](int64_t i, int64_t v) { es[i].list_base = v; }, lds);
   __shared__ int32_t *buf;
@@ -288,8 +296,10 @@ __global__ __launch_bounds__(kBlock) void k_list_write(const IterArgs A) {
   IterScalars *it = A.it;
   if (it->abort) return;
   EState *es = A.es;
+  const int64_t G = active_groups(it->list_tiles, gridDim.x);
+  if (blockIdx.x >= G) return;
   int64_t tb, te;
-  block_share(it->list_tiles, tb, te);
+  block_share_g(it->list_tiles, G, tb, te);
   int64_t run = A.blk_off_a[blockIdx.x];
   for (int64_t t = tb; t < te; ++t) {
     if (threadIdx.x == 0) sh_e = last_le(A.E, t, [&](int i) { return es[i].list_tile0; });
@@ -336,8 +346,10 @@ __global__ __launch_bounds__(kBlock) void k_dom_frontier(const IterArgs A) {
   IterScalars *it = A.it;
   if (it->abort || A.D == 0) return;
   EState *es = A.es;
+  const int64_t G = active_groups(it->node_tiles, gridDim.x);
+  if (blockIdx.x >= G) return;
   int64_t tb, te;
-  block_share(it->node_tiles, tb, te);
+  block_share_g(it->node_tiles, G, tb, te);
   NodeCursor ncur;
   for (int64_t t = tb; t < te; ++t) {
     if (threadIdx.x == 0) sh_e = ncur.at(A, t);
@@ -497,19 +509,23 @@ __device__ __forceinline__ bool const_checks_hold(const IterArgs &A, const DStep
   return true;
 }
 
-__global__ __launch_bounds__(kBlock) void k_lookup(const IterArgs A) {
-  __shared__ int64_t lds[2 * kWaves];
-  __shared__ int sh_e, sh_ok;
+template <int LB, int OB, bool FACTOR>
+__device__ __forceinline__ void lookup_body(const IterArgs &A, int64_t *lds, int &sh_e, int &sh_ok,
+                                            unsigned long long *s_cnt) {
   IterScalars *it = A.it;
   if (it->abort) return;
   EState *es = A.es;
+  const int64_t G = active_groups(it->node_tiles, gridDim.x);
+  if (blockIdx.x >= G) return;
   int64_t tb, te;
-  block_share(it->node_tiles, tb, te);
+  block_share_g(it->node_tiles, G, tb, te);
   NodeCursor ncur;
   int64_t bnz = 0, bw = 0;
-  EntryAcc acc, qacc;
+  EntryAcc acc;
+  // label entries read and segment lookups: per thread over a tile, then in LDS while the
+  // entry stays the same, then to the entry's query
+  int cur = -1;
   int64_t *p_nz = &es[0].nz, *p_w = &es[0].w;
-  int64_t *p_lab = A.qstats + QS_LABEL, *p_lk = A.qstats + QS_LOOKUP;
   for (int64_t t = tb; t < te; ++t) {
     if (threadIdx.x == 0) sh_e = ncur.at(A, t);
     __syncthreads();
@@ -521,38 +537,52 @@ __global__ __launch_bounds__(kBlock) void k_lookup(const IterArgs A) {
     const int64_t i0 = (t - sld(&es[e].node_tile0)) * kTileNodes, pn = sld(&es[e].prev_n);
     const int32_t *const eprev = sld(&es[e].prev);
     const int64_t enode0 = sld(&es[e].node0);
-    int64_t cnz = 0, cw = 0, clab = 0, clk = 0;
+    int64_t cnz = 0, cw = 0;
+    uint32_t cnt = 0;   // this thread's label entries read (bits 0-21) and lookups (22-31) in the tile
+    bool factor_over = false;
+    if (threadIdx.x == 0 && e != cur) {   // the previous entry's counters go to its query
+      if (cur >= 0 && (s_cnt[0] | s_cnt[1])) {
+        int64_t *qs = A.qstats + (int64_t)A.ent[cur].q * QS_N;
+        atomicAdd((unsigned long long *)&qs[QS_LABEL], s_cnt[0]);
+        atomicAdd((unsigned long long *)&qs[QS_LOOKUP], s_cnt[1]);
+      }
+      s_cnt[0] = s_cnt[1] = 0;
+    }
+    cur = e;
     const bool counted = counted_only(S);
     constexpr int RN = kTileNodes / kBlock;
     // the parent bindings, then their rows, of all of the thread's nodes first (independent loads)
     const int32_t *src = eprev + (int64_t)S.src * pn;
-    const int64_t *ptr = S.dir ? A.g.ptr[1] : A.g.ptr[0];
-    int64_t ra[RN], re[RN];
+    const void *ptr = S.dir ? A.g.ptr[1] : A.g.ptr[0];
+    using I = OffT<OB>;   // entry positions at the offsets' width
+    I ra[RN], re[RN];
     for (int r = 0; r < RN; ++r) {
       const int64_t i = i0 + r * kBlock + threadIdx.x;
       ra[r] = re[r] = 0;
       if (i < pn && S.kind != STEP_LIST) {
         const int32_t b = S.kind == STEP_SEG ? gld(src + i) : S.src;
-        ra[r] = gld(ptr + b);
-        re[r] = gld(ptr + b + 1);
+        ra[r] = off_w<OB>(ptr, b);
+        re[r] = off_w<OB>(ptr, (int64_t)b + 1);
       }
     }
     for (int r = 0; r < RN; ++r) {
       const int64_t i = i0 + r * kBlock + threadIdx.x;
       if (i >= pn) break;
-      int64_t lo = 0, hi = 0;
-      int probes = 0;
+      I lo = 0, hi = 0;
+      int probes = 0, lookups = 0;   // label entries read, segment lookups of this node
       int dir = S.dir, gen = 0;
       if (S.kind != STEP_LIST) {
-        label_range(S.dir ? A.g.lab[1] : A.g.lab[0], ra[r], re[r], S.label, lo, hi, probes);
-        const int64_t plo = lo, phi = hi;
-        int64_t c0lo = 0, c0hi = 0;
-        ++clk;
+        label_range_w<LB>(S.dir ? A.g.lab[1] : A.g.lab[0], ra[r], re[r], S.label, lo, hi, probes);
+        probes = label_reads(ra[r], re[r], lo, hi);
+        const I plo = lo, phi = hi;
+        I c0lo = 0, c0hi = 0;
+        ++lookups;
         for (int k = 0; k < min(S.nchk, kMaxGen) && hi > lo; ++k) {   // read the shortest bound segment
           const DCheck ck = A.checks[S.chk0 + k];
-          int64_t clo, chi;
-          ++clk;
-          seg_find(A.g, ck.dir, eprev[(int64_t)ck.col * pn + i], ck.label, clo, chi, probes);
+          I clo, chi;
+          ++lookups;
+          int unused = 0;
+          seg_find_w<LB, OB>(A.g, ck.dir, eprev[(int64_t)ck.col * pn + i], ck.label, clo, chi, unused);
           if (k == 0) { c0lo = clo; c0hi = chi; }
           if (chi - clo < hi - lo) { lo = clo; hi = chi; dir = ck.dir; gen = k + 1; }
         }
@@ -561,39 +591,71 @@ __global__ __launch_bounds__(kBlock) void k_lookup(const IterArgs A) {
           it->chk_lo[gn] = gen == 1 ? plo : c0lo;
           it->chk_hi[gn] = gen == 1 ? phi : c0hi;
         }
-        clab += probes;
       } else {
-        hi = es[e].list_n;
+        hi = (I)es[e].list_n;
       }
       if (!sh_ok) hi = lo;
       const int64_t gn = enode0 + i;
-      it->lo[gn] = seg_ref(lo, dir, gen);
-      it->len[gn] = counted ? 0 : hi - lo;   // a counted level's nodes take no part in the passes after the scan
       cnz += (hi > lo) && !counted;
-      cw += hi - lo;
+      int64_t len = hi - lo;
+      if (FACTOR && counted && S.nfactor > 0 && len > 0) {   // a factor level: times the further leaves' segments
+        for (int k = 0; k < S.nfactor && len > 0; ++k) {
+          const DCheck ck = A.checks[S.chk0 + k];
+          I clo, chi;
+          ++lookups;
+          seg_find_w<LB, OB>(A.g, ck.dir, eprev[(int64_t)ck.col * pn + i], ck.label, clo, chi, probes);
+          const int64_t f = (int64_t)chi - clo;
+          if (f > 0 && len > kFactorCap / f) { len = kFactorCap; factor_over = true; }
+          else len *= f;
+        }
+      }
+      it->lo[gn] = seg_ref(lo, dir, gen);
+      cnt += (uint32_t)probes + ((uint32_t)lookups << 22);
+      it->len[gn] = counted ? 0 : hi - lo;   // a counted level's nodes take no part in the passes after the scan
+      cw += len;
     }
-    {   // two reductions for four sums: entries above bit 11, non-empty nodes (at most kTileNodes)
-        // below; label entries read above bit 24, segment lookups (at most 64 per node) below
-      int64_t pk = (cw << 11) | cnz, pl = (clab << 24) | clk;
-      block_sum2_i64(pk, pl, lds);
-      cnz = pk & 2047;
-      cw = pk >> 11;
-      clk = pl & ((1 << 24) - 1);
-      clab = pl >> 24;
+    {   // one reduction for both: entries above bit 11, non-empty nodes (at most kTileNodes) below;
+        // a counted level has no non-empty nodes: its sums go unshifted (a factor level's products)
+      const int64_t pk = block_sum_i64(counted ? cw : (cw << 11) | cnz, lds);
+      cnz = counted ? 0 : pk & 2047;
+      cw = counted ? pk : pk >> 11;
+      if (threadIdx.x == 0) acc.add(e, cnz, cw, p_nz, p_w, kEsStride);
     }
-    if (threadIdx.x == 0) {
-      acc.add(e, cnz, cw, p_nz, p_w, kEsStride);
-      qacc.add(d.q, clab, clk, p_lab, p_lk, QS_N);
+    {   // the wave's sums (DPP scan, the total in lane 63), one LDS add each per wave
+      const int64_t wsum = wave_incl_scan_i64(((int64_t)(cnt >> 22) << 32) | (cnt & ((1u << 22) - 1)));
+      if ((threadIdx.x & 63) == 63 && wsum) {
+        atomicAdd(&s_cnt[0], (unsigned long long)(wsum & 0xffffffffll));
+        atomicAdd(&s_cnt[1], (unsigned long long)(wsum >> 32));
+      }
     }
+    if (factor_over) A.qstats[(int64_t)d.q * QS_N + QS_OVERFLOW] = 3;
     bnz += cnz;
     bw += counted ? 0 : cw;
   }
+  __syncthreads();
   if (threadIdx.x == 0) {
     acc.flush(p_nz, p_w, kEsStride);
-    qacc.flush(p_lab, p_lk, QS_N);
+    if (cur >= 0 && (s_cnt[0] | s_cnt[1])) {
+      int64_t *qs = A.qstats + (int64_t)A.ent[cur].q * QS_N;
+      atomicAdd((unsigned long long *)&qs[QS_LABEL], s_cnt[0]);
+      atomicAdd((unsigned long long *)&qs[QS_LOOKUP], s_cnt[1]);
+    }
     A.blk_a[blockIdx.x] = bnz;
     A.blk_b[blockIdx.x] = bw;
   }
+}
+
+// FACTOR: the launch holds a count-only factor level (its own variant: the product loop
+// costs registers that every other level would pay for in occupancy)
+// One instance per stored width pair (labels LB bytes, offsets OB bytes), chosen on the host:
+// each carries only its own width's code, and so only its own register count.
+template <int LB, int OB, bool FACTOR>
+__global__ __launch_bounds__(kBlock) void k_lookup(const IterArgs A) {
+  __shared__ int64_t lds[kWaves];
+  __shared__ int sh_e, sh_ok;
+  __shared__ unsigned long long s_cnt[2];
+  if (threadIdx.x == 0) s_cnt[0] = s_cnt[1] = 0;
+  lookup_body<LB, OB, FACTOR>(A, lds, sh_e, sh_ok, s_cnt);
 }
 
 // Allocate the tree level of entry e (es[e].cnt children) in the tree arena and
@@ -635,8 +697,9 @@ __global__ __launch_bounds__(1024) void k_scan_nodes(const IterArgs A) {
   IterScalars *it = A.it;
   if (it->abort) return;
   EState *es = A.es;
-  wg_scan(A.grid, [&](int64_t i) { return A.blk_a[i]; }, [&](int64_t i, int64_t v) { A.blk_off_a[i] = v; }, lds);
-  wg_scan(A.grid, [&](int64_t i) { return A.blk_b[i]; }, [&](int64_t i, int64_t v) { A.blk_off_b[i] = v; }, lds);
+  const int64_t G = active_groups(it->node_tiles, A.grid);
+  wg_scan(G, [&](int64_t i) { return A.blk_a[i]; }, [&](int64_t i, int64_t v) { A.blk_off_a[i] = v; }, lds);
+  wg_scan(G, [&](int64_t i) { return A.blk_b[i]; }, [&](int64_t i, int64_t v) { A.blk_off_b[i] = v; }, lds);
   const int64_t nz = wg_scan(A.E, [&](int64_t i) { return es[i].nz; }, [&](int64_t i, int64_t v) { es[i].nz_base = v; }, lds);
   // entry offsets and the block offsets above leave out counted levels, as the node lengths do
   const int64_t w = wg_scan(A.E, [&](int64_t i) { return counted_only(A.steps[A.ent[i].step]) ? (int64_t)0 : es[i].w; },
@@ -703,8 +766,10 @@ __global__ __launch_bounds__(kBlock) void k_nz_write(const IterArgs A) {
   IterScalars *it = A.it;
   if (it->abort) return;
   EState *es = A.es;
+  const int64_t G = active_groups(it->node_tiles, gridDim.x);
+  if (blockIdx.x >= G) return;
   int64_t tb, te;
-  block_share(it->node_tiles, tb, te);
+  block_share_g(it->node_tiles, G, tb, te);
   NodeCursor ncur;
   int64_t run_nz = A.blk_off_a[blockIdx.x], run_w = A.blk_off_b[blockIdx.x];
   for (int64_t t = tb; t < te; ++t) {
@@ -719,7 +784,10 @@ __global__ __launch_bounds__(kBlock) void k_nz_write(const IterArgs A) {
     int nzc = 0;
     for (int k = 0; k < NPT; ++k) {
       len[k] = lo[k] = 0;
-      if (i0 + k < pn) { len[k] = gld(it->len + n0 + i0 + k); lo[k] = gld(it->lo + n0 + i0 + k); }
+      if (i0 + k < pn) {
+        len[k] = gld(it->len + n0 + i0 + k);
+        lo[k] = gld(it->lo + n0 + i0 + k);
+      }
       nzc += len[k] > 0;
       ws += len[k];
     }
@@ -890,6 +958,7 @@ __device__ __forceinline__ int32_t candidate(const IterArgs &A, const EState &E,
 // check is replaced by the parent edge's.
 // clo/chi: bounds of the first tested segment (found by the lookup), searched
 // directly; the others are located by row and label first.
+template <int LB, int OB>
 __device__ __forceinline__ bool test_candidate(const IterArgs &A, const EState &E, const DStep &S, int32_t node,
                                                int gen, int64_t clo, int64_t chi, int32_t c, int &probes, int &ftests,
                                                int &ctests) {
@@ -922,10 +991,10 @@ __device__ __forceinline__ bool test_candidate(const IterArgs &A, const EState &
       label = ck.label;
       dir = ck.dir;
     }
-    if (!seg_has(A.g, dir, b, label, c, probes)) return false;
+    if (!seg_has_w<LB, OB>(A.g, dir, b, label, c, probes)) return false;
   }
   for (int k = 0; k < S.nself; ++k)
-    if (!seg_has(A.g, 0, c, A.ints[S.self0 + k], c, probes)) return false;
+    if (!seg_has_w<LB, OB>(A.g, 0, c, A.ints[S.self0 + k], c, probes)) return false;
   return true;
 }
 
@@ -933,9 +1002,8 @@ __device__ __forceinline__ bool test_candidate(const IterArgs &A, const EState &
 // entries per tile, per entry and per workgroup. A workgroup takes a
 // contiguous tile range; test-free entries in it are passed over whole, the
 // tiles of tested entries are dealt to its waves.
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_expand_count(const IterArgs A) {
-  __shared__ WaveTile Wt[kWaves];
-  __shared__ int64_t red4[kWaves][4];
+template <int LB, int OB>
+__device__ __forceinline__ void expand_count_body(const IterArgs &A, WaveTile *Wt, int64_t (*red4)[4]) {
   IterScalars *it = A.it;
   if (it->abort) return;
   EState *es = A.es;
@@ -943,8 +1011,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
   WaveTile &W = Wt[wv];
   for (int i = lane; i < kTileWork; i += 64) W.kmap[i] = 0;
   wave_lds_sync();
+  const int64_t G = active_groups(it->work_tiles, gridDim.x);
+  if (blockIdx.x >= G) return;
   int64_t tb, te;
-  block_share(it->work_tiles, tb, te);
+  block_share_g(it->work_tiles, G, tb, te);
   int64_t free_items = 0, w_cnt = 0, w_pr = 0, w_ft = 0, w_ct = 0;
   for (int64_t t = tb; t < te;) {
     const int e = uniform(gld(&it->tiles[t].e));
@@ -973,7 +1043,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
           const int32_t c = candidate(A, E, S, W, k, p);
           int64_t clo = 0, chi = 0;
           if (S.nchk > 0) { clo = gld(it->nz_chk_lo + dt.k0 + k); chi = gld(it->nz_chk_hi + dt.k0 + k); }
-          ok = test_candidate(A, E, S, W.node[k], W.dg[k] >> 1, clo, chi, c, pr, ft, ct);
+          ok = test_candidate<LB, OB>(A, E, S, W.node[k], W.dg[k] >> 1, clo, chi, c, pr, ft, ct);
         }
         const uint64_t bal = __ballot(ok);
         if (lane == 0) gst(vw + r, bal);
@@ -1008,12 +1078,19 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
   }
 }
 
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_expand_count(const IterArgs A) {
+  __shared__ WaveTile Wt[kWaves];
+  __shared__ int64_t red4[kWaves][4];
+  GS_WITH_WIDTHS(A.g, (expand_count_body<LB, OB>(A, Wt, red4)));
+}
+
 __global__ __launch_bounds__(1024) void k_scan_expand(const IterArgs A) {
   __shared__ int64_t lds[1024];
   IterScalars *it = A.it;
   if (it->abort) return;
   EState *es = A.es;
-  wg_scan(A.grid, [&](int64_t i) { return A.blk_a[i]; }, [&](int64_t i, int64_t v) { A.blk_off_a[i] = v; }, lds);
+  wg_scan(active_groups(it->work_tiles, A.grid), [&](int64_t i) { return A.blk_a[i]; },
+          [&](int64_t i, int64_t v) { A.blk_off_a[i] = v; }, lds);
   // the same sums as the tiles carry (levels counted without tiles take no positions)
   const int64_t tot = wg_scan(A.E, [&](int64_t i) { return counted_only(A.steps[A.ent[i].step]) ? (int64_t)0 : es[i].cnt; },
                               [&](int64_t i, int64_t v) { es[i].out_base = v; }, lds);
@@ -1035,8 +1112,10 @@ __global__ __launch_bounds__(kBlock) void k_tile_offsets(const IterArgs A) {
   IterScalars *it = A.it;
   if (it->abort) return;
   EState *es = A.es;
+  const int64_t G = active_groups(it->work_tiles, gridDim.x);
+  if (blockIdx.x >= G) return;
   int64_t tb, te;
-  block_share(it->work_tiles, tb, te);
+  block_share_g(it->work_tiles, G, tb, te);
   int64_t run = A.blk_off_a[blockIdx.x];
   for (int64_t c0 = tb; c0 < te; c0 += kBlock) {
     const int64_t t = c0 + threadIdx.x;
@@ -1253,7 +1332,19 @@ hipError_t launch_iteration(const IterArgs &A, hipStream_t s, hipEvent_t *ev) {
     GS_LAUNCH(KS_DOM_PUSH, k_dom_push, G, B);
     GS_LAUNCH(KS_DOM_PULL, k_dom_pull, G, B);
   }
-  GS_LAUNCH(KS_LOOKUP, k_lookup, G, B);
+  {
+    const int w = (A.g.lab8 ? 0 : 2) + (A.g.off32 ? 0 : 1) + (A.has_factor ? 4 : 0);
+    switch (w) {
+      case 0: GS_LAUNCH(KS_LOOKUP, (k_lookup<1, 4, false>), G, B); break;
+      case 1: GS_LAUNCH(KS_LOOKUP, (k_lookup<1, 8, false>), G, B); break;
+      case 2: GS_LAUNCH(KS_LOOKUP, (k_lookup<2, 4, false>), G, B); break;
+      case 3: GS_LAUNCH(KS_LOOKUP, (k_lookup<2, 8, false>), G, B); break;
+      case 4: GS_LAUNCH(KS_LOOKUP, (k_lookup<1, 4, true>), G, B); break;
+      case 5: GS_LAUNCH(KS_LOOKUP, (k_lookup<1, 8, true>), G, B); break;
+      case 6: GS_LAUNCH(KS_LOOKUP, (k_lookup<2, 4, true>), G, B); break;
+      default: GS_LAUNCH(KS_LOOKUP, (k_lookup<2, 8, true>), G, B); break;
+    }
+  }
   GS_LAUNCH(KS_SCAN_NODES, k_scan_nodes, dim3(1), W1);
   GS_LAUNCH(KS_NZ_WRITE, k_nz_write, G, B);
   if (A.has_tested) GS_LAUNCH(KS_EXPAND_COUNT, k_expand_count, G, B);

@@ -17,6 +17,7 @@ struct IterArgs {
   int32_t has_list;        // any LIST step among the entries
   int32_t has_tested;      // any entry whose candidates face a test (else no count and tile-offset passes)
   int32_t has_checks;      // any entry with exact checks (cycle-closing edges)
+  int32_t has_factor;      // any entry at a count-only factor level (the lookup variant that multiplies)
   int32_t grid;            // workgroups of the fixed-grid kernels
   int32_t wgrid;           // workgroups of the write pass (as many as are resident at once)
   const DStep *steps;

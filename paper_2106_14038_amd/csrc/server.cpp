@@ -265,6 +265,10 @@ hipError_t upload_slot(ServerImpl &S, Active *a, hipStream_t s) {
 int retire(ServerImpl &S, Active *a, int32_t *const *lp_all, int32_t *const *lc_all, const int64_t *qs_all,
            const int64_t *lvl_n_all, hipStream_t s) {
   Engine &E = *S.E;
+  if (qs_all[(size_t)a->slot * QS_N + QS_OVERFLOW] == 3) {
+    set_error("a node's product of leaf segments exceeds 2^50 (count-only factor)");
+    return GS_ERANGE;
+  }
   Result *R = new Result();
   R->eng = &E;
   hipError_t e = hipSuccess;
@@ -371,6 +375,7 @@ void loop(ServerImpl &S) {
       L.has_list |= one.has_list;
       L.has_tested |= one.has_tested;
       L.has_checks |= one.has_checks;
+      L.has_factor |= one.has_factor;
     }
     uint64_t wlo, whi;
     window(S, wlo, whi);
@@ -387,7 +392,7 @@ void loop(ServerImpl &S) {
     if (e == hipSuccess) e = hipMemcpyAsync(E.d_arenas, ar, sizeof(ar), hipMemcpyHostToDevice, s);
     IterArgs A{};
     A.g = E.g; A.ent = S.d_ents; A.E = (int32_t)L.ents.size(); A.S = (int32_t)L.seeds.size();
-    A.D = (int32_t)L.doms.size(); A.nclear = (int32_t)L.clears.size(); A.has_list = L.has_list; A.has_tested = L.has_tested; A.has_checks = L.has_checks; A.grid = E.grid; A.wgrid = E.wgrid;
+    A.D = (int32_t)L.doms.size(); A.nclear = (int32_t)L.clears.size(); A.has_list = L.has_list; A.has_tested = L.has_tested; A.has_checks = L.has_checks; A.has_factor = L.has_factor; A.grid = E.grid; A.wgrid = E.wgrid;
     A.steps = S.d_steps; A.filt = S.d_filt; A.checks = S.d_checks; A.ints = S.d_ints; A.cconst = S.d_cc;
     A.seeds = S.d_seeds; A.doms = S.d_doms; A.fcount = S.d_fc; A.clear = S.d_clear; A.es = S.d_es; A.it = S.d_it;
     A.lvl_ptr = S.d_lvlp; A.lvl_cptr = S.d_lvlc; A.lvl_n = S.d_lvln; A.qstats = S.d_qs;
@@ -419,7 +424,7 @@ void loop(ServerImpl &S) {
     // level pointers and counters of every slot, once, when some query finishes now
     bool finishing = false;
     for (Active *a : S.active)
-      if (lvl_n[(size_t)a->slot * kMaxLevels + a->level] >= 0 && !ar[1].overflow && a->level + 1 == a->qi.plan.n_vars)
+      if (lvl_n[(size_t)a->slot * kMaxLevels + a->level] >= 0 && !ar[1].overflow && a->level + 1 == a->qi.nlev)
         finishing = true;
     if (finishing) {
       e = hipMemcpyAsync(lp_all.data(), S.d_lvlp, sizeof(void *) * lp_all.size(), hipMemcpyDeviceToHost, s);
@@ -453,7 +458,7 @@ void loop(ServerImpl &S) {
         continue;
       }
       a->level++;
-      if (a->level == a->qi.plan.n_vars) {   // rows leave the ring now: the new level needs no reference
+      if (a->level == a->qi.nlev) {   // rows leave the ring now: the new level needs no reference
         const int rc = retire(S, a, lp_all.data(), lc_all.data(), qs_all.data(), lvl_n.data(), s);
         if (rc != GS_OK) finish(S, a->req.ticket, rc, nullptr);
         release(S, a);

@@ -128,3 +128,17 @@ def row_digest(rows, width):
         x ^= h
         n += 1
     return n, s, x
+
+
+def row_digest_np(rows):
+    """row_digest for an (n, k) int32 array, vectorised (same hash, uint64 arithmetic)."""
+    rows = np.asarray(rows)
+    n, k = rows.shape
+    with np.errstate(over="ignore"):
+        h = np.full(n, k, dtype=np.uint64)
+        for i in range(k):
+            z = h + np.uint64(0x9E3779B97F4A7C15) + rows[:, i].astype(np.uint32).astype(np.uint64)
+            z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+            z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+            h = z ^ (z >> np.uint64(31))
+        return n, int(h.sum(dtype=np.uint64)), int(np.bitwise_xor.reduce(h)) if n else 0

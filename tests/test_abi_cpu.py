@@ -48,6 +48,72 @@ def test_planner_example_6_2():
     assert info.parent_edge[0] == -1
 
 
+def test_planner_example_6_1_direction():
+    # Section 6.1.1, Example 6.1: roots v0 and v3, groups {v0v1, v0v2}, {v2v1}, {v3v2}
+    ex = json.load(open(os.path.join(GOLD, "query_example_7_2.json")))
+    q = ex["query"]
+    q = {"n_qv": q["n_qv"], "qv_const": q["qv_const"], "edges": [tuple(e) for e in q["edges"]]}
+    info = gs.gs_plan_query(q, traversal=gs.GS_TRAVERSAL_DIRECTION)
+    plan = ex["example_6_1_direction_roots"]
+    assert list(info.roots[:info.n_roots]) == plan["roots"]
+    groups = {}
+    for k, (a, _, b) in enumerate(q["edges"]):
+        groups.setdefault(info.edge_group[k], []).append([a, b])
+    assert [sorted(groups[g]) for g in sorted(groups)] == plan["groups"]
+    assert list(info.group_vertex[:info.n_groups]) == [0, 2, 3]
+    # a level reached by the traversal reads its edge along its direction (from the bound
+    # source); the further root v3 has an edge to v2, placed before it, and the single binding
+    # tree binds it through that edge, read against its direction
+    level = {v: j for j, v in enumerate(info.order[:info.n_vars])}
+    for j in range(info.n_vars):
+        pe = info.parent_edge[j]
+        v = info.order[j]
+        if v == plan["roots"][0]:
+            assert pe == -1
+            continue
+        a, _, b = q["edges"][pe]
+        if v in plan["roots"]:
+            assert a == v and level[b] < j
+        else:
+            assert b == v and level[a] < j
+
+
+def test_planner_direction_cycle_and_constants():
+    # a directed cycle has no vertex without incoming edges: the root is the one with the most
+    # outgoing edges (lowest index on ties); with a constant the degree-driven plan applies
+    cyc = {"n_qv": 3, "qv_const": [-1, -1, -1], "edges": [(0, 1, 1), (1, 1, 2), (2, 1, 0)]}
+    info = gs.gs_plan_query(cyc, traversal=gs.GS_TRAVERSAL_DIRECTION)
+    assert list(info.roots[:info.n_roots]) == [0] and list(info.group_vertex[:info.n_groups]) == [0, 1, 2]
+    cq = {"n_qv": 4, "qv_const": [-1, 5, -1, -1], "edges": [(0, 1, 1), (0, 2, 2), (2, 3, 3)]}
+    a = gs.gs_plan_query(cq, traversal=gs.GS_TRAVERSAL_DIRECTION)
+    b = gs.gs_plan_query(cq, traversal=gs.GS_TRAVERSAL_DEGREE)
+    assert list(a.order[:a.n_vars]) == list(b.order[:b.n_vars]) and list(a.roots[:1]) == list(b.roots[:1])
+
+
+def test_planner_direction_valid_on_random_queries():
+    rng = random.Random(5)
+    for _ in range(500):
+        nv = rng.randint(1, 8)
+        q = random_query(rng, 50, 5, nv, rng.randint(0, 1), connected=rng.random() < 0.7)
+        deg = [0] * q["n_qv"]
+        for a, _, b in q["edges"]:
+            deg[a] += 1
+            deg[b] += 1
+        if any(d == 0 and q["qv_const"][i] < 0 for i, d in enumerate(deg)):
+            continue
+        info = gs.gs_plan_query(q, traversal=gs.GS_TRAVERSAL_DIRECTION)
+        _check_plan_valid(q, info)
+        roots = list(info.roots[:info.n_roots])
+        level = {v: j for j, v in enumerate(info.order[:info.n_vars])}
+        for j in range(info.n_vars):
+            v, pe = info.order[j], info.parent_edge[j]
+            if pe < 0:   # bound by nothing earlier: no edge to an earlier level
+                assert all(not ((a == v and b in level and level[b] < j) or (b == v and a in level and level[a] < j))
+                           for a, _, b in q["edges"]), (q, j)
+            elif all(c < 0 for c in q["qv_const"]) and v not in roots:
+                assert q["edges"][pe][2] == v   # generating edges are read along their direction
+
+
 def test_planner_constants_first():
     # (?x p c) and (?x q ?y), (?y r ?z): the constant's edge is evaluated first and ?x is the root
     q = {"n_qv": 4, "qv_const": [-1, 5, -1, -1], "edges": [(0, 1, 1), (0, 2, 2), (2, 3, 3)]}

@@ -66,18 +66,32 @@ def test_graph_replays_match_eager():
         gs.gs_engine_destroy(graph)
 
 
-def test_autotune_keeps_results():
+def test_autotune_keeps_results_and_is_recorded(tmp_path):
+    """The tuned pair changes no result; it is recorded in the autotune cache for the
+    graph's sizes, and an engine loading a graph of those sizes starts from it."""
     trip = workload.c0_graph()
     n, P = workload.C0["n"], workload.C0["n_labels"]
     qs = workload.walk_queries(trip, n, 41, "triangle", 6) + workload.walk_queries(trip, n, 41, "star5", 6)
-    eng = gs.gs_engine_create(gs.options(tree_bytes=1 << 30, scratch_bytes=1 << 28))
+    cache = str(tmp_path / "tune.txt")
+    eng = gs.gs_engine_create(gs.options(tree_bytes=1 << 30, scratch_bytes=1 << 28, autotune_cache=cache.encode()))
     try:
         gs.gs_load_triples(eng, n, P, trip)
         before = batch_results(eng, qs)
         tr = gs.gs_autotune(eng, qs)
-        assert tr.n_tried == 12 and tr.best_ms <= tr.default_ms and tr.grid_blocks > 0
+        assert tr.n_tried == 15 and tr.best_ms <= tr.default_ms and tr.grid_blocks > 0
         after = batch_results(eng, qs)
         for (c0, r0), (c1, r1) in zip(before, after):
+            assert c0 == c1 and np.array_equal(r0, r1)
+        line = open(cache).read().split()
+        assert [int(x) for x in line[:4]] == [n, gs.gs_graph_info(eng)[2], P, tr.grid_blocks]
+        assert abs(float(line[4]) - tr.push_pull_theta) < 1e-6
+    finally:
+        gs.gs_engine_destroy(eng)
+    eng = gs.gs_engine_create(gs.options(tree_bytes=1 << 30, scratch_bytes=1 << 28, autotune_cache=cache.encode()))
+    try:
+        gs.gs_load_triples(eng, n, P, trip)
+        again = batch_results(eng, qs)
+        for (c0, r0), (c1, r1) in zip(before, again):
             assert c0 == c1 and np.array_equal(r0, r1)
     finally:
         gs.gs_engine_destroy(eng)

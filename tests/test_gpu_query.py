@@ -106,6 +106,153 @@ def test_random_tiny_graphs_vs_brute_force(seed):
             gs.gs_engine_destroy(e)
 
 
+@pytest.mark.parametrize("seed", range(2))
+def test_direction_driven_plans_vs_brute_force(seed):
+    """Section 6.1.1: the direction-driven traversal (several roots, generating edges read
+    along their direction) gives the rows of every assignment, as the degree-driven one."""
+    rng = random.Random(700 + seed)
+    for case in range(30):
+        n, P = rng.randint(2, 9), rng.randint(1, 3)
+        trip = workload.uniform_graph(rng.randrange(1 << 30), n, P, rng.randint(1, n * n * P))
+        e = make_engine(trip, n, P, traversal=gs.GS_TRAVERSAL_DIRECTION, domain_mode=rng.choice([0, 1, 2, 3]))
+        try:
+            for _ in range(4):
+                nv = rng.randint(2, 4)
+                q = random_query(rng, n, P, nv, 0, n_edges=rng.randint(nv - 1, nv + 2), connected=rng.random() < 0.8)
+                if has_isolated_var(q):
+                    continue
+                print(f"[direction] seed={seed} case={case} q={q}", flush=True)
+                bf = brute_force(trip, n, P, q)
+                cnt, rows = engine_rows(gs, e, q)
+                assert cnt == len(bf) and np.array_equal(rows.reshape(-1, nv), bf.reshape(-1, nv)), q
+        finally:
+            gs.gs_engine_destroy(e)
+
+
+def test_direction_driven_c0_walks(c0):
+    trip, n, P, G = c0
+    e = make_engine(trip, n, P, traversal=gs.GS_TRAVERSAL_DIRECTION)
+    try:
+        qs = []
+        for shape in ("chain4", "star5", "snowflake8", "triangle", "mixed"):
+            qs += workload.walk_queries(trip, n, 9, shape, 8, const_prob=0.0, max_consts=0)
+        for i, q in enumerate(qs):
+            ocnt = ocount(G, q, 50_000_000)
+            if ocnt < 0 or ocnt > 2_000_000:
+                continue
+            ocnt, orows = G.eval(q, rows_cap=ocnt + 1)
+            cnt, rows = engine_rows(gs, e, q)
+            assert cnt == ocnt and np.array_equal(rows, orows), (i, q)
+    finally:
+        gs.gs_engine_destroy(e)
+
+
+def _star_with_tail(rng, n, P, n_leaves, tail):
+    """A chain of `tail` edges from v0, then `n_leaves` leaves on its last vertex, each edge in
+    a random direction and label; with probability 1/4 a constant replaces v0."""
+    nv = 1 + tail + n_leaves
+    edges = []
+    for t in range(tail):
+        edges.append((t, rng.randint(1, P), t + 1) if rng.random() < 0.5 else (t + 1, rng.randint(1, P), t))
+    c = tail
+    for k in range(n_leaves):
+        w = tail + 1 + k
+        edges.append((c, rng.randint(1, P), w) if rng.random() < 0.5 else (w, rng.randint(1, P), c))
+    consts = [-1] * nv
+    if tail > 0 and rng.random() < 0.25:
+        consts[0] = rng.randrange(n)
+    return {"n_qv": nv, "qv_const": consts, "edges": edges}
+
+
+@pytest.mark.parametrize("seed", range(2))
+def test_count_only_factorised_vs_brute_force(seed):
+    """Count-only evaluation counts trailing independent leaves as a product of their segment
+    lengths (the per-path trees of Section 7.1, Example 7.1, in counting form): counts equal
+    brute force; the same queries with rows kept give the same count."""
+    rng = random.Random(900 + seed)
+    for case in range(25):
+        n, P = rng.randint(2, 8), rng.randint(1, 3)
+        trip = workload.uniform_graph(rng.randrange(1 << 30), n, P, rng.randint(1, n * n * P))
+        e = make_engine(trip, n, P)
+        try:
+            for _ in range(4):
+                q = _star_with_tail(rng, n, P, rng.randint(2, 4), rng.randint(0, 2))
+                print(f"[factor] seed={seed} case={case} q={q}", flush=True)
+                bf = brute_force(trip, n, P, q)
+                r = gs.gs_query_run(e, q, gs.GS_COUNT_ONLY)
+                try:
+                    assert gs.gs_result_count(r) == len(bf), q
+                finally:
+                    gs.gs_result_free(r)
+                cnt, _ = engine_rows(gs, e, q)
+                assert cnt == len(bf), q
+        finally:
+            gs.gs_engine_destroy(e)
+
+
+def test_count_only_factorised_power_law_stars():
+    """Stars (2 to 5 leaves, mixed directions and labels, some behind a one-edge tail) on a
+    small power-law graph with hubs, count-only, batched: equal to the oracle's message-passing
+    count, also far beyond what the tree arena could hold as rows; where a hub's product passes
+    2^50 the query fails with GS_ERANGE, and then the oracle's count is above 2^50 too."""
+    n, P = 20000, 4
+    trip = workload.chunglu_graph(5, n, P, 200_000, beta=2.0, zipf_s=1.1)
+    G = oracle.Graph(trip, n, P)
+    rng = random.Random(77)
+    qs, want = [], []
+    while len(qs) < 40:
+        k, tail = rng.randint(2, 5), rng.randint(0, 1)
+        q = _star_with_tail(rng, n, P, k, tail)
+        q["qv_const"] = [-1] * q["n_qv"]
+        try:
+            w = G.count_acyclic(q)
+        except OverflowError:
+            w = -1
+        qs.append(q)
+        want.append(w)
+    e = make_engine(trip, n, P, tree_bytes=64 << 20)
+    try:
+        big = 0
+        for i, q in enumerate(qs):
+            try:
+                r = gs.gs_query_run(e, q, gs.GS_COUNT_ONLY)
+            except gs.GsError as err:
+                assert err.status == gs.GS_ERANGE and (want[i] < 0 or want[i] > 1 << 50), (i, q, want[i])
+                continue
+            got = gs.gs_result_count(r)
+            gs.gs_result_free(r)
+            assert got == want[i], (i, q)
+            big += got > (64 << 20) // 4
+        assert big >= 5
+        ok = [i for i in range(len(qs)) if 0 <= want[i] <= 1 << 50]
+        rs = gs.gs_batch_run(e, [qs[i] for i in ok], gs.GS_COUNT_ONLY)
+        try:
+            assert [gs.gs_result_count(r) for r in rs] == [want[i] for i in ok]
+        finally:
+            for r in rs:
+                gs.gs_result_free(r)
+    finally:
+        gs.gs_engine_destroy(e)
+
+
+def test_count_only_factor_overflow_is_erange():
+    """A product beyond 2^50 per node is reported as GS_ERANGE, not as a wrong count."""
+    n = 40
+    trip = np.array([(0, 1, o) for o in range(n)], dtype=np.int32).reshape(-1)   # one hub, 40 objects
+    q = {"n_qv": 12, "qv_const": [-1] * 12, "edges": [(0, 1, k) for k in range(1, 12)]}   # 40^11 > 2^50
+    e = make_engine(trip, n, 1)
+    try:
+        with pytest.raises(gs.GsError) as err:
+            gs.gs_query_run(e, q, gs.GS_COUNT_ONLY)
+        assert err.value.status == gs.GS_ERANGE
+        q8 = {"n_qv": 9, "qv_const": [-1] * 9, "edges": [(0, 1, k) for k in range(1, 9)]}   # 40^8 < 2^50
+        r = gs.gs_query_run(e, q8, gs.GS_COUNT_ONLY)
+        assert gs.gs_result_count(r) == 40 ** 8
+        gs.gs_result_free(r)
+    finally:
+        gs.gs_engine_destroy(e)
+
+
 def test_constant_only_queries():
     trip = np.array([[0, 1, 1], [1, 2, 2], [2, 1, 2]], np.int32)
     e = make_engine(trip, 3, 2)
@@ -312,10 +459,12 @@ def test_scratch_overflow_in_a_middle_level_is_a_clean_enomem(scratch_mb):
     the engine answers the next query normally. With 8 MB the overflow comes in
     the iteration set-up of level 3 (16 B per parent node, 10^6 parents), with
     24 MB in the node pass's allocation (20 B per non-empty parent more), after
-    which test-free levels would otherwise have been published unwritten."""
+    which test-free levels would otherwise have been published unwritten. The
+    chain has six vertices: count-only evaluation counts its last two leaves as
+    a product without building them, and level 3 is still built in both modes."""
     n, P = 10_000, 1
     trip = workload.uniform_graph(3, n, P, 100_000)   # out-degree ~10: levels grow ~10x
-    chain = {"n_qv": 5, "qv_const": [-1] * 5, "edges": [(0, 1, 1), (1, 1, 2), (2, 1, 3), (3, 1, 4)]}
+    chain = {"n_qv": 6, "qv_const": [-1] * 6, "edges": [(0, 1, 1), (1, 1, 2), (2, 1, 3), (3, 1, 4), (4, 1, 5)]}
     small = {"n_qv": 2, "qv_const": [-1, -1], "edges": [(0, 1, 1)]}
     # levels 0-2 need a few MB of temporaries, level 3 (10^6 parents) tens of MB
     e = make_engine(trip, n, P, scratch_bytes=scratch_mb << 20, tree_bytes=1 << 30)
