@@ -170,6 +170,17 @@ void gs_engine_destroy(gs_engine *engine);
 gs_status gs_load_triples(gs_engine *engine, int64_t n_vertices, int32_t n_labels,
                           const gs_triple *triples, int64_t m, int mem_kind);
 
+/* One-shot load for one query (Section 6.2.1 and 6.2.2, step 1: only the
+ * triples whose predicate the query names): as gs_load_triples, but the
+ * triples whose predicate is not among labels[0, n_keep) (1-based) are
+ * dropped on the device before the matrix is built, so a query that reads
+ * only those predicates evaluates as on the whole dataset, with the device
+ * holding and sorting only its part. Every triple is still range-checked.
+ * Errors: as gs_load_triples; GS_ERANGE also for a label outside [1, n_labels]. */
+gs_status gs_load_triples_labels(gs_engine *engine, int64_t n_vertices, int32_t n_labels,
+                                 const gs_triple *triples, int64_t m, int mem_kind, const int32_t *labels,
+                                 int32_t n_keep);
+
 /* Sizes after loading: vertices, labels, distinct triples, device bytes held. */
 gs_status gs_graph_info(const gs_engine *engine, int64_t *n, int32_t *n_labels, int64_t *m_distinct,
                         uint64_t *device_bytes);
@@ -249,6 +260,84 @@ gs_status gs_plan_query(gs_engine *engine, const gs_query *query, gs_plan_info *
 /* As gs_plan_query with the traversal chosen explicitly (GS_TRAVERSAL_ENGINE:
  * the engine's option; degree-driven without an engine). */
 gs_status gs_plan_query_ex(gs_engine *engine, const gs_query *query, int32_t traversal, gs_plan_info *out);
+
+/* ---- per-query reduced matrix (Section 6.2.1, 6.2.2; Ex. 6.3, 6.4) ------------ */
+
+typedef struct gs_reduced gs_reduced;   /* device arrays of one query's reduced matrix */
+
+typedef struct {
+  int64_t n;                 /* vertices: M has n + 1 entries per part */
+  int64_t rows[2];           /* kept rows (part 0, row-wise) and kept columns (part 1, column-wise) */
+  int64_t nnz[2];            /* nonzeros of each part */
+  int32_t n_labels[2];       /* predicates each part keeps (0: the part is empty) */
+  int32_t labels[2][64];     /* those predicates, 1-based, ascending */
+} gs_reduced_info;
+
+/* The reduced matrix of one query, built on the device from the resident one.
+ * The predicates of each part follow the traversal's edge groups (see
+ * gs_plan_query_ex; traversal as there): with the direction-driven traversal
+ * and no constant, one row-wise part with every predicate of the query
+ * (Section 6.2.1); otherwise (Section 6.2.2) an edge evaluated in the group of
+ * its subject puts its predicate in the row-wise part and one evaluated in the
+ * group of its object in the column-wise part, an edge out of a constant in
+ * the row-wise part and an edge into a constant in the column-wise part. Each
+ * part keeps the nonzeros of its predicates, drops the rows (columns) left
+ * empty and numbers the kept ones in order. *out is freed with
+ * gs_reduced_free (its device memory comes from hipMalloc on the engine's
+ * device; it does not depend on the engine afterwards). Errors: GS_ESTATE (no
+ * data, or a server running), GS_EINVAL, GS_EUNSUPPORTED (more than 64
+ * predicates in a part), GS_ENOMEM, GS_EDEVICE. */
+gs_status gs_lspm_reduce(gs_engine *engine, const gs_query *query, int32_t traversal, gs_reduced **out);
+
+gs_status gs_reduced_get_info(const gs_reduced *reduced, gs_reduced_info *out);
+
+/* Copy part `part` (0 row-wise, 1 column-wise) to host buffers: M (n + 1
+ * int64: M[i + 1] - M[i] == 1 exactly when row i is kept, and then M[i] is
+ * its index among the kept rows), P (rows + 1 int64 offsets into val / idx per
+ * kept row), val (nnz int32, the 1-based predicates) and idx (nnz int32, the
+ * other endpoint: column for part 0, row for part 1); a kept row's entries in
+ * ascending (predicate, endpoint) order. Any pointer may be NULL to skip that
+ * array. Errors: GS_EINVAL, GS_EDEVICE. */
+gs_status gs_reduced_export(const gs_reduced *reduced, int32_t part, int64_t *M, int64_t *P, int32_t *val,
+                            int32_t *idx);
+
+/* Release the reduced matrix. NULL is ignored. */
+gs_status gs_reduced_free(gs_reduced *reduced);
+
+/* ---- N-Triples dictionary encoding (Section 6.2.1, step 2) ------------------- */
+
+typedef struct gs_dict gs_dict;   /* integer triples and the dictionaries that decode them */
+
+/* Encode N-Triples text (len bytes, lines separated by LF or CRLF; blank lines
+ * and # comments skipped): each line "subject predicate object ." becomes one
+ * int32 triple. Subjects and objects share one dictionary numbered from 0,
+ * predicates have their own numbered from 1, each in order of first
+ * appearance (a line's subject before its object). A term is keyed by its
+ * bytes as written: an IRI <...>, a blank node _:label (ASCII letters, digits,
+ * "_" and "-"), a literal "..." with its escapes and an optional @tag (ASCII
+ * letters, digits and "-") or ^^<datatype>. Repeated lines stay repeated (the
+ * loaders remove repeats). The text is copied. Errors: GS_EINVAL (malformed
+ * line; the message names it), GS_ERANGE (more than 2^31 vertices), GS_ENOMEM. */
+gs_status gs_encode_ntriples(const char *text, int64_t len, gs_dict **out);
+
+/* Sizes: triples (lines), distinct subjects and objects, distinct predicates. */
+gs_status gs_dict_info(const gs_dict *dict, int64_t *n_triples, int64_t *n_vertices, int32_t *n_labels);
+
+/* The triples, n_triples * 3 int32 (s, p, o) into host memory, in line order. */
+gs_status gs_dict_triples(const gs_dict *dict, int32_t *out);
+
+/* The term of a vertex id / 1-based predicate: *len gets its length; up to
+ * cap - 1 bytes and a terminating zero go to buf (buf may be NULL to ask for
+ * the length). Errors: GS_ERANGE. */
+gs_status gs_dict_vertex(const gs_dict *dict, int64_t id, char *buf, int64_t cap, int64_t *len);
+gs_status gs_dict_label(const gs_dict *dict, int32_t label, char *buf, int64_t cap, int64_t *len);
+
+/* Ids of a term: *id = -1 (*label = 0) when the text has no such term. */
+gs_status gs_dict_find_vertex(const gs_dict *dict, const char *term, int64_t len, int64_t *id);
+gs_status gs_dict_find_label(const gs_dict *dict, const char *term, int64_t len, int32_t *label);
+
+/* Release the dictionary. NULL is ignored. */
+gs_status gs_dict_free(gs_dict *dict);
 
 /* ---- plain and batched evaluation ------------------------------------------- */
 

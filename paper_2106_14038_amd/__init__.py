@@ -77,6 +77,11 @@ class gs_plan_info(ctypes.Structure):
                 ("edge_group", ctypes.c_int32 * 64), ("n_roots", ctypes.c_int32), ("roots", ctypes.c_int32 * 64)]
 
 
+class gs_reduced_info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("rows", ctypes.c_int64 * 2), ("nnz", ctypes.c_int64 * 2),
+                ("n_labels", ctypes.c_int32 * 2), ("labels", (ctypes.c_int32 * 64) * 2)]
+
+
 class gs_kernel_stat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char_p), ("launches", ctypes.c_int64), ("ms", ctypes.c_double),
                 ("bytes_alg", ctypes.c_double), ("bytes_impl", ctypes.c_double)]
@@ -103,6 +108,19 @@ SIGNATURES = {
     "gs_engine_create": ([_P(gs_options), _P(_vp)], ctypes.c_int),
     "gs_engine_destroy": ([_vp], None),
     "gs_load_triples": ([_vp, _i64, _i32, _vp, _i64, ctypes.c_int], ctypes.c_int),
+    "gs_load_triples_labels": ([_vp, _i64, _i32, _vp, _i64, ctypes.c_int, _vp, _i32], ctypes.c_int),
+    "gs_lspm_reduce": ([_vp, _P(gs_query), _i32, _P(_vp)], ctypes.c_int),
+    "gs_reduced_get_info": ([_vp, _P(gs_reduced_info)], ctypes.c_int),
+    "gs_reduced_export": ([_vp, _i32, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "gs_reduced_free": ([_vp], ctypes.c_int),
+    "gs_encode_ntriples": ([ctypes.c_char_p, _i64, _P(_vp)], ctypes.c_int),
+    "gs_dict_info": ([_vp, _P(_i64), _P(_i64), _P(_i32)], ctypes.c_int),
+    "gs_dict_triples": ([_vp, _vp], ctypes.c_int),
+    "gs_dict_vertex": ([_vp, _i64, ctypes.c_char_p, _i64, _P(_i64)], ctypes.c_int),
+    "gs_dict_label": ([_vp, _i32, ctypes.c_char_p, _i64, _P(_i64)], ctypes.c_int),
+    "gs_dict_find_vertex": ([_vp, ctypes.c_char_p, _i64, _P(_i64)], ctypes.c_int),
+    "gs_dict_find_label": ([_vp, ctypes.c_char_p, _i64, _P(_i32)], ctypes.c_int),
+    "gs_dict_free": ([_vp], ctypes.c_int),
     "gs_graph_info": ([_vp, _P(_i64), _P(_i32), _P(_i64), _P(_u64)], ctypes.c_int),
     "gs_lspm_export": ([_vp, ctypes.c_int, _vp, _vp, _vp], ctypes.c_int),
     "gs_label_stats": ([_vp, _vp, _vp, _vp], ctypes.c_int),
@@ -218,6 +236,99 @@ def gs_lspm_export(engine, orientation: int):
     lab = np.zeros(max(m, 1), np.int32)
     _check(lib().gs_lspm_export(engine, orientation, ptr.ctypes.data, idx.ctypes.data, lab.ctypes.data))
     return ptr, idx[:m], lab[:m]
+
+
+def query_labels(q: dict) -> list:
+    """The predicates (1-based) a query names: what gs_load_triples_labels keeps for it."""
+    return sorted({int(p) for _, p, _ in q["edges"]})
+
+
+def gs_load_triples_labels(engine, n_vertices: int, n_labels: int, triples, labels):
+    """gs_load_triples keeping only the triples whose predicate is in `labels` (1-based)."""
+    keep = np.ascontiguousarray(labels, dtype=np.int32)
+    if hasattr(triples, "data_ptr") and getattr(triples, "is_cuda", False):
+        t = triples.contiguous()
+        _check(lib().gs_load_triples_labels(engine, n_vertices, n_labels, ctypes.c_void_p(t.data_ptr()),
+                                            t.numel() // 3, GS_MEM_DEVICE, keep.ctypes.data, len(keep)))
+        return
+    a = np.ascontiguousarray(triples, dtype=np.int32).reshape(-1, 3)
+    _check(lib().gs_load_triples_labels(engine, n_vertices, n_labels, a.ctypes.data_as(ctypes.c_void_p), len(a),
+                                        GS_MEM_HOST, keep.ctypes.data, len(keep)))
+
+
+def gs_lspm_reduce(engine, q: dict, traversal: int = GS_TRAVERSAL_ENGINE):
+    """The query's reduced matrix: a dict with its info and, per part (0 row-wise, 1
+    column-wise), the arrays M, P, val, idx (host copies)."""
+    h = ctypes.c_void_p()
+    _check(lib().gs_lspm_reduce(engine, ctypes.byref(make_query(q)), traversal, ctypes.byref(h)))
+    try:
+        info = gs_reduced_info()
+        _check(lib().gs_reduced_get_info(h, ctypes.byref(info)))
+        out = {"n": info.n, "parts": []}
+        for o in range(2):
+            rows, nnz = info.rows[o], info.nnz[o]
+            M = np.zeros(info.n + 1, np.int64)
+            P = np.zeros(rows + 1, np.int64)
+            val = np.zeros(max(nnz, 1), np.int32)
+            idx = np.zeros(max(nnz, 1), np.int32)
+            _check(lib().gs_reduced_export(h, o, M.ctypes.data, P.ctypes.data, val.ctypes.data, idx.ctypes.data))
+            out["parts"].append({"labels": list(info.labels[o][:info.n_labels[o]]), "rows": rows, "nnz": nnz,
+                                 "M": M, "P": P, "val": val[:nnz], "idx": idx[:nnz]})
+        return out
+    finally:
+        lib().gs_reduced_free(h)
+
+
+class NTriplesDict:
+    """Integer triples and dictionaries of N-Triples text (gs_encode_ntriples)."""
+
+    def __init__(self, text):
+        data = text.encode("utf-8") if isinstance(text, str) else bytes(text)
+        self._h = ctypes.c_void_p()
+        self._lib = lib()
+        _check(self._lib.gs_encode_ntriples(data, len(data), ctypes.byref(self._h)))
+        nt, nv, nl = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+        _check(self._lib.gs_dict_info(self._h, ctypes.byref(nt), ctypes.byref(nv), ctypes.byref(nl)))
+        self.n_triples, self.n_vertices, self.n_labels = nt.value, nv.value, nl.value
+
+    def triples(self) -> np.ndarray:
+        out = np.zeros((self.n_triples, 3), np.int32)
+        _check(self._lib.gs_dict_triples(self._h, out.ctypes.data))
+        return out
+
+    def _term(self, f, key) -> str:
+        n = ctypes.c_int64()
+        _check(f(self._h, key, None, 0, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value + 1)
+        _check(f(self._h, key, buf, n.value + 1, ctypes.byref(n)))
+        return buf.raw[:n.value].decode("utf-8")
+
+    def vertex(self, i: int) -> str:
+        return self._term(self._lib.gs_dict_vertex, i)
+
+    def label(self, p: int) -> str:
+        return self._term(self._lib.gs_dict_label, p)
+
+    def find_vertex(self, term: str) -> int:
+        b = term.encode("utf-8")
+        out = ctypes.c_int64()
+        _check(self._lib.gs_dict_find_vertex(self._h, b, len(b), ctypes.byref(out)))
+        return out.value
+
+    def find_label(self, term: str) -> int:
+        b = term.encode("utf-8")
+        out = ctypes.c_int32()
+        _check(self._lib.gs_dict_find_label(self._h, b, len(b), ctypes.byref(out)))
+        return out.value
+
+    def __del__(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.gs_dict_free(self._h)
+            self._h = ctypes.c_void_p()
+
+
+def gs_encode_ntriples(text) -> NTriplesDict:
+    return NTriplesDict(text)
 
 
 def gs_label_stats(engine):

@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 OUT = os.path.join(PKG, "libgsmart.so")
-SOURCES = ["lspm.hip", "query.hip", "engine.cpp", "planner.cpp", "capi.cpp", "server.cpp"]
+SOURCES = ["lspm.hip", "query.hip", "engine.cpp", "planner.cpp", "capi.cpp", "server.cpp", "ntriples.cpp"]
 ARCH = os.environ.get("GS_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
          "-packed-fp32-ops", "-I", os.path.join(ROOT, "include"), "-I", HERE, "-Wall", "-Wno-unused-function",

@@ -9,6 +9,7 @@
 
 #include "engine.hpp"
 #include "gsmart.h"
+#include "lspm.hpp"
 #include "query.hpp"
 
 namespace gs {
@@ -194,6 +195,17 @@ gs_status gs_load_triples(gs_engine *engine, int64_t n_vertices, int32_t n_label
     }
   }
   return (gs_status)rc;
+}
+
+gs_status gs_load_triples_labels(gs_engine *engine, int64_t n_vertices, int32_t n_labels, const gs_triple *triples,
+                                 int64_t m, int mem_kind, const int32_t *labels, int32_t n_keep) {
+  if (!engine) { set_error("null engine"); return GS_EINVAL; }
+  if (mem_kind != GS_MEM_HOST && mem_kind != GS_MEM_DEVICE) { set_error("bad mem_kind"); return GS_EINVAL; }
+  if (n_keep < 0 || (n_keep > 0 && !labels)) { set_error("bad label list"); return GS_EINVAL; }
+  std::lock_guard<std::mutex> lk(engine->e.mu);
+  static const int32_t none = 0;
+  return (gs_status)load_triples(engine->e, n_vertices, n_labels, triples, m, mem_kind, n_keep ? labels : &none,
+                                 n_keep);
 }
 
 gs_status gs_graph_info(const gs_engine *engine, int64_t *n, int32_t *n_labels, int64_t *m_distinct,
@@ -426,6 +438,144 @@ gs_status gs_plan_query_ex(gs_engine *engine, const gs_query *query, int32_t tra
     out->edge_group[k] = q.edge_first[k] ? P.edge_group[q.edge_map[k]] : -1;
   out->n_roots = (int32_t)std::min<size_t>(P.roots.size(), 64);
   for (int r = 0; r < out->n_roots; ++r) out->roots[r] = P.roots[r];
+  return GS_OK;
+}
+
+// ---- per-query reduced matrix
+}  // extern "C"
+
+struct gs_reduced {
+  int device = 0;
+  int64_t n = 0, rows[2] = {0, 0}, nnz[2] = {0, 0};
+  std::vector<int32_t> labels[2];   // 1-based, ascending
+  int64_t *M[2] = {nullptr, nullptr}, *P[2] = {nullptr, nullptr};
+  int32_t *val[2] = {nullptr, nullptr}, *idx[2] = {nullptr, nullptr};
+  ~gs_reduced() {
+    for (int o = 0; o < 2; ++o) {
+      (void)hipFree(M[o]);
+      (void)hipFree(P[o]);
+      (void)hipFree(val[o]);
+      (void)hipFree(idx[o]);
+    }
+  }
+};
+
+extern "C" {
+
+gs_status gs_lspm_reduce(gs_engine *engine, const gs_query *query, int32_t traversal, gs_reduced **out) {
+  if (!engine || !query || !out) { set_error("null argument"); return GS_EINVAL; }
+  *out = nullptr;
+  Engine &E = engine->e;
+  if (!E.loaded) { set_error("no dataset loaded"); return GS_ESTATE; }
+  // the traversal's edge groups (Section 6.1), then each edge's part (Section 6.2.1 / 6.2.2)
+  gs_plan_info info;
+  gs_status rc = gs_plan_query_ex(engine, query, traversal, &info);
+  if (rc != GS_OK) return rc;
+  if (query->n_edges > 64) { set_error("more than 64 query edges"); return GS_EUNSUPPORTED; }
+  const int32_t trav = traversal == GS_TRAVERSAL_ENGINE ? E.opt.traversal : traversal;
+  bool has_const = false;
+  for (int v = 0; v < query->n_qv; ++v) has_const |= query->qv_const[v] >= 0;
+  std::vector<int32_t> part_labels[2];
+  auto add = [&](int o, int32_t p) {
+    if (std::find(part_labels[o].begin(), part_labels[o].end(), p) == part_labels[o].end()) part_labels[o].push_back(p);
+  };
+  for (int k = 0; k < query->n_edges; ++k) {
+    const gs_edge &e = query->edges[k];
+    if (trav == GS_TRAVERSAL_DIRECTION && !has_const) { add(0, e.label); continue; }
+    const bool cs = query->qv_const[e.src] >= 0, co = query->qv_const[e.dst] >= 0;
+    if (cs || co) {   // out of a constant: row-wise; into a constant: column-wise
+      if (cs) add(0, e.label);
+      if (co) add(1, e.label);
+      continue;
+    }
+    const int g = info.edge_group[k];
+    if (g < 0) continue;   // a repeated edge: evaluated with its first copy
+    add(info.group_vertex[g] == e.src ? 0 : 1, e.label);
+  }
+  std::lock_guard<std::mutex> lk(E.mu);
+  if (E.serving) { set_error("a server is running on this engine"); return GS_ESTATE; }
+  HIPRET(hipSetDevice(E.device));
+  hipStream_t s = E.stream;
+  gs_reduced *r = new (std::nothrow) gs_reduced;
+  if (!r) { set_error("out of host memory"); return GS_ENOMEM; }
+  r->device = E.device;
+  r->n = E.g.n;
+  const int64_t n = E.g.n;
+  struct Tmp {
+    std::vector<void *> p;
+    ~Tmp() { for (void *x : p) (void)hipFree(x); }
+    void *get(size_t b) { void *x = nullptr; if (hipMalloc(&x, b) != hipSuccess) return nullptr; p.push_back(x); return x; }
+  } tmp;
+  auto fail = [&](gs_status st, const std::string &msg) { delete r; set_error(msg); return st; };
+  for (int o = 0; o < 2; ++o) {
+    std::sort(part_labels[o].begin(), part_labels[o].end());
+    r->labels[o] = part_labels[o];
+    if ((int)part_labels[o].size() > 64) return fail(GS_EUNSUPPORTED, "more than 64 predicates in a part");
+    if (hipMalloc((void **)&r->M[o], 8 * (size_t)(n + 1)) != hipSuccess) return fail(GS_ENOMEM, "out of device memory");
+    const int nk = (int)part_labels[o].size();
+    if (nk == 0) {   // an empty part: no kept row
+      if (hipMemsetAsync(r->M[o], 0, 8 * (size_t)(n + 1), s) != hipSuccess) return fail(GS_EDEVICE, "memset");
+      if (hipMalloc((void **)&r->P[o], 8) != hipSuccess) return fail(GS_ENOMEM, "out of device memory");
+      if (hipMemsetAsync(r->P[o], 0, 8, s) != hipSuccess) return fail(GS_EDEVICE, "memset");
+      continue;
+    }
+    std::vector<int32_t> k0(part_labels[o]);
+    for (int32_t &x : k0) x -= 1;   // stored 0-based
+    int32_t *klab = (int32_t *)tmp.get(4 * 64);
+    uint32_t *cnt = (uint32_t *)tmp.get(4 * (size_t)n), *ne = (uint32_t *)tmp.get(4 * (size_t)n);
+    int64_t *pos = (int64_t *)tmp.get(8 * (size_t)(n + 1)), *parts = (int64_t *)tmp.get(8 * 256);
+    if (!klab || !cnt || !ne || !pos || !parts) return fail(GS_ENOMEM, "out of device memory");
+    if (hipMemcpyAsync(klab, k0.data(), 4 * k0.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+        reduce_count(E.g, o, klab, nk, cnt, ne, pos, r->M[o], parts, s) != hipSuccess)
+      return fail(GS_EDEVICE, "reduction count pass failed");
+    int64_t tot[2] = {0, 0};
+    if (hipMemcpyAsync(&tot[0], pos + n, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(&tot[1], r->M[o] + n, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return fail(GS_EDEVICE, "reduction sizes");
+    r->nnz[o] = tot[0];
+    r->rows[o] = tot[1];
+    if (hipMalloc((void **)&r->P[o], 8 * (size_t)(tot[1] + 1)) != hipSuccess ||
+        hipMalloc((void **)&r->val[o], 4 * (size_t)std::max<int64_t>(tot[0], 1)) != hipSuccess ||
+        hipMalloc((void **)&r->idx[o], 4 * (size_t)std::max<int64_t>(tot[0], 1)) != hipSuccess)
+      return fail(GS_ENOMEM, "out of device memory for the reduced matrix");
+    if (reduce_write(E.g, o, klab, nk, cnt, pos, r->M[o], r->P[o], r->val[o], r->idx[o], s) != hipSuccess ||
+        hipMemcpyAsync(r->P[o] + tot[1], &r->nnz[o], 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return fail(GS_EDEVICE, "reduction write pass failed");
+  }
+  *out = r;
+  return GS_OK;
+}
+
+gs_status gs_reduced_get_info(const gs_reduced *r, gs_reduced_info *out) {
+  if (!r || !out) { set_error("null argument"); return GS_EINVAL; }
+  memset(out, 0, sizeof *out);
+  out->n = r->n;
+  for (int o = 0; o < 2; ++o) {
+    out->rows[o] = r->rows[o];
+    out->nnz[o] = r->nnz[o];
+    out->n_labels[o] = (int32_t)r->labels[o].size();
+    for (size_t k = 0; k < r->labels[o].size() && k < 64; ++k) out->labels[o][k] = r->labels[o][k];
+  }
+  return GS_OK;
+}
+
+gs_status gs_reduced_export(const gs_reduced *r, int32_t part, int64_t *M, int64_t *P, int32_t *val, int32_t *idx) {
+  if (!r || part < 0 || part > 1) { set_error("bad argument"); return GS_EINVAL; }
+  HIPRET(hipSetDevice(r->device));
+  if (M) HIPRET(hipMemcpy(M, r->M[part], 8 * (size_t)(r->n + 1), hipMemcpyDeviceToHost));
+  if (P) HIPRET(hipMemcpy(P, r->P[part], 8 * (size_t)(r->rows[part] + 1), hipMemcpyDeviceToHost));
+  if (val && r->nnz[part]) HIPRET(hipMemcpy(val, r->val[part], 4 * (size_t)r->nnz[part], hipMemcpyDeviceToHost));
+  if (idx && r->nnz[part]) HIPRET(hipMemcpy(idx, r->idx[part], 4 * (size_t)r->nnz[part], hipMemcpyDeviceToHost));
+  return GS_OK;
+}
+
+gs_status gs_reduced_free(gs_reduced *r) {
+  if (r) {
+    (void)hipSetDevice(r->device);
+    delete r;
+  }
   return GS_OK;
 }
 

@@ -91,7 +91,8 @@ static hipError_t alloc_orientation(void *vctx, int orient, int64_t m2, LspmOut 
   return hipSuccess;
 }
 
-int load_triples(Engine &E, int64_t n, int32_t P, const gs_triple *t, int64_t m, int mem_kind) {
+int load_triples(Engine &E, int64_t n, int32_t P, const gs_triple *t, int64_t m, int mem_kind, const int32_t *keep,
+                 int32_t n_keep) {
   if (E.loaded) { set_error("dataset already loaded"); return GS_ESTATE; }
   if (n <= 0 || n > 2147483647LL) { set_error("vertex count must be in [1, 2^31-1]"); return GS_ERANGE; }
   if (P <= 0 || P > 65536) { set_error("label count must be in [1, 65536]"); return GS_ERANGE; }
@@ -115,11 +116,38 @@ int load_triples(Engine &E, int64_t n, int32_t P, const gs_triple *t, int64_t m,
     if (e != hipSuccess) { release(); set_error(hipGetErrorString(e)); return GS_EDEVICE; }
     d_trip = d;
   }
+  if (keep && m > 0) {   // only the listed predicates (Section 6.2.1 / 6.2.2, step 1)
+    std::vector<uint32_t> km((size_t)P / 32 + 2, 0u);
+    for (int32_t k = 0; k < n_keep; ++k) {
+      if (keep[k] < 1 || keep[k] > P) { release(); set_error("a kept label is outside [1, n_labels]"); return GS_ERANGE; }
+      km[(size_t)keep[k] >> 5] |= 1u << (keep[k] & 31);
+    }
+    uint32_t *d_keep = (uint32_t *)take(4 * km.size());
+    int64_t *parts = (int64_t *)take(8 * (size_t)G + 64);
+    int32_t *ferr = (int32_t *)take(64);
+    if (!d_keep || !parts || !ferr) { release(); set_error("out of device memory while loading"); return GS_ENOMEM; }
+    HIPCHK(hipMemcpyAsync(d_keep, km.data(), 4 * km.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemsetAsync(ferr, 0, 4, s));
+    int64_t *d_kept = parts + G;
+    HIPCHK(filter_triples(d_trip, m, n, P, d_keep, parts, G, d_kept, ferr, nullptr, s));
+    int64_t kept = 0;
+    int32_t bad = 0;
+    HIPCHK(hipMemcpyAsync(&kept, d_kept, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&bad, ferr, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (bad) { release(); set_error("a triple has s/o outside [0, n) or p outside [1, P]"); return GS_ERANGE; }
+    int32_t *d_f = (int32_t *)take(sizeof(gs_triple) * (size_t)std::max<int64_t>(kept, 1));
+    if (!d_f) { release(); set_error("out of device memory for the kept triples"); return GS_ENOMEM; }
+    HIPCHK(filter_triples(d_trip, m, n, P, d_keep, parts, G, d_kept, ferr, d_f, s));
+    d_trip = d_f;
+    m = kept;
+  }
+  const int64_t mk = std::max<int64_t>(m, 1);
   LspmBuildArgs a{};
   a.triples = d_trip; a.m = m; a.n = n; a.P = P; a.grid = G; a.stream = s;
-  a.hi0 = (uint64_t *)take(8 * mm); a.hi1 = (uint64_t *)take(8 * mm);
-  a.lo0 = (uint32_t *)take(4 * mm); a.lo1 = (uint32_t *)take(4 * mm);
-  a.row = (int32_t *)take(4 * mm);
+  a.hi0 = (uint64_t *)take(8 * mk); a.hi1 = (uint64_t *)take(8 * mk);
+  a.lo0 = (uint32_t *)take(4 * mk); a.lo1 = (uint32_t *)take(4 * mk);
+  a.row = (int32_t *)take(4 * mk);
   a.hist = (uint32_t *)take(4 * 256 * (size_t)G);
   a.off = (int64_t *)take(8 * 256 * (size_t)G);
   a.blk = (int64_t *)take(8 * (size_t)G);
@@ -385,7 +413,7 @@ void compile_query(const Engine &E, QInfo &qi, bool count_only, int slot, Tables
 // Work lists of one iteration: query qs[i] produces its level `level[i]`.
 void build_iteration(const Tables &T, const std::vector<const QInfo *> &qs, const std::vector<int> &level,
                      IterLists &L) {
-  L.ents.clear(); L.doms.clear(); L.clears.clear(); L.seeds.clear(); L.has_list = 0; L.has_tested = 0; L.has_checks = 0; L.has_factor = 0;
+  L.ents.clear(); L.doms.clear(); L.clears.clear(); L.seeds.clear(); L.has_list = 0; L.has_tested = 0; L.has_checks = 0; L.has_factor = 0; L.has_exact = 0;
   for (size_t i = 0; i < qs.size(); ++i) {
     const QInfo &qi = *qs[i];
     const int t = level[i];
@@ -406,6 +434,7 @@ void build_iteration(const Tables &T, const std::vector<const QInfo *> &qs, cons
       const bool filtered = ps.kind == STEP_LIST ? false : !ps.filters.empty();
       if (filtered || !ps.checks.empty() || !ps.self_labels.empty()) L.has_tested = 1;
       if (!ps.checks.empty()) L.has_checks = 1;
+      if (!ps.checks.empty() || !ps.self_labels.empty()) L.has_exact = 1;
     }
     L.ents.push_back(e);
   }
@@ -431,17 +460,24 @@ void account_iteration(Engine &E, const hipEvent_t *ev, const IterScalars &I, co
       case KS_EXPAND_COUNT: {  // tested levels only: ids, staged node records, filter words, parent bindings,
         const double Wt = (double)I.w_tested;   // probes, valid bits
         b = 4 * Wt + 20 * nz * (W > 0 ? Wt / W : 0) + 8.0 * I.ftests + 4.0 * I.ctests + 4.0 * I.probes + Wt / 8;
+        // the method's own: each candidate id of a tested level read once, the filter words it tests,
+        // the entries the exact checks' searches read
+        alg = 4 * Wt + 8.0 * I.ftests + 4.0 * I.probes;
         break;
       }
       case KS_EXPAND_WRITE:   // valid bits, staged node records, candidate ids + copies read + columns written;
-                              // the method's own bytes: a candidate id read per entry, a tree node (parent,
+                              // the method's own bytes: a candidate id read per entry of an untested level
+                              // (a tested level's were read by the count pass) and a tree node (parent,
                               // vertex) written per child
         b = W / 8 + 20 * nz + write_bytes;
-        alg = 4 * W + 8 * children;
+        alg = 4 * (W - (double)I.w_tested) + 8 * children;
         break;
       case KS_LOOKUP:         // parent binding, offset pair, segment written (the lookups of cycle-closing
-                              // segments at cyclic levels are not counted)
-        b = 36.0 * I.nodes_total; break;
+                              // segments at cyclic levels are not counted); the method's own: a tree node
+                              // read per parent, the label entries and offset pairs of the segment lookups
+        b = 36.0 * I.nodes_total;
+        alg = 8.0 * I.nodes_total + (double)E.lab_bytes * I.lk_labels + 2.0 * E.off_bytes * I.lk_lookups;
+        break;
       case KS_NZ_WRITE:
         b = 16.0 * I.nodes_total + 20 * nz; break;
       default: break;
@@ -572,6 +608,7 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
     A.has_tested = its[t].has_tested;
     A.has_checks = its[t].has_checks;
     A.has_factor = its[t].has_factor;
+    A.has_exact = its[t].has_exact;
     A.grid = E.grid;
     A.wgrid = E.wgrid;
     A.steps = (const DStep *)dp(tab_off + o_steps);

@@ -134,6 +134,7 @@ struct IterLists {                   // host work lists of one iteration
   int32_t has_tested = 0;
   int32_t has_checks = 0;
   int32_t has_factor = 0;
+  int32_t has_exact = 0;
 };
 
 int plan_query(const Engine &E, const gs_query &q, QInfo &qi, std::string &msg);
@@ -151,7 +152,9 @@ hipError_t launch_const_only(const DevGraph &g, const DConst *cc, int n, int64_t
 
 // Plan-compile-run a batch; results appended to out (one per query).
 int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector<Result *> &out, double *ms);
-int load_triples(Engine &E, int64_t n, int32_t P, const gs_triple *t, int64_t m, int mem_kind);
+// keep / n_keep: when keep is not NULL, only the triples whose (1-based) predicate is listed
+int load_triples(Engine &E, int64_t n, int32_t P, const gs_triple *t, int64_t m, int mem_kind,
+                 const int32_t *keep = nullptr, int32_t n_keep = 0);
 int result_rows(Result &R, int64_t first, int64_t n, void *dst, int mem_kind, int64_t *written);
 int result_prune(Result &R);
 int result_digest(Result &R, uint64_t *hsum, uint64_t *hxor);

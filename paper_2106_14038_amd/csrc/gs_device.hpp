@@ -134,6 +134,9 @@ struct IterScalars {
   int64_t ctests;          // exact checks started (each reads one parent binding)
   int64_t probes;          // label / id entries touched by binary searches
   int64_t w_tested;        // candidate entries of levels that test their candidates
+  // work counters of the node pass
+  int64_t lk_labels;       // label entries read while locating label sub-segments
+  int64_t lk_lookups;      // segment lookups (offset pairs read)
 };
 
 // Kernel slots of one iteration, for optional event timing.

@@ -159,13 +159,61 @@ __device__ int64_t wg_scan(int64_t L, Get get, Set set, int64_t *lds) {
   }
   __syncthreads();
   int64_t run = off + inc - s;
-  for (int64_t i = b; i < e; ++i) {
-    const int64_t v = get(i);
-    set(i, run);
-    run += v;
+  if (per == 1) {   // one element per thread: its value is s, no second read
+    if (b < e) set(b, run);
+  } else {
+    for (int64_t i = b; i < e; ++i) {
+      const int64_t v = get(i);
+      set(i, run);
+      run += v;
+    }
   }
   __syncthreads();
   return total;
+}
+
+// K exclusive scans of the same length at once (one pass, one exchange through LDS): get(i, v)
+// fills v[0..K) for element i, set(i, off) receives the K offsets. lds holds K * kWaves-of-
+// the-workgroup entries. The totals go to total[0..K).
+template <int K, class Get, class Set>
+__device__ void wg_scan_k(int64_t L, Get get, Set set, int64_t *lds, int64_t (&total)[K]) {
+  const int t = threadIdx.x, T = blockDim.x;
+  const int lane = t & 63, w = t >> 6, nw = T >> 6;
+  const int64_t per = (L + T - 1) / T;
+  const int64_t b = min(L, (int64_t)t * per), e = min(L, b + per);
+  int64_t s[K], v[K], run[K];
+  for (int k = 0; k < K; ++k) s[k] = 0;
+  for (int64_t i = b; i < e; ++i) {
+    get(i, v);
+    for (int k = 0; k < K; ++k) s[k] += v[k];
+  }
+  for (int k = 0; k < K; ++k) {
+    const int64_t inc = wave_incl_scan_i64(s[k]);
+    if (lane == 63) lds[k * nw + w] = inc;
+    run[k] = inc - s[k];
+  }
+  __syncthreads();
+  for (int k = 0; k < K; ++k) {
+    int64_t off = 0, tot = 0;
+    for (int i = 0; i < nw; ++i) {
+      const int64_t c = lds[k * nw + i];
+      if (i < w) off += c;
+      tot += c;
+    }
+    run[k] += off;
+    total[k] = tot;
+  }
+  __syncthreads();
+  if (per == 1) {   // one element per thread: no second read
+    if (b < e) set(b, run);
+  } else {
+    for (int64_t i = b; i < e; ++i) {
+      get(i, v);
+      set(i, run);
+      for (int k = 0; k < K; ++k) run[k] += v[k];
+    }
+  }
+  __syncthreads();
 }
 
 // Block g of gridDim.x takes the contiguous share [lo, hi) of [0, total).

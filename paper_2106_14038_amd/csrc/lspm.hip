@@ -336,4 +336,165 @@ hipError_t lspm_build_orientation(const LspmBuildArgs &a, int orient, LspmOut &o
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ query-driven load
+// Step 1 of Section 6.2.1 / 6.2.2: only the triples whose predicate the query
+// names. Per-workgroup counts over contiguous chunks, one scan of the counts,
+// then each chunk writes its kept triples in input order from its offset.
+// keep: bit p for the 1-based predicate p. Ids and labels are range-checked.
+__device__ __forceinline__ bool triple_ok(int32_t s, int32_t p, int32_t o, int64_t n, int32_t P) {
+  return s >= 0 && s < n && o >= 0 && o < n && p >= 1 && p <= P;
+}
+
+__global__ __launch_bounds__(kBlock) void k_filter_count(const int32_t *trip, int64_t m, int64_t n, int32_t P,
+                                                         const uint32_t *keep, int64_t *parts, int32_t *err) {
+  __shared__ int64_t lds[kWaves];
+  int64_t b, e;
+  block_share(m, b, e);
+  int64_t c = 0;
+  bool bad = false;
+  for (int64_t i = b + threadIdx.x; i < e; i += kBlock) {
+    const int32_t s = trip[3 * i], p = trip[3 * i + 1], o = trip[3 * i + 2];
+    if (!triple_ok(s, p, o, n, P)) { bad = true; continue; }
+    c += (keep[p >> 5] >> (p & 31)) & 1u;
+  }
+  if (bad) atomicOr(err, 1);
+  c = block_sum_i64(c, lds);
+  if (threadIdx.x == 0) parts[blockIdx.x] = c;
+}
+
+__global__ __launch_bounds__(kBlock) void k_filter_write(const int32_t *trip, int64_t m, int64_t n, int32_t P,
+                                                         const uint32_t *keep, const int64_t *parts, int32_t *out) {
+  __shared__ int64_t lds[kWaves];
+  int64_t b, e;
+  block_share(m, b, e);
+  int64_t run = parts[blockIdx.x];
+  for (int64_t c0 = b; c0 < e; c0 += kBlock) {
+    const int64_t i = c0 + threadIdx.x;
+    int32_t s = 0, p = 0, o = 0;
+    bool k = false;
+    if (i < e) {
+      s = trip[3 * i];
+      p = trip[3 * i + 1];
+      o = trip[3 * i + 2];
+      k = triple_ok(s, p, o, n, P) && ((keep[p >> 5] >> (p & 31)) & 1u);
+    }
+    int64_t tot;
+    const int64_t x = block_excl_scan_i64(k ? 1 : 0, tot, lds);
+    if (k) {
+      int32_t *w = out + 3 * (run + x);
+      w[0] = s;
+      w[1] = p;
+      w[2] = o;
+    }
+    run += tot;
+  }
+}
+
+hipError_t filter_triples(const int32_t *trip, int64_t m, int64_t n, int32_t P, const uint32_t *keep,
+                          int64_t *parts, int G, int64_t *total, int32_t *err, int32_t *out_or_null,
+                          hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  if (!out_or_null) {   // counting pass: parts scanned in place, the kept count into *total
+    hipLaunchKernelGGL(k_filter_count, dim3(G), dim3(kBlock), 0, s, trip, m, n, P, keep, parts, err);
+    hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(1024), 0, s, parts, (int64_t)G, parts, total);
+  } else {
+    hipLaunchKernelGGL(k_filter_write, dim3(G), dim3(kBlock), 0, s, trip, m, n, P, keep, (const int64_t *)parts,
+                       out_or_null);
+  }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ per-query reduction
+// One part of the reduced matrix (Section 6.2.1 step 3-4, Section 6.2.2 steps
+// 3-5; Ex. 6.3, 6.4) from the resident one: the entries of each row (column)
+// whose label is kept, rows left empty dropped. Rows are sorted by (label, id),
+// so a row's kept entries are the sub-segments of the kept labels, which are
+// taken in ascending order. klab: kept 0-based labels, ascending (at most 64).
+template <int LB, int OB>
+__global__ __launch_bounds__(kBlock) void k_red_count(const DevGraph g, int dir, const int32_t *klab, int nk,
+                                                      uint32_t *cnt, uint32_t *nonempty) {
+  __shared__ int32_t sk[64];
+  if (threadIdx.x < nk) sk[threadIdx.x] = klab[threadIdx.x];
+  __syncthreads();
+  const void *ptr = dir ? g.ptr[1] : g.ptr[0];
+  const void *lab = dir ? g.lab[1] : g.lab[0];
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < g.n; i += (int64_t)gridDim.x * kBlock) {
+    const OffT<OB> a = off_w<OB>(ptr, i), e = off_w<OB>(ptr, i + 1);
+    int64_t c = 0;
+    for (int k = 0; k < nk && a < e; ++k) {
+      OffT<OB> lo, hi;
+      int unused = 0;
+      label_range_w<LB>(lab, a, e, sk[k], lo, hi, unused);
+      c += hi - lo;
+    }
+    cnt[i] = (uint32_t)c;
+    nonempty[i] = c > 0 ? 1u : 0u;
+  }
+}
+
+template <int LB, int OB>
+__global__ __launch_bounds__(kBlock) void k_red_write(const DevGraph g, int dir, const int32_t *klab, int nk,
+                                                      const uint32_t *cnt, const int64_t *pos, const int64_t *M,
+                                                      int64_t *P, int32_t *val, int32_t *idx) {
+  __shared__ int32_t sk[64];
+  if (threadIdx.x < nk) sk[threadIdx.x] = klab[threadIdx.x];
+  __syncthreads();
+  const void *ptr = dir ? g.ptr[1] : g.ptr[0];
+  const void *lab = dir ? g.lab[1] : g.lab[0];
+  const int32_t *ids = dir ? g.idx[1] : g.idx[0];
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < g.n; i += (int64_t)gridDim.x * kBlock) {
+    if (cnt[i] == 0) continue;
+    int64_t w = pos[i];
+    P[M[i]] = w;
+    const OffT<OB> a = off_w<OB>(ptr, i), e = off_w<OB>(ptr, i + 1);
+    for (int k = 0; k < nk; ++k) {
+      OffT<OB> lo, hi;
+      int unused = 0;
+      label_range_w<LB>(lab, a, e, sk[k], lo, hi, unused);
+      for (OffT<OB> x = lo; x < hi; ++x, ++w) {
+        val[w] = sk[k] + 1;
+        idx[w] = ids[x];
+      }
+    }
+  }
+}
+
+// Exclusive scan of L uint32 values into out[0, L) and the total into out[L].
+static hipError_t scan_u32(const uint32_t *in, int64_t L, int64_t *out, int64_t *parts, hipStream_t s) {
+  const int np = 256;
+  hipLaunchKernelGGL(k_scan_parts, dim3(np), dim3(kBlock), 0, s, in, L, parts);
+  hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(1024), 0, s, parts, (int64_t)np, parts, out + L);
+  hipLaunchKernelGGL(k_scan_apply, dim3(np), dim3(kBlock), 0, s, in, L, (const int64_t *)parts, out);
+  return hipGetLastError();
+}
+
+template <int LB, int OB>
+static void launch_red_count(int G, hipStream_t s, const DevGraph &g, int dir, const int32_t *klab, int nk,
+                             uint32_t *cnt, uint32_t *nonempty) {
+  hipLaunchKernelGGL((k_red_count<LB, OB>), dim3(G), dim3(kBlock), 0, s, g, dir, klab, nk, cnt, nonempty);
+}
+
+template <int LB, int OB>
+static void launch_red_write(int G, hipStream_t s, const DevGraph &g, int dir, const int32_t *klab, int nk,
+                             const uint32_t *cnt, const int64_t *pos, const int64_t *M, int64_t *P, int32_t *val,
+                             int32_t *idx) {
+  hipLaunchKernelGGL((k_red_write<LB, OB>), dim3(G), dim3(kBlock), 0, s, g, dir, klab, nk, cnt, pos, M, P, val, idx);
+}
+
+hipError_t reduce_count(const DevGraph &g, int dir, const int32_t *klab, int nk, uint32_t *cnt, uint32_t *nonempty,
+                        int64_t *pos, int64_t *M, int64_t *parts, hipStream_t s) {
+  const int G = grid_for(g.n, 4096);
+  GS_WITH_WIDTHS(g, (launch_red_count<LB, OB>(G, s, g, dir, klab, nk, cnt, nonempty)));
+  hipError_t e = scan_u32(cnt, g.n, pos, parts, s);
+  if (e != hipSuccess) return e;
+  return scan_u32(nonempty, g.n, M, parts, s);
+}
+
+hipError_t reduce_write(const DevGraph &g, int dir, const int32_t *klab, int nk, const uint32_t *cnt,
+                        const int64_t *pos, const int64_t *M, int64_t *P, int32_t *val, int32_t *idx, hipStream_t s) {
+  const int G = grid_for(g.n, 4096);
+  GS_WITH_WIDTHS(g, (launch_red_write<LB, OB>(G, s, g, dir, klab, nk, cnt, pos, M, P, val, idx)));
+  return hipGetLastError();
+}
+
 }  // namespace gs

@@ -4,6 +4,8 @@
 
 #include <cstdint>
 
+#include "gs_device.hpp"
+
 namespace gs {
 
 struct LspmOut {            // one orientation, allocated by the caller once the distinct count is known
@@ -41,5 +43,21 @@ hipError_t fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s);
 hipError_t narrow_offsets(const int64_t *in, int32_t *out, int64_t n, hipStream_t s);
 hipError_t narrow_labels(const uint16_t *in, uint8_t *out, int64_t n, hipStream_t s);
 hipError_t scan_i64(const int64_t *in, int64_t L, int64_t *out, int64_t *total, hipStream_t s);
+
+// Triples whose predicate has its bit set in keep, in input order. With out NULL: counts per
+// workgroup of a grid of G into parts (G int64, scanned in place) and the kept count into
+// *total, with *err set on a triple out of range; with out: writes the kept triples.
+hipError_t filter_triples(const int32_t *trip, int64_t m, int64_t n, int32_t P, const uint32_t *keep,
+                          int64_t *parts, int G, int64_t *total, int32_t *err, int32_t *out_or_null,
+                          hipStream_t s);
+
+// Per-query reduced matrix, one part (dir 0 row-wise, 1 column-wise) over the kept 0-based labels
+// klab[0, nk) (device, ascending, nk <= 64): counts and non-empty flags per row, their exclusive
+// scans pos and M (n + 1 int64 each, the totals at index n; parts: 256 int64 of scratch), then
+// the kept rows' offsets P[M[i]] and their entries (val 1-based labels, idx the other endpoint).
+hipError_t reduce_count(const DevGraph &g, int dir, const int32_t *klab, int nk, uint32_t *cnt, uint32_t *nonempty,
+                        int64_t *pos, int64_t *M, int64_t *parts, hipStream_t s);
+hipError_t reduce_write(const DevGraph &g, int dir, const int32_t *klab, int nk, const uint32_t *cnt,
+                        const int64_t *pos, const int64_t *M, int64_t *P, int32_t *val, int32_t *idx, hipStream_t s);
 
 }  // namespace gs

@@ -140,6 +140,8 @@ __global__ __launch_bounds__(1024) void k_it_setup(const IterArgs A) {
     it->ftests = 0;
     it->ctests = 0;
     it->probes = 0;
+    it->lk_labels = 0;
+    it->lk_lookups = 0;
   }
   if (dead) return;
   for (int e = threadIdx.x; e < A.E; e += blockDim.x) {
@@ -159,12 +161,18 @@ __global__ __launch_bounds__(1024) void k_it_setup(const IterArgs A) {
   }
   for (int d = threadIdx.x; d < A.D; d += blockDim.x) A.fcount[d] = 0;
   __syncthreads();
-  const int64_t nodes = wg_scan(A.E, [&](int64_t i) { return es[i].prev_n; },
-                                [&](int64_t i, int64_t v) { es[i].node0 = v; }, lds);
-  const int64_t ntiles = wg_scan(A.E, [&](int64_t i) { return ceil_div(es[i].prev_n, kTileNodes); },
-                                 [&](int64_t i, int64_t v) { es[i].node_tile0 = v; }, lds);
-  const int64_t ltiles = wg_scan(A.E, [&](int64_t i) { return ceil_div(es[i].list_words, kTileWords); },
-                                 [&](int64_t i, int64_t v) { es[i].list_tile0 = v; }, lds);
+  int64_t tot3[3];   // nodes, node tiles, list tiles
+  wg_scan_k<3>(
+      A.E,
+      [&](int64_t i, int64_t *v) {
+        const int64_t pn = es[i].prev_n;
+        v[0] = pn;
+        v[1] = ceil_div(pn, kTileNodes);
+        v[2] = ceil_div(es[i].list_words, kTileWords);
+      },
+      [&](int64_t i, const int64_t *o) { es[i].node0 = o[0]; es[i].node_tile0 = o[1]; es[i].list_tile0 = o[2]; },
+      lds, tot3);
+  const int64_t nodes = tot3[0], ntiles = tot3[1], ltiles = tot3[2];
   if (threadIdx.x == 0) {
     it->nodes_total = nodes;
     it->node_tiles = ntiles;
@@ -545,6 +553,8 @@ __device__ __forceinline__ void lookup_body(const IterArgs &A, int64_t *lds, int
         int64_t *qs = A.qstats + (int64_t)A.ent[cur].q * QS_N;
         atomicAdd((unsigned long long *)&qs[QS_LABEL], s_cnt[0]);
         atomicAdd((unsigned long long *)&qs[QS_LOOKUP], s_cnt[1]);
+        s_cnt[2] += s_cnt[0];
+        s_cnt[3] += s_cnt[1];
       }
       s_cnt[0] = s_cnt[1] = 0;
     }
@@ -555,14 +565,16 @@ __device__ __forceinline__ void lookup_body(const IterArgs &A, int64_t *lds, int
     const int32_t *src = eprev + (int64_t)S.src * pn;
     const void *ptr = S.dir ? A.g.ptr[1] : A.g.ptr[0];
     using I = OffT<OB>;   // entry positions at the offsets' width
-    I ra[RN], re[RN];
+    I ra[RN];             // row starts, and row lengths (a row holds fewer than 2^31 entries)
+    int32_t rn[RN];
     for (int r = 0; r < RN; ++r) {
       const int64_t i = i0 + r * kBlock + threadIdx.x;
-      ra[r] = re[r] = 0;
+      ra[r] = 0;
+      rn[r] = 0;
       if (i < pn && S.kind != STEP_LIST) {
         const int32_t b = S.kind == STEP_SEG ? gld(src + i) : S.src;
         ra[r] = off_w<OB>(ptr, b);
-        re[r] = off_w<OB>(ptr, (int64_t)b + 1);
+        rn[r] = (int32_t)(off_w<OB>(ptr, (int64_t)b + 1) - ra[r]);
       }
     }
     for (int r = 0; r < RN; ++r) {
@@ -572,8 +584,9 @@ __device__ __forceinline__ void lookup_body(const IterArgs &A, int64_t *lds, int
       int probes = 0, lookups = 0;   // label entries read, segment lookups of this node
       int dir = S.dir, gen = 0;
       if (S.kind != STEP_LIST) {
-        label_range_w<LB>(S.dir ? A.g.lab[1] : A.g.lab[0], ra[r], re[r], S.label, lo, hi, probes);
-        probes = label_reads(ra[r], re[r], lo, hi);
+        const I re = ra[r] + rn[r];
+        label_range_w<LB>(S.dir ? A.g.lab[1] : A.g.lab[0], ra[r], re, S.label, lo, hi, probes);
+        probes = label_reads(ra[r], re, lo, hi);
         const I plo = lo, phi = hi;
         I c0lo = 0, c0hi = 0;
         ++lookups;
@@ -640,6 +653,9 @@ __device__ __forceinline__ void lookup_body(const IterArgs &A, int64_t *lds, int
       atomicAdd((unsigned long long *)&qs[QS_LABEL], s_cnt[0]);
       atomicAdd((unsigned long long *)&qs[QS_LOOKUP], s_cnt[1]);
     }
+    // the launch's totals, for per-kernel byte accounting
+    if (s_cnt[0] + s_cnt[2]) atomicAdd((unsigned long long *)&it->lk_labels, s_cnt[0] + s_cnt[2]);
+    if (s_cnt[1] + s_cnt[3]) atomicAdd((unsigned long long *)&it->lk_lookups, s_cnt[1] + s_cnt[3]);
     A.blk_a[blockIdx.x] = bnz;
     A.blk_b[blockIdx.x] = bw;
   }
@@ -653,8 +669,8 @@ template <int LB, int OB, bool FACTOR>
 __global__ __launch_bounds__(kBlock) void k_lookup(const IterArgs A) {
   __shared__ int64_t lds[kWaves];
   __shared__ int sh_e, sh_ok;
-  __shared__ unsigned long long s_cnt[2];
-  if (threadIdx.x == 0) s_cnt[0] = s_cnt[1] = 0;
+  __shared__ unsigned long long s_cnt[4];   // this entry's label reads and lookups, then the earlier entries'
+  if (threadIdx.x == 0) s_cnt[0] = s_cnt[1] = s_cnt[2] = s_cnt[3] = 0;
   lookup_body<LB, OB, FACTOR>(A, lds, sh_e, sh_ok, s_cnt);
 }
 
@@ -698,16 +714,23 @@ __global__ __launch_bounds__(1024) void k_scan_nodes(const IterArgs A) {
   if (it->abort) return;
   EState *es = A.es;
   const int64_t G = active_groups(it->node_tiles, A.grid);
-  wg_scan(G, [&](int64_t i) { return A.blk_a[i]; }, [&](int64_t i, int64_t v) { A.blk_off_a[i] = v; }, lds);
-  wg_scan(G, [&](int64_t i) { return A.blk_b[i]; }, [&](int64_t i, int64_t v) { A.blk_off_b[i] = v; }, lds);
-  const int64_t nz = wg_scan(A.E, [&](int64_t i) { return es[i].nz; }, [&](int64_t i, int64_t v) { es[i].nz_base = v; }, lds);
+  int64_t tot2[2], tot3[3];
+  wg_scan_k<2>(
+      G, [&](int64_t i, int64_t *v) { v[0] = A.blk_a[i]; v[1] = A.blk_b[i]; },
+      [&](int64_t i, const int64_t *o) { A.blk_off_a[i] = o[0]; A.blk_off_b[i] = o[1]; }, lds, tot2);
   // entry offsets and the block offsets above leave out counted levels, as the node lengths do
-  const int64_t w = wg_scan(A.E, [&](int64_t i) { return counted_only(A.steps[A.ent[i].step]) ? (int64_t)0 : es[i].w; },
-                            [&](int64_t i, int64_t v) { es[i].w_base = v; }, lds);
-  const int64_t wt = wg_scan(A.E, [&](int64_t i) {
-                               return counted_only(A.steps[A.ent[i].step]) ? (int64_t)0 : ceil_div(es[i].w, kTileWork);
-                             },
-                             [&](int64_t i, int64_t v) { es[i].w_tile0 = v; }, lds);
+  wg_scan_k<3>(
+      A.E,
+      [&](int64_t i, int64_t *v) {
+        const bool c = counted_only(A.steps[A.ent[i].step]);
+        const int64_t ew = es[i].w;
+        v[0] = es[i].nz;
+        v[1] = c ? 0 : ew;
+        v[2] = c ? 0 : ceil_div(ew, kTileWork);
+      },
+      [&](int64_t i, const int64_t *o) { es[i].nz_base = o[0]; es[i].w_base = o[1]; es[i].w_tile0 = o[2]; }, lds,
+      tot3);
+  const int64_t nz = tot3[0], w = tot3[1], wt = tot3[2];
   __shared__ int64_t wtest;
   __shared__ int32_t sh_abort;
   if (threadIdx.x == 0) wtest = 0;
@@ -1002,7 +1025,7 @@ __device__ __forceinline__ bool test_candidate(const IterArgs &A, const EState &
 // entries per tile, per entry and per workgroup. A workgroup takes a
 // contiguous tile range; test-free entries in it are passed over whole, the
 // tiles of tested entries are dealt to its waves.
-template <int LB, int OB>
+template <int LB, int OB, bool FILTERS_ONLY>
 __device__ __forceinline__ void expand_count_body(const IterArgs &A, WaveTile *Wt, int64_t (*red4)[4]) {
   IterScalars *it = A.it;
   if (it->abort) return;
@@ -1035,19 +1058,57 @@ __device__ __forceinline__ void expand_count_body(const IterArgs &A, WaveTile *W
       stage_tile(it, dt, nwin, load_slot(it, dt, nwin), W);
       uint64_t *vw = (uint64_t *)(it->valid + u * (kTileWork / 32));
       int c_tile = 0;
-      for (int r = 0; r < kItemsPerLane; ++r) {
-        const int p = r * 64 + lane;
-        const int k = take_node(W, p);
-        bool ok = false;
-        if (p < dt.n) {
-          const int32_t c = candidate(A, E, S, W, k, p);
-          int64_t clo = 0, chi = 0;
-          if (S.nchk > 0) { clo = gld(it->nz_chk_lo + dt.k0 + k); chi = gld(it->nz_chk_hi + dt.k0 + k); }
-          ok = test_candidate<LB, OB>(A, E, S, W.node[k], W.dg[k] >> 1, clo, chi, c, pr, ft, ct);
+      if constexpr (FILTERS_ONLY) {
+        // bitmap filters only: four of the lane's candidates at a time, then each filter's words
+        // for the four, every round a batch of independent loads (instead of two or more
+        // dependent round trips per item)
+#pragma unroll
+        for (int h = 0; h < kItemsPerLane; h += 4) {
+          int32_t cv[4];
+          uint32_t live = 0;   // bit r: item h + r exists and has passed the filters tested so far
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int p = (h + r) * 64 + lane;
+            const int k = take_node(W, p);
+            cv[r] = 0;
+            if (p < dt.n) {
+              cv[r] = candidate(A, E, S, W, k, p);
+              live |= 1u << r;
+            }
+          }
+          for (int f = S.list_nfilt; f < S.nfilt && live; ++f) {
+            // the 32-bit half of the 64-bit bitmap word that holds each bit (little-endian words)
+            const uint32_t *bm = (const uint32_t *)A.filt[S.filt0 + f];
+            uint32_t wd[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) wd[r] = gld(bm + (cv[r] >> 5));   // word 0 for absent items
+            ft += __popc(live);
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              if (!((wd[r] >> (cv[r] & 31)) & 1u)) live &= ~(1u << r);
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const uint64_t bal = __ballot((live >> r) & 1u);
+            if (lane == 0) gst(vw + h + r, bal);
+            c_tile += __popcll(bal);
+          }
         }
-        const uint64_t bal = __ballot(ok);
-        if (lane == 0) gst(vw + r, bal);
-        c_tile += __popcll(bal);
+      } else {
+        for (int r = 0; r < kItemsPerLane; ++r) {
+          const int p = r * 64 + lane;
+          const int k = take_node(W, p);
+          bool ok = false;
+          if (p < dt.n) {
+            const int32_t c = candidate(A, E, S, W, k, p);
+            int64_t clo = 0, chi = 0;
+            if (S.nchk > 0) { clo = gld(it->nz_chk_lo + dt.k0 + k); chi = gld(it->nz_chk_hi + dt.k0 + k); }
+            ok = test_candidate<LB, OB>(A, E, S, W.node[k], W.dg[k] >> 1, clo, chi, c, pr, ft, ct);
+          }
+          const uint64_t bal = __ballot(ok);
+          if (lane == 0) gst(vw + r, bal);
+          c_tile += __popcll(bal);
+        }
       }
       wave_lds_sync();
       if (lane == 0) it->tiles[u].cnt = c_tile;
@@ -1078,10 +1139,14 @@ __device__ __forceinline__ void expand_count_body(const IterArgs &A, WaveTile *W
   }
 }
 
+// One instance per stored width pair, chosen on the host (as the lookup), and one for launches
+// whose entries test bitmap filters only: that variant batches the loads of several items, which
+// in the general one would cost registers (and spills) that its exact checks need.
+template <int LB, int OB, bool FILTERS_ONLY>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_expand_count(const IterArgs A) {
   __shared__ WaveTile Wt[kWaves];
   __shared__ int64_t red4[kWaves][4];
-  GS_WITH_WIDTHS(A.g, (expand_count_body<LB, OB>(A, Wt, red4)));
+  expand_count_body<LB, OB, FILTERS_ONLY>(A, Wt, red4);
 }
 
 __global__ __launch_bounds__(1024) void k_scan_expand(const IterArgs A) {
@@ -1347,7 +1412,18 @@ hipError_t launch_iteration(const IterArgs &A, hipStream_t s, hipEvent_t *ev) {
   }
   GS_LAUNCH(KS_SCAN_NODES, k_scan_nodes, dim3(1), W1);
   GS_LAUNCH(KS_NZ_WRITE, k_nz_write, G, B);
-  if (A.has_tested) GS_LAUNCH(KS_EXPAND_COUNT, k_expand_count, G, B);
+  if (A.has_tested) {
+    switch ((A.g.lab8 ? 0 : 2) + (A.g.off32 ? 0 : 1) + (A.has_exact ? 0 : 4)) {
+      case 0: GS_LAUNCH(KS_EXPAND_COUNT, (k_expand_count<1, 4, false>), G, B); break;
+      case 1: GS_LAUNCH(KS_EXPAND_COUNT, (k_expand_count<1, 8, false>), G, B); break;
+      case 2: GS_LAUNCH(KS_EXPAND_COUNT, (k_expand_count<2, 4, false>), G, B); break;
+      case 3: GS_LAUNCH(KS_EXPAND_COUNT, (k_expand_count<2, 8, false>), G, B); break;
+      case 4: GS_LAUNCH(KS_EXPAND_COUNT, (k_expand_count<1, 4, true>), G, B); break;
+      case 5: GS_LAUNCH(KS_EXPAND_COUNT, (k_expand_count<1, 8, true>), G, B); break;
+      case 6: GS_LAUNCH(KS_EXPAND_COUNT, (k_expand_count<2, 4, true>), G, B); break;
+      default: GS_LAUNCH(KS_EXPAND_COUNT, (k_expand_count<2, 8, true>), G, B); break;
+    }
+  }
   GS_LAUNCH(KS_SCAN_EXPAND, k_scan_expand, dim3(1), W1);
   if (A.has_tested) GS_LAUNCH(KS_TILE_OFFSETS, k_tile_offsets, G, B);
   GS_LAUNCH(KS_EXPAND_WRITE, k_expand_write, dim3((unsigned)A.wgrid), B);

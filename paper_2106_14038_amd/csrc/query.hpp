@@ -18,6 +18,8 @@ struct IterArgs {
   int32_t has_tested;      // any entry whose candidates face a test (else no count and tile-offset passes)
   int32_t has_checks;      // any entry with exact checks (cycle-closing edges)
   int32_t has_factor;      // any entry at a count-only factor level (the lookup variant that multiplies)
+  int32_t has_exact;       // any entry whose candidates face exact checks or self loops (else the count
+                           // pass variant for bitmap filters only)
   int32_t grid;            // workgroups of the fixed-grid kernels
   int32_t wgrid;           // workgroups of the write pass (as many as are resident at once)
   const DStep *steps;
