@@ -167,20 +167,69 @@ def batched_set_leg(gs, eng, qset, wave=1024):
     return out
 
 
-def serve_leg(gs, eng, qset, rates, seconds, seed=7):
-    """Open-loop Poisson arrivals at each rate, served with continuous batching; the same
-    trace served one query at a time (FIFO) by the plain engine as the baseline."""
+def traversal_leg(gs, torch, trip, qs_graph, qset):
+    """Direction-driven against degree-driven traversal (Section 6.1; the paper's Tables 5
+    and 6 compare the two) on the constant-free queries of the batched set (queries with
+    constants always take the degree-driven order): the same queries, one at a time and as
+    one count-only batch, on an engine with each traversal; every count against the stored
+    oracle count."""
+    recs = [q for q in qset["queries"] if all(c < 0 for c in q["query"]["qv_const"])]
+    if not recs:
+        return None
+    queries = [q["query"] for q in recs]
+    expect = [q["count"] for q in recs]
+    out = {"queries": len(queries)}
+    for name, mode in (("degree", gs.GS_TRAVERSAL_DEGREE), ("direction", gs.GS_TRAVERSAL_DIRECTION)):
+        e = gs.gs_engine_create(gs.options(device=0, hip_stream=torch.cuda.current_stream().cuda_stream,
+                                           traversal=mode))
+        t = torch.from_numpy(trip).cuda()
+        gs.gs_load_triples(e, qs_graph["n"], qs_graph["n_labels"], t)
+        del t
+        for r in gs.gs_batch_run(e, queries, gs.GS_COUNT_ONLY):   # warm-up
+            gs.gs_result_free(r)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rs = gs.gs_batch_run(e, queries, gs.GS_COUNT_ONLY)
+        got = [gs.gs_result_count(r) for r in rs]
+        T = sum(gs.gs_result_stats(r).t_total for r in rs)
+        for r in rs:
+            gs.gs_result_free(r)
+        tb = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        plain = []
+        for q in queries:
+            r = gs.gs_query_run(e, q, gs.GS_COUNT_ONLY)
+            plain.append(gs.gs_result_count(r))
+            gs.gs_result_free(r)
+        tp = time.perf_counter() - t0
+        gs.gs_engine_destroy(e)
+        if got != expect or plain != expect:
+            raise SystemExit(f"{name} traversal: counts differ from the stored oracle counts")
+        out[name] = {"batched_ms": tb * 1e3, "plain_ms": tp * 1e3, "traversed_triples": int(T),
+                     "batched_queries_per_s": len(queries) / tb, "plain_queries_per_s": len(queries) / tp}
+    log(f"traversals: {out}")
+    return out
+
+
+def serve_leg(gs, eng, qset, rates, seconds, warmup_s=1.0, seed=7):
+    """Open-loop Poisson arrivals at each rate for warmup_s + seconds: requests (the served
+    query set, cycled) are served with continuous batching; latency is arrival to result on
+    the host, counted for the requests that arrive after the warm-up. The same trace is then
+    served live, first come first served, by the plain engine (one query at a time, waiting
+    for arrivals when idle) over the same window; requests it has not finished by the window's
+    end plus 10 s are reported as backlog (their latency is at least that long)."""
     import workload
     queries = [q["query"] for q in qset["queries"]]
+    expect = [q["count"] for q in qset["queries"]]
     out = {}
+    total = warmup_s + seconds
     for rate in rates:
-        arr = workload.poisson_arrivals(seed, rate, seconds)
+        arr = workload.poisson_arrivals(seed, rate, total)
         srv = gs.gs_server_start(eng, gs.gs_server_options(max_active=1024, tree_budget_bytes=0,
                                                            flags=gs.GS_COUNT_ONLY))
         t0 = time.perf_counter()
-        tickets = []
         pending = {}
-        lat = []
+        lat, wrong, errors = [], 0, 0
         i = 0
         while i < len(arr) or pending:
             now = time.perf_counter() - t0
@@ -189,33 +238,52 @@ def serve_leg(gs, eng, qset, rates, seconds, seed=7):
                 pending[tk] = i
                 i += 1
             for tk, status, r in gs.gs_poll_ready(srv):
-                if r is not None:
+                k = pending.pop(tk, None)
+                if r is None:
+                    errors += 1
+                    continue
+                if gs.gs_result_count(r) != expect[k % len(queries)]:
+                    wrong += 1
+                if arr[k] >= warmup_s:
                     lat.append(gs.gs_result_stats(r).latency_ms)
-                    gs.gs_result_free(r)
-                pending.pop(tk, None)
-            if i >= len(arr) and time.perf_counter() - t0 > seconds + 60:
+                gs.gs_result_free(r)
+            if i >= len(arr) and time.perf_counter() - t0 > total + 60:
                 break
         span = time.perf_counter() - t0
         st = gs.gs_server_stop(srv)
         lat = np.array(lat)
-        # FIFO baseline: the plain engine takes requests in arrival order
-        t_free, plat = 0.0, []
-        for k, ta in enumerate(arr[:min(len(arr), 2000)]):
-            t_start = max(ta, t_free)
-            t1 = time.perf_counter()
+        measured = int((arr >= warmup_s).sum())
+        # live FIFO baseline with the plain engine over the same trace
+        t0 = time.perf_counter()
+        plat, k, deadline = [], 0, total + 10.0
+        while k < len(arr) and time.perf_counter() - t0 < deadline:
+            now = time.perf_counter() - t0
+            if arr[k] > now:
+                time.sleep(min(arr[k] - now, 0.0005))
+                continue
             r = gs.gs_query_run(eng, queries[k % len(queries)], gs.GS_COUNT_ONLY)
             gs.gs_result_free(r)
-            t_free = t_start + (time.perf_counter() - t1)
-            plat.append((t_free - ta) * 1e3)
+            if arr[k] >= warmup_s:
+                plat.append((time.perf_counter() - t0 - arr[k]) * 1e3)
+            k += 1
+        fifo_span = time.perf_counter() - t0
+        backlog = int(((arr >= warmup_s) & (np.arange(len(arr)) >= k)).sum())
         plat = np.array(plat)
         out[str(int(rate))] = {
-            "requests": int(len(arr)), "completed": int(st.completed), "queries_per_s": len(lat) / span,
+            "requests": int(len(arr)), "measured_requests": measured, "warmup_s": warmup_s,
+            "measured_s": seconds, "completed": int(st.completed), "admitted": int(st.submitted),
+            "rejected": int(st.rejected), "requeued": int(st.requeued), "errors": errors,
+            "counts_wrong": wrong, "queries_per_s": st.completed / span,
             "p50_ms": float(np.percentile(lat, 50)) if len(lat) else None,
             "p99_ms": float(np.percentile(lat, 99)) if len(lat) else None,
             "max_active": int(st.max_active_seen), "iterations": int(st.iterations),
-            "plain_fifo_p50_ms": float(np.percentile(plat, 50)), "plain_fifo_p99_ms": float(np.percentile(plat, 99)),
-            "plain_fifo_queries_per_s": len(plat) / max(t_free - arr[0], 1e-9) if len(plat) else None}
+            "plain_fifo_completed": int(k), "plain_fifo_backlog": backlog,
+            "plain_fifo_p50_ms": float(np.percentile(plat, 50)) if len(plat) else None,
+            "plain_fifo_p99_ms": float(np.percentile(plat, 99)) if len(plat) else None,
+            "plain_fifo_queries_per_s": k / fifo_span}
         log(f"served {rate}/s: {out[str(int(rate))]}")
+        if wrong or errors:
+            raise SystemExit(f"served {rate}/s: {wrong} counts differ from the stored oracle counts, {errors} errors")
     return out
 
 
@@ -276,6 +344,20 @@ def _find(d, suffix):
     return sorted(out)
 
 
+def per_kernel_simple(d, counter):
+    """Average per dispatch of one counter, per kernel name, over the runs under d."""
+    import csv
+    acc = {}
+    for p in _find(d, "counter_collection.csv"):
+        with open(p) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] != counter:
+                    continue
+                a = acc.setdefault(r["Kernel_Name"].split("(")[0], {})
+                a[r["Dispatch_Id"]] = a.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
+    return {k: sum(v.values()) / len(v) for k, v in acc.items()}
+
+
 def summarize_rocprof(args):
     """Short text summaries of rocprofv3 output for profiles/ (kernel statistics,
     or per-kernel HBM counters scaled by the copy probe's reading)."""
@@ -292,6 +374,43 @@ def summarize_rocprof(args):
             name = r["Name"].split("(")[0][:60]
             lines.append(f"{name:60s} {int(r['Calls']):7d} {float(r['TotalDurationNs']) / 1e6:10.3f} "
                          f"{float(r['AverageNs']) / 1e3:10.2f} {float(r['Percentage']):6.2f}")
+    elif args.summarize == "counters":
+        # per kernel and counter: the average per dispatch over the runs in --dirs (one counter
+        # group per run); HBM bytes scaled by the plain copy's reading; L2 hit rate
+        acc = {}
+        for d in args.dirs.split(","):
+            for p in _find(d, "counter_collection.csv"):
+                with open(p) as f:
+                    for r in csv.DictReader(f):
+                        name = r["Kernel_Name"].split("(")[0].replace("gs::", "")
+                        a = acc.setdefault(name, {}).setdefault(r["Counter_Name"], {})
+                        a[r["Dispatch_Id"]] = a.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
+        def avg(name, c):
+            v = acc.get(name, {}).get(c)
+            return (sum(v.values()) / len(v), len(v)) if v else (None, 0)
+        fscale = wscale = None
+        if args.copy_fetch_dir and args.copy_write_dir:
+            cf = max(v for k, v in per_kernel_simple(args.copy_fetch_dir, "FETCH_SIZE").items())
+            cw = max(v for k, v in per_kernel_simple(args.copy_write_dir, "WRITE_SIZE").items())
+            fscale, wscale = (1 << 30) / (cf * 1024.0), (1 << 30) / (cw * 1024.0)
+            lines.append(f"copy probe: FETCH_SIZE {cf:.1f} KiB, WRITE_SIZE {cw:.1f} KiB for 1 GiB each way; "
+                         f"scales {fscale:.3f} / {wscale:.3f}")
+        wanted = [k.strip() for k in args.kernels.split(",")] if args.kernels else sorted(acc)
+        for name in wanted:
+            if name not in acc:
+                continue
+            lines.append(f"kernel: {name}")
+            for c in sorted(acc[name]):
+                v, nd = avg(name, c)
+                lines.append(f"  {c}: {v:.1f} per dispatch ({nd} dispatches)")
+            f, _ = avg(name, "FETCH_SIZE")
+            w, _ = avg(name, "WRITE_SIZE")
+            if f is not None and w is not None and fscale:
+                lines.append(f"  hbm_bytes_per_dispatch: {f * 1024 * fscale + w * 1024 * wscale:.0f}")
+            h, _ = avg(name, "TCC_HIT_sum")
+            mi, _ = avg(name, "TCC_MISS_sum")
+            if h is not None and mi is not None and h + mi > 0:
+                lines.append(f"  l2_hit_rate: {h / (h + mi):.3f}")
     else:
         def per_kernel(d):
             acc = {}
@@ -338,22 +457,99 @@ def summarize_rocprof(args):
     print(text, end="")
 
 
+def profile_leg(gs, torch, args, qs, trip):
+    """One leg alone (warm-up passes, then `steps` passes), each pass logged: the plain
+    form (the query set one query at a time), the batched step, or the batched query set
+    as one count-only batch."""
+    eng = gs.gs_engine_create(gs.options(device=0, hip_stream=torch.cuda.current_stream().cuda_stream))
+    t = torch.from_numpy(trip).cuda()
+    gs.gs_load_triples(eng, qs["n"], qs["n_labels"], t)
+    del t
+    queries = [q["query"] for q in (load_queryset("c2") if args.profile_leg == "set" else qs)["queries"]]
+    for i in range(args.warmup + args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if args.profile_leg == "plain":
+            for q in queries:
+                gs.gs_result_free(gs.gs_query_run(eng, q))
+        else:
+            flags = gs.GS_COUNT_ONLY if args.profile_leg == "set" else 0
+            for r in gs.gs_batch_run(eng, queries, flags):
+                gs.gs_result_free(r)
+        torch.cuda.synchronize()
+        log(f"{args.profile_leg} pass {i}: {(time.perf_counter() - t0) * 1e3:.2f} ms")
+    gs.gs_engine_destroy(eng)
+
+
+def c4_profile_leg(gs, torch, args):
+    """The 2B-triple step alone on an engine without per-kernel events (for rocprofv3): the
+    graph drawn on the device and loaded, then warm-up and timed passes of the step (the
+    selective queries batched with rows kept, the large ones count-only in waves), each logged."""
+    import workload
+    qs = load_queryset(c4_set_name(args))
+    sel = [q["query"] for q in qs["queries"] if q["group"] == "selective"]
+    large = [q["query"] for q in qs["queries"] if q["group"] == "large"]
+    trip = workload.c4_stream(qs["scale"]).device_graph(qs["draws"])
+    eng = gs.gs_engine_create(gs.options(device=0, hip_stream=torch.cuda.current_stream().cuda_stream, **C4_OPTS))
+    gs.gs_load_triples(eng, qs["n"], qs["n_labels"], trip)
+    del trip
+    torch.cuda.empty_cache()
+    wave = max(len(large), 1)
+    for i in range(args.warmup + args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for r in gs.gs_batch_run(eng, sel):
+            gs.gs_result_free(r)
+        j = 0
+        while j < len(large):
+            try:
+                rs = gs.gs_batch_run(eng, large[j:j + wave], gs.GS_COUNT_ONLY)
+            except gs.GsError as err:
+                if err.status != gs.GS_ENOMEM or wave == 1:
+                    raise
+                wave = max(1, wave // 2)   # the batch's trees exceed the arena: smaller waves
+                continue
+            for r in rs:
+                gs.gs_result_free(r)
+            j += wave
+        torch.cuda.synchronize()
+        log(f"c4 pass {i}: {(time.perf_counter() - t0) * 1e3:.2f} ms (large queries in waves of {wave})")
+    gs.gs_engine_destroy(eng)
+
+
+def c4_set_name(args):
+    name = args.c4_set
+    if name == "c4" and not os.path.exists(os.path.join(ROOT, "workload", "data", "c4_queries.json")):
+        log("the 2B-triple query set is not generated: the same recipe at 1% scale instead")
+        name = "c4s0.01"
+    return name
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c1")
+    ap.add_argument("--workload", default="c4", choices=["c1", "c4"])
+    ap.add_argument("--no-c1", action="store_true", help="with --workload c4: leave out the power-law graph legs")
+    ap.add_argument("--c4-set", default="c4", choices=["c4", "c4s0.01"],
+                    help="the 2B-triple query set, or the same recipe at 1%% scale")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-seconds", type=float, default=2.0)
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--no-graphs", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-batched-set", action="store_true")
     ap.add_argument("--copy-probe", action="store_true", help="run the HBM counter reference copy and exit")
-    ap.add_argument("--summarize", choices=["trace", "traffic"], help="summarise rocprofv3 output and exit")
+    ap.add_argument("--profile-leg", choices=["plain", "batched", "set", "c4"],
+                    help="run only that leg, on an engine without per-kernel events, and exit (for rocprofv3)")
+    ap.add_argument("--summarize", choices=["trace", "traffic", "counters"],
+                    help="summarise rocprofv3 output and exit")
     ap.add_argument("--dir")
+    ap.add_argument("--dirs", help="comma-separated rocprofv3 output folders (--summarize counters)")
+    ap.add_argument("--kernels", help="comma-separated kernel names (--summarize counters)")
     ap.add_argument("--fetch-dir")
     ap.add_argument("--write-dir")
     ap.add_argument("--copy-fetch-dir")
@@ -377,17 +573,329 @@ def main():
 
     import torch
     import paper_2106_14038_amd as gs
+    torch.cuda.set_device(0)
 
-    qs = load_queryset(args.workload)
+    if args.profile_leg == "c4":
+        c4_profile_leg(gs, torch, args)
+        return
+    if args.workload == "c4" and not args.profile_leg:
+        out = run_c4(args, gs, torch)
+        if not args.no_c1:
+            log("power-law graph legs (batched step, batched set, served)")
+            out["c1"] = run_c1(args, gs, torch, secondary=True)
+        print(json.dumps(out), flush=True)
+        return
+    print(json.dumps(run_c1(args, gs, torch)), flush=True)
+
+
+C4_OPTS = dict(tree_bytes=64 << 30, scratch_bytes=16 << 30, offset_bytes=8)
+
+
+def tune_cache_path(wl):
+    import tempfile
+    path = os.path.join(tempfile.gettempdir(), f"gsmart_autotune_{wl}_{os.getpid()}.txt")
+    if os.path.exists(path):
+        os.remove(path)
+    return path
+
+
+def autotune(gs, eng, calib, args):
+    """The autotuner on a calibration subset of the timed queries (count only): the fastest
+    workgroup count of the fixed-grid kernels and push/pull threshold, recorded in the engine's
+    autotune cache so that the later engines of the run start from it."""
+    if args.no_autotune:
+        return None
+    t = time.perf_counter()
+    r = gs.gs_autotune(eng, calib)
+    out = {"grid_blocks": r.grid_blocks, "push_pull_theta": r.push_pull_theta, "best_ms": r.best_ms,
+           "default_ms": r.default_ms, "tried": r.n_tried, "calibration_queries": len(calib),
+           "block_size": 256, "tune_s": time.perf_counter() - t}
+    log(f"autotune: {out}")
+    return out
+
+
+def step_roofline_of(B_alg, kstats, steps, wall_ms):
+    """The whole step against HBM: the method's algorithmic bytes of every query (ids,
+    label entries, offset pairs, tree nodes written and read, bitmap words) over the summed
+    kernel time of the step, and over its wall time."""
+    kms = sum(v["ms"] for v in kstats.values()) / steps
+    impl = sum(v["bytes_impl"] for v in kstats.values()) / steps
+    return {"bytes_alg_per_step": B_alg, "kernel_ms_per_step": kms, "wall_ms_per_step": wall_ms,
+            "achieved_GBps": B_alg / (kms / 1e3) / 1e9, "frac": B_alg / (kms / 1e3) / 1e9 / HBM_PEAK_GBS,
+            "wall_frac": B_alg / (wall_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+            "bytes_impl_per_step": impl, "impl_GBps": impl / (kms / 1e3) / 1e9,
+            "launches_per_step": sum(v["launches"] for v in kstats.values()) / steps}
+
+
+def kernel_table(ks, steps):
+    return {n: {"ms_per_step": v["ms"] / steps, "launches_per_step": v["launches"] / steps,
+                "alg_GBps": (v["bytes_alg"] / (v["ms"] / 1e3) / 1e9) if v["ms"] > 0 and v["bytes_alg"] > 0 else None,
+                "impl_GBps": (v["bytes_impl"] / (v["ms"] / 1e3) / 1e9) if v["ms"] > 0 and v["bytes_impl"] > 0
+                else None}
+            for n, v in ks.items()}
+
+
+def dominant_roofline(ks, workload_name):
+    name, k = max(ks.items(), key=lambda kv: kv[1]["ms"])
+    achieved = k["bytes_alg"] / (k["ms"] / 1e3) / 1e9 if k["ms"] > 0 and k["bytes_alg"] > 0 else None
+    return {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS if achieved else None,
+            "traffic": measured_traffic(name, workload_name),
+            "alg_bytes_per_launch": k["bytes_alg"] / max(k["launches"], 1),
+            "impl_bytes_per_launch": k["bytes_impl"] / max(k["launches"], 1),
+            "avg_launch_ms": k["ms"] / max(k["launches"], 1), "launches": k["launches"]}
+
+
+def c4_cpu_baseline(torch, trip, qs, sel, label_nnz, per_query_T, budget_s):
+    """The oracle on a bounded sample of the 2B-triple workload: the selective queries (in set
+    order) whose labels hold at most 3e7 triples together, up to 24 of them; the oracle's index
+    holds only the triples of those queries' labels (a query reads no other triple, so its rows
+    are those over the whole graph: each digest is checked against the stored one). Timed on one
+    thread and on every host core; index build not timed."""
+    import oracle
+    pick, labels, tot = [], set(), 0
+    for i, q in enumerate(sel):
+        L = {p for _, p, _ in q["query"]["edges"]}
+        nz = sum(label_nnz[p - 1] for p in L - labels)
+        if sum(label_nnz[p - 1] for p in L) <= 30_000_000 and tot + nz <= 100_000_000:
+            pick.append(i)
+            labels |= L
+            tot += nz
+        if len(pick) == 24:
+            break
+    lab_t = torch.tensor(sorted(labels), dtype=torch.int32, device=trip.device)
+    sub = trip[torch.isin(trip[:, 1], lab_t)].cpu().numpy()
+    t0 = time.time()
+    G = oracle.Graph(sub, qs["n"], qs["n_labels"])
+    index_s = time.time() - t0
+    nproc = os.cpu_count() or 1
+
+    def run(threads):
+        done, T, secs = 0, 0, 0.0
+        for i in pick:
+            q = sel[i]
+            t1 = time.perf_counter()
+            d = G.digest(q["query"], threads=threads)
+            secs += time.perf_counter() - t1
+            assert d == (q["count"], int(q["digest_sum"]), int(q["digest_xor"])), "oracle digest differs"
+            T += per_query_T[i]
+            done += 1
+            if secs > budget_s:
+                break
+        return {"value": T / secs if secs > 0 else None, "queries": done, "seconds": secs,
+                "queries_per_s": done / secs if secs > 0 else None}
+
+    one, allc = run(1), run(nproc)
+    log(f"cpu baseline (2B-triple graph): one thread {one}, {nproc} threads {allc}")
+    return {"value": allc["value"], "unit": "triples/s", "cores": nproc, "kind": "oracle",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "sample": f"{len(pick)} selective queries of the 2B-triple set (set order, those whose labels hold "
+                      f"at most 3e7 triples); the oracle's index holds the {len(sub)} triples of their labels "
+                      f"(built in {index_s:.1f}s, not timed); count and row digest, each checked against the "
+                      f"stored digest; value = the engine's traversed-triple count of the queries done / oracle "
+                      f"seconds; one thread: {one['queries']} queries in {one['seconds']:.1f}s",
+            "one_core": one, "all_cores": allc}
+
+
+def run_c4(args, gs, torch):
+    """The 2B-triple graph: a step evaluates the whole query set once, the 256 selective queries
+    as one batch with rows kept and the large ones (up to 1e9 rows) count-only, batched in waves
+    that fit the tree arena. Instrumented run (per-kernel events) for the kernel table and the
+    roofline; the headline replays the step's launches from captured hipGraphs on an engine
+    without events; the plain form runs the same queries one at a time."""
+    import workload
+    name = c4_set_name(args)
+    qs = load_queryset(name)
+    sel = [q for q in qs["queries"] if q["group"] == "selective"]
+    large = [q for q in qs["queries"] if q["group"] == "large"]
+    st = workload.c4_stream(qs["scale"])
+    t0 = time.time()
+    trip = st.device_graph(qs["draws"])
+    torch.cuda.synchronize()
+    gen_s = time.time() - t0
+    log(f"2B-triple graph: {trip.shape[0]} draws on the device in {gen_s:.1f}s")
+    stream = torch.cuda.current_stream().cuda_stream
+
+    cache = tune_cache_path("c4")
+
+    def engine(**kw):
+        e = gs.gs_engine_create(gs.options(device=0, hip_stream=stream, autotune_cache=cache.encode(), **C4_OPTS,
+                                           **kw))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        gs.gs_load_triples(e, qs["n"], qs["n_labels"], trip)
+        torch.cuda.synchronize()
+        return e, (time.perf_counter() - t1) * 1e3
+
+    wave = [len(large)]
+
+    def step(e):
+        rs = gs.gs_batch_run(e, [q["query"] for q in sel])
+        counts = [gs.gs_result_count(r) for r in rs]
+        stats = [gs.gs_result_stats(r) for r in rs]
+        for r in rs:
+            gs.gs_result_free(r)
+        i = 0
+        while i < len(large):
+            try:
+                rs = gs.gs_batch_run(e, [q["query"] for q in large[i:i + wave[0]]], gs.GS_COUNT_ONLY)
+            except gs.GsError as err:
+                if err.status != gs.GS_ENOMEM or wave[0] == 1:
+                    raise
+                wave[0] = max(1, wave[0] // 2)   # the batch's trees exceed the arena: smaller waves
+                continue
+            counts += [gs.gs_result_count(r) for r in rs]
+            stats += [gs.gs_result_stats(r) for r in rs]
+            for r in rs:
+                gs.gs_result_free(r)
+            i += wave[0]
+        return counts, stats
+
+    expect = [q["count"] for q in sel + large]
+    eng, load_ms = engine(profile_kernels=1)
+    n, P, m, dev_bytes = gs.gs_graph_info(eng)
+    assert (n, P, m) == (qs["n"], qs["n_labels"], qs["m"]), "stored graph sizes differ"
+    label_nnz = gs.gs_label_stats(eng)[0]
+    log(f"load {load_ms:.0f} ms, {m} distinct triples, {dev_bytes / 2**30:.1f} GiB on the device")
+    tune = autotune(gs, eng, [q["query"] for q in sel[::4]], args)
+    for _ in range(max(args.warmup, 1)):
+        counts, stats = step(eng)
+    if counts != expect:
+        raise SystemExit("2B-triple set: counts differ from the stored oracle counts")
+    gs.gs_kernel_stats(eng, reset=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        counts, stats = step(eng)
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t1) * 1e3 / args.steps
+    ks = gs.gs_kernel_stats(eng, reset=True)
+    T = sum(x.t_total for x in stats)
+    per_query_T = [x.t_total for x in stats]
+    B_alg = sum(x.bytes_alg for x in stats)
+    step_batched = step_roofline_of(B_alg, ks, args.steps, ms_step)
+    roofline = dominant_roofline(ks, "c4")
+    kernels = kernel_table(ks, args.steps)
+    log(f"2B-triple batched step: {ms_step:.2f} ms (events), {T} traversed triples, roofline {step_batched}")
+    step_plain = None
+    if not args.no_plain:   # plain form's kernel time, with events
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for q in sel:
+            gs.gs_result_free(gs.gs_query_run(eng, q["query"]))
+        for q in large:
+            gs.gs_result_free(gs.gs_query_run(eng, q["query"], gs.GS_COUNT_ONLY))
+        torch.cuda.synchronize()
+        pw = (time.perf_counter() - t1) * 1e3
+        step_plain = step_roofline_of(B_alg, gs.gs_kernel_stats(eng, reset=True), 1, pw)
+        log(f"2B-triple plain roofline: {step_plain}")
+    gs.gs_engine_destroy(eng)
+    torch.cuda.empty_cache()
+
+    eng, _ = engine(use_graphs=0 if args.no_graphs else 1)
+    for _ in range(max(args.warmup, 1)):
+        gcounts, _ = step(eng)
+    assert gcounts == expect
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        step(eng)
+    torch.cuda.synchronize()
+    gms = (time.perf_counter() - t1) * 1e3 / args.steps
+    log(f"2B-triple batched step replayed: {gms:.2f} ms")
+    plain = None
+    if not args.no_plain:
+        for q in sel[:4]:
+            gs.gs_result_free(gs.gs_query_run(eng, q["query"]))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        pc = []
+        for q in sel:
+            r = gs.gs_query_run(eng, q["query"])
+            pc.append(gs.gs_result_count(r))
+            gs.gs_result_free(r)
+        ts = time.perf_counter() - t1
+        for q in large:
+            r = gs.gs_query_run(eng, q["query"], gs.GS_COUNT_ONLY)
+            pc.append(gs.gs_result_count(r))
+            gs.gs_result_free(r)
+        torch.cuda.synchronize()
+        pe = time.perf_counter() - t1
+        assert pc == expect
+        plain = {"queries_per_s": len(expect) / pe, "triples_per_s": T / pe, "ms_per_pass": pe * 1e3,
+                 "selective_queries_per_s": len(sel) / ts}
+        log(f"2B-triple plain: {plain}")
+    streamed = None
+    if large:   # rows of the smallest large query, streamed to the host in chunks
+        rec = min(large, key=lambda q: q["count"])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        r = gs.gs_query_run(eng, rec["query"])
+        t2 = time.perf_counter()
+        k = gs.gs_result_width(r)
+        got = 0
+        chunk = 1 << 24
+        for first in range(0, rec["count"], chunk):
+            got += len(gs.gs_result_rows(r, first, chunk))
+        t3 = time.perf_counter()
+        gs.gs_result_free(r)
+        assert got == rec["count"]
+        streamed = {"rows": got, "width": k, "evaluate_ms": (t2 - t1) * 1e3, "stream_ms": (t3 - t2) * 1e3,
+                    "rows_per_s": got / (t3 - t2), "host_GBps": got * k * 4 / (t3 - t2) / 1e9,
+                    "chunk_rows": chunk}
+        log(f"streamed rows: {streamed}")
+    gs.gs_engine_destroy(eng)
+    torch.cuda.empty_cache()
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = c4_cpu_baseline(torch, trip, qs, sel, label_nnz, per_query_T, args.cpu_budget)
+    del trip
+    torch.cuda.empty_cache()
+    nq = len(expect)
+    head_ms = gms
+    return {
+        "metric": METRIC, "value": T / (head_ms / 1e3), "unit": "triples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head_ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": f"{name}: the distinct triples among {qs['draws']} Chung-Lu draws (beta 2.0), "
+                               f"N={qs['n']}, M={qs['m']} distinct, {qs['n_labels']} Zipf(1.1) labels, typed 20% "
+                               f"object domains, 64-bit row offsets; {len(sel)} selective walk queries with "
+                               f"constants (rows kept) and {len(large)} large ones (1e7..1e9 rows, count only), "
+                               f"batched form",
+                   "queries": nq, "total_rows": int(sum(expect)), "parallelism": "single GPU",
+                   "launch": "hipGraph replay" if not args.no_graphs else "eager launches",
+                   "large_wave": wave[0]},
+        "batched": {"queries_per_s": nq / (head_ms / 1e3), "triples_per_s": T / (head_ms / 1e3),
+                    "ms_per_step": head_ms, "instrumented_ms_per_step": ms_step},
+        "plain": plain,
+        "batched_over_plain_queries_per_s": (nq / (head_ms / 1e3)) / plain["queries_per_s"] if plain else None,
+        "streamed_rows": streamed,
+        "load_ms": load_ms, "generate_s": gen_s, "device_graph_GiB": dev_bytes / 2**30, "autotune": tune,
+        "roofline": roofline,
+        "step_roofline": {"batched": step_batched, "plain": step_plain},
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+    }
+
+
+def run_c1(args, gs, torch, secondary=False):
+    """The power-law graph: the batched step over its 100 queries (instrumented and
+    replayed), the plain form, the batched query set and the served form."""
+    wl = "c1"
+    qs = load_queryset(wl)
     queries = [q["query"] for q in qs["queries"]]
     expect = [q["count"] for q in qs["queries"]]
     t0 = time.time()
     trip = graph_for(qs)
     log(f"graph {len(trip)} triples in {time.time() - t0:.1f}s")
 
-    torch.cuda.set_device(0)
+    if args.profile_leg:
+        profile_leg(gs, torch, args, qs, trip)
+        return None
     dev_trip = torch.from_numpy(trip).cuda()
-    opts = gs.options(device=0, profile_kernels=1, hip_stream=torch.cuda.current_stream().cuda_stream)
+    cache = tune_cache_path(wl)
+    opts = gs.options(device=0, profile_kernels=1, hip_stream=torch.cuda.current_stream().cuda_stream,
+                      autotune_cache=cache.encode())
     eng = gs.gs_engine_create(opts)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -396,6 +904,7 @@ def main():
     load_ms = (time.perf_counter() - t1) * 1e3
     del dev_trip
     log(f"load {load_ms:.1f} ms")
+    tune = autotune(gs, eng, queries[::2], args)
 
     def batched_step():
         return batched_step_on(gs, eng, queries)
@@ -424,35 +933,11 @@ def main():
     value = T / (ms_step / 1e3)
     log(f"batched: {ms_step:.2f} ms/step, {T} traversed triples/step, {value:.3e} triples/s")
 
-    def step_roofline(kstats, steps, wall_ms):
-        """The whole step against HBM: the method's algorithmic bytes of every query (ids,
-        label entries, offset pairs, tree nodes written and read, bitmap words) over the summed
-        kernel time of the step, and over its wall time."""
-        kms = sum(v["ms"] for v in kstats.values()) / steps
-        impl = sum(v["bytes_impl"] for v in kstats.values()) / steps
-        return {"bytes_alg_per_step": B_alg, "kernel_ms_per_step": kms, "wall_ms_per_step": wall_ms,
-                "achieved_GBps": B_alg / (kms / 1e3) / 1e9, "frac": B_alg / (kms / 1e3) / 1e9 / HBM_PEAK_GBS,
-                "wall_frac": B_alg / (wall_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
-                "bytes_impl_per_step": impl, "impl_GBps": impl / (kms / 1e3) / 1e9}
-
-    step_batched = step_roofline(ks, args.steps, ms_step)
+    step_batched = step_roofline_of(B_alg, ks, args.steps, ms_step)
     log(f"batched step roofline: {step_batched}")
 
-    # dominant kernel over the timed region (the method's bytes of that kernel)
-    dom = max(ks.items(), key=lambda kv: kv[1]["ms"])
-    name, k = dom
-    achieved = k["bytes_alg"] / (k["ms"] / 1e3) / 1e9 if k["ms"] > 0 and k["bytes_alg"] > 0 else None
-    roofline = {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS if achieved else None,
-                "traffic": measured_traffic(name, args.workload),
-                "alg_bytes_per_launch": k["bytes_alg"] / max(k["launches"], 1),
-                "impl_bytes_per_launch": k["bytes_impl"] / max(k["launches"], 1),
-                "avg_launch_ms": k["ms"] / max(k["launches"], 1), "launches": k["launches"]}
-    kernels = {n: {"ms_per_step": v["ms"] / args.steps, "launches_per_step": v["launches"] / args.steps,
-                   "alg_GBps": (v["bytes_alg"] / (v["ms"] / 1e3) / 1e9) if v["ms"] > 0 and v["bytes_alg"] > 0 else None,
-                   "impl_GBps": (v["bytes_impl"] / (v["ms"] / 1e3) / 1e9) if v["ms"] > 0 and v["bytes_impl"] > 0
-                   else None}
-               for n, v in ks.items()}
+    roofline = dominant_roofline(ks, wl)   # the dominant kernel over the timed region (the method's bytes)
+    kernels = kernel_table(ks, args.steps)
 
     step_plain = None
     if not args.no_plain:   # the plain form's kernel time: the same queries one at a time, with events
@@ -464,15 +949,14 @@ def main():
         torch.cuda.synchronize()
         pwall = (time.perf_counter() - tp0) * 1e3
         kp = gs.gs_kernel_stats(eng, reset=True)
-        step_plain = step_roofline(kp, 1, pwall)
-        step_plain["launches_per_pass"] = sum(v["launches"] for v in kp.values())
-        step_batched["launches_per_step"] = sum(v["launches"] for v in ks.values()) / args.steps
+        step_plain = step_roofline_of(B_alg, kp, 1, pwall)
         log(f"plain step roofline: {step_plain}")
 
     gs.gs_engine_destroy(eng)   # the instrumented engine has served its purpose
 
     def fresh_engine(**kw):
-        e = gs.gs_engine_create(gs.options(device=0, hip_stream=torch.cuda.current_stream().cuda_stream, **kw))
+        e = gs.gs_engine_create(gs.options(device=0, hip_stream=torch.cuda.current_stream().cuda_stream,
+                                           autotune_cache=cache.encode(), **kw))
         t = torch.from_numpy(trip).cuda()
         gs.gs_load_triples(e, qs["n"], qs["n_labels"], t)
         del t
@@ -481,8 +965,8 @@ def main():
     # the baselines and the other forms run without per-kernel events
     c2 = os.path.join(ROOT, "workload", "data", "c2_queries.json")
     c3 = os.path.join(ROOT, "workload", "data", "c3_queries.json")
-    want_set = not args.no_batched_set and os.path.exists(c2) and args.workload == "c1"
-    want_serve = not args.no_serve and os.path.exists(c3) and args.workload == "c1"
+    want_set = not args.no_batched_set and os.path.exists(c2)
+    want_serve = not args.no_serve and os.path.exists(c3)
     leng = fresh_engine() if (not args.no_plain or want_set or want_serve) else None
     plain = None
     if not args.no_plain:
@@ -518,12 +1002,13 @@ def main():
         gs.gs_engine_destroy(geng)
 
     batched_set = batched_set_leg(gs, leng, load_queryset("c2")) if want_set else None
+    traversals = traversal_leg(gs, torch, trip, qs, load_queryset("c2")) if want_set else None
     served = (serve_leg(gs, leng, load_queryset("c3"), [1000.0, 5000.0, 20000.0], args.serve_seconds)
               if want_serve else None)
     if leng is not None:
         gs.gs_engine_destroy(leng)
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not secondary:
         cpu = cpu_baseline(trip, qs, per_query_T, args.cpu_budget)
 
     # the headline: the batched step as a production caller runs it, replayed from its hipGraph
@@ -536,7 +1021,7 @@ def main():
         "metric": METRIC, "value": head_value, "unit": "triples/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": head_ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int32", "data": "synthetic",
-        "config": {"workload": f"{args.workload}: Chung-Lu beta 2.1, N={qs['n']}, M={qs['m']}, "
+        "config": {"workload": f"{wl}: Chung-Lu beta 2.1, N={qs['n']}, M={qs['m']}, "
                                f"{qs['n_labels']} Zipf(1.1) labels, typed 20% object domains; "
                                f"{len(queries)} walk queries (chain-4, star-5, snowflake-8, triangle), "
                                f"batched form",
@@ -549,14 +1034,16 @@ def main():
         "batched_over_plain_queries_per_s": ((graphs or {}).get("queries_per_s", len(queries) / (ms_step / 1e3))
                                              / plain["queries_per_s"]) if plain else None,
         "batched_set": batched_set,
+        "traversals": traversals,
         "served": served,
         "load_ms": load_ms,
+        "autotune": tune,
         "roofline": roofline,
         "step_roofline": {"batched": step_batched, "plain": step_plain},
         "kernels": kernels,
         "cpu_baseline": cpu,
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 if __name__ == "__main__":
