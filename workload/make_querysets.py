@@ -8,7 +8,7 @@ same stream is tried. Run from the repository root:
 
     python -m workload.make_querysets [--set c1|c2|c3] [--scale 1.0] [--per-shape 25] [--total 1024]
     python -m workload.make_querysets --set c1 --digests   (add row digests to an existing set)
-    python -m workload.make_querysets --set c4 --work-cap 50000000 --per-shape 12 --shape-budget 1800
+    python -m workload.make_querysets --set c4 --work-cap 50000000 --per-shape 12 --shape-budget 1500 --procs 6
 
 c1: 25 queries per shape (chain-4, star-5, snowflake-8, triangle), counts in
 [1, 1e9]; c2: the batched set, 4 shapes x 8 count decades (1..1e8) x 32 queries with
