@@ -62,6 +62,7 @@ Engine::~Engine() {
   for (int o = 0; o < 2; ++o) { dfree(d_ptr[o]); dfree(d_idx[o]); dfree(d_lab[o]); dfree(d_bm[o]); }
   dfree(tree_base);
   dfree(scratch_base);
+  dfree(seed_pool);
   dfree(d_arenas);
   for (hipEvent_t e : events) (void)hipEventDestroy(e);
   for (GraphEntry &g : graphs) { (void)hipGraphExecDestroy(g.exec); (void)hipGraphDestroy(g.graph); }
@@ -300,7 +301,7 @@ int plan_query(const Engine &E, const gs_query &q, QInfo &qi, std::string &msg) 
 
 // Append query qi's step programs to T; its counters and tree levels use slot `slot`.
 void compile_query(const Engine &E, QInfo &qi, bool count_only, int slot, Tables &T,
-                   const std::function<uint64_t *()> &next_bitmap) {
+                   const std::function<uint64_t *(bool)> &next_bitmap) {
   const Plan &P = qi.plan;
   const int64_t words = E.g.words;
   qi.slot = slot;
@@ -311,13 +312,13 @@ void compile_query(const Engine &E, QInfo &qi, bool count_only, int slot, Tables
   std::vector<int32_t> seed_at(P.seeds.size());
   for (size_t k = 0; k < P.seeds.size(); ++k) {
     seed_at[k] = (int32_t)T.seeds.size();
-    T.seeds.push_back({next_bitmap(), P.seeds[k].c, P.seeds[k].label, P.seeds[k].dir, slot});
+    T.seeds.push_back({next_bitmap(true), P.seeds[k].c, P.seeds[k].label, P.seeds[k].dir, slot});
   }
   qi.nseed = (int32_t)P.seeds.size();
   qi.dom0 = (int32_t)T.doms.size();
   qi.ndom = (int32_t)P.domains.size();
   std::vector<DDomain> qd(P.domains.size());
-  for (size_t k = 0; k < P.domains.size(); ++k) { qd[k].F = next_bitmap(); qd[k].D = next_bitmap(); }
+  for (size_t k = 0; k < P.domains.size(); ++k) { qd[k].F = next_bitmap(false); qd[k].D = next_bitmap(false); }
   auto filter_ptr = [&](const FilterRef &f) -> const uint64_t * {
     switch (f.kind) {
       case F_LABEL_OUT: return E.g.bm[0] + (int64_t)f.arg * words;
@@ -418,7 +419,10 @@ void build_iteration(const Tables &T, const std::vector<const QInfo *> &qs, cons
     const QInfo &qi = *qs[i];
     const int t = level[i];
     if (t == 0)
-      for (int k = 0; k < qi.nseed; ++k) { L.seeds.push_back(T.seeds[qi.seed0 + k]); L.clears.push_back(T.seeds[qi.seed0 + k].bm); }
+      for (int k = 0; k < qi.nseed; ++k) {
+        L.seeds.push_back(T.seeds[qi.seed0 + k]);
+        if (!T.seeds_zeroed) L.clears.push_back(T.seeds[qi.seed0 + k].bm);
+      }
     DEntry e{qi.slot, t, qi.step0 + t, (int32_t)L.doms.size(), 0, 0};
     for (int k = 0; k < qi.ndom; ++k) {
       if (T.dom_step[qi.dom0 + k] != t) continue;
@@ -507,15 +511,36 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
     if (rc != GS_OK) { set_error("query " + std::to_string(i) + ": " + msg); return rc; }
   }
 
-  // 2. compile step programs; bitmaps at the front of this run's arena block
-  int64_t n_bitmaps = 0;
-  for (int i = 0; i < nq; ++i) n_bitmaps += (int64_t)Q[i].plan.seeds.size() + 2 * (int64_t)Q[i].plan.domains.size();
+  // 2. compile step programs; domain bitmaps at the front of this run's arena block, seed
+  // bitmaps from the engine's zeroed seed pool
+  int64_t n_bitmaps = 0, n_seed_bm = 0;
+  for (int i = 0; i < nq; ++i) {
+    n_bitmaps += 2 * (int64_t)Q[i].plan.domains.size();
+    n_seed_bm += (int64_t)Q[i].plan.seeds.size();
+  }
+  if (n_seed_bm > E.seed_pool_cap || (E.seed_pool_dirty && E.seed_pool)) {
+    if (n_seed_bm > E.seed_pool_cap) {
+      const int64_t cap = std::max<int64_t>(n_seed_bm, 2 * E.seed_pool_cap);
+      E.dfree(E.seed_pool);
+      E.seed_pool = nullptr;
+      E.seed_pool_cap = 0;
+      E.seed_pool = (uint64_t *)E.dmalloc(sizeof(uint64_t) * (size_t)words * (size_t)cap);
+      if (!E.seed_pool) { set_error("out of device memory for seed bitmaps"); return GS_ENOMEM; }
+      E.seed_pool_cap = cap;
+    }
+    HIPCHK(hipMemsetAsync(E.seed_pool, 0, sizeof(uint64_t) * (size_t)words * (size_t)E.seed_pool_cap, s));
+    E.seed_pool_dirty = false;
+  }
   uint64_t off = align256(E.tree_top);
   const uint64_t bm_off = off;
   off += align256((uint64_t)n_bitmaps * words * 8);
-  int64_t next_bm = 0;
-  auto next_bitmap = [&]() { return (uint64_t *)(E.tree_base + bm_off + (uint64_t)(next_bm++) * words * 8); };
+  int64_t next_bm = 0, next_seed = 0;
+  auto next_bitmap = [&](bool seed) {
+    if (seed) return E.seed_pool + (uint64_t)(next_seed++) * words;
+    return (uint64_t *)(E.tree_base + bm_off + (uint64_t)(next_bm++) * words * 8);
+  };
   Tables T;
+  T.seeds_zeroed = true;
   for (int i = 0; i < nq; ++i) {
     compile_query(E, Q[i], count_only, i, T, next_bitmap);
     maxk = std::max(maxk, Q[i].nlev);
@@ -636,12 +661,17 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
   }
   uint64_t *zero_p = (uint64_t *)dp(o_lvlp);
   const int64_t zero_n = (int64_t)((zero_end - o_lvlp) / 8);
+  const DSeed *all_seeds = (const DSeed *)dp(tab_off + o_seeds);
+  const int32_t n_seeds = (int32_t)seeds.size();
   auto launch_all = [&]() -> hipError_t {
     hipError_t e = zero_words(zero_p, zero_n, s);
     for (int t = 0; t < maxk && e == hipSuccess; ++t)
       e = launch_iteration(iargs[t], s, prof ? &E.events[(size_t)2 * KS_N * t] : nullptr);
+    // the seed bitmaps go back to zero: the words the seeds set (after an abort too)
+    if (e == hipSuccess && n_seeds > 0) e = launch_unseed(E.g, all_seeds, n_seeds, E.grid, s);
     return e;
   };
+  E.seed_pool_dirty = n_seeds > 0;   // until the run has finished: a failure leaves set bits behind
   HIPCHK(hipEventRecord(ev0, s));
   if (graphs) {
     // FNV-1a over every launch argument: equal keys launch identical kernels with identical arguments
@@ -651,6 +681,7 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
       for (size_t i = 0; i < n; ++i) { key ^= c[i]; key *= 1099511628211ull; }
     };
     mix(&zero_p, sizeof zero_p); mix(&zero_n, sizeof zero_n); mix(&maxk, sizeof maxk);
+    mix(&all_seeds, sizeof all_seeds); mix(&n_seeds, sizeof n_seeds);
     for (const IterArgs &A : iargs) mix(&A, sizeof A);
     Engine::GraphEntry *ge = nullptr;
     for (Engine::GraphEntry &g : E.graphs) if (g.key == key) ge = &g;
@@ -708,6 +739,7 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
   HIPCHK(hipMemcpyAsync(down, dp(o_lvlp), blk_bytes, hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(down + blk_bytes, E.d_arenas, sizeof(ar), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  E.seed_pool_dirty = false;
   auto hp = [&](uint64_t o) { return (const void *)(down + (o - o_lvlp)); };
   std::vector<int64_t> lvl_n((size_t)nq * kMaxLevels), qst((size_t)nq * QS_N), zero_res(nq);
   int32_t rflags[RF_N] = {0, 0};

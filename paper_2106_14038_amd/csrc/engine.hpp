@@ -74,6 +74,13 @@ struct Engine {
   int run_counter = 0;
   bool serving = false;            // a server owns the tree arena: direct evaluation is refused
 
+  // seed bitmaps of direct evaluation (grown on demand): all zero between runs, each run
+  // clearing after itself only the words its seeds set (a seed of a low-degree constant sets a
+  // few bits of an N-bit bitmap; clearing whole bitmaps per run cost more than the seeding)
+  uint64_t *seed_pool = nullptr;
+  int64_t seed_pool_cap = 0;       // bitmaps
+  bool seed_pool_dirty = false;    // a run failed after seeding: zero the pool again first
+
   // per-run workspaces (grown on demand)
   void *work = nullptr;
   size_t work_bytes = 0;
@@ -123,6 +130,7 @@ struct Tables {                      // compiled step programs of a set of queri
   std::vector<DDomain> doms;
   std::vector<int32_t> dom_step;
   std::vector<int32_t> var_rank;
+  bool seeds_zeroed = false;         // seed bitmaps come zeroed (the engine's seed pool): no clear pass
 };
 
 struct IterLists {                   // host work lists of one iteration
@@ -138,8 +146,9 @@ struct IterLists {                   // host work lists of one iteration
 };
 
 int plan_query(const Engine &E, const gs_query &q, QInfo &qi, std::string &msg);
+// next_bitmap(seed): a bitmap for a seed (true) or a domain (false)
 void compile_query(const Engine &E, QInfo &qi, bool count_only, int slot, Tables &T,
-                   const std::function<uint64_t *()> &next_bitmap);
+                   const std::function<uint64_t *(bool)> &next_bitmap);
 void build_iteration(const Tables &T, const std::vector<const QInfo *> &qs, const std::vector<int> &level,
                      IterLists &L);
 void account_iteration(Engine &E, const hipEvent_t *ev, const IterScalars &I, const IterLists &L, double write_bytes,

@@ -191,9 +191,11 @@ __global__ __launch_bounds__(1024) void k_it_setup(const IterArgs A) {
 
 // Zero every bitmap on the iteration's clear list.
 __global__ __launch_bounds__(kBlock) void k_clear(const IterArgs A) {
-  const int64_t W = A.g.words, total = (int64_t)A.nclear * W;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x)
-    A.clear[i / W][i % W] = 0ull;
+  const int64_t W = A.g.words, stride = (int64_t)gridDim.x * blockDim.x;
+  for (int32_t b = 0; b < A.nclear; ++b) {
+    uint64_t *bm = A.clear[b];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < W; i += stride) bm[i] = 0ull;
+  }
 }
 
 // Constant edges (c, p, x) / (x, p, c): the segment of c -> bitmap of x's candidates.
@@ -622,9 +624,11 @@ __device__ __forceinline__ void lookup_body(const IterArgs &A, int64_t *lds, int
           else len *= f;
         }
       }
-      it->lo[gn] = seg_ref(lo, dir, gen);
       cnt += (uint32_t)probes + ((uint32_t)lookups << 22);
-      it->len[gn] = counted ? 0 : hi - lo;   // a counted level's nodes take no part in the passes after the scan
+      if (!counted) {   // a counted level's nodes take no part in the passes after the scan
+        it->lo[gn] = seg_ref(lo, dir, gen);
+        it->len[gn] = hi - lo;
+      }
       cw += len;
     }
     {   // one reduction for both: entries above bit 11, non-empty nodes (at most kTileNodes) below;
@@ -799,6 +803,10 @@ __global__ __launch_bounds__(kBlock) void k_nz_write(const IterArgs A) {
     if (threadIdx.x == 0) sh_e = ncur.at(A, t);
     __syncthreads();
     const int e = uniform(sh_e);
+    if (counted_only(A.steps[A.ent[e].step])) {   // no segments recorded, no children, no tiles
+      __syncthreads();   // sh_e is rewritten for the next tile
+      continue;
+    }
     const int64_t i0 = (t - es[e].node_tile0) * kTileNodes + (int64_t)NPT * threadIdx.x, pn = es[e].prev_n;
     const int64_t ew = es[e].w, etile0 = es[e].w_tile0, wb = es[e].w_base, n0 = es[e].node0;
     int32_t *const cptr = es[e].cptr;
@@ -1373,6 +1381,32 @@ int expand_write_blocks_per_cu() {
       hipSuccess || nb < 1)
     nb = 4;
   return nb;
+}
+
+// Seed bitmaps back to zero after a run (they are kept zero between runs): a seed whose
+// segment is short clears the words its ids fall in, one with a segment longer than a
+// quarter of the bitmap's words clears the whole bitmap. Plain stores of zero: lanes that
+// meet in a word write the same value.
+__global__ __launch_bounds__(kBlock) void k_unseed(const DevGraph g, const DSeed *seeds, int32_t n) {
+  for (int32_t i = blockIdx.x; i < n; i += gridDim.x) {
+    const DSeed sd = seeds[i];
+    int64_t lo, hi;
+    int probes = 0;
+    seg_find(g, sd.dir, sd.c, sd.label, lo, hi, probes);
+    if (hi - lo > g.words / 4) {
+      for (int64_t w = threadIdx.x; w < g.words; w += kBlock) sd.bm[w] = 0ull;
+    } else {
+      const int32_t *ids = sd.dir ? g.idx[1] : g.idx[0];
+      for (int64_t x = lo + threadIdx.x; x < hi; x += kBlock) sd.bm[ids[x] >> 6] = 0ull;
+    }
+  }
+}
+
+hipError_t launch_unseed(const DevGraph &g, const DSeed *seeds, int32_t n, int grid, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_unseed, dim3((unsigned)std::min<int64_t>(n, std::max(grid, 1))), dim3(kBlock), 0, s, g,
+                     seeds, n);
+  return hipGetLastError();
 }
 
 hipError_t launch_iteration(const IterArgs &A, hipStream_t s, hipEvent_t *ev) {

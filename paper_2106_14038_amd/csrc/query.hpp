@@ -59,6 +59,9 @@ int expand_write_blocks_per_cu();
 
 // ev: null, or 2 * KS_N events recorded around each launch (slot k: ev[2k], ev[2k+1]).
 hipError_t launch_iteration(const IterArgs &A, hipStream_t s, hipEvent_t *ev = nullptr);
+// After a run: the n seeds' bitmaps back to zero (the words their segments set, or the whole
+// bitmap for a long segment); grid: workgroups at most.
+hipError_t launch_unseed(const DevGraph &g, const DSeed *seeds, int32_t n, int grid, hipStream_t s);
 hipError_t launch_list_only(const IterArgs &A, hipStream_t s);
 hipError_t launch_domain_only(const IterArgs &A, hipStream_t s);
 

@@ -225,7 +225,7 @@ int admit(ServerImpl &S, Request &rq, std::vector<Active *> &fresh) {
   for (int k = 0; k < need_bm; ++k) { a->bitmaps.push_back(S.free_bm.back()); S.free_bm.pop_back(); }
   int next = 0;
   const int64_t words = E.g.words;
-  auto next_bitmap = [&]() { return S.pool + (uint64_t)a->bitmaps[next++] * words; };
+  auto next_bitmap = [&](bool) { return S.pool + (uint64_t)a->bitmaps[next++] * words; };
   compile_query(E, a->qi, a->count_only, a->slot, a->T, next_bitmap);
   if (!rebase_tables(a->qi, a->T, a->slot) ||
       a->T.doms.size() > (size_t)kIterDomPerQuery * std::max<size_t>(1, a->qi.plan.n_vars)) {
