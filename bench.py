@@ -122,10 +122,10 @@ def cpu_baseline(trip, qs, per_query_T, budget_s, threads_all=None):
 
 
 def batched_set_leg(gs, eng, qset, wave=1024):
-    """The batched query set (1024 queries of the four shapes, counts 1..1e7): batched in
-    waves of `wave` queries (count only, each wave's trees freed before the next; by default
-    the whole set in one batch) vs the same queries one at a time; every count against the
-    stored oracle count."""
+    """The batched query set (the four shapes stratified by count decade): batched in waves of
+    `wave` queries (count only, each wave's trees freed before the next; by default the whole
+    set in one batch) vs the same queries one at a time, overall and per count decade; every
+    count against the stored oracle count."""
     import torch
     queries = [q["query"] for q in qset["queries"]]
     expect = [q["count"] for q in qset["queries"]]
@@ -150,19 +150,39 @@ def batched_set_leg(gs, eng, qset, wave=1024):
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
     t0 = time.perf_counter()
-    plain = []
+    plain, plain_s = [], []
     for q in queries:
-        r = gs.gs_query_run(eng, q, gs.GS_COUNT_ONLY)
+        t1 = time.perf_counter()
+        r = gs.gs_query_run(eng, q, gs.GS_COUNT_ONLY)   # returns after its stream has finished
         plain.append(gs.gs_result_count(r))
         gs.gs_result_free(r)
+        plain_s.append(time.perf_counter() - t1)
     torch.cuda.synchronize()
     tp = time.perf_counter() - t0
     if plain != expect:
         raise SystemExit("batched set: plain counts differ from the stored oracle counts")
+    # per count decade: that decade's queries as one batch against the same queries one at a time
+    decades = []
+    for d in range(9):
+        idx = [i for i, c in enumerate(expect) if 10 ** d <= max(c, 1) < 10 ** (d + 1)]
+        if not idx:
+            continue
+        sub = [queries[i] for i in idx]
+        for r in gs.gs_batch_run(eng, sub, gs.GS_COUNT_ONLY):   # warm-up
+            gs.gs_result_free(r)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for r in gs.gs_batch_run(eng, sub, gs.GS_COUNT_ONLY):
+            gs.gs_result_free(r)
+        torch.cuda.synchronize()
+        b = time.perf_counter() - t1
+        p_ = sum(plain_s[i] for i in idx)
+        decades.append({"counts": f"[1e{d}, 1e{d + 1})", "queries": len(idx), "batched_ms": b * 1e3,
+                        "plain_ms": p_ * 1e3, "speedup": p_ / b})
     out = {"queries": len(queries), "wave": wave, "batched_queries_per_s": len(queries) / tb,
            "plain_queries_per_s": len(queries) / tp, "speedup": tp / tb, "batched_ms": tb * 1e3,
            "plain_ms": tp * 1e3, "traversed_triples": int(T), "batched_triples_per_s": T / tb,
-           "counts_match_oracle": True}
+           "counts_match_oracle": True, "per_decade": decades}
     log(f"batched set: {out}")
     return out
 
@@ -382,7 +402,7 @@ def summarize_rocprof(args):
             for p in _find(d, "counter_collection.csv"):
                 with open(p) as f:
                     for r in csv.DictReader(f):
-                        name = r["Kernel_Name"].split("(")[0].replace("gs::", "")
+                        name = r["Kernel_Name"].split("(")[0].split("<")[0].replace("gs::", "")
                         a = acc.setdefault(name, {}).setdefault(r["Counter_Name"], {})
                         a[r["Dispatch_Id"]] = a.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
         def avg(name, c):
@@ -417,7 +437,8 @@ def summarize_rocprof(args):
             for p in _find(d, "counter_collection.csv"):
                 with open(p) as f:
                     for r in csv.DictReader(f):
-                        name = r["Kernel_Name"].split("(")[0]
+                        # all instances of a templated kernel together, as the engine's timing slots
+                        name = r["Kernel_Name"].split("(")[0].split("<")[0]
                         a = acc.setdefault((name, r["Counter_Name"]), {})
                         a[r["Dispatch_Id"]] = a.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
             return {k: (sum(v.values()) / len(v), len(v)) for k, v in acc.items()}
@@ -445,7 +466,10 @@ def summarize_rocprof(args):
         if args.bench_json:
             with open(args.bench_json) as f:
                 b = json.loads([ln for ln in f if ln.startswith("{")][-1])
-            alg = b["roofline"].get("alg_bytes_per_launch")
+            roof = b["roofline"]
+            if roof.get("kernel", "") not in args.kernel and isinstance(b.get("c1"), dict):
+                roof = b["c1"]["roofline"]   # the power-law legs of a 2B-triple run
+            alg = roof.get("alg_bytes_per_launch") if roof.get("kernel", "") in args.kernel else None
             if alg:
                 lines.append(f"alg_bytes_per_launch: {alg:.0f}")
                 lines.append(f"hbm_over_alg: {hbm / alg:.3f}")
@@ -670,19 +694,26 @@ def c4_cpu_baseline(torch, trip, qs, sel, label_nnz, per_query_T, budget_s):
     index_s = time.time() - t0
     nproc = os.cpu_count() or 1
 
-    def run(threads):
-        done, T, secs = 0, 0, 0.0
-        for i in pick:
-            q = sel[i]
-            t1 = time.perf_counter()
-            d = G.digest(q["query"], threads=threads)
-            secs += time.perf_counter() - t1
-            assert d == (q["count"], int(q["digest_sum"]), int(q["digest_xor"])), "oracle digest differs"
-            T += per_query_T[i]
-            done += 1
-            if secs > budget_s:
-                break
-        return {"value": T / secs if secs > 0 else None, "queries": done, "seconds": secs,
+    from concurrent.futures import ThreadPoolExecutor
+
+    def one_query(i):
+        q = sel[i]
+        d = G.digest(q["query"], threads=1)
+        assert d == (q["count"], int(q["digest_sum"]), int(q["digest_xor"])), "oracle digest differs"
+        return per_query_T[i]
+
+    def run(workers):
+        # whole passes over the sample until half the budget is spent; with several workers the
+        # queries of a pass run side by side (the oracle's calls release the interpreter lock)
+        done, T, passes = 0, 0, 0
+        t1 = time.perf_counter()
+        with ThreadPoolExecutor(max_workers=workers) as ex:
+            while passes == 0 or time.perf_counter() - t1 < budget_s / 2:
+                T += sum(ex.map(one_query, pick))
+                done += len(pick)
+                passes += 1
+        secs = time.perf_counter() - t1
+        return {"value": T / secs if secs > 0 else None, "queries": done, "passes": passes, "seconds": secs,
                 "queries_per_s": done / secs if secs > 0 else None}
 
     one, allc = run(1), run(nproc)
@@ -690,10 +721,13 @@ def c4_cpu_baseline(torch, trip, qs, sel, label_nnz, per_query_T, budget_s):
     return {"value": allc["value"], "unit": "triples/s", "cores": nproc, "kind": "oracle",
             "cpu_model": cpu_model(), "nproc": os.cpu_count(),
             "sample": f"{len(pick)} selective queries of the 2B-triple set (set order, those whose labels hold "
-                      f"at most 3e7 triples); the oracle's index holds the {len(sub)} triples of their labels "
-                      f"(built in {index_s:.1f}s, not timed); count and row digest, each checked against the "
-                      f"stored digest; value = the engine's traversed-triple count of the queries done / oracle "
-                      f"seconds; one thread: {one['queries']} queries in {one['seconds']:.1f}s",
+                      f"at most 3e7 triples), in whole passes for {budget_s / 2:.0f}s per setting; the oracle's "
+                      f"index holds the {len(sub)} triples of their labels (built in {index_s:.1f}s, not timed); "
+                      f"count and row digest, each checked against the stored digest; value = the engine's "
+                      f"traversed-triple count of the queries done / oracle seconds; one thread: "
+                      f"{one['queries']} queries ({one['passes']} passes) in {one['seconds']:.1f}s; "
+                      f"{nproc} threads, one query each at a time: {allc['queries']} queries in "
+                      f"{allc['seconds']:.1f}s",
             "one_core": one, "all_cores": allc}
 
 

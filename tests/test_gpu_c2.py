@@ -1,10 +1,10 @@
 """The batched query set at full size (power-law graph, N = 10M, M = 100M,
-256 labels; 1024 queries of the four shapes with random constants, counts
-spread over decades 1 .. 1e7): every query's rows from the batched form (in
-waves of 128) have the oracle's count and order-independent row digest stored
-with the set; the whole set as one count-only batch (the configuration the
-benchmark times) gives every stored count; the plain form gives the same
-digests on a seeded sample."""
+256 labels; walk queries of the four shapes with 0-2 constants, stratified by
+shape and count decade over 1 .. 1e8): every query's rows from the batched
+form (in waves of up to 128) have the oracle's count and, where the set holds
+one, its order-independent row digest; the whole set as one count-only batch
+(the configuration the benchmark times) gives every stored count; the plain
+form gives the same digests on a seeded sample."""
 import json
 import os
 
@@ -33,19 +33,27 @@ def test_c2_batched_counts_match_oracle():
     eng = gs.gs_engine_create(gs.options())
     try:
         gs.gs_load_triples(eng, qs["n"], qs["n_labels"], trip)
-        digests = [(q["count"], int(q["digest_sum"]), int(q["digest_xor"])) for q in qs["queries"]] \
-            if "digest_sum" in qs["queries"][0] else None
-        got = []
-        for i in range(0, len(queries), 128):
-            print(f"[c2] wave {i // 128}", flush=True)
-            rs = gs.gs_batch_run(eng, queries[i:i + 128])
+        # the oracle's digest where it has one (its backtracking has a time limit per query:
+        # the set lists the queries left with their count only)
+        digests = [(q["count"], int(q["digest_sum"]), int(q["digest_xor"])) if "digest_sum" in q else None
+                   for q in qs["queries"]]
+        assert sum(d is not None for d in digests) >= len(digests) - len(qs.get("no_digest", []))
+        got, i, wave = [], 0, 128
+        while i < len(queries):
+            print(f"[c2] queries {i}.. in a wave of {wave}", flush=True)
+            try:
+                rs = gs.gs_batch_run(eng, queries[i:i + wave])
+            except gs.GsError as err:   # the wave's trees exceed the tree arena: smaller waves
+                assert err.status == gs.GS_ENOMEM and wave > 1
+                wave //= 2
+                continue
             got += [gs.gs_result_digest(r) for r in rs]
             for r in rs:
                 gs.gs_result_free(r)
+            i += wave
         assert [g[0] for g in got] == expect
-        if digests:
-            bad = [i for i, (g, d) in enumerate(zip(got, digests)) if g != d]
-            assert not bad, bad[:10]
+        bad = [i for i, (g, d) in enumerate(zip(got, digests)) if d is not None and g != d]
+        assert not bad, bad[:10]
         print("[c2] the whole set as one batch", flush=True)   # the configuration the benchmark times
         rs = gs.gs_batch_run(eng, queries, gs.GS_COUNT_ONLY)
         whole = [gs.gs_result_count(r) for r in rs]

@@ -8,6 +8,8 @@ same stream is tried. Run from the repository root:
 
     python -m workload.make_querysets [--set c1|c2|c3] [--scale 1.0] [--per-shape 25] [--total 1024]
     python -m workload.make_querysets --set c1 --digests   (add row digests to an existing set)
+    python -m workload.make_querysets --set c2 --per-bucket 32 --shape-budget 900 --procs 3
+    python -m workload.make_querysets --set c2 --digests --digest-timeout 300 --procs 6
     python -m workload.make_querysets --set c4 --work-cap 50000000 --per-shape 12 --shape-budget 1500 --procs 6
 
 c1: 25 queries per shape (chain-4, star-5, snowflake-8, triangle), counts in
@@ -216,21 +218,75 @@ def c4_set(args, t0):
     print("wrote", path, {k: len(v) for k, v in sel.items()}, "large", len(large), flush=True)
 
 
-def add_digests(path, threads, t0):
+def _digest_child(q, conn):
+    try:
+        conn.send(_G.digest(q, threads=1, support_filter=True))
+    except Exception as e:   # noqa: BLE001 - reported to the parent
+        conn.send(repr(e))
+    conn.close()
+
+
+def add_digests(path, procs, t0, timeout_s=0.0):
     """Add the oracle's order-independent row digest (count, sum and XOR of the row
-    hashes) to every query of an existing set file, evaluated by backtracking on
-    `threads` host threads; the digest's count must equal the stored count."""
+    hashes) to every query of an existing set file, evaluated by backtracking; the
+    digest's count must equal the stored count. timeout_s > 0: each query's
+    backtracking runs in a forked child, `procs` at a time, and one that has not
+    finished after timeout_s seconds is stopped: that query keeps its count without a
+    digest, and the set lists it under "no_digest"."""
     with open(path) as f:
         out = json.load(f)
-    for i, rec in enumerate(out["queries"]):
-        q = dict(rec["query"])
-        q["edges"] = [tuple(e) for e in q["edges"]]
-        ts = time.time()
-        cnt, hs, hx = _G.digest(q, threads=threads, support_filter=True)
+    recs = out["queries"]
+
+    def finish(i, res, ts):
+        rec = recs[i]
+        if isinstance(res, str):
+            raise SystemExit(f"query {i}: oracle error {res}")
+        cnt, hs, hx = res
         if cnt != rec["count"]:
             raise SystemExit(f"query {i}: backtracking count {cnt} != stored count {rec['count']}")
         rec["digest_sum"], rec["digest_xor"] = str(hs), str(hx)
         print(f"digest {i} {rec['shape']} count={cnt} {time.time() - ts:.1f}s ({time.time() - t0:.0f}s)", flush=True)
+
+    todo = [i for i, r in enumerate(recs) if "digest_sum" not in r]
+    skipped = []
+    if timeout_s <= 0:
+        for i in todo:
+            q = dict(recs[i]["query"])
+            q["edges"] = [tuple(e) for e in q["edges"]]
+            ts = time.time()
+            finish(i, _G.digest(q, threads=procs, support_filter=True), ts)
+    else:
+        ctx = mp.get_context("fork")
+        running = {}   # i -> (process, parent end of the pipe, start)
+        while todo or running:
+            while todo and len(running) < procs:
+                i = todo.pop(0)
+                q = dict(recs[i]["query"])
+                q["edges"] = [tuple(e) for e in q["edges"]]
+                a, b = ctx.Pipe(duplex=False)
+                p = ctx.Process(target=_digest_child, args=(q, b))
+                p.start()
+                b.close()
+                running[i] = (p, a, time.time())
+            time.sleep(0.05)
+            for i in list(running):
+                p, a, ts = running[i]
+                if a.poll():
+                    res = a.recv()
+                    p.join()
+                    del running[i]
+                    finish(i, res, ts)
+                elif time.time() - ts > timeout_s:
+                    p.kill()
+                    p.join()
+                    del running[i]
+                    skipped.append(i)
+                    print(f"digest {i} {recs[i]['shape']} count={recs[i]['count']}: stopped after {timeout_s:.0f}s",
+                          flush=True)
+    if skipped:
+        out["no_digest"] = sorted(skipped)
+        out["no_digest_note"] = (f"the oracle's backtracking did not finish within {timeout_s:.0f}s for these "
+                                 "queries: their counts (message passing) stand without a row digest")
     out["digest"] = ("row digest: count, sum mod 2^64 and XOR of per-row hashes (oracle.c), rows listing the "
                      "variables in ascending query-vertex index")
     with open(path + ".tmp", "w") as f:
@@ -253,6 +309,8 @@ def main():
     ap.add_argument("--procs", type=int, default=min(8, os.cpu_count() or 1))
     ap.add_argument("--shape-budget", type=float, default=1200.0, help="seconds per shape (batched set)")
     ap.add_argument("--digests", action="store_true", help="add row digests to the existing set file")
+    ap.add_argument("--digest-timeout", type=float, default=0.0,
+                    help="with --digests: seconds per query in a forked child (0: no limit, in process)")
     ap.add_argument("--per-bucket", type=int, default=32, help="batched set: queries per shape and count decade")
     args = ap.parse_args()
     t0 = time.time()
@@ -269,7 +327,8 @@ def main():
            "note": "counts written by the oracle (workload/make_querysets.py)", "queries": []}
     sc = "" if args.scale == 1.0 else f"s{args.scale:g}"
     if args.digests:
-        add_digests(os.path.join(ROOT, "workload", "data", f"{args.set}{sc}_queries.json"), args.procs, t0)
+        add_digests(os.path.join(ROOT, "workload", "data", f"{args.set}{sc}_queries.json"), args.procs, t0,
+                    args.digest_timeout)
         return
     ctx = mp.get_context("fork")
     if args.set != "c1":
