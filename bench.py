@@ -355,6 +355,17 @@ def copy_probe(gib=1):
     print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "launches": 5}), flush=True)
 
 
+def kernel_base_name(raw):
+    """A kernel's name for the summaries: the engine's templated kernels (one instance per stored
+    width and variant) under one name, as its timing slots; other kernels as rocprofv3 names them."""
+    name = raw.replace("(anonymous namespace)::", "").split("(")[0]
+    if name.startswith("void "):
+        name = name[5:]
+    if name.startswith("gs::"):
+        name = name[4:].split("<")[0]
+    return name
+
+
 def _find(d, suffix):
     out = []
     for root, _, files in os.walk(d):
@@ -391,7 +402,8 @@ def summarize_rocprof(args):
         rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
         lines.append(f"{'kernel':60s} {'calls':>7s} {'total_ms':>10s} {'avg_us':>10s} {'pct':>6s}")
         for r in rows[:24]:
-            name = r["Name"].split("(")[0][:60]
+            nm = r["Name"].replace("(anonymous namespace)::", "")
+            name = nm.split("(")[0][:60]
             lines.append(f"{name:60s} {int(r['Calls']):7d} {float(r['TotalDurationNs']) / 1e6:10.3f} "
                          f"{float(r['AverageNs']) / 1e3:10.2f} {float(r['Percentage']):6.2f}")
     elif args.summarize == "counters":
@@ -402,7 +414,7 @@ def summarize_rocprof(args):
             for p in _find(d, "counter_collection.csv"):
                 with open(p) as f:
                     for r in csv.DictReader(f):
-                        name = r["Kernel_Name"].split("(")[0].split("<")[0].replace("gs::", "")
+                        name = kernel_base_name(r["Kernel_Name"])
                         a = acc.setdefault(name, {}).setdefault(r["Counter_Name"], {})
                         a[r["Dispatch_Id"]] = a.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
         def avg(name, c):
@@ -437,8 +449,7 @@ def summarize_rocprof(args):
             for p in _find(d, "counter_collection.csv"):
                 with open(p) as f:
                     for r in csv.DictReader(f):
-                        # all instances of a templated kernel together, as the engine's timing slots
-                        name = r["Kernel_Name"].split("(")[0].split("<")[0]
+                        name = kernel_base_name(r["Kernel_Name"])
                         a = acc.setdefault((name, r["Counter_Name"]), {})
                         a[r["Dispatch_Id"]] = a.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
             return {k: (sum(v.values()) / len(v), len(v)) for k, v in acc.items()}
