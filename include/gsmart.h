@@ -30,7 +30,9 @@
  *    destroy/free/stop call. A gs_engine is not re-entrant: calls on one
  *    engine must not overlap, except the gs_server_* calls, which lock.
  *  - Work runs on the stream given in gs_options (NULL: the library's own).
- *    Calls that return host data synchronise that stream.
+ *    Calls that return host data synchronise that stream. Device inputs are
+ *    read in that stream's order: data written on another stream must be
+ *    complete (synchronised) before the call.
  */
 #ifndef GSMART_H
 #define GSMART_H
