@@ -275,8 +275,11 @@ __device__ __forceinline__ void label_range_short(const void *lab, I a, I e, uin
       const uint64_t w0 = gld(p), w1 = gld(p + 1);
       x0 = sh ? (w0 >> (8 * sh)) | (w1 << (64 - 8 * sh)) : w0;   // entries a .. a+7, one byte each
     } else {
-      const uint64_t *p = (const uint64_t *)((const uint16_t *)lab + base);
-      const uint64_t w0 = gld(p), w1 = gld(p + 1), w2 = gld(p + 2), w3 = gld(p + 3);
+      // two 16-byte loads (base is 16-byte aligned)
+      typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
+      const u64x2 *p = (const u64x2 *)((const uint16_t *)lab + base);
+      const u64x2 wa = gld(p), wb = gld(p + 1);
+      const uint64_t w0 = wa.x, w1 = wa.y, w2 = wb.x, w3 = wb.y;
       const bool q = sh >= 4;
       const int r = sh & 3;
       uint64_t y0 = q ? w1 : w0, y1 = q ? w2 : w1, y2 = q ? w3 : w2;
@@ -316,11 +319,14 @@ __device__ __forceinline__ void label_range_w(const void *lab, I a, I e, int32_t
   const uint32_t key = (uint32_t)label;
   const void *row = (const char *)lab + (int64_t)a * LB;
   const int32_t n = (int32_t)(e - a);
+  // while the two intervals coincide (every probe so far missed the label's entries) the
+  // bounds read the same entry: one load serves both
   int32_t l1 = 0, h1 = n, l2 = 0, h2 = n;
   while (l1 < h1 || l2 < h2) {
-    const bool s1 = l1 < h1, s2 = l2 < h2;
+    const bool s1 = l1 < h1, s2 = l2 < h2, same = l1 == l2 && h1 == h2;
     const int32_t m1 = (l1 + h1) >> 1, m2 = (l2 + h2) >> 1;
-    const uint32_t v1 = s1 ? lab_w<LB>(row, m1) : 0u, v2 = s2 ? lab_w<LB>(row, m2) : 0u;
+    const uint32_t v1 = s1 ? lab_w<LB>(row, m1) : 0u;
+    const uint32_t v2 = same ? v1 : s2 ? lab_w<LB>(row, m2) : 0u;
     if (s1) { if (v1 < key) l1 = m1 + 1; else h1 = m1; }
     if (s2) { if (v2 <= key) l2 = m2 + 1; else h2 = m2; }
   }
