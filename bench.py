@@ -496,7 +496,8 @@ def profile_leg(gs, torch, args, qs, trip):
     """One leg alone (warm-up passes, then `steps` passes), each pass logged: the plain
     form (the query set one query at a time), the batched step, or the batched query set
     as one count-only batch."""
-    eng = gs.gs_engine_create(gs.options(device=0, hip_stream=torch.cuda.current_stream().cuda_stream))
+    eng = gs.gs_engine_create(gs.options(device=0, hip_stream=torch.cuda.current_stream().cuda_stream,
+                                         grid_blocks=args.grid_blocks))
     t = torch.from_numpy(trip).cuda()
     gs.gs_load_triples(eng, qs["n"], qs["n_labels"], t)
     del t
@@ -525,7 +526,8 @@ def c4_profile_leg(gs, torch, args):
     sel = [q["query"] for q in qs["queries"] if q["group"] == "selective"]
     large = [q["query"] for q in qs["queries"] if q["group"] == "large"]
     trip = workload.c4_stream(qs["scale"]).device_graph(qs["draws"])
-    eng = gs.gs_engine_create(gs.options(device=0, hip_stream=torch.cuda.current_stream().cuda_stream, **C4_OPTS))
+    eng = gs.gs_engine_create(gs.options(device=0, hip_stream=torch.cuda.current_stream().cuda_stream,
+                                         grid_blocks=args.grid_blocks, **C4_OPTS))
     gs.gs_load_triples(eng, qs["n"], qs["n_labels"], trip)
     del trip
     torch.cuda.empty_cache()
@@ -580,6 +582,9 @@ def main():
     ap.add_argument("--copy-probe", action="store_true", help="run the HBM counter reference copy and exit")
     ap.add_argument("--profile-leg", choices=["plain", "batched", "set", "c4"],
                     help="run only that leg, on an engine without per-kernel events, and exit (for rocprofv3)")
+    ap.add_argument("--grid-blocks", type=int, default=0,
+                    help="--profile-leg: workgroups of the fixed-grid kernels (the autotuner's choice in the "
+                         "bench line being profiled; 0 = the engine's default)")
     ap.add_argument("--summarize", choices=["trace", "traffic", "counters"],
                     help="summarise rocprofv3 output and exit")
     ap.add_argument("--dir")
