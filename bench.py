@@ -406,6 +406,19 @@ def summarize_rocprof(args):
             name = nm.split("(")[0][:60]
             lines.append(f"{name:60s} {int(r['Calls']):7d} {float(r['TotalDurationNs']) / 1e6:10.3f} "
                          f"{float(r['AverageNs']) / 1e3:10.2f} {float(r['Percentage']):6.2f}")
+        # the engine's kernels with their template instances together (the bench's per-kernel
+        # figures count every instance of a kernel)
+        merged = {}
+        for r in rows:
+            base = kernel_base_name(r["Name"])
+            if not r["Name"].replace("void ", "").startswith("gs::"):
+                continue
+            c, t = merged.get(base, (0, 0.0))
+            merged[base] = (c + int(r["Calls"]), t + float(r["TotalDurationNs"]))
+        lines.append("engine kernels, template instances together:")
+        lines.append(f"{'kernel':60s} {'calls':>7s} {'total_ms':>10s} {'avg_us':>10s}")
+        for base, (c, t) in sorted(merged.items(), key=lambda kv: -kv[1][1])[:16]:
+            lines.append(f"{base:60s} {c:7d} {t / 1e6:10.3f} {t / c / 1e3:10.2f}")
     elif args.summarize == "counters":
         # per kernel and counter: the average per dispatch over the runs in --dirs (one counter
         # group per run); HBM bytes scaled by the plain copy's reading; L2 hit rate
