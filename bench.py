@@ -510,7 +510,7 @@ def profile_leg(gs, torch, args, qs, trip):
     form (the query set one query at a time), the batched step, or the batched query set
     as one count-only batch."""
     eng = gs.gs_engine_create(gs.options(device=0, hip_stream=torch.cuda.current_stream().cuda_stream,
-                                         grid_blocks=args.grid_blocks))
+                                         grid_blocks=args.grid_blocks, write_block=args.write_block))
     t = torch.from_numpy(trip).cuda()
     gs.gs_load_triples(eng, qs["n"], qs["n_labels"], t)
     del t
@@ -540,7 +540,7 @@ def c4_profile_leg(gs, torch, args):
     large = [q["query"] for q in qs["queries"] if q["group"] == "large"]
     trip = workload.c4_stream(qs["scale"]).device_graph(qs["draws"])
     eng = gs.gs_engine_create(gs.options(device=0, hip_stream=torch.cuda.current_stream().cuda_stream,
-                                         grid_blocks=args.grid_blocks, **C4_OPTS))
+                                         grid_blocks=args.grid_blocks, write_block=args.write_block, **C4_OPTS))
     gs.gs_load_triples(eng, qs["n"], qs["n_labels"], trip)
     del trip
     torch.cuda.empty_cache()
@@ -598,6 +598,9 @@ def main():
     ap.add_argument("--grid-blocks", type=int, default=0,
                     help="--profile-leg: workgroups of the fixed-grid kernels (the autotuner's choice in the "
                          "bench line being profiled; 0 = the engine's default)")
+    ap.add_argument("--write-block", type=int, default=0,
+                    help="--profile-leg: threads per write-pass workgroup (the autotuner's choice in the bench "
+                         "line being profiled; 0 = the engine's default)")
     ap.add_argument("--summarize", choices=["trace", "traffic", "counters"],
                     help="summarise rocprofv3 output and exit")
     ap.add_argument("--dir")
@@ -662,7 +665,7 @@ def autotune(gs, eng, calib, args):
     r = gs.gs_autotune(eng, calib)
     out = {"grid_blocks": r.grid_blocks, "push_pull_theta": r.push_pull_theta, "best_ms": r.best_ms,
            "default_ms": r.default_ms, "tried": r.n_tried, "calibration_queries": len(calib),
-           "block_size": 256, "tune_s": time.perf_counter() - t}
+           "write_block": r.write_block, "tune_s": time.perf_counter() - t}
     log(f"autotune: {out}")
     return out
 
@@ -820,7 +823,9 @@ def run_c4(args, gs, torch):
     assert (n, P, m) == (qs["n"], qs["n_labels"], qs["m"]), "stored graph sizes differ"
     label_nnz = gs.gs_label_stats(eng)[0]
     log(f"load {load_ms:.0f} ms, {m} distinct triples, {dev_bytes / 2**30:.1f} GiB on the device")
-    tune = autotune(gs, eng, [q["query"] for q in sel[::4]], args)
+    # calibration: a quarter of the selective queries and the large ones, whose levels hold most
+    # of the step's lookups (count only, one batch)
+    tune = autotune(gs, eng, [q["query"] for q in sel[::4] + large], args)
     for _ in range(max(args.warmup, 1)):
         counts, stats = step(eng)
     if counts != expect:

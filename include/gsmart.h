@@ -113,6 +113,8 @@ typedef struct {
   const char *autotune_cache; /* optional text file of tuned settings: gs_autotune records its choice for
                                  the loaded graph's sizes there, gs_load_triples applies a recorded one */
   int32_t traversal;          /* GS_TRAVERSAL_*: the planner's traversal for queries without constants */
+  int32_t write_block;        /* threads per workgroup of the write pass: 128, 256 or 512; 0 = 256 (a recorded
+                                 autotune setting replaces it at load) */
 } gs_options;
 
 /* Query-graph traversal that orders the evaluation (Section 6.1): degree-driven
@@ -409,17 +411,20 @@ gs_status gs_kernel_stats(gs_engine *engine, gs_kernel_stat *out, int32_t cap, i
 
 /* Autotuner: evaluates the given queries (count only, batched) under every
  * candidate workgroup count of the fixed-grid kernels (2, 4, 8, 12 and 16 per
- * compute unit) and push/pull threshold (0.25, 1, 4), keeps the fastest pair
+ * compute unit) and push/pull threshold (0.25, 1, 4), then, with the fastest
+ * pair, under every workgroup size of the write pass (128, 256 or 512 threads,
+ * as many workgroups as the device holds at once); keeps the fastest setting
  * for this engine's later calls, and reports it; with gs_options.autotune_cache
- * set, the pair is also recorded there for the loaded graph's sizes (n, m, P),
- * and a later engine loading a graph of those sizes starts from it. Results
- * are unchanged by the choice. Errors as gs_batch_run. */
+ * set, the setting is also recorded there for the loaded graph's sizes (n, m,
+ * P), and a later engine loading a graph of those sizes starts from it.
+ * Results are unchanged by the choice. Errors as gs_batch_run. */
 typedef struct {
   int32_t grid_blocks;
   float push_pull_theta;
-  double best_ms;             /* device time of the calibration batch with the chosen pair */
+  double best_ms;             /* device time of the calibration batch with the chosen setting */
   double default_ms;          /* same with the engine's settings before tuning */
   int32_t n_tried;
+  int32_t write_block;        /* threads per workgroup of the write pass */
 } gs_tune_result;
 gs_status gs_autotune(gs_engine *engine, const gs_query *queries, int32_t nq, gs_tune_result *out);
 

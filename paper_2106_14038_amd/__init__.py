@@ -58,7 +58,7 @@ class gs_options(ctypes.Structure):
                 ("push_pull_theta", ctypes.c_float), ("grid_blocks", ctypes.c_int32),
                 ("use_graphs", ctypes.c_int32), ("profile_kernels", ctypes.c_int32),
                 ("offset_bytes", ctypes.c_int32), ("autotune_cache", ctypes.c_char_p),
-                ("traversal", ctypes.c_int32)]
+                ("traversal", ctypes.c_int32), ("write_block", ctypes.c_int32)]
 
 
 class gs_query_stats(ctypes.Structure):
@@ -89,7 +89,7 @@ class gs_kernel_stat(ctypes.Structure):
 
 class gs_tune_result(ctypes.Structure):
     _fields_ = [("grid_blocks", ctypes.c_int32), ("push_pull_theta", ctypes.c_float), ("best_ms", ctypes.c_double),
-                ("default_ms", ctypes.c_double), ("n_tried", ctypes.c_int32)]
+                ("default_ms", ctypes.c_double), ("n_tried", ctypes.c_int32), ("write_block", ctypes.c_int32)]
 
 
 class gs_server_options(ctypes.Structure):

@@ -76,37 +76,51 @@ void *scratch_ptr(int device) {
 }
 
 // Autotune cache: one line per graph, "n m P grid theta".
-bool tune_cache_lookup(const Engine &E, const char *path, int *grid, float *theta) {
+// One line per graph size: n m P grid theta write_block (lines of five fields: 256 threads).
+static bool tune_line(const char *line, long long &n, long long &m, int &P, int &g, float &th, int &wb) {
+  wb = 256;
+  const int k = sscanf(line, "%lld %lld %d %d %f %d", &n, &m, &P, &g, &th, &wb);
+  return k >= 5;
+}
+
+bool tune_cache_lookup(const Engine &E, const char *path, int *grid, float *theta, int *write_block) {
   FILE *f = fopen(path, "r");
   if (!f) return false;
+  char line[256];
   long long n, m;
-  int P, g;
+  int P, g, wb;
   float th;
   bool hit = false;
-  while (fscanf(f, "%lld %lld %d %d %f", &n, &m, &P, &g, &th) == 5)
-    if (n == E.g.n && m == E.g.m && P == E.g.P && g > 0) { *grid = g; *theta = th; hit = true; }
+  while (fgets(line, sizeof line, f))
+    if (tune_line(line, n, m, P, g, th, wb) && n == E.g.n && m == E.g.m && P == E.g.P && g > 0) {
+      *grid = g;
+      *theta = th;
+      *write_block = wb;
+      hit = true;
+    }
   fclose(f);
   return hit;
 }
 
-bool tune_cache_store(const Engine &E, const char *path, int grid, float theta) {
+bool tune_cache_store(const Engine &E, const char *path, int grid, float theta, int write_block) {
   std::vector<std::string> keep;
   if (FILE *f = fopen(path, "r")) {
+    char line[256];
     long long n, m;
-    int P, g;
+    int P, g, wb;
     float th;
-    while (fscanf(f, "%lld %lld %d %d %f", &n, &m, &P, &g, &th) == 5) {
-      if (n == E.g.n && m == E.g.m && P == E.g.P) continue;
-      char line[128];
-      snprintf(line, sizeof line, "%lld %lld %d %d %g\n", n, m, P, g, th);
-      keep.push_back(line);
+    while (fgets(line, sizeof line, f)) {
+      if (!tune_line(line, n, m, P, g, th, wb) || (n == E.g.n && m == E.g.m && P == E.g.P)) continue;
+      char out[160];
+      snprintf(out, sizeof out, "%lld %lld %d %d %g %d\n", n, m, P, g, th, wb);
+      keep.push_back(out);
     }
     fclose(f);
   }
   FILE *f = fopen(path, "w");
   if (!f) return false;
   for (const std::string &l : keep) fputs(l.c_str(), f);
-  fprintf(f, "%lld %lld %d %d %g\n", (long long)E.g.n, (long long)E.g.m, E.g.P, grid, theta);
+  fprintf(f, "%lld %lld %d %d %g %d\n", (long long)E.g.n, (long long)E.g.m, E.g.P, grid, theta, write_block);
   return fclose(f) == 0;
 }
 
@@ -131,6 +145,10 @@ gs_status gs_engine_create(const gs_options *options, gs_engine **out) {
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) { set_error("no HIP device"); return GS_EDEVICE; }
   if (o.device < 0 || o.device >= ndev) { set_error("device ordinal out of range"); return GS_EINVAL; }
+  if (o.write_block != 0 && o.write_block != 128 && o.write_block != 256 && o.write_block != 512) {
+    set_error("write_block must be 0, 128, 256 or 512");
+    return GS_EINVAL;
+  }
   gs_engine *ge = new (std::nothrow) gs_engine();
   if (!ge) return GS_ENOMEM;
   Engine &E = ge->e;
@@ -150,7 +168,8 @@ gs_status gs_engine_create(const gs_options *options, gs_engine **out) {
   if (hipGetDeviceProperties(&prop, E.device) == hipSuccess) E.cus = prop.multiProcessorCount;
   E.grid = o.grid_blocks > 0 ? o.grid_blocks : 12 * E.cus;
   if (E.grid > 8192) E.grid = 8192;
-  E.wgrid = expand_write_blocks_per_cu() * E.cus;
+  E.wwaves = o.write_block ? o.write_block / 64 : 4;
+  E.wgrid = expand_write_blocks_per_cu(E.wwaves) * E.cus;
   if (o.hip_stream) {
     E.stream = (hipStream_t)o.hip_stream;
   } else {
@@ -187,11 +206,15 @@ gs_status gs_load_triples(gs_engine *engine, int64_t n_vertices, int32_t n_label
   Engine &E = engine->e;
   const int rc = load_triples(E, n_vertices, n_labels, triples, m, mem_kind);
   if (rc == GS_OK && E.opt.autotune_cache) {   // a recorded tuning for a graph of these sizes
-    int grid = 0;
+    int grid = 0, wb = 256;
     float theta = 0;
-    if (tune_cache_lookup(E, E.opt.autotune_cache, &grid, &theta)) {
+    if (tune_cache_lookup(E, E.opt.autotune_cache, &grid, &theta, &wb)) {
       E.grid = std::min(grid, 8192);
       E.opt.push_pull_theta = theta;
+      if (wb == 128 || wb == 256 || wb == 512) {
+        E.wwaves = wb / 64;
+        E.wgrid = expand_write_blocks_per_cu(E.wwaves) * E.cus;
+      }
     }
   }
   return (gs_status)rc;
@@ -350,7 +373,7 @@ gs_status gs_bitmap_and_compact(gs_engine *engine, const uint64_t *const *bitmap
   ar[1] = {0, E.scratch_cap, 0, 0};
   HIPRET(hipMemcpyAsync(E.d_arenas, ar, sizeof ar, hipMemcpyHostToDevice, s));
   IterArgs A{};
-  A.g = E.g; A.ent = en; A.E = 1; A.grid = E.grid; A.wgrid = E.wgrid; A.steps = st; A.filt = ft; A.es = es; A.it = it;
+  A.g = E.g; A.ent = en; A.E = 1; A.grid = E.grid; A.wgrid = E.wgrid; A.wwaves = E.wwaves; A.steps = st; A.filt = ft; A.es = es; A.it = it;
   A.lvl_ptr = lp; A.lvl_n = ln; A.qstats = qs; A.scratch = E.d_arenas + 1; A.scratch_base = E.scratch_base;
   A.tree = E.d_arenas; A.tree_base = E.tree_base; A.has_list = 1;
   A.blk_a = blk; A.blk_b = blk + E.grid; A.blk_off_a = blk + 2 * E.grid; A.blk_off_b = blk + 3 * E.grid;
@@ -652,11 +675,26 @@ gs_status gs_autotune(gs_engine *engine, const gs_query *queries, int32_t nq, gs
       if (rc == GS_OK && ms < out->best_ms) { out->best_ms = ms; out->grid_blocks = grid; out->push_pull_theta = th; }
     }
   }
+  // then the write pass's workgroup size (2, 4 or 8 waves) under the chosen pair
+  const int ww0 = E.wwaves, wg0 = E.wgrid;
+  out->write_block = 64 * ww0;
+  for (int nw : {2, 4, 8}) {
+    if (rc != GS_OK || nw == ww0) continue;
+    E.wwaves = nw;
+    E.wgrid = expand_write_blocks_per_cu(nw) * E.cus;
+    double ms = 0;
+    rc = trial(out->grid_blocks, out->push_pull_theta, ms);
+    out->n_tried++;
+    if (rc == GS_OK && ms < out->best_ms) { out->best_ms = ms; out->write_block = 64 * nw; }
+  }
   E.opt.profile_kernels = prof0;
-  if (rc != GS_OK) { E.grid = grid0; E.opt.push_pull_theta = theta0; return (gs_status)rc; }
+  if (rc != GS_OK) { E.grid = grid0; E.opt.push_pull_theta = theta0; E.wwaves = ww0; E.wgrid = wg0; return (gs_status)rc; }
   E.grid = out->grid_blocks;
   E.opt.push_pull_theta = out->push_pull_theta;
-  if (E.opt.autotune_cache && !tune_cache_store(E, E.opt.autotune_cache, out->grid_blocks, out->push_pull_theta)) {
+  E.wwaves = out->write_block / 64;
+  E.wgrid = expand_write_blocks_per_cu(E.wwaves) * E.cus;
+  if (E.opt.autotune_cache &&
+      !tune_cache_store(E, E.opt.autotune_cache, out->grid_blocks, out->push_pull_theta, out->write_block)) {
     set_error(std::string("cannot write the autotune cache ") + E.opt.autotune_cache);
     return GS_EINVAL;
   }

@@ -636,6 +636,7 @@ int run_batch(Engine &E, const gs_query *qs, int nq, uint32_t flags, std::vector
     A.has_exact = its[t].has_exact;
     A.grid = E.grid;
     A.wgrid = E.wgrid;
+    A.wwaves = E.wwaves;
     A.steps = (const DStep *)dp(tab_off + o_steps);
     A.filt = (const uint64_t *const *)dp(tab_off + o_filt);
     A.checks = (const DCheck *)dp(tab_off + o_chk);

@@ -48,6 +48,7 @@ struct Engine {
   gs_options opt{};
   int grid = 3072;    // fixed-grid kernels: 12 workgroups per CU unless the options say otherwise
   int wgrid = 1024;   // write-pass workgroups: as many as the device holds at once
+  int wwaves = 4;     // waves per write-pass workgroup (2, 4 or 8; the autotuner may change it)
   int cus = 256;
 
   // matrix

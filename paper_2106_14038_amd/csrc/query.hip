@@ -1213,8 +1213,11 @@ __global__ __launch_bounds__(kBlock) void k_tile_offsets(const IterArgs A) {
 // item's output position is ranked first (tile offset + item for test-free
 // levels, + rank among the valid items otherwise); then each lane reads the
 // nodes and candidates of all its items before it issues their stores.
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_expand_write(const IterArgs A) {
-  __shared__ WaveTile Wt[kWaves];
+// NW waves per workgroup (2, 4 or 8): every wave works on its own tiles with its own staging
+// slot, so the workgroup size only sets how the waves are grouped onto compute units.
+template <int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(6))) void k_expand_write(const IterArgs A) {
+  __shared__ WaveTile Wt[NW];
   const IterScalars *it = A.it;
   if (sld(&it->abort)) return;
   const EState *es = A.es;
@@ -1226,8 +1229,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
   wave_lds_sync();
   const DTile *tiles = sld(&it->tiles);
   const uint32_t *valid = sld(&it->valid);
-  const int64_t ntiles = sld(&it->work_tiles), stride = (int64_t)gridDim.x * kWaves;
-  int64_t t = (int64_t)blockIdx.x * kWaves + wv;
+  const int64_t ntiles = sld(&it->work_tiles), stride = (int64_t)gridDim.x * NW;
+  int64_t t = (int64_t)blockIdx.x * NW + wv;
   if (t >= ntiles) return;
   DTile d1 = sld(tiles + t), d1n = sld(tiles + t + 1), d2{}, d2n{};
   int nw1 = win_nodes(d1, d1n);
@@ -1375,11 +1378,13 @@ __global__ __launch_bounds__(kBlock) void k_row_digest(int32_t *const *lvl_ptr, 
 }
 
 // ---------------------------------------------------------------- launchers
-int expand_write_blocks_per_cu() {
+int expand_write_blocks_per_cu(int waves) {
+  const void *k = waves == 2   ? reinterpret_cast<const void *>(k_expand_write<2>)
+                  : waves == 8 ? reinterpret_cast<const void *>(k_expand_write<8>)
+                               : reinterpret_cast<const void *>(k_expand_write<4>);
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(k_expand_write), kBlock, 0) !=
-      hipSuccess || nb < 1)
-    nb = 4;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 64 * waves, 0) != hipSuccess || nb < 1)
+    nb = 16 / waves;
   return nb;
 }
 
@@ -1460,7 +1465,9 @@ hipError_t launch_iteration(const IterArgs &A, hipStream_t s, hipEvent_t *ev) {
   }
   GS_LAUNCH(KS_SCAN_EXPAND, k_scan_expand, dim3(1), W1);
   if (A.has_tested) GS_LAUNCH(KS_TILE_OFFSETS, k_tile_offsets, G, B);
-  GS_LAUNCH(KS_EXPAND_WRITE, k_expand_write, dim3((unsigned)A.wgrid), B);
+  if (A.wwaves == 2) GS_LAUNCH(KS_EXPAND_WRITE, k_expand_write<2>, dim3((unsigned)A.wgrid), dim3(128));
+  else if (A.wwaves == 8) GS_LAUNCH(KS_EXPAND_WRITE, k_expand_write<8>, dim3((unsigned)A.wgrid), dim3(512));
+  else GS_LAUNCH(KS_EXPAND_WRITE, k_expand_write<4>, dim3((unsigned)A.wgrid), B);
 #undef GS_LAUNCH
   return hipGetLastError();
 }

@@ -22,6 +22,7 @@ struct IterArgs {
                            // pass variant for bitmap filters only)
   int32_t grid;            // workgroups of the fixed-grid kernels
   int32_t wgrid;           // workgroups of the write pass (as many as are resident at once)
+  int32_t wwaves;          // waves per workgroup of the write pass: 2, 4 or 8
   const DStep *steps;
   const uint64_t *const *filt;
   const DCheck *checks;
@@ -54,8 +55,8 @@ struct IterArgs {
 };
 enum RunFlag { RF_SCRATCH = 0, RF_WRITE = 1, RF_N = 2 };
 
-// Workgroups of the write pass one compute unit holds at once.
-int expand_write_blocks_per_cu();
+// Workgroups of the write pass, with `waves` waves each (2, 4 or 8), that one compute unit holds at once.
+int expand_write_blocks_per_cu(int waves);
 
 // ev: null, or 2 * KS_N events recorded around each launch (slot k: ev[2k], ev[2k+1]).
 hipError_t launch_iteration(const IterArgs &A, hipStream_t s, hipEvent_t *ev = nullptr);

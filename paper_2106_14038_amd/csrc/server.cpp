@@ -393,7 +393,7 @@ void loop(ServerImpl &S) {
     if (e == hipSuccess) e = hipMemcpyAsync(E.d_arenas, ar, sizeof(ar), hipMemcpyHostToDevice, s);
     IterArgs A{};
     A.g = E.g; A.ent = S.d_ents; A.E = (int32_t)L.ents.size(); A.S = (int32_t)L.seeds.size();
-    A.D = (int32_t)L.doms.size(); A.nclear = (int32_t)L.clears.size(); A.has_list = L.has_list; A.has_tested = L.has_tested; A.has_checks = L.has_checks; A.has_factor = L.has_factor; A.has_exact = L.has_exact; A.grid = E.grid; A.wgrid = E.wgrid;
+    A.D = (int32_t)L.doms.size(); A.nclear = (int32_t)L.clears.size(); A.has_list = L.has_list; A.has_tested = L.has_tested; A.has_checks = L.has_checks; A.has_factor = L.has_factor; A.has_exact = L.has_exact; A.grid = E.grid; A.wgrid = E.wgrid; A.wwaves = E.wwaves;
     A.steps = S.d_steps; A.filt = S.d_filt; A.checks = S.d_checks; A.ints = S.d_ints; A.cconst = S.d_cc;
     A.seeds = S.d_seeds; A.doms = S.d_doms; A.fcount = S.d_fc; A.clear = S.d_clear; A.es = S.d_es; A.it = S.d_it;
     A.lvl_ptr = S.d_lvlp; A.lvl_cptr = S.d_lvlc; A.lvl_n = S.d_lvln; A.qstats = S.d_qs;

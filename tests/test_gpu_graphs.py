@@ -78,13 +78,14 @@ def test_autotune_keeps_results_and_is_recorded(tmp_path):
         gs.gs_load_triples(eng, n, P, trip)
         before = batch_results(eng, qs)
         tr = gs.gs_autotune(eng, qs)
-        assert tr.n_tried == 15 and tr.best_ms <= tr.default_ms and tr.grid_blocks > 0
+        assert tr.n_tried == 17 and tr.best_ms <= tr.default_ms and tr.grid_blocks > 0
+        assert tr.write_block in (128, 256, 512)
         after = batch_results(eng, qs)
         for (c0, r0), (c1, r1) in zip(before, after):
             assert c0 == c1 and np.array_equal(r0, r1)
         line = open(cache).read().split()
         assert [int(x) for x in line[:4]] == [n, gs.gs_graph_info(eng)[2], P, tr.grid_blocks]
-        assert abs(float(line[4]) - tr.push_pull_theta) < 1e-6
+        assert abs(float(line[4]) - tr.push_pull_theta) < 1e-6 and int(line[5]) == tr.write_block
     finally:
         gs.gs_engine_destroy(eng)
     eng = gs.gs_engine_create(gs.options(tree_bytes=1 << 30, scratch_bytes=1 << 28, autotune_cache=cache.encode()))
@@ -95,3 +96,25 @@ def test_autotune_keeps_results_and_is_recorded(tmp_path):
             assert c0 == c1 and np.array_equal(r0, r1)
     finally:
         gs.gs_engine_destroy(eng)
+    # every write-pass workgroup size, applied from a recorded setting, gives the same rows
+    for wb in (128, 256, 512):
+        with open(cache, "w") as f:
+            f.write(f"{line[0]} {line[1]} {line[2]} {line[3]} {line[4]} {wb}\n")
+        eng = gs.gs_engine_create(gs.options(tree_bytes=1 << 30, scratch_bytes=1 << 28, autotune_cache=cache.encode()))
+        try:
+            gs.gs_load_triples(eng, n, P, trip)
+            got = batch_results(eng, qs)
+            for (c0, r0), (c1, r1) in zip(before, got):
+                assert c0 == c1 and np.array_equal(r0, r1), wb
+        finally:
+            gs.gs_engine_destroy(eng)
+        eng = gs.gs_engine_create(gs.options(tree_bytes=1 << 30, scratch_bytes=1 << 28, write_block=wb))
+        try:
+            gs.gs_load_triples(eng, n, P, trip)
+            got = batch_results(eng, qs)
+            for (c0, r0), (c1, r1) in zip(before, got):
+                assert c0 == c1 and np.array_equal(r0, r1), wb
+        finally:
+            gs.gs_engine_destroy(eng)
+    with pytest.raises(gs.GsError):
+        gs.gs_engine_create(gs.options(write_block=100))
